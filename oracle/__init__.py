@@ -1,0 +1,359 @@
+"""CPU oracle for two-party arithmetic secret sharing over Z/2^64.
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It wraps ``liboracle.so`` (built
+from ``oracle.c`` with gcc) through ctypes and takes/returns numpy arrays.
+Ring elements are ``numpy.uint64``; signed fixed-point values ``numpy.int64``.
+
+The C file holds every step of the method (section 5 and App. C.1.1 of the
+paper); ``bigint`` holds an arbitrary-precision twin for tiny shapes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+i8p = ctypes.POINTER(ctypes.c_int8)
+dblp = ctypes.POINTER(ctypes.c_double)
+U64 = ctypes.c_uint64
+I64 = ctypes.c_int64
+SZ = ctypes.c_size_t
+INT = ctypes.c_int
+
+SLOT_SHARE, SLOT_A0, SLOT_A1, SLOT_B0, SLOT_B1, SLOT_C0 = range(6)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        sig = {
+            "orc_num_threads": (INT, []),
+            "orc_sm64_mix": (U64, [U64]),
+            "orc_sm64_at": (U64, [U64, U64]),
+            "orc_prg": (U64, [U64, U64, U64, U64]),
+            "orc_prg_fill": (None, [U64, U64, U64, SZ, u64p]),
+            "orc_encode": (SZ, [dblp, SZ, INT, i64p]),
+            "orc_decode": (None, [u64p, SZ, INT, dblp]),
+            "orc_share": (None, [u64p, SZ, INT, U64, U64, u64p, u64p]),
+            "orc_reveal": (None, [u64p, u64p, SZ, u64p]),
+            "orc_add": (None, [u64p, u64p, SZ, u64p]),
+            "orc_truncate": (None, [u64p, SZ, INT]),
+            "orc_ring_gemm": (None, [I64, I64, I64, u64p, u64p, u64p]),
+            "orc_ring_gemm_at": (None, [I64, I64, I64, u64p, u64p, I64, i64p, i64p, u64p]),
+            "orc_conv1d_lout": (I64, [I64, I64, I64]),
+            "orc_conv1d": (None, [I64] * 6 + [u64p, u64p, u64p]),
+            "orc_conv1d_at": (None, [I64] * 6 + [u64p, u64p, I64, i64p, i64p, i64p, u64p]),
+            "orc_dealer_mul": (None, [U64, U64, SZ] + [u64p] * 6),
+            "orc_dealer_square": (None, [U64, U64, SZ] + [u64p] * 4),
+            "orc_dealer_matmul": (None, [U64, U64, I64, I64, I64] + [u64p] * 6),
+            "orc_dealer_matmul_c_at": (None, [U64, U64, I64, I64, I64] + [u64p] * 4
+                                       + [I64, i64p, i64p, u64p, u64p]),
+            "orc_dealer_conv1d": (None, [U64, U64] + [I64] * 6 + [u64p] * 6),
+            "orc_beaver_mul": (None, [SZ] + [u64p] * 10 + [INT, u64p, u64p]),
+            "orc_beaver_square": (None, [SZ] + [u64p] * 6 + [INT, u64p, u64p]),
+            "orc_beaver_matmul": (None, [I64, I64, I64] + [u64p] * 10 + [INT, u64p, u64p]),
+            "orc_beaver_matmul_at": (None, [I64, I64, I64] + [u64p] * 10
+                                     + [INT, I64, i64p, i64p, u64p, u64p]),
+            "orc_beaver_conv1d": (None, [I64] * 6 + [u64p] * 10 + [INT, u64p, u64p]),
+            "orc_limbs": (None, [u64p, SZ, i8p]),
+            "orc_limb_gemm": (INT, [I64, I64, I64, u64p, u64p, I64, u64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _u(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(u64p)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(i64p)
+
+
+def _out(shape):
+    a = np.zeros(shape, dtype=np.uint64)
+    return a, a.ctypes.data_as(u64p)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+# ----------------------------------------------------------------- PRG
+def sm64_mix(z):
+    return int(lib().orc_sm64_mix(int(z) & (2**64 - 1)))
+
+
+def sm64_at(s, i):
+    return int(lib().orc_sm64_at(int(s) & (2**64 - 1), int(i)))
+
+
+def prg(seed, tag, slot, idx):
+    return int(lib().orc_prg(seed, tag, slot, idx))
+
+
+def prg_fill(seed, tag, slot, n):
+    out, p = _out(n)
+    lib().orc_prg_fill(seed, tag, slot, n, p)
+    return out
+
+
+# ----------------------------------------------------------------- fixed point
+def encode(x, frac_bits=16):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(x.shape, dtype=np.int64)
+    bad = lib().orc_encode(x.ctypes.data_as(dblp), x.size, frac_bits, out.ctypes.data_as(i64p))
+    if bad:
+        raise OverflowError(f"element {bad - 1} does not fit the int64 fixed-point range")
+    return out
+
+
+def decode(v, frac_bits=16):
+    v, p = _u(np.asarray(v).view(np.uint64) if np.asarray(v).dtype == np.int64 else v)
+    out = np.zeros(v.shape, dtype=np.float64)
+    lib().orc_decode(p, v.size, frac_bits, out.ctypes.data_as(dblp))
+    return out
+
+
+# ----------------------------------------------------------------- sharing
+def as_ring(x):
+    """int64 fixed-point values -> their ring elements (same bits)."""
+    x = np.ascontiguousarray(x)
+    return x.view(np.uint64) if x.dtype == np.int64 else x.astype(np.uint64)
+
+
+def share(x, src, seed, tag):
+    x, px = _u(as_ring(x))
+    s0, p0 = _out(x.shape)
+    s1, p1 = _out(x.shape)
+    lib().orc_share(px, x.size, src, seed, tag, p0, p1)
+    return s0, s1
+
+
+def reveal(s0, s1):
+    s0, p0 = _u(s0)
+    s1, p1 = _u(s1)
+    out, po = _out(s0.shape)
+    lib().orc_reveal(p0, p1, s0.size, po)
+    return out
+
+
+def add(x, y):
+    x, px = _u(x)
+    y, py = _u(y)
+    out, po = _out(x.shape)
+    lib().orc_add(px, py, x.size, po)
+    return out
+
+
+def truncate(s, bits):
+    s = np.array(s, dtype=np.uint64, copy=True)
+    lib().orc_truncate(s.ctypes.data_as(u64p), s.size, bits)
+    return s
+
+
+# ----------------------------------------------------------------- products
+def ring_gemm(A, B):
+    A, pa = _u(A)
+    B, pb = _u(B)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    C, pc = _out((M, N))
+    lib().orc_ring_gemm(M, N, K, pa, pb, pc)
+    return C
+
+
+def ring_gemm_at(A, B, rows, cols):
+    A, pa = _u(A)
+    B, pb = _u(B)
+    M, K = A.shape
+    N = B.shape[1]
+    rows, pr = _i(rows)
+    cols, pcl = _i(cols)
+    out, po = _out(rows.size)
+    lib().orc_ring_gemm_at(M, N, K, pa, pb, rows.size, pr, pcl, po)
+    return out
+
+
+def conv1d_lout(L, ksz, stride):
+    return int(lib().orc_conv1d_lout(L, ksz, stride))
+
+
+def conv1d(x, w, stride):
+    x, px = _u(x)
+    w, pw = _u(w)
+    Bt, Cin, L = x.shape
+    Cout, Cin2, ksz = w.shape
+    assert Cin == Cin2
+    Lout = conv1d_lout(L, ksz, stride)
+    y, py = _out((Bt, Cout, Lout))
+    lib().orc_conv1d(Bt, Cin, L, Cout, ksz, stride, px, pw, py)
+    return y
+
+
+def conv1d_at(x, w, stride, bs, os_, ls):
+    x, px = _u(x)
+    w, pw = _u(w)
+    Bt, Cin, L = x.shape
+    Cout, _, ksz = w.shape
+    bs, pb = _i(bs)
+    os_, po_ = _i(os_)
+    ls, pl = _i(ls)
+    out, po = _out(bs.size)
+    lib().orc_conv1d_at(Bt, Cin, L, Cout, ksz, stride, px, pw, bs.size, pb, po_, pl, po)
+    return out
+
+
+# ----------------------------------------------------------------- dealer
+class Triple:
+    """Shares of a Beaver triple (a, b, c): a[p], b[p], c[p] for p in {0, 1}.
+    For a square pair c is None and b = a^2."""
+
+    def __init__(self, a, b, c=None):
+        self.a, self.b, self.c = a, b, c
+
+
+def dealer_mul(dseed, tag, n):
+    bufs = [_out(n) for _ in range(6)]
+    lib().orc_dealer_mul(dseed, tag, n, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
+
+
+def dealer_square(dseed, tag, n):
+    bufs = [_out(n) for _ in range(4)]
+    lib().orc_dealer_square(dseed, tag, n, *[p for _, p in bufs])
+    a0, a1, b0, b1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1))
+
+
+def dealer_matmul(dseed, tag, M, N, K):
+    shapes = [(M, K), (M, K), (K, N), (K, N), (M, N), (M, N)]
+    bufs = [_out(s) for s in shapes]
+    lib().orc_dealer_matmul(dseed, tag, M, N, K, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
+
+
+def dealer_matmul_ab(dseed, tag, M, N, K):
+    """a_p and b_p of a matrix triple (PRG fills only, no product)."""
+    a0 = prg_fill(dseed, tag, SLOT_A0, M * K).reshape(M, K)
+    a1 = prg_fill(dseed, tag, SLOT_A1, M * K).reshape(M, K)
+    b0 = prg_fill(dseed, tag, SLOT_B0, K * N).reshape(K, N)
+    b1 = prg_fill(dseed, tag, SLOT_B1, K * N).reshape(K, N)
+    return (a0, a1), (b0, b1)
+
+
+def dealer_matmul_c_at(dseed, tag, M, N, K, a, b, rows, cols):
+    (a0, pa0), (a1, pa1) = _u(a[0]), _u(a[1])
+    (b0, pb0), (b1, pb1) = _u(b[0]), _u(b[1])
+    rows, pr = _i(rows)
+    cols, pcl = _i(cols)
+    c0, pc0 = _out(rows.size)
+    c1, pc1 = _out(rows.size)
+    lib().orc_dealer_matmul_c_at(dseed, tag, M, N, K, pa0, pa1, pb0, pb1, rows.size, pr, pcl,
+                                 pc0, pc1)
+    return c0, c1
+
+
+def dealer_conv1d(dseed, tag, Bt, Cin, L, Cout, ksz, stride):
+    Lout = conv1d_lout(L, ksz, stride)
+    shapes = [(Bt, Cin, L)] * 2 + [(Cout, Cin, ksz)] * 2 + [(Bt, Cout, Lout)] * 2
+    bufs = [_out(s) for s in shapes]
+    lib().orc_dealer_conv1d(dseed, tag, Bt, Cin, L, Cout, ksz, stride, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
+
+
+# ----------------------------------------------------------------- Beaver
+def beaver_mul(x, y, t, trunc_bits):
+    n = x[0].size
+    args = [_u(v) for v in (x[0], x[1], y[0], y[1], t.a[0], t.a[1], t.b[0], t.b[1], t.c[0],
+                            t.c[1])]
+    z0, p0 = _out(x[0].shape)
+    z1, p1 = _out(x[0].shape)
+    lib().orc_beaver_mul(n, *[p for _, p in args], trunc_bits, p0, p1)
+    return z0, z1
+
+
+def beaver_square(x, t, trunc_bits):
+    n = x[0].size
+    args = [_u(v) for v in (x[0], x[1], t.a[0], t.a[1], t.b[0], t.b[1])]
+    z0, p0 = _out(x[0].shape)
+    z1, p1 = _out(x[0].shape)
+    lib().orc_beaver_square(n, *[p for _, p in args], trunc_bits, p0, p1)
+    return z0, z1
+
+
+def beaver_matmul(x, y, t, trunc_bits):
+    M, K = x[0].shape
+    N = y[0].shape[1]
+    args = [_u(v) for v in (x[0], x[1], y[0], y[1], t.a[0], t.a[1], t.b[0], t.b[1], t.c[0],
+                            t.c[1])]
+    z0, p0 = _out((M, N))
+    z1, p1 = _out((M, N))
+    lib().orc_beaver_matmul(M, N, K, *[p for _, p in args], trunc_bits, p0, p1)
+    return z0, z1
+
+
+def beaver_matmul_at(x, y, a, b, c_at, trunc_bits, rows, cols):
+    M, K = x[0].shape
+    N = y[0].shape[1]
+    args = [_u(v) for v in (x[0], x[1], y[0], y[1], a[0], a[1], b[0], b[1], c_at[0], c_at[1])]
+    rows, pr = _i(rows)
+    cols, pcl = _i(cols)
+    z0, p0 = _out(rows.size)
+    z1, p1 = _out(rows.size)
+    lib().orc_beaver_matmul_at(M, N, K, *[p for _, p in args], trunc_bits, rows.size, pr, pcl,
+                               p0, p1)
+    return z0, z1
+
+
+def beaver_conv1d(x, w, t, stride, trunc_bits):
+    Bt, Cin, L = x[0].shape
+    Cout, _, ksz = w[0].shape
+    Lout = conv1d_lout(L, ksz, stride)
+    args = [_u(v) for v in (x[0], x[1], w[0], w[1], t.a[0], t.a[1], t.b[0], t.b[1], t.c[0],
+                            t.c[1])]
+    z0, p0 = _out((Bt, Cout, Lout))
+    z1, p1 = _out((Bt, Cout, Lout))
+    lib().orc_beaver_conv1d(Bt, Cin, L, Cout, ksz, stride, *[p for _, p in args], trunc_bits,
+                            p0, p1)
+    return z0, z1
+
+
+# ----------------------------------------------------------------- limbs (test helpers)
+def limbs(v):
+    v, pv = _u(v)
+    d = np.zeros(v.shape + (8,), dtype=np.int8)
+    lib().orc_limbs(pv, v.size, d.ctypes.data_as(i8p))
+    return d
+
+
+def limb_gemm(A, B, kchunk):
+    A, pa = _u(A)
+    B, pb = _u(B)
+    M, K = A.shape
+    N = B.shape[1]
+    C, pc = _out((M, N))
+    rc = lib().orc_limb_gemm(M, N, K, pa, pb, kchunk, pc)
+    if rc != 0:
+        raise OverflowError("an int32 chunk sum overflowed")
+    return C

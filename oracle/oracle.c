@@ -1,0 +1,482 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for two-party
+ * arithmetic secret sharing over the ring Z/2^64 (CrypTen, Knott et al.,
+ * NeurIPS 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path (the
+ * HIP library) shares no code, header, table or helper with this file and must
+ * never call it.
+ *
+ * Every ring element is a uint64_t; C unsigned arithmetic wraps modulo 2^64,
+ * which is exactly the ring of the paper (section 5.1, App. C.1.1: Q = 2^64).
+ * The signed view of an element v is the two's-complement int64 with the same
+ * bits.  Loops are the textbook definitions, with no blocking or fusion.  The
+ * only liberty taken is OpenMP over independent output rows in the GEMM and
+ * convolution loops; each output element is still the plain sum over k taken
+ * in increasing k.
+ *
+ * Parity status: every function here is pinned by the CPU test-suite against
+ * facts fixed outside this file (published PRG outputs, the paper's worked
+ * example, Python arbitrary-precision products, numpy's uint64 matmul, the
+ * truncation error law and closed forms).  See the test files for the pins.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef uint64_t u64;
+typedef int64_t i64;
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based PRG.                                                        */
+/*                                                                           */
+/* The paper fixes no generator; it asks only that the parties draw          */
+/* pseudorandom zero-shares from synchronised seeds (section 5.1) and that   */
+/* the trusted third party draws uniform triples (section 5.2).  We use the  */
+/* SplitMix64 generator (Steele, Lea and Flood, "Fast splittable             */
+/* pseudorandom number generators", OOPSLA 2014): a stream with state s      */
+/* returns, as its i-th output (i = 0, 1, ...), mix(s + (i+1)*GAMMA).         */
+/* Domains are nested streams:                                               */
+/*   T = output number `tag`  of the stream with state `seed`                */
+/*   S = output number `slot` of the stream with state T                     */
+/*   G(seed, tag, slot, idx) = output number `idx` of the stream with state S */
+/* ------------------------------------------------------------------------ */
+#define SM_GAMMA 0x9e3779b97f4a7c15ULL
+
+u64 orc_sm64_mix(u64 z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+/* i-th output (0-based) of the SplitMix64 stream whose state starts at s */
+u64 orc_sm64_at(u64 s, u64 i) { return orc_sm64_mix(s + (i + 1) * SM_GAMMA); }
+
+u64 orc_prg(u64 seed, u64 tag, u64 slot, u64 idx) {
+  u64 t = orc_sm64_at(seed, tag);
+  u64 s = orc_sm64_at(t, slot);
+  return orc_sm64_at(s, idx);
+}
+
+void orc_prg_fill(u64 seed, u64 tag, u64 slot, size_t n, u64 *out) {
+  for (size_t i = 0; i < n; ++i) out[i] = orc_prg(seed, tag, slot, (u64)i);
+}
+
+/* PRG slots (domains inside one tag). */
+enum { SLOT_SHARE = 0, SLOT_A0 = 1, SLOT_A1 = 2, SLOT_B0 = 3, SLOT_B1 = 4, SLOT_C0 = 5 };
+
+/* ------------------------------------------------------------------------ */
+/* Fixed-point encoding (section 5.1, App. C.1.1): x = round(B * x_R) with    */
+/* B = 2^L; decoding is x / B.  Rounding is to nearest with ties to even      */
+/* (C rint() in the default rounding mode).  Values whose encoding does not  */
+/* fit a signed 64-bit integer are rejected: returns the index+1 of the      */
+/* first offending element, 0 on success.                                    */
+/* ------------------------------------------------------------------------ */
+size_t orc_encode(const double *x, size_t n, int frac_bits, i64 *out) {
+  const double scale = ldexp(1.0, frac_bits);
+  for (size_t i = 0; i < n; ++i) {
+    double r = rint(x[i] * scale);
+    if (!(r >= -9223372036854775808.0 && r < 9223372036854775808.0)) return i + 1;
+    out[i] = (i64)r;
+  }
+  return 0;
+}
+
+void orc_decode(const u64 *v, size_t n, int frac_bits, double *out) {
+  const double scale = ldexp(1.0, frac_bits);
+  for (size_t i = 0; i < n; ++i) out[i] = (double)(i64)v[i] / scale;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sharing and reveal (section 5.1).                                          */
+/* Two parties: the zero-share is (-m, m) with m = G(seed, tag, SHARE, i);    */
+/* the source party adds its value, so s_src = x - m and s_other = m.         */
+/* ------------------------------------------------------------------------ */
+void orc_share(const u64 *x, size_t n, int src, u64 seed, u64 tag, u64 *s0, u64 *s1) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 m = orc_prg(seed, tag, SLOT_SHARE, (u64)i);
+    u64 zs_src = (u64)0 - m; /* the two zero-share entries sum to 0 mod Q */
+    u64 zs_other = m;
+    if (src == 0) {
+      s0[i] = x[i] + zs_src;
+      s1[i] = zs_other;
+    } else {
+      s0[i] = zs_other;
+      s1[i] = x[i] + zs_src;
+    }
+  }
+}
+
+/* x = sum_p [x]_p mod Q */
+void orc_reveal(const u64 *s0, const u64 *s1, size_t n, u64 *out) {
+  for (size_t i = 0; i < n; ++i) out[i] = s0[i] + s1[i];
+}
+
+/* Private addition (App. C.1.1, Addition): each party adds its own shares. */
+void orc_add(const u64 *x, const u64 *y, size_t n, u64 *out) {
+  for (size_t i = 0; i < n; ++i) out[i] = x[i] + y[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Truncation (App. C.1.1, Truncation; Table 1: zero rounds for two parties).  */
+/* Each party divides its own share, read as a signed integer, by 2^bits,    */
+/* rounding toward minus infinity.  Written as an explicit floor division.   */
+/* ------------------------------------------------------------------------ */
+static i64 floor_div_pow2(i64 v, int bits) {
+  if (bits == 0) return v;
+  const i64 d = (i64)1 << bits;
+  i64 q = v / d; /* C division truncates toward zero */
+  i64 r = v % d;
+  if (r != 0 && v < 0) q -= 1;
+  return q;
+}
+
+void orc_truncate(u64 *s, size_t n, int bits) {
+  for (size_t i = 0; i < n; ++i) s[i] = (u64)floor_div_pow2((i64)s[i], bits);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Plain ring products.                                                      */
+/* ------------------------------------------------------------------------ */
+/* C[i][j] = sum_k A[i][k] * B[k][j] mod 2^64; A is MxK, B is KxN, row-major. */
+void orc_ring_gemm(i64 M, i64 N, i64 K, const u64 *A, const u64 *B, u64 *C) {
+#pragma omp parallel for schedule(static)
+  for (i64 i = 0; i < M; ++i) {
+    u64 *c = C + i * N;
+    for (i64 j = 0; j < N; ++j) c[j] = 0;
+    for (i64 k = 0; k < K; ++k) {
+      const u64 a = A[i * K + k];
+      const u64 *b = B + k * N;
+      for (i64 j = 0; j < N; ++j) c[j] += a * b[j];
+    }
+  }
+}
+
+/* The same definition evaluated only at the listed (row, col) positions. */
+void orc_ring_gemm_at(i64 M, i64 N, i64 K, const u64 *A, const u64 *B, i64 npts,
+                      const i64 *rows, const i64 *cols, u64 *out) {
+  (void)M;
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    u64 acc = 0;
+    for (i64 k = 0; k < K; ++k) acc += A[rows[t] * K + k] * B[k * N + cols[t]];
+    out[t] = acc;
+  }
+}
+
+/* 1-D convolution, valid padding:
+ *   y[b][o][l] = sum_{c,j} w[o][c][j] * x[b][c][l*stride + j]
+ * x is [Bt][Cin][L], w is [Cout][Cin][ksz], y is [Bt][Cout][Lout] with
+ * Lout = (L - ksz)/stride + 1. */
+i64 orc_conv1d_lout(i64 L, i64 ksz, i64 stride) { return L < ksz ? 0 : (L - ksz) / stride + 1; }
+
+void orc_conv1d(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, const u64 *x,
+                const u64 *w, u64 *y) {
+  const i64 Lout = orc_conv1d_lout(L, ksz, stride);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (i64 b = 0; b < Bt; ++b)
+    for (i64 o = 0; o < Cout; ++o)
+      for (i64 l = 0; l < Lout; ++l) {
+        u64 acc = 0;
+        for (i64 c = 0; c < Cin; ++c)
+          for (i64 j = 0; j < ksz; ++j)
+            acc += w[(o * Cin + c) * ksz + j] * x[(b * Cin + c) * L + l * stride + j];
+        y[(b * Cout + o) * Lout + l] = acc;
+      }
+}
+
+/* The same definition at listed output positions (b, o, l). */
+void orc_conv1d_at(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, const u64 *x,
+                   const u64 *w, i64 npts, const i64 *bs, const i64 *os, const i64 *ls,
+                   u64 *out) {
+  (void)Bt;
+  (void)Cout;
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    u64 acc = 0;
+    for (i64 c = 0; c < Cin; ++c)
+      for (i64 j = 0; j < ksz; ++j)
+        acc += w[(os[t] * Cin + c) * ksz + j] * x[(bs[t] * Cin + c) * L + ls[t] * stride + j];
+    out[t] = acc;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trusted third party (section 4 and App. C.1.1, Multiplication): draws      */
+/* a and b uniformly, sets c = f(a, b), and hands each party additive shares. */
+/*   a_p = G(dseed, tag, A_p, i),  b_p = G(dseed, tag, B_p, i),               */
+/*   c_0 = G(dseed, tag, C_0, i),  c_1 = c - c_0.                             */
+/* For the square pair (App. C.1.1, Square) b = a^2, so b_1 = a^2 - b_0.     */
+/* ------------------------------------------------------------------------ */
+void orc_dealer_mul(u64 dseed, u64 tag, size_t n, u64 *a0, u64 *a1, u64 *b0, u64 *b1,
+                    u64 *c0, u64 *c1) {
+  for (size_t i = 0; i < n; ++i) {
+    a0[i] = orc_prg(dseed, tag, SLOT_A0, i);
+    a1[i] = orc_prg(dseed, tag, SLOT_A1, i);
+    b0[i] = orc_prg(dseed, tag, SLOT_B0, i);
+    b1[i] = orc_prg(dseed, tag, SLOT_B1, i);
+    u64 a = a0[i] + a1[i], b = b0[i] + b1[i];
+    u64 c = a * b;
+    c0[i] = orc_prg(dseed, tag, SLOT_C0, i);
+    c1[i] = c - c0[i];
+  }
+}
+
+void orc_dealer_square(u64 dseed, u64 tag, size_t n, u64 *a0, u64 *a1, u64 *b0, u64 *b1) {
+  for (size_t i = 0; i < n; ++i) {
+    a0[i] = orc_prg(dseed, tag, SLOT_A0, i);
+    a1[i] = orc_prg(dseed, tag, SLOT_A1, i);
+    u64 a = a0[i] + a1[i];
+    b0[i] = orc_prg(dseed, tag, SLOT_B0, i);
+    b1[i] = a * a - b0[i];
+  }
+}
+
+/* Matrix triple: a is MxK, b is KxN, c = a @ b is MxN. */
+void orc_dealer_matmul(u64 dseed, u64 tag, i64 M, i64 N, i64 K, u64 *a0, u64 *a1, u64 *b0,
+                       u64 *b1, u64 *c0, u64 *c1) {
+  orc_prg_fill(dseed, tag, SLOT_A0, (size_t)(M * K), a0);
+  orc_prg_fill(dseed, tag, SLOT_A1, (size_t)(M * K), a1);
+  orc_prg_fill(dseed, tag, SLOT_B0, (size_t)(K * N), b0);
+  orc_prg_fill(dseed, tag, SLOT_B1, (size_t)(K * N), b1);
+  u64 *a = (u64 *)malloc(sizeof(u64) * (size_t)(M * K));
+  u64 *b = (u64 *)malloc(sizeof(u64) * (size_t)(K * N));
+  u64 *c = (u64 *)malloc(sizeof(u64) * (size_t)(M * N));
+  orc_add(a0, a1, (size_t)(M * K), a);
+  orc_add(b0, b1, (size_t)(K * N), b);
+  orc_ring_gemm(M, N, K, a, b, c);
+  orc_prg_fill(dseed, tag, SLOT_C0, (size_t)(M * N), c0);
+  for (i64 i = 0; i < M * N; ++i) c1[i] = c[i] - c0[i];
+  free(a);
+  free(b);
+  free(c);
+}
+
+/* Matrix triple evaluated at listed output positions only: fills c0, c1 at
+ * (rows[t], cols[t]).  a_p and b_p are the full PRG fills (cheap). */
+void orc_dealer_matmul_c_at(u64 dseed, u64 tag, i64 M, i64 N, i64 K, const u64 *a0,
+                            const u64 *a1, const u64 *b0, const u64 *b1, i64 npts,
+                            const i64 *rows, const i64 *cols, u64 *c0, u64 *c1) {
+  (void)M;
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    u64 c = 0;
+    for (i64 k = 0; k < K; ++k) {
+      u64 a = a0[rows[t] * K + k] + a1[rows[t] * K + k];
+      u64 b = b0[k * N + cols[t]] + b1[k * N + cols[t]];
+      c += a * b;
+    }
+    c0[t] = orc_prg(dseed, tag, SLOT_C0, (u64)(rows[t] * N + cols[t]));
+    c1[t] = c - c0[t];
+  }
+}
+
+/* Convolution triple: a has activation shape [Bt][Cin][L], b has weight
+ * shape [Cout][Cin][ksz], c = conv1d(a, b) has shape [Bt][Cout][Lout]. */
+void orc_dealer_conv1d(u64 dseed, u64 tag, i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz,
+                       i64 stride, u64 *a0, u64 *a1, u64 *b0, u64 *b1, u64 *c0, u64 *c1) {
+  const i64 nx = Bt * Cin * L, nw = Cout * Cin * ksz;
+  const i64 ny = Bt * Cout * orc_conv1d_lout(L, ksz, stride);
+  orc_prg_fill(dseed, tag, SLOT_A0, (size_t)nx, a0);
+  orc_prg_fill(dseed, tag, SLOT_A1, (size_t)nx, a1);
+  orc_prg_fill(dseed, tag, SLOT_B0, (size_t)nw, b0);
+  orc_prg_fill(dseed, tag, SLOT_B1, (size_t)nw, b1);
+  u64 *a = (u64 *)malloc(sizeof(u64) * (size_t)nx);
+  u64 *b = (u64 *)malloc(sizeof(u64) * (size_t)nw);
+  u64 *c = (u64 *)malloc(sizeof(u64) * (size_t)(ny > 0 ? ny : 1));
+  orc_add(a0, a1, (size_t)nx, a);
+  orc_add(b0, b1, (size_t)nw, b);
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, a, b, c);
+  orc_prg_fill(dseed, tag, SLOT_C0, (size_t)ny, c0);
+  for (i64 i = 0; i < ny; ++i) c1[i] = c[i] - c0[i];
+  free(a);
+  free(b);
+  free(c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Beaver multiplication (section 5.2 and App. C.1.1, Multiplication):        */
+/*   [eps] = [x] - [a],  [delta] = [y] - [b]    (each party, locally)          */
+/*   eps, delta revealed                         (one round)                   */
+/*   [z]_p = [c]_p + eps [b]_p + [a]_p delta  (+ eps delta for party 0 only)  */
+/* then each party truncates its share by 2^trunc_bits (0 = no truncation).   */
+/* ------------------------------------------------------------------------ */
+void orc_beaver_mul(size_t n, const u64 *x0, const u64 *x1, const u64 *y0, const u64 *y1,
+                    const u64 *a0, const u64 *a1, const u64 *b0, const u64 *b1, const u64 *c0,
+                    const u64 *c1, int trunc_bits, u64 *z0, u64 *z1) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 e0 = x0[i] - a0[i], e1 = x1[i] - a1[i]; /* [eps]_p   */
+    u64 d0 = y0[i] - b0[i], d1 = y1[i] - b1[i]; /* [delta]_p */
+    u64 eps = e0 + e1, delta = d0 + d1;         /* open      */
+    z0[i] = c0[i] + eps * b0[i] + a0[i] * delta + eps * delta;
+    z1[i] = c1[i] + eps * b1[i] + a1[i] * delta;
+  }
+  orc_truncate(z0, n, trunc_bits);
+  orc_truncate(z1, n, trunc_bits);
+}
+
+/* Square with a Beaver pair (a, b = a^2) (App. C.1.1, Square):
+ *   [eps] = [x] - [a];  eps revealed;  [x^2] = [b] + 2 eps [a] + eps^2
+ * with the public eps^2 added by party 0 only. */
+void orc_beaver_square(size_t n, const u64 *x0, const u64 *x1, const u64 *a0, const u64 *a1,
+                       const u64 *b0, const u64 *b1, int trunc_bits, u64 *z0, u64 *z1) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 eps = (x0[i] - a0[i]) + (x1[i] - a1[i]);
+    z0[i] = b0[i] + 2 * eps * a0[i] + eps * eps;
+    z1[i] = b1[i] + 2 * eps * a1[i];
+  }
+  orc_truncate(z0, n, trunc_bits);
+  orc_truncate(z1, n, trunc_bits);
+}
+
+/* Beaver matrix product (App. C.1.1: the same identity for any bilinear f).
+ * Keeps the factor order of the matrix product:
+ *   [z]_p = [c]_p + eps @ [b]_p + [a]_p @ delta (+ eps @ delta for party 0).
+ * x_p: MxK, y_p: KxN, a_p: MxK, b_p: KxN, c_p and z_p: MxN. */
+void orc_beaver_matmul(i64 M, i64 N, i64 K, const u64 *x0, const u64 *x1, const u64 *y0,
+                       const u64 *y1, const u64 *a0, const u64 *a1, const u64 *b0,
+                       const u64 *b1, const u64 *c0, const u64 *c1, int trunc_bits, u64 *z0,
+                       u64 *z1) {
+  const size_t nA = (size_t)(M * K), nB = (size_t)(K * N), nC = (size_t)(M * N);
+  u64 *eps = (u64 *)malloc(sizeof(u64) * (nA ? nA : 1));
+  u64 *delta = (u64 *)malloc(sizeof(u64) * (nB ? nB : 1));
+  u64 *t = (u64 *)malloc(sizeof(u64) * (nC ? nC : 1));
+  for (size_t i = 0; i < nA; ++i) eps[i] = (x0[i] - a0[i]) + (x1[i] - a1[i]);
+  for (size_t i = 0; i < nB; ++i) delta[i] = (y0[i] - b0[i]) + (y1[i] - b1[i]);
+  /* party 0 */
+  for (size_t i = 0; i < nC; ++i) z0[i] = c0[i];
+  orc_ring_gemm(M, N, K, eps, b0, t);
+  for (size_t i = 0; i < nC; ++i) z0[i] += t[i];
+  orc_ring_gemm(M, N, K, a0, delta, t);
+  for (size_t i = 0; i < nC; ++i) z0[i] += t[i];
+  orc_ring_gemm(M, N, K, eps, delta, t);
+  for (size_t i = 0; i < nC; ++i) z0[i] += t[i];
+  /* party 1 */
+  for (size_t i = 0; i < nC; ++i) z1[i] = c1[i];
+  orc_ring_gemm(M, N, K, eps, b1, t);
+  for (size_t i = 0; i < nC; ++i) z1[i] += t[i];
+  orc_ring_gemm(M, N, K, a1, delta, t);
+  for (size_t i = 0; i < nC; ++i) z1[i] += t[i];
+  orc_truncate(z0, nC, trunc_bits);
+  orc_truncate(z1, nC, trunc_bits);
+  free(eps);
+  free(delta);
+  free(t);
+}
+
+/* The same protocol evaluated at listed output positions.  c0/c1 are the
+ * triple's c shares AT THOSE POSITIONS (length npts). */
+void orc_beaver_matmul_at(i64 M, i64 N, i64 K, const u64 *x0, const u64 *x1, const u64 *y0,
+                          const u64 *y1, const u64 *a0, const u64 *a1, const u64 *b0,
+                          const u64 *b1, const u64 *c0_at, const u64 *c1_at, int trunc_bits,
+                          i64 npts, const i64 *rows, const i64 *cols, u64 *z0, u64 *z1) {
+  (void)M;
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    const i64 i = rows[t], j = cols[t];
+    u64 s_eb0 = 0, s_eb1 = 0, s_ad0 = 0, s_ad1 = 0, s_ed = 0;
+    for (i64 k = 0; k < K; ++k) {
+      u64 eps = (x0[i * K + k] - a0[i * K + k]) + (x1[i * K + k] - a1[i * K + k]);
+      u64 delta = (y0[k * N + j] - b0[k * N + j]) + (y1[k * N + j] - b1[k * N + j]);
+      s_eb0 += eps * b0[k * N + j];
+      s_eb1 += eps * b1[k * N + j];
+      s_ad0 += a0[i * K + k] * delta;
+      s_ad1 += a1[i * K + k] * delta;
+      s_ed += eps * delta;
+    }
+    z0[t] = c0_at[t] + s_eb0 + s_ad0 + s_ed;
+    z1[t] = c1_at[t] + s_eb1 + s_ad1;
+  }
+  orc_truncate(z0, (size_t)npts, trunc_bits);
+  orc_truncate(z1, (size_t)npts, trunc_bits);
+}
+
+/* Beaver convolution: the bilinear f is conv1d(activation, weight).
+ * x_p, a_p: [Bt][Cin][L];  y_p, b_p: [Cout][Cin][ksz];  c_p, z_p: [Bt][Cout][Lout].
+ *   [z]_p = [c]_p + conv(eps, [b]_p) + conv([a]_p, delta) (+ conv(eps, delta), p = 0) */
+void orc_beaver_conv1d(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, const u64 *x0,
+                       const u64 *x1, const u64 *y0, const u64 *y1, const u64 *a0,
+                       const u64 *a1, const u64 *b0, const u64 *b1, const u64 *c0,
+                       const u64 *c1, int trunc_bits, u64 *z0, u64 *z1) {
+  const i64 Lout = orc_conv1d_lout(L, ksz, stride);
+  const size_t nx = (size_t)(Bt * Cin * L), nw = (size_t)(Cout * Cin * ksz);
+  const size_t ny = (size_t)(Bt * Cout * Lout);
+  u64 *eps = (u64 *)malloc(sizeof(u64) * (nx ? nx : 1));
+  u64 *delta = (u64 *)malloc(sizeof(u64) * (nw ? nw : 1));
+  u64 *t = (u64 *)malloc(sizeof(u64) * (ny ? ny : 1));
+  for (size_t i = 0; i < nx; ++i) eps[i] = (x0[i] - a0[i]) + (x1[i] - a1[i]);
+  for (size_t i = 0; i < nw; ++i) delta[i] = (y0[i] - b0[i]) + (y1[i] - b1[i]);
+  for (size_t i = 0; i < ny; ++i) z0[i] = c0[i];
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, eps, b0, t);
+  for (size_t i = 0; i < ny; ++i) z0[i] += t[i];
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, a0, delta, t);
+  for (size_t i = 0; i < ny; ++i) z0[i] += t[i];
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, eps, delta, t);
+  for (size_t i = 0; i < ny; ++i) z0[i] += t[i];
+  for (size_t i = 0; i < ny; ++i) z1[i] = c1[i];
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, eps, b1, t);
+  for (size_t i = 0; i < ny; ++i) z1[i] += t[i];
+  orc_conv1d(Bt, Cin, L, Cout, ksz, stride, a1, delta, t);
+  for (size_t i = 0; i < ny; ++i) z1[i] += t[i];
+  orc_truncate(z0, ny, trunc_bits);
+  orc_truncate(z1, ny, trunc_bits);
+  free(eps);
+  free(delta);
+  free(t);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Signed 8-bit limb decomposition (a test helper for the limb GEMM form;     */
+/* not a step of the protocol).  For v in Z/2^64:                            */
+/*   u = v + 0x8080808080808080 (mod 2^64),  d_i = byte_i(u) - 128,          */
+/* so d_i is in [-128, 127] and sum_i d_i 2^(8i) = v (mod 2^64).              */
+/* ------------------------------------------------------------------------ */
+void orc_limbs(const u64 *v, size_t n, int8_t *d /* n x 8 */) {
+  for (size_t t = 0; t < n; ++t) {
+    u64 u = v[t] + 0x8080808080808080ULL;
+    for (int i = 0; i < 8; ++i) d[t * 8 + i] = (int8_t)((int)((u >> (8 * i)) & 0xff) - 128);
+  }
+}
+
+/* Ring GEMM through limbs: C = sum_{i+j<=7} 2^(8(i+j)) (D_i @ E_j) mod 2^64,
+ * where each D_i @ E_j is an exact integer matrix product accumulated in
+ * int32 over chunks of at most kchunk terms (each chunk's partial sum is then
+ * sign-extended to 64 bits).  Returns -1 if some chunk sum would leave int32. */
+int orc_limb_gemm(i64 M, i64 N, i64 K, const u64 *A, const u64 *B, i64 kchunk, u64 *C) {
+  int8_t *dA = (int8_t *)malloc((size_t)(M * K * 8 > 0 ? M * K * 8 : 1));
+  int8_t *dB = (int8_t *)malloc((size_t)(K * N * 8 > 0 ? K * N * 8 : 1));
+  orc_limbs(A, (size_t)(M * K), dA);
+  orc_limbs(B, (size_t)(K * N), dB);
+  int bad = 0;
+  for (i64 r = 0; r < M; ++r)
+    for (i64 c = 0; c < N; ++c) {
+      u64 acc = 0;
+      for (int i = 0; i < 8; ++i)
+        for (int j = 0; i + j < 8; ++j)
+          for (i64 k0 = 0; k0 < K; k0 += kchunk) {
+            i64 part = 0; /* exact */
+            for (i64 k = k0; k < K && k < k0 + kchunk; ++k)
+              part += (i64)dA[(r * K + k) * 8 + i] * (i64)dB[(k * N + c) * 8 + j];
+            if (part > INT32_MAX || part < INT32_MIN) bad = 1;
+            acc += (u64)(i64)(int32_t)part << (8 * (i + j));
+          }
+      C[r * N + c] = acc;
+    }
+  free(dA);
+  free(dB);
+  return bad ? -1 : 0;
+}
