@@ -138,6 +138,7 @@ void orc_add(const u64 *x, const u64 *y, size_t n, u64 *out) {
 /* ------------------------------------------------------------------------ */
 static i64 floor_div_pow2(i64 v, int bits) {
   if (bits == 0) return v;
+  if (bits == 63) return v < 0 ? -1 : 0; /* 2^63 itself is not an int64 */
   const i64 d = (i64)1 << bits;
   i64 q = v / d; /* C division truncates toward zero */
   i64 r = v % d;

@@ -242,10 +242,12 @@ def test_beaver_matmul_zero_triple_is_plain_gemm():
 
 
 # ------------------------------------------------------------------ truncation
-def test_truncate_floor_division():
-    v = ring([0, 1, 65535, 65536, -1, -65536, -65537, (1 << 63) - 1, -(1 << 63)])
-    got = [bigint.s64(t) for t in pyints(oracle.truncate(v, 16))]
-    assert got == [bigint.s64(x) // 65536 for x in pyints(v)]
+@pytest.mark.parametrize("bits", [1, 15, 16, 17, 32, 62, 63])
+def test_truncate_floor_division(bits):
+    v = np.concatenate([ring([0, 1, 65535, 65536, -1, -65536, -65537, (1 << 63) - 1,
+                              -(1 << 63), 1 << 62, -(1 << 62)]), rand_ring(4, 200)])
+    got = [bigint.s64(t) for t in pyints(oracle.truncate(v, bits))]
+    assert got == [bigint.s64(x) // (1 << bits) for x in pyints(v)]
     assert np.array_equal(oracle.truncate(v, 0), v)
 
 
