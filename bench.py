@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark: secure int64-ring GEMM on one MI355X.
+
+One step is one pass of the whole hot path over one 4096x4096x4096 problem
+with inputs resident in HBM: both operands secret-shared (PRZS), a fresh
+matrix Beaver triple from the dealer, the Beaver matmul (mask, device-local
+open, each party's finish GEMM with fused 2^16 truncation) in the limb (INT8
+matrix core) form, and the reveal.  `value` is plaintext-equivalent ring
+operations 2*M*N*K per step divided by the step time (Tops/s).
+
+Also reported (outside the timed region): the ring GEMM alone in both forms
+and the limb form's speedup, the Beaver element-wise product rate against
+HBM bandwidth, the secure MLP (784-1024-1024-10, batch 128) latency, the
+roofline of the dominant kernel from HIP events around every GEMM launch,
+and the CPU oracle timed on a bounded slice of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("secure int64-ring GEMM Tops/s (limb-MFMA vs plain, bit-exact); Beaver mul elem/s")
+INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 matrix peak, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+M = N = K = 4096
+FRAC = 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="limb8", choices=["limb8", "plain"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(both parties share the one device; see DESIGN.md for how the path shards)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2109_00984_amd as mpc
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    data_seed, party_seed, dealer_seed = workloads.seeds(3)
+    ctx = mpc.Context(device=0, seed=party_seed)
+    dev = torch.device("cuda", 0)
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+    log("bench: generating 4096x4096 uniform uint64 operands")
+    Xh = workloads.uniform_u64(data_seed, (M, K))
+    Yh = workloads.uniform_u64(data_seed + 1, (K, N))
+    X, Y = to_dev(Xh), to_dev(Yh)
+    x = mpc.SharedPair(ctx.empty((M, K)), ctx.empty((M, K)))
+    y = mpc.SharedPair(ctx.empty((K, N)), ctx.empty((K, N)))
+    t = mpc.TripleShares(ctx.empty((M, K)), ctx.empty((M, K)), ctx.empty((K, N)),
+                         ctx.empty((K, N)), ctx.empty((M, N)), ctx.empty((M, N)))
+    z = mpc.SharedPair(ctx.empty((M, N)), ctx.empty((M, N)))
+    r = ctx.empty((M, N))
+    dims = (M, N, K)
+
+    def step():
+        ctx.share(X, 0, 1, out=x)
+        ctx.share(Y, 1, 2, out=y)
+        ctx.dealer_into(mpc.TRIPLE_MATMUL, dealer_seed, 3, dims, t)
+        ctx.beaver_matmul(x, y, t, FRAC, args.form, out=z)
+        ctx.reveal(z, out=r)
+
+    ctx.profile(True)
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    ctx.profile_read()  # clear
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    elapsed = t1 - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = 2.0 * M * N * K * args.steps / elapsed / 1e12
+    log(f"bench: {ms_per_step:.3f} ms/step, {value:.2f} Tops/s")
+
+    # dominant kernel: the ring GEMM launches of the timed region
+    g = prof[args.form]
+    avg_ms = g["total_ms"] / max(1, g["launches"])
+    if args.form == "limb8":
+        per_launch_ops = 72.0 * g["ring_macs"] / max(1, g["launches"])  # 36 int8 MACs per ring MAC
+        achieved = per_launch_ops / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
+                    "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                    "kernel": "k_limb_gemm", "launches": g["launches"],
+                    "avg_launch_ms": round(avg_ms, 4),
+                    "work_per_launch": "72 int8 ops per ring multiply-accumulate (36 limb pairs)"}
+    else:
+        per_launch_ops = 2.0 * g["ring_macs"] / max(1, g["launches"])
+        achieved = per_launch_ops / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": None,
+                    "unit": "Tops/s (ring)", "frac": None, "traffic": None,
+                    "kernel": "k_plain_gemm", "launches": g["launches"],
+                    "avg_launch_ms": round(avg_ms, 4)}
+
+    # sample of the final step's output for the CPU-oracle leg
+    rows_needed = 256
+    z_rows = (z.s0[:rows_needed].cpu().numpy().view(np.uint64),
+              z.s1[:rows_needed].cpu().numpy().view(np.uint64))
+
+    extras = {}
+    if not args.no_extras:
+        extras = secondary(ctx, mpc, torch, workloads, X, Y)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(Xh, Yh, party_seed, dealer_seed, z_rows)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Tops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (uniform uint64 operands, seeded)",
+        "config": {"workload": "secure ring GEMM 4096x4096x4096 over Z/2^64: share both "
+                               "operands, dealer matrix triple, Beaver matmul with 2^16 "
+                               "truncation, reveal",
+                   "M": M, "N": N, "K": K, "form": args.form, "frac_bits": FRAC,
+                   "parties": 2, "parallelism": "single GPU, two party streams"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def _event_time(torch, stream, fn, reps):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    e.record(stream)
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def secondary(ctx, mpc, torch, workloads, X, Y):
+    ex = {}
+    # ring GEMM alone, both forms, timed with the library's launch events
+    C = ctx.empty((M, N))
+    ctx.profile(True)
+    for form, reps in (("limb8", 5), ("plain", 2)):
+        ctx.ring_gemm(X, Y, form, out=C)  # warm
+        ctx.profile_read()
+        for _ in range(reps):
+            ctx.ring_gemm(X, Y, form, out=C)
+        g = ctx.profile_read()[form]
+        ms = g["total_ms"] / g["launches"]
+        ex[f"ring_gemm_4096_{form}_tops"] = round(2.0 * M * N * K / (ms * 1e-3) / 1e12, 3)
+        ex[f"ring_gemm_4096_{form}_ms"] = round(ms, 4)
+        log(f"bench: ring GEMM 4096^3 {form}: {ms:.3f} ms")
+    ctx.profile(False)
+    ex["limb_over_plain_speedup"] = round(ex["ring_gemm_4096_plain_ms"] / ex["ring_gemm_4096_limb8_ms"], 2)
+    C0 = ctx.ring_gemm(X, Y, "limb8")
+    C1 = ctx.ring_gemm(X, Y, "plain")
+    ctx.sync()
+    ex["ring_gemm_forms_bit_identical"] = bool(torch.equal(C0, C1))
+    del C, C0, C1
+
+    # Beaver element-wise product (fused mask/open/finish/truncate), HBM-bound
+    n = 1 << 26
+    x = ctx.share(X.view(-1)[:n].contiguous(), 0, 11)
+    y = ctx.share(Y.view(-1)[:n].contiguous(), 1, 12)
+    tm = ctx.dealer(mpc.TRIPLE_MUL, 5, 13, (n,))
+    zz = mpc.SharedPair(ctx.empty((n,)), ctx.empty((n,)))
+    ctx.beaver_mul(x, y, tm, 16, out=zz)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.beaver_mul(x, y, tm, 16, out=zz), 10)
+    ex["beaver_mul_n"] = n
+    ex["beaver_mul_elem_per_s"] = round(n / (ms * 1e-3), 1)
+    ex["beaver_mul_hbm_GBps_algorithmic"] = round(96.0 * n / (ms * 1e-3) / 1e9, 1)
+    ex["beaver_mul_hbm_frac"] = round(ex["beaver_mul_hbm_GBps_algorithmic"] / HBM_PEAK_GBS, 4)
+    log(f"bench: Beaver mul n=2^26: {ms:.3f} ms")
+    del x, y, tm, zz
+
+    # secure MLP 784-1024-1024-10, batch 128, square activations
+    for form in ("plain", "limb8"):
+        ex[f"mlp_ms_{form}"] = round(mlp_latency(ctx, mpc, torch, workloads, form), 4)
+    log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
+    ctx.sync()
+    return ex
+
+
+def mlp_latency(ctx, mpc, torch, workloads, form):
+    cfg = workloads.MLP
+    B, dims = cfg["batch"], cfg["dims"]
+    dseed = workloads.seeds(2)[2]
+    X = mpc.encode(workloads.uniform(1002, (B, dims[0]), -1, 1), FRAC)
+    Ws = [mpc.encode(workloads.uniform(1102 + i, (dims[i], dims[i + 1]), -1, 1), FRAC)
+          for i in range(3)]
+    dv = lambda a: torch.from_numpy(a).to(ctx.device)
+    x = ctx.share(dv(X), 0, 100)
+    ws = [ctx.share(dv(W), 1, 101 + i) for i, W in enumerate(Ws)]
+    trip = [ctx.dealer(mpc.TRIPLE_MATMUL, dseed, 200 + i, (B, dims[i + 1], dims[i]))
+            for i in range(3)]
+    pairs = [ctx.dealer(mpc.TRIPLE_SQUARE, dseed, 300 + i, (B * dims[i + 1],)) for i in range(2)]
+
+    def forward():
+        h = x
+        for i in range(3):
+            h = ctx.beaver_matmul(h, ws[i], trip[i], FRAC, form)
+            if i < 2:
+                flat = mpc.SharedPair(h.s0.view(-1), h.s1.view(-1))
+                sq = ctx.beaver_mul(flat, None, pairs[i], FRAC)
+                h = mpc.SharedPair(sq.s0.view(B, dims[i + 1]), sq.s1.view(B, dims[i + 1]))
+        return h
+
+    forward()
+    ctx.sync()
+    return _event_time(torch, ctx.streams[0], forward, 20)
+
+
+def cpu_baseline(Xh, Yh, party_seed, dealer_seed, z_rows):
+    """The CPU oracle on the first `rows` rows of the same workload (row slices of
+    a row-major PRG fill are the same draws as in the full problem)."""
+    import oracle
+
+    def run(rows):
+        t0 = time.perf_counter()
+        xs = oracle.share(Xh[:rows], 0, party_seed, 1)
+        ys = oracle.share(Yh, 1, party_seed, 2)
+        tr = oracle.dealer_matmul(dealer_seed, 3, rows, N, K)
+        zz = oracle.beaver_matmul(xs, ys, tr, FRAC)
+        oracle.reveal(*zz)
+        return time.perf_counter() - t0, zz
+
+    rows = 16
+    dt, zz = run(rows)
+    log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
+    if dt < 8.0:
+        rows = int(min(256, max(rows, rows * 15.0 / dt)))
+        rows -= rows % 8
+        dt, zz = run(rows)
+        log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
+    match = bool(np.array_equal(zz[0], z_rows[0][:rows]) and np.array_equal(zz[1], z_rows[1][:rows]))
+    return {"value": round(2.0 * rows * N * K / dt / 1e12, 6), "unit": "Tops/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of the 4096^3 step (share, dealer, Beaver matmul, "
+                      f"truncate, reveal) in the CPU oracle; {dt:.1f} s",
+            "sample_matches_gpu_bit_exact": match}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,231 @@
+/*
+ * mpc.h -- C ABI of libmpc: two-party arithmetic secret sharing over the ring
+ * Z/2^64 on one AMD MI355X (gfx950).
+ *
+ * The operations are those of CrypTen (Knott et al., NeurIPS 2021): additive
+ * sharing of fixed-point values (section 5.1), Beaver multiplication of shared
+ * values and its bilinear variants (section 5.2 and App. C.1.1), the square
+ * with a Beaver pair (App. C.1.1, Square), local share truncation (App. C.1.1,
+ * Truncation; zero rounds for two parties per Table 1) and reveal.
+ *
+ * Conventions for every call below.
+ *   - Ring elements are uint64_t; arithmetic wraps modulo 2^64.  A fixed-point
+ *     value with f fractional bits is the ring element whose signed 64-bit
+ *     reading is round(x * 2^f).
+ *   - Unless a parameter says "host", every pointer is a DEVICE pointer on the
+ *     context's device, 8-byte aligned, to a dense row-major array owned by the
+ *     caller.  The library owns only the context and its workspace.
+ *   - Both parties' shares live on the one GPU as separate buffers ("party 0"
+ *     and "party 1"), and the context holds one HIP stream per party.  Every
+ *     call is issued on party 0's stream: it sees all work the caller ordered
+ *     before it on that stream, and work the caller orders after it on that
+ *     stream sees its results.  Work local to party 1 (its truncation) is
+ *     forked onto party 1's stream with an event and joined back before the
+ *     call returns.  Steps that need both parties (opening a masked value,
+ *     reveal, the dealer) are device-local sums on party 0's stream; nothing
+ *     crosses a network or a second GPU.
+ *   - Every call is asynchronous with respect to the host.  Argument errors are
+ *     reported synchronously; faults in kernels are reported by mpc_sync().
+ *   - No call throws, aborts or prints.  Outputs must not alias inputs unless a
+ *     call says so (MPC_E_ALIAS).
+ *   - Sizes are element counts.  n = 0 (or an empty matrix) is valid and does
+ *     nothing.
+ *   - Randomness: G(seed, tag, slot, i) is a counter-based SplitMix64 value
+ *     (Steele, Lea and Flood, OOPSLA 2014): with out_i(s) = mix(s + (i+1)γ),
+ *     T = out_tag(seed), S = out_slot(T), G = out_i(S).  Slots: 0 share mask,
+ *     1 a_0, 2 a_1, 3 b_0, 4 b_1, 5 c_0.  Equal (seed, tag) always regenerate
+ *     identical shares and triples; reusing a triple is the caller's bug.
+ */
+#ifndef MPC_H
+#define MPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPC_OK = 0,
+  MPC_E_INVAL = -1,       /* null pointer, misalignment, bad enum or bit count */
+  MPC_E_SHAPE = -2,       /* negative or inconsistent sizes */
+  MPC_E_ALIAS = -3,       /* an output overlaps an input */
+  MPC_E_NOMEM = -4,       /* workspace allocation failed */
+  MPC_E_HIP = -5,         /* a HIP runtime call failed (see mpc_last_hip_error) */
+  MPC_E_UNSUPPORTED = -6, /* valid request this build does not support */
+  MPC_E_RANGE = -7        /* a real value does not fit the fixed-point range */
+} mpc_status;
+
+/* Form of the ring matrix product.
+ *   PLAIN: uint64 wraparound multiply-accumulate on the vector ALUs.
+ *   LIMB8: each operand split into eight signed 8-bit limbs; the 36 limb
+ *          pairs (i, j) with i + j <= 7 are multiplied on INT8 matrix cores
+ *          with exact int32 accumulation (K split so no sum can overflow) and
+ *          combined as sum 2^(8(i+j)) D_i E_j mod 2^64.  Bit-identical to PLAIN.
+ *   AUTO:  the library's choice (LIMB8 unless the problem is tiny). */
+typedef enum { MPC_FORM_PLAIN = 0, MPC_FORM_LIMB8 = 1, MPC_FORM_AUTO = 2 } mpc_form;
+
+typedef enum {
+  MPC_TRIPLE_MUL = 0,    /* element-wise: a, b, c = a*b, all of length n          */
+  MPC_TRIPLE_SQUARE = 1, /* Beaver pair: a and b = a*a of length n; c unused      */
+  MPC_TRIPLE_MATMUL = 2, /* a: MxK, b: KxN, c = a@b: MxN                          */
+  MPC_TRIPLE_CONV1D = 3  /* a: activation [B][Cin][L], b: weight [Cout][Cin][k],
+                            c = conv1d(a, b): [B][Cout][Lout]                     */
+} mpc_triple_kind;
+
+/* Additive shares of a Beaver triple: party p holds a_p, b_p, c_p. */
+typedef struct {
+  uint64_t *a0, *a1, *b0, *b1, *c0, *c1;
+} mpc_triple;
+
+/* 1-D convolution with valid padding: Lout = (length - ksize) / stride + 1. */
+typedef struct {
+  int64_t batch, cin, length, cout, ksize, stride;
+} mpc_conv1d_shape;
+
+typedef struct mpc_ctx mpc_ctx;
+
+/* Counters kept by a context: opens (one per Beaver product, the only
+ * communication round of the protocol), bytes a two-GPU deployment would send
+ * per party for those opens, kernel launches and GEMM problems issued. */
+typedef struct {
+  uint64_t opens, open_bytes_per_party, truncations, launches, gemm_problems;
+} mpc_stats;
+
+const char *mpc_status_str(mpc_status s);
+/* Last HIP error code seen by the library in this process (0 if none). */
+int mpc_last_hip_error(void);
+
+/* ---- host-only fixed-point codec (section 5.1) ------------------------- */
+/* out[i] = round-half-even(x[i] * 2^frac_bits) as int64.  x and out are HOST
+ * pointers.  MPC_E_RANGE if a value (or NaN) does not fit; out is then
+ * partially written.  frac_bits in [0, 62]. */
+mpc_status mpc_encode(const double *x, size_t n, int frac_bits, int64_t *out);
+/* out[i] = (double)v[i] / 2^frac_bits.  HOST pointers. */
+mpc_status mpc_decode(const int64_t *v, size_t n, int frac_bits, double *out);
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds `device` and the two party streams (hipStream_t values).  stream0 may
+ * be NULL, the device's null stream; stream1 NULL makes the library create and
+ * own a stream for party 1.  `seed` is the parties' synchronised PRG seed used
+ * for sharing. */
+mpc_status mpc_ctx_create(int device, void *stream0, void *stream1, uint64_t seed,
+                          mpc_ctx **out);
+mpc_status mpc_ctx_destroy(mpc_ctx *ctx);
+/* Waits for both party streams; reports kernel faults. */
+mpc_status mpc_sync(mpc_ctx *ctx);
+mpc_status mpc_ctx_stats(const mpc_ctx *ctx, mpc_stats *out);
+/* Pre-sizes the library-owned workspace to at least `bytes` (optional; calls
+ * grow it on demand, synchronising both streams when they do). */
+mpc_status mpc_reserve(mpc_ctx *ctx, size_t bytes);
+
+/* ---- sharing (section 5.1) --------------------------------------------- */
+/* Party `src` (0 or 1) secret-shares the ring elements x[0..n):
+ *   m_i = G(seed, tag, 0, i);  s_src = x - m;  s_other = m.
+ * x, s0, s1: device arrays of n.  s0/s1 must not overlap x or each other. */
+mpc_status mpc_share(mpc_ctx *ctx, const uint64_t *x, size_t n, int src, uint64_t tag,
+                     uint64_t *s0, uint64_t *s1);
+/* out = s0 + s1 mod 2^64 (read it as int64 for the signed value).  out may
+ * alias s0 or s1. */
+mpc_status mpc_reveal(mpc_ctx *ctx, const uint64_t *s0, const uint64_t *s1, size_t n,
+                      uint64_t *out);
+/* Local truncation, in place: each party replaces its share s by
+ * floor(s64(s) / 2^bits) on its own stream.  bits in [0, 63]. */
+mpc_status mpc_truncate(mpc_ctx *ctx, uint64_t *s0, uint64_t *s1, size_t n, int bits);
+
+/* ---- trusted third party (section 4; App. C.1.1) ------------------------ */
+/* Draws a fresh triple from the dealer's own seed:
+ *   a_p = G(dseed, tag, 1+p, i), b_p = G(dseed, tag, 3+p, i),
+ *   c_0 = G(dseed, tag, 5, i),   c_1 = f(a_0 + a_1, b_0 + b_1) - c_0,
+ * f being *, @ or conv1d per `kind`; for SQUARE b_1 = (a_0 + a_1)^2 - b_0.
+ * dims: MUL/SQUARE {n}; MATMUL {M, N, K}; CONV1D the six fields of
+ * mpc_conv1d_shape in order.  `out` is a HOST struct of device pointers sized
+ * for the kind (c0/c1 ignored for SQUARE). */
+mpc_status mpc_dealer_triples(mpc_ctx *ctx, mpc_triple_kind kind, uint64_t dseed, uint64_t tag,
+                              const int64_t *dims, const mpc_triple *out);
+
+/* ---- Beaver products (section 5.2; App. C.1.1) -------------------------- */
+/* Element-wise product of shared x and y with an element-wise triple:
+ *   eps = sum_p (x_p - a_p), delta = sum_p (y_p - b_p)   (the one open)
+ *   z_p = c_p + eps*b_p + a_p*delta (+ eps*delta for party 0)
+ * With y0 == y1 == NULL it is the square with a Beaver pair (a, b = a^2):
+ *   z_p = b_p + 2*eps*a_p (+ eps^2 for party 0).
+ * Then each party truncates by trunc_bits (0 = none, else 1..63).  All arrays
+ * have n elements; `t` is a HOST struct of device pointers.  z may not
+ * overlap any input. */
+mpc_status mpc_beaver_mul(mpc_ctx *ctx, size_t n, const uint64_t *x0, const uint64_t *x1,
+                          const uint64_t *y0, const uint64_t *y1, const mpc_triple *t,
+                          int trunc_bits, uint64_t *z0, uint64_t *z1);
+
+/* Matrix product of shared X (MxK) and Y (KxN) with a matrix triple:
+ *   z_p = c_p + eps @ b_p + (a_p + [p = 0] eps) @ delta,  then truncation.
+ * Each party's finish is one ring GEMM of M x N x 2K over the concatenations
+ * [eps | a_p + [p=0] eps] and [b_p ; delta]; both parties' GEMMs are issued as
+ * one launch on party 0's stream.  z_p: MxN. */
+mpc_status mpc_beaver_matmul(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const uint64_t *x0,
+                             const uint64_t *x1, const uint64_t *y0, const uint64_t *y1,
+                             const mpc_triple *t, int trunc_bits, mpc_form form, uint64_t *z0,
+                             uint64_t *z1);
+
+/* Convolution of a shared activation x [B][Cin][L] with a shared weight
+ * w [Cout][Cin][k] (valid padding) with a CONV1D triple, lowered onto the ring
+ * GEMM (weights as the left operand, im2col of the activation as the right):
+ *   z_p = c_p + conv(eps, b_p) + conv(a_p + [p=0] eps, delta), then truncation.
+ * z_p: [B][Cout][Lout]. */
+mpc_status mpc_beaver_conv1d(mpc_ctx *ctx, const mpc_conv1d_shape *shape, const uint64_t *x0,
+                             const uint64_t *x1, const uint64_t *w0, const uint64_t *w1,
+                             const mpc_triple *t, int trunc_bits, mpc_form form, uint64_t *z0,
+                             uint64_t *z1);
+
+/* Public ring GEMM C = A @ B mod 2^64 (A: MxK, B: KxN, C: MxN), on party 0's
+ * stream: the kernel both Beaver forms use, exposed for comparison. */
+mpc_status mpc_ring_gemm(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const uint64_t *A,
+                         const uint64_t *B, uint64_t *C, mpc_form form);
+
+/* ---- measurement -------------------------------------------------------- */
+/* While enabled, every ring GEMM launch the context issues is bracketed by two
+ * HIP events on the stream it is launched on (party 0's).  mpc_profile_read
+ * waits for both party streams, then returns per form the number of GEMM
+ * launches since the last read, their summed event-measured duration and
+ * their algorithmic work (ring multiply-accumulates M*N*K over true, unpadded
+ * sizes; the limb form also performs 36 int8 multiply-accumulates per ring
+ * one), and clears the record.  Either output pointer may be NULL. */
+typedef struct {
+  uint64_t launches;
+  double total_ms;
+  double ring_macs;
+} mpc_gemm_timing;
+mpc_status mpc_profile_enable(mpc_ctx *ctx, int on);
+mpc_status mpc_profile_read(mpc_ctx *ctx, mpc_gemm_timing *limb8, mpc_gemm_timing *plain);
+
+/* ---- batching form ------------------------------------------------------ */
+/* One Beaver matmul of a group (all pointers device, as in mpc_beaver_matmul). */
+typedef struct {
+  int64_t M, N, K;
+  const uint64_t *x0, *x1, *y0, *y1;
+  mpc_triple t;
+  uint64_t *z0, *z1;
+} mpc_matmul_desc;
+
+/* Many independent Beaver matmuls of uneven shapes: one open launch and one
+ * persistent GEMM launch for all problems and both parties.  `descs` is a
+ * HOST array of `count` descriptors. */
+mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
+                                     int trunc_bits, mpc_form form);
+
+/* Stream capture of the context's work into a HIP graph: begin, issue calls,
+ * end.  Party 0's stream must not be the null stream.  The workspace must
+ * already be large enough (issue the same calls once eagerly first, or call
+ * mpc_reserve).  mpc_graph_launch replays the graph on party 0's stream;
+ * mpc_graph_destroy frees it. */
+mpc_status mpc_graph_begin(mpc_ctx *ctx);
+mpc_status mpc_graph_end(mpc_ctx *ctx, void **graph_exec);
+mpc_status mpc_graph_launch(mpc_ctx *ctx, void *graph_exec);
+mpc_status mpc_graph_destroy(void *graph_exec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPC_H */

@@ -1,0 +1,368 @@
+"""Python binding of libmpc: two-party arithmetic secret sharing over Z/2^64
+on one MI355X.
+
+Argument marshalling only: tensors are torch ``int64`` CUDA (HIP) tensors whose
+bits are ring elements; their ``data_ptr()`` and the party streams' handles are
+passed to the C ABI of ``include/mpc.h``, and every step runs in the library's
+HIP kernels.  There is no fallback: if ``libmpc.so`` is missing or does not
+load, importing this package raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpc.so")
+
+FORM_PLAIN, FORM_LIMB8, FORM_AUTO = 0, 1, 2
+TRIPLE_MUL, TRIPLE_SQUARE, TRIPLE_MATMUL, TRIPLE_CONV1D = 0, 1, 2, 3
+FORMS = {"plain": FORM_PLAIN, "limb8": FORM_LIMB8, "auto": FORM_AUTO}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2109_00984_amd/build.py "
+                      "(or __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+VP = ctypes.c_void_p
+I64 = ctypes.c_int64
+U64 = ctypes.c_uint64
+SZ = ctypes.c_size_t
+INT = ctypes.c_int
+
+
+class Triple(ctypes.Structure):
+    _fields_ = [("a0", VP), ("a1", VP), ("b0", VP), ("b1", VP), ("c0", VP), ("c1", VP)]
+
+
+class Conv1dShape(ctypes.Structure):
+    _fields_ = [("batch", I64), ("cin", I64), ("length", I64), ("cout", I64), ("ksize", I64),
+                ("stride", I64)]
+
+
+class MatmulDesc(ctypes.Structure):
+    _fields_ = [("M", I64), ("N", I64), ("K", I64), ("x0", VP), ("x1", VP), ("y0", VP),
+                ("y1", VP), ("t", Triple), ("z0", VP), ("z1", VP)]
+
+
+class GemmTiming(ctypes.Structure):
+    _fields_ = [("launches", U64), ("total_ms", ctypes.c_double), ("ring_macs", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("opens", U64), ("open_bytes_per_party", U64), ("truncations", U64),
+                ("launches", U64), ("gemm_problems", U64)]
+
+
+_SIGS = {
+    "mpc_status_str": (ctypes.c_char_p, [INT]),
+    "mpc_last_hip_error": (INT, []),
+    "mpc_encode": (INT, [VP, SZ, INT, VP]),
+    "mpc_decode": (INT, [VP, SZ, INT, VP]),
+    "mpc_ctx_create": (INT, [INT, VP, VP, U64, ctypes.POINTER(VP)]),
+    "mpc_ctx_destroy": (INT, [VP]),
+    "mpc_sync": (INT, [VP]),
+    "mpc_ctx_stats": (INT, [VP, ctypes.POINTER(Stats)]),
+    "mpc_reserve": (INT, [VP, SZ]),
+    "mpc_share": (INT, [VP, VP, SZ, INT, U64, VP, VP]),
+    "mpc_reveal": (INT, [VP, VP, VP, SZ, VP]),
+    "mpc_truncate": (INT, [VP, VP, VP, SZ, INT]),
+    "mpc_dealer_triples": (INT, [VP, INT, U64, U64, ctypes.POINTER(I64), ctypes.POINTER(Triple)]),
+    "mpc_beaver_mul": (INT, [VP, SZ, VP, VP, VP, VP, ctypes.POINTER(Triple), INT, VP, VP]),
+    "mpc_beaver_matmul": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), INT,
+                                INT, VP, VP]),
+    "mpc_beaver_conv1d": (INT, [VP, ctypes.POINTER(Conv1dShape), VP, VP, VP, VP,
+                                ctypes.POINTER(Triple), INT, INT, VP, VP]),
+    "mpc_ring_gemm": (INT, [VP, I64, I64, I64, VP, VP, VP, INT]),
+    "mpc_beaver_matmul_grouped": (INT, [VP, SZ, ctypes.POINTER(MatmulDesc), INT, INT]),
+    "mpc_profile_enable": (INT, [VP, INT]),
+    "mpc_profile_read": (INT, [VP, ctypes.POINTER(GemmTiming), ctypes.POINTER(GemmTiming)]),
+    "mpc_graph_begin": (INT, [VP]),
+    "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
+    "mpc_graph_launch": (INT, [VP, VP]),
+    "mpc_graph_destroy": (INT, [VP]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class MPCError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _lib.mpc_status_str(status).decode()
+        if status == -5:
+            msg += f" (hip error {_lib.mpc_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+        self.status = status
+
+
+def _check(status, where):
+    if status != 0:
+        raise MPCError(status, where)
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+# ------------------------------------------------------------------ host codec
+def encode(x, frac_bits=16):
+    """Host-side fixed-point encoding: round-half-even(x * 2^frac_bits) -> int64."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty(x.shape, dtype=np.int64)
+    _check(_lib.mpc_encode(x.ctypes.data, x.size, frac_bits, out.ctypes.data), "mpc_encode")
+    return out
+
+
+def decode(v, frac_bits=16):
+    if isinstance(v, torch.Tensor):
+        v = v.cpu().numpy()
+    v = np.ascontiguousarray(v).view(np.int64)
+    out = np.empty(v.shape, dtype=np.float64)
+    _check(_lib.mpc_decode(v.ctypes.data, v.size, frac_bits, out.ctypes.data), "mpc_decode")
+    return out
+
+
+# ------------------------------------------------------------------ helpers
+def _ptr(t):
+    return VP(t.data_ptr()) if t is not None else VP(0)
+
+
+class SharedPair:
+    """Party 0's and party 1's shares of one secret tensor."""
+
+    def __init__(self, s0, s1):
+        self.s0, self.s1 = s0, s1
+
+    @property
+    def shape(self):
+        return self.s0.shape
+
+    def __iter__(self):
+        return iter((self.s0, self.s1))
+
+
+class TripleShares:
+    """Device buffers of a Beaver triple: a = (a0, a1), b = (b0, b1), c = (c0, c1)."""
+
+    def __init__(self, a0, a1, b0, b1, c0=None, c1=None):
+        self.a0, self.a1, self.b0, self.b1, self.c0, self.c1 = a0, a1, b0, b1, c0, c1
+
+    def struct(self):
+        return Triple(*[(VP(t.data_ptr()) if t is not None else VP(0))
+                        for t in (self.a0, self.a1, self.b0, self.b1, self.c0, self.c1)])
+
+
+class Context:
+    """One library context: a device, two party streams and the parties' seed.
+
+    Party 0's stream defaults to torch's current stream, so tensors torch
+    allocates and frees on that stream are ordered with the library's work
+    (torch's caching allocator may hand a freed block to the next allocation
+    on that stream at once); party 1's stream is a new stream at the default
+    priority, used only inside calls.  Pass ``streams`` to override; then the
+    caller keeps every tensor alive (or calls ``record_stream``) until the
+    work on those streams is done.
+    """
+
+    def __init__(self, device=0, seed=0, streams=None):
+        self.device = torch.device("cuda", device)
+        if streams is None:
+            streams = (torch.cuda.current_stream(self.device),
+                       torch.cuda.Stream(device=self.device))
+        self.streams = streams
+        h = VP()
+        _check(_lib.mpc_ctx_create(device, VP(streams[0].cuda_stream),
+                                   VP(streams[1].cuda_stream), seed, ctypes.byref(h)),
+               "mpc_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mpc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -------------------------------------------------------------- basics
+    def _check_t(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if t.device != self.device or t.dtype != torch.int64 or not t.is_contiguous():
+                raise ValueError("expected contiguous int64 tensors on " + str(self.device))
+
+    def empty(self, shape):
+        return torch.empty(shape, dtype=torch.int64, device=self.device)
+
+    def sync(self):
+        _check(_lib.mpc_sync(self._h), "mpc_sync")
+
+    def stats(self):
+        s = Stats()
+        _check(_lib.mpc_ctx_stats(self._h, ctypes.byref(s)), "mpc_ctx_stats")
+        return {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+
+    def profile(self, on=True):
+        """Bracket every ring GEMM launch with HIP events (see mpc_profile_read)."""
+        _check(_lib.mpc_profile_enable(self._h, 1 if on else 0), "mpc_profile_enable")
+
+    def profile_read(self):
+        lm, pl = GemmTiming(), GemmTiming()
+        _check(_lib.mpc_profile_read(self._h, ctypes.byref(lm), ctypes.byref(pl)),
+               "mpc_profile_read")
+        as_dict = lambda g: {"launches": int(g.launches), "total_ms": float(g.total_ms),
+                             "ring_macs": float(g.ring_macs)}
+        return {"limb8": as_dict(lm), "plain": as_dict(pl)}
+
+    def reserve(self, nbytes):
+        _check(_lib.mpc_reserve(self._h, int(nbytes)), "mpc_reserve")
+
+    def share(self, x, src, tag, out=None):
+        self._check_t(x)
+        s0, s1 = (self.empty(x.shape), self.empty(x.shape)) if out is None else (out.s0, out.s1)
+        _check(_lib.mpc_share(self._h, _ptr(x), x.numel(), src, tag, _ptr(s0), _ptr(s1)),
+               "mpc_share")
+        return SharedPair(s0, s1)
+
+    def reveal(self, x, out=None):
+        self._check_t(x.s0, x.s1)
+        out = self.empty(x.shape) if out is None else out
+        _check(_lib.mpc_reveal(self._h, _ptr(x.s0), _ptr(x.s1), x.s0.numel(), _ptr(out)),
+               "mpc_reveal")
+        return out
+
+    def truncate(self, x, bits):
+        self._check_t(x.s0, x.s1)
+        _check(_lib.mpc_truncate(self._h, _ptr(x.s0), _ptr(x.s1), x.s0.numel(), bits),
+               "mpc_truncate")
+        return x
+
+    # -------------------------------------------------------------- dealer
+    def dealer(self, kind, dseed, tag, dims):
+        """Allocates and fills a triple of `kind` (TRIPLE_*) with shape `dims`."""
+        if kind in (TRIPLE_MUL, TRIPLE_SQUARE):
+            (n,) = dims
+            sa = sb = sc = (n,)
+        elif kind == TRIPLE_MATMUL:
+            M, N, K = dims
+            sa, sb, sc = (M, K), (K, N), (M, N)
+        elif kind == TRIPLE_CONV1D:
+            B, cin, L, cout, k, s = dims
+            lout = (L - k) // s + 1 if L >= k else 0
+            sa, sb, sc = (B, cin, L), (cout, cin, k), (B, cout, lout)
+        else:
+            raise ValueError("unknown triple kind")
+        t = TripleShares(self.empty(sa), self.empty(sa), self.empty(sb), self.empty(sb),
+                         None if kind == TRIPLE_SQUARE else self.empty(sc),
+                         None if kind == TRIPLE_SQUARE else self.empty(sc))
+        self.dealer_into(kind, dseed, tag, dims, t)
+        return t
+
+    def dealer_into(self, kind, dseed, tag, dims, t):
+        d = (I64 * 6)(*list(dims) + [0] * (6 - len(dims)))
+        st = t.struct()
+        _check(_lib.mpc_dealer_triples(self._h, kind, dseed, tag, d, ctypes.byref(st)),
+               "mpc_dealer_triples")
+        return t
+
+    # -------------------------------------------------------------- Beaver
+    def beaver_mul(self, x, y, t, trunc_bits=0, out=None):
+        """y=None selects the square with a Beaver pair (t.a, t.b = a^2)."""
+        ts = [x.s0, x.s1, t.a0, t.a1, t.b0, t.b1]
+        if y is not None:
+            ts += [y.s0, y.s1, t.c0, t.c1]
+        self._check_t(*ts)
+        n = x.s0.numel()
+        z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        st = t.struct()
+        _check(_lib.mpc_beaver_mul(self._h, n, _ptr(x.s0), _ptr(x.s1),
+                                   _ptr(y.s0 if y is not None else None),
+                                   _ptr(y.s1 if y is not None else None), ctypes.byref(st),
+                                   trunc_bits, _ptr(z.s0), _ptr(z.s1)), "mpc_beaver_mul")
+        return z
+
+    def beaver_matmul(self, x, y, t, trunc_bits=0, form="auto", out=None):
+        M, K = x.s0.shape
+        K2, N = y.s0.shape
+        if K != K2:
+            raise ValueError("inner dimensions differ")
+        self._check_t(x.s0, x.s1, y.s0, y.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
+        z = out if out is not None else SharedPair(self.empty((M, N)), self.empty((M, N)))
+        st = t.struct()
+        _check(_lib.mpc_beaver_matmul(self._h, M, N, K, _ptr(x.s0), _ptr(x.s1), _ptr(y.s0),
+                                      _ptr(y.s1), ctypes.byref(st), trunc_bits, FORMS[form],
+                                      _ptr(z.s0), _ptr(z.s1)), "mpc_beaver_matmul")
+        return z
+
+    def beaver_conv1d(self, x, w, t, stride, trunc_bits=0, form="auto", out=None):
+        B, cin, L = x.s0.shape
+        cout, cin2, k = w.s0.shape
+        if cin != cin2:
+            raise ValueError("channel counts differ")
+        self._check_t(x.s0, x.s1, w.s0, w.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
+        lout = (L - k) // stride + 1 if L >= k else 0
+        shape = Conv1dShape(B, cin, L, cout, k, stride)
+        z = out if out is not None else SharedPair(self.empty((B, cout, lout)),
+                                                   self.empty((B, cout, lout)))
+        st = t.struct()
+        _check(_lib.mpc_beaver_conv1d(self._h, ctypes.byref(shape), _ptr(x.s0), _ptr(x.s1),
+                                      _ptr(w.s0), _ptr(w.s1), ctypes.byref(st), trunc_bits,
+                                      FORMS[form], _ptr(z.s0), _ptr(z.s1)), "mpc_beaver_conv1d")
+        return z
+
+    def ring_gemm(self, A, B, form="auto", out=None):
+        M, K = A.shape
+        K2, N = B.shape
+        if K != K2:
+            raise ValueError("inner dimensions differ")
+        self._check_t(A, B)
+        C = out if out is not None else self.empty((M, N))
+        _check(_lib.mpc_ring_gemm(self._h, M, N, K, _ptr(A), _ptr(B), _ptr(C), FORMS[form]),
+               "mpc_ring_gemm")
+        return C
+
+    def beaver_matmul_grouped(self, problems, trunc_bits=0, form="auto", outs=None):
+        """problems: list of (x, y, triple); returns the list of output pairs."""
+        descs = (MatmulDesc * max(1, len(problems)))()
+        results = []
+        for i, (x, y, t) in enumerate(problems):
+            M, K = x.s0.shape
+            N = y.s0.shape[1]
+            self._check_t(x.s0, x.s1, y.s0, y.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
+            z = outs[i] if outs is not None else SharedPair(self.empty((M, N)),
+                                                            self.empty((M, N)))
+            results.append(z)
+            descs[i] = MatmulDesc(M, N, K, x.s0.data_ptr(), x.s1.data_ptr(), y.s0.data_ptr(),
+                                  y.s1.data_ptr(), t.struct(), z.s0.data_ptr(), z.s1.data_ptr())
+        _check(_lib.mpc_beaver_matmul_grouped(self._h, len(problems), descs, trunc_bits,
+                                              FORMS[form]), "mpc_beaver_matmul_grouped")
+        return results
+
+    # -------------------------------------------------------------- graphs
+    def graph_begin(self):
+        _check(_lib.mpc_graph_begin(self._h), "mpc_graph_begin")
+
+    def graph_end(self):
+        g = VP()
+        _check(_lib.mpc_graph_end(self._h, ctypes.byref(g)), "mpc_graph_end")
+        return g
+
+    def graph_launch(self, g):
+        _check(_lib.mpc_graph_launch(self._h, g), "mpc_graph_launch")
+
+    @staticmethod
+    def graph_destroy(g):
+        _check(_lib.mpc_graph_destroy(g), "mpc_graph_destroy")

@@ -1,0 +1,1210 @@
+// api.cpp -- the C ABI of libmpc (declared in include/mpc.h): context and
+// workspace management, argument validation and the orchestration of the
+// kernels for each protocol step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "mpc.h"
+
+using namespace mpc;
+
+namespace {
+
+int g_last_hip_error = 0;
+
+#define HIPCHK(expr)                             \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) {                      \
+      g_last_hip_error = (int)_e;                \
+      return MPC_E_HIP;                          \
+    }                                            \
+  } while (0)
+
+#define CHK(expr)                 \
+  do {                            \
+    mpc_status _s = (expr);       \
+    if (_s != MPC_OK) return _s;  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Host staging slot for descriptor tables: a pinned buffer, its device mirror
+// and an event marking the end of the call that last used it.
+struct UploadSlot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+constexpr int kSlots = 16;
+
+}  // namespace
+
+struct mpc_ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t s[2] = {nullptr, nullptr};
+  bool own[2] = {false, false};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t side = nullptr;  // non-blocking stream for uploads made during capture
+  uint64_t seed = 0;
+  uint8_t* ws = nullptr;
+  size_t ws_cap = 0;
+  UploadSlot slots[kSlots];
+  int next_slot = 0;
+  int cur_slot = -1;
+  bool capturing = false;
+  std::vector<void*> capture_allocs;
+  mpc_stats stats{};
+  // event timing of GEMM launches
+  struct TimedLaunch {
+    hipEvent_t start, stop;
+    int form;
+    double ring_macs;
+  };
+  bool profiling = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+bool two_streams(const mpc_ctx* c) { return c->s[0] != c->s[1]; }
+
+mpc_status set_device(mpc_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  return MPC_OK;
+}
+
+// Call protocol: every call is issued on party 0's stream.  Work local to
+// party 1 is forked onto party 1's stream and joined back before the call
+// returns, so both streams are idle-equivalent between calls and anything the
+// caller ordered before the call on party 0's stream is visible to it.
+// fork: party 1's stream waits for everything issued so far on party 0's.
+mpc_status fork(mpc_ctx* c) {
+  if (!two_streams(c)) return MPC_OK;
+  HIPCHK(hipEventRecord(c->ev[0], c->s[0]));
+  HIPCHK(hipStreamWaitEvent(c->s[1], c->ev[0], 0));
+  return MPC_OK;
+}
+
+// join: party 0's stream waits for everything issued so far on party 1's.
+mpc_status join(mpc_ctx* c) {
+  if (!two_streams(c)) return MPC_OK;
+  HIPCHK(hipEventRecord(c->ev[1], c->s[1]));
+  HIPCHK(hipStreamWaitEvent(c->s[0], c->ev[1], 0));
+  return MPC_OK;
+}
+
+mpc_status sync_all(mpc_ctx* c) {
+  HIPCHK(hipStreamSynchronize(c->s[0]));
+  if (two_streams(c)) HIPCHK(hipStreamSynchronize(c->s[1]));
+  return MPC_OK;
+}
+
+// Makes the workspace at least `bytes`.  Growing frees the old buffer, so it
+// first waits for both streams; it is refused while a graph is being captured.
+mpc_status ensure_ws(mpc_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_cap) return MPC_OK;
+  if (c->capturing) return MPC_E_NOMEM;
+  CHK(sync_all(c));
+  if (c->ws) HIPCHK(hipFree(c->ws));
+  c->ws = nullptr;
+  c->ws_cap = 0;
+  size_t cap = align_up(bytes + bytes / 4, 1 << 20);
+  if (hipMalloc((void**)&c->ws, cap) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return MPC_E_NOMEM;
+  }
+  c->ws_cap = cap;
+  return MPC_OK;
+}
+
+// Bump allocator over the workspace for one call.
+struct Carve {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Carve(uint8_t* b) : base(b) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = (T*)(base + off);
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+// Builder of one descriptor blob uploaded once per call.
+struct Blob {
+  std::vector<uint8_t> bytes;
+  template <class T>
+  size_t add(const T* src, size_t count) {
+    size_t off = align_up(bytes.size(), 64);
+    bytes.resize(off + align_up(count * sizeof(T), 64));
+    if (count) std::memcpy(bytes.data() + off, src, count * sizeof(T));
+    return off;
+  }
+};
+
+// Uploads the blob; returns the device base address.  Eager calls use a ring
+// of pinned slots (a slot is reused only after the call that used it has
+// finished on the GPU); during capture the blob gets its own device buffer,
+// filled before the graph exists, so the graph holds no copy node.
+mpc_status upload(mpc_ctx* c, const Blob& b, uint8_t** dev) {
+  const size_t n = std::max<size_t>(b.bytes.size(), 64);
+  if (c->capturing) {
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, n));
+    c->capture_allocs.push_back(d);
+    HIPCHK(hipMemcpyAsync(d, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice, c->side));
+    HIPCHK(hipStreamSynchronize(c->side));
+    *dev = (uint8_t*)d;
+    return MPC_OK;
+  }
+  UploadSlot& sl = c->slots[c->next_slot];
+  c->cur_slot = c->next_slot;
+  c->next_slot = (c->next_slot + 1) % kSlots;
+  if (sl.pending) {
+    HIPCHK(hipEventSynchronize(sl.done));
+    sl.pending = false;
+  }
+  if (sl.cap < n) {
+    if (sl.host) HIPCHK(hipHostFree(sl.host));
+    if (sl.dev) HIPCHK(hipFree(sl.dev));
+    sl.host = sl.dev = nullptr;
+    sl.cap = 0;
+    const size_t cap = align_up(n * 2, 1 << 16);
+    HIPCHK(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
+    HIPCHK(hipMalloc(&sl.dev, cap));
+    sl.cap = cap;
+  }
+  std::memcpy(sl.host, b.bytes.data(), b.bytes.size());
+  HIPCHK(hipMemcpyAsync(sl.dev, sl.host, b.bytes.size(), hipMemcpyHostToDevice, c->s[0]));
+  *dev = (uint8_t*)sl.dev;
+  return MPC_OK;
+}
+
+// Marks the end of a call: the current upload slot may be reused once party
+// 0's stream passes this point.
+mpc_status end_call(mpc_ctx* c) {
+  if (c->cur_slot >= 0 && !c->capturing) {
+    UploadSlot& sl = c->slots[c->cur_slot];
+    HIPCHK(hipEventRecord(sl.done, c->s[0]));
+    sl.pending = true;
+  }
+  c->cur_slot = -1;
+  return MPC_OK;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
+
+mpc_status check_ptr(const void* p, size_t n) {
+  if (n == 0) return MPC_OK;
+  if (!p || !aligned8(p)) return MPC_E_INVAL;
+  return MPC_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + na * 8, b0 = (uintptr_t)b, b1 = b0 + nb * 8;
+  return a0 < b1 && b0 < a1;
+}
+
+mpc_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return MPC_OK;
+  g_last_hip_error = (int)e;
+  return MPC_E_HIP;
+}
+
+mpc_status take_event(mpc_ctx* c, hipEvent_t* e) {
+  if (!c->event_pool.empty()) {
+    *e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return MPC_OK;
+  }
+  HIPCHK(hipEventCreate(e));
+  return MPC_OK;
+}
+
+// Brackets one GEMM launch with events when profiling (never inside a capture).
+struct LaunchTimer {
+  mpc_ctx* c;
+  bool on;
+  mpc_ctx::TimedLaunch rec{};
+  LaunchTimer(mpc_ctx* ctx, int form, double macs) : c(ctx), on(ctx->profiling && !ctx->capturing) {
+    rec.form = form;
+    rec.ring_macs = macs;
+  }
+  mpc_status start() {
+    if (!on) return MPC_OK;
+    CHK(take_event(c, &rec.start));
+    CHK(take_event(c, &rec.stop));
+    HIPCHK(hipEventRecord(rec.start, c->s[0]));
+    return MPC_OK;
+  }
+  mpc_status stop() {
+    if (!on) return MPC_OK;
+    HIPCHK(hipEventRecord(rec.stop, c->s[0]));
+    c->timed.push_back(rec);
+    return MPC_OK;
+  }
+};
+
+OutView rowmajor_view(i64 N) { return OutView{N, std::max<i64>(N, 1), 0}; }
+
+mpc_form resolve_form(mpc_form f, i64 M, i64 N, i64 K) {
+  if (f != MPC_FORM_AUTO) return f;
+  const double work = (double)M * (double)N * (double)K;
+  return work >= (double)(1 << 22) ? MPC_FORM_LIMB8 : MPC_FORM_PLAIN;
+}
+
+// ------------------------------------------------------------------ GEMM issue
+// A ring GEMM request in terms of uint64 operands; both forms are built from it.
+struct Operand {
+  int kind;  // kPackRow (left, row-major), kPackCol (right, row-major KxN), kPackIm2col
+  const u64* src;
+  const u64* add;
+  i64 ld;
+  i64 cin, len, ksz, stride, lout;  // im2col geometry
+};
+
+struct GemmReq {
+  i64 M, N, K0, K1;
+  Operand A0, A1, B0, B1;  // A1/B1 unused when K1 == 0
+  Epilogue ep;
+};
+
+Operand left_rowmajor(const u64* p, i64 ld, const u64* add = nullptr) {
+  Operand o{};
+  o.kind = kPackRow;
+  o.src = p;
+  o.add = add;
+  o.ld = ld;
+  return o;
+}
+Operand right_rowmajor(const u64* p, i64 ld, const u64* add = nullptr) {
+  Operand o{};
+  o.kind = kPackCol;
+  o.src = p;
+  o.add = add;
+  o.ld = ld;
+  return o;
+}
+Operand right_im2col(const u64* p, const u64* add, const mpc_conv1d_shape& s, i64 lout) {
+  Operand o{};
+  o.kind = kPackIm2col;
+  o.src = p;
+  o.add = add;
+  o.cin = s.cin;
+  o.len = s.length;
+  o.ksz = s.ksize;
+  o.stride = s.stride;
+  o.lout = lout;
+  return o;
+}
+
+// Workspace needed to issue `reqs` in the given form (im2col operands of the
+// plain form are materialised; the limb form packs every distinct operand).
+struct Plan {
+  // distinct operands are identified by (kind, src, add) so shared ones (eps,
+  // delta) are packed or lowered once.
+  std::vector<Operand> ops;
+  std::vector<i64> op_rows, op_k;
+  int find_or_add(const Operand& o, i64 rows, i64 K) {
+    for (size_t i = 0; i < ops.size(); ++i)
+      if (ops[i].kind == o.kind && ops[i].src == o.src && ops[i].add == o.add && op_rows[i] == rows &&
+          op_k[i] == K)
+        return (int)i;
+    ops.push_back(o);
+    op_rows.push_back(rows);
+    op_k.push_back(K);
+    return (int)ops.size() - 1;
+  }
+};
+
+size_t packed_bytes(i64 rows, i64 K) { return (size_t)limb_rblocks(rows) * limb_kblocks(K) * kLimbBlockBytes; }
+
+// Issues a list of ring GEMMs (one launch per K chunk) on party 0's stream.
+// The workspace region starting at `cv` must be reserved by the caller with
+// gemm_ws_bytes().
+size_t gemm_ws_bytes(const std::vector<GemmReq>& reqs, mpc_form form) {
+  Plan plan;
+  size_t bytes = 0;
+  for (const GemmReq& r : reqs) {
+    const Operand* A[2] = {&r.A0, &r.A1};
+    const Operand* B[2] = {&r.B0, &r.B1};
+    const i64 Ks[2] = {r.K0, r.K1};
+    for (int sgm = 0; sgm < 2; ++sgm) {
+      if (sgm == 1 && r.K1 == 0) break;
+      const int na = (int)plan.ops.size();
+      int ia = plan.find_or_add(*A[sgm], r.M, Ks[sgm]);
+      if (ia == na) bytes += form == MPC_FORM_LIMB8 ? align_up(packed_bytes(r.M, Ks[sgm])) : 0;
+      const int nb = (int)plan.ops.size();
+      int ib = plan.find_or_add(*B[sgm], r.N, Ks[sgm]);
+      if (ib == nb) {
+        if (form == MPC_FORM_LIMB8) bytes += align_up(packed_bytes(r.N, Ks[sgm]));
+        else if (B[sgm]->kind == kPackIm2col) bytes += align_up((size_t)(Ks[sgm] * r.N) * 8);
+      }
+    }
+  }
+  return bytes;
+}
+
+mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form form, Carve& cv,
+                       Blob& blob, std::vector<std::pair<int, size_t>>* /*unused*/ = nullptr) {
+  hipStream_t st = c->s[0];
+  const size_t nreq = reqs.size();
+  if (!nreq) return MPC_OK;
+  Plan plan;
+  std::vector<int> ia[2], ib[2];
+  for (int s = 0; s < 2; ++s) {
+    ia[s].assign(nreq, -1);
+    ib[s].assign(nreq, -1);
+  }
+  for (size_t q = 0; q < nreq; ++q) {
+    const GemmReq& r = reqs[q];
+    ia[0][q] = plan.find_or_add(r.A0, r.M, r.K0);
+    ib[0][q] = plan.find_or_add(r.B0, r.N, r.K0);
+    if (r.K1) {
+      ia[1][q] = plan.find_or_add(r.A1, r.M, r.K1);
+      ib[1][q] = plan.find_or_add(r.B1, r.N, r.K1);
+    }
+  }
+  const size_t nops = plan.ops.size();
+
+  if (form == MPC_FORM_PLAIN) {
+    // materialise im2col operands, then one plain launch
+    std::vector<const u64*> mat(nops, nullptr);
+    for (size_t i = 0; i < nops; ++i) {
+      const Operand& o = plan.ops[i];
+      if (o.kind == kPackIm2col) {
+        const i64 K = plan.op_k[i], N = plan.op_rows[i];
+        u64* col = cv.take<u64>((size_t)(K * N));
+        const i64 B = o.lout ? N / o.lout : 0;
+        CHK(hip_status(launch_im2col(st, o.src, o.add, B, o.cin, o.len, o.ksz, o.stride, o.lout, col)));
+        c->stats.launches++;
+        mat[i] = col;
+      }
+    }
+    std::vector<PlainProblem> probs(nreq);
+    std::vector<int> tstart(nreq + 1, 0);
+    for (size_t q = 0; q < nreq; ++q) {
+      const GemmReq& r = reqs[q];
+      PlainProblem& p = probs[q];
+      p.M = r.M;
+      p.N = r.N;
+      p.K0 = r.K0;
+      p.K1 = r.K1;
+      auto seg_a = [&](int s, const u64** ptr, const u64** add, i64* ld) {
+        const Operand& o = plan.ops[ia[s][q]];
+        *ptr = o.src;
+        *add = o.add;
+        *ld = o.ld;
+      };
+      auto seg_b = [&](int s, const u64** ptr, const u64** add, i64* ld) {
+        const int i = ib[s][q];
+        const Operand& o = plan.ops[i];
+        if (o.kind == kPackIm2col) {
+          *ptr = mat[i];
+          *add = nullptr;
+          *ld = r.N;
+        } else {
+          *ptr = o.src;
+          *add = o.add;
+          *ld = o.ld;
+        }
+      };
+      seg_a(0, &p.A0, &p.A0add, &p.lda0);
+      seg_b(0, &p.B0, &p.B0add, &p.ldb0);
+      if (r.K1) {
+        const u64* dummy;
+        seg_a(1, &p.A1, &dummy, &p.lda1);
+        seg_b(1, &p.B1, &dummy, &p.ldb1);
+        if (plan.ops[ia[1][q]].add || (plan.ops[ib[1][q]].add && plan.ops[ib[1][q]].kind != kPackIm2col))
+          return MPC_E_UNSUPPORTED;  // second segments never carry an addend
+      } else {
+        p.A1 = nullptr;
+        p.B1 = nullptr;
+        p.lda1 = p.ldb1 = 0;
+      }
+      p.ep = r.ep;
+      tstart[q + 1] = tstart[q] + plain_tiles(r.M, r.N);
+    }
+    const size_t oprob = blob.add(probs.data(), nreq);
+    const size_t otile = blob.add(tstart.data(), nreq + 1);
+    uint8_t* dev = nullptr;
+    CHK(upload(c, blob, &dev));
+    TileMap map{(int)nreq, (const int*)(dev + otile)};
+    double macs = 0;
+    for (const GemmReq& r : reqs) macs += (double)r.M * (double)r.N * (double)(r.K0 + r.K1);
+    LaunchTimer tm(c, MPC_FORM_PLAIN, macs);
+    CHK(tm.start());
+    CHK(hip_status(launch_plain_gemm(st, (const PlainProblem*)(dev + oprob), map, tstart[nreq])));
+    CHK(tm.stop());
+    c->stats.launches++;
+    c->stats.gemm_problems += nreq;
+    return MPC_OK;
+  }
+
+  // ---- limb form: pack every distinct operand, then chunked GEMM launches
+  std::vector<PackJob> jobs(nops);
+  std::vector<i64> bstart(nops + 1, 0);
+  for (size_t i = 0; i < nops; ++i) {
+    const Operand& o = plan.ops[i];
+    PackJob& j = jobs[i];
+    j.kind = o.kind;
+    j.rows = plan.op_rows[i];
+    j.K = plan.op_k[i];
+    j.src = o.src;
+    j.add = o.add;
+    j.ld = o.ld;
+    j.cin = o.cin;
+    j.len = o.len;
+    j.ksz = o.ksz;
+    j.stride = o.stride;
+    j.lout = o.lout;
+    j.rblocks = limb_rblocks(j.rows);
+    j.kblocks = limb_kblocks(j.K);
+    j.dst = cv.take<uint8_t>((size_t)(j.rblocks * j.kblocks) * kLimbBlockBytes);
+    bstart[i + 1] = bstart[i] + j.rblocks * j.kblocks;
+  }
+  // chunk plan
+  int max_chunks = 1;
+  std::vector<int> nchunks(nreq);
+  for (size_t q = 0; q < nreq; ++q) {
+    const int kbt = (int)(limb_kblocks(reqs[q].K0) + (reqs[q].K1 ? limb_kblocks(reqs[q].K1) : 0));
+    nchunks[q] = std::max(1, (kbt + kLimbMaxKBlocks - 1) / kLimbMaxKBlocks);
+    max_chunks = std::max(max_chunks, nchunks[q]);
+  }
+  const size_t ojobs = blob.add(jobs.data(), nops);
+  const size_t obstart = blob.add(bstart.data(), nops + 1);
+  std::vector<size_t> oprob(max_chunks), otile(max_chunks);
+  std::vector<int> ttotal(max_chunks, 0), tcount(max_chunks, 0);
+  std::vector<double> cmacs(max_chunks, 0.0);
+  for (int ch = 0; ch < max_chunks; ++ch) {
+    std::vector<LimbProblem> probs;
+    std::vector<int> tstart(1, 0);
+    for (size_t q = 0; q < nreq; ++q) {
+      if (ch >= nchunks[q]) continue;
+      const GemmReq& r = reqs[q];
+      LimbProblem p{};
+      p.M = r.M;
+      p.N = r.N;
+      p.kb0 = (int)limb_kblocks(r.K0);
+      p.kb1 = r.K1 ? (int)limb_kblocks(r.K1) : 0;
+      const int kbt = p.kb0 + p.kb1;
+      p.kb_begin = ch * kLimbMaxKBlocks;
+      p.kb_end = std::min(kbt, (ch + 1) * kLimbMaxKBlocks);
+      if (p.kb_begin > p.kb_end) p.kb_begin = p.kb_end;
+      p.PA0 = jobs[ia[0][q]].dst;
+      p.PB0 = jobs[ib[0][q]].dst;
+      p.PA1 = r.K1 ? jobs[ia[1][q]].dst : nullptr;
+      p.PB1 = r.K1 ? jobs[ib[1][q]].dst : nullptr;
+      p.mblocks = limb_rblocks(r.M);
+      p.nblocks = limb_rblocks(r.N);
+      p.ep = r.ep;
+      if (ch > 0) {
+        p.ep.accumulate = 1;
+        p.ep.Cadd = nullptr;
+      }
+      if (ch + 1 < nchunks[q]) p.ep.trunc_bits = 0;
+      probs.push_back(p);
+      tstart.push_back(tstart.back() + limb_tiles(r.M, r.N));
+      // true (unpadded) k values covered by this chunk
+      const i64 Kt = r.K0 + r.K1;
+      auto true_k = [&](i64 kb) {  // true k values before concatenated k-block kb
+        const i64 kb0 = p.kb0;
+        return kb <= kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - kb0) * 32, r.K1);
+      };
+      const i64 kspan = std::min(Kt, true_k(p.kb_end)) - std::min(Kt, true_k(p.kb_begin));
+      cmacs[ch] += (double)r.M * (double)r.N * (double)kspan;
+    }
+    oprob[ch] = blob.add(probs.data(), probs.size());
+    otile[ch] = blob.add(tstart.data(), tstart.size());
+    ttotal[ch] = tstart.back();
+    tcount[ch] = (int)probs.size();
+  }
+  uint8_t* dev = nullptr;
+  CHK(upload(c, blob, &dev));
+  CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs), (const i64*)(dev + obstart), (int)nops,
+                             bstart[nops])));
+  c->stats.launches++;
+  for (int ch = 0; ch < max_chunks; ++ch) {
+    TileMap map{tcount[ch], (const int*)(dev + otile[ch])};
+    LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[ch]);
+    CHK(tm.start());
+    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[ch]), map, ttotal[ch], c->num_cu)));
+    CHK(tm.stop());
+    c->stats.launches++;
+  }
+  c->stats.gemm_problems += nreq;
+  return MPC_OK;
+}
+
+mpc_status check_trunc(int bits) { return (bits < 0 || bits > 63) ? MPC_E_INVAL : MPC_OK; }
+mpc_status check_form(mpc_form f) {
+  return (f == MPC_FORM_PLAIN || f == MPC_FORM_LIMB8 || f == MPC_FORM_AUTO) ? MPC_OK : MPC_E_INVAL;
+}
+
+Epilogue make_ep(const u64* cadd, int csign, int trunc, u64* out, OutView v) {
+  Epilogue e{};
+  e.Cadd = cadd;
+  e.csign = csign;
+  e.trunc_bits = trunc;
+  e.accumulate = 0;
+  e.Out = out;
+  e.view = v;
+  return e;
+}
+
+i64 conv_lout(const mpc_conv1d_shape& s) {
+  return s.length < s.ksize ? 0 : (s.length - s.ksize) / s.stride + 1;
+}
+
+mpc_status check_conv(const mpc_conv1d_shape* s) {
+  if (!s) return MPC_E_INVAL;
+  if (s->batch < 0 || s->cin < 0 || s->length < 0 || s->cout < 0 || s->ksize <= 0 || s->stride <= 0)
+    return MPC_E_SHAPE;
+  return MPC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== API
+extern "C" {
+
+const char* mpc_status_str(mpc_status s) {
+  switch (s) {
+    case MPC_OK: return "ok";
+    case MPC_E_INVAL: return "invalid argument";
+    case MPC_E_SHAPE: return "invalid shape";
+    case MPC_E_ALIAS: return "output overlaps an input";
+    case MPC_E_NOMEM: return "workspace allocation failed";
+    case MPC_E_HIP: return "HIP runtime error";
+    case MPC_E_UNSUPPORTED: return "unsupported";
+    case MPC_E_RANGE: return "value outside the fixed-point range";
+  }
+  return "unknown status";
+}
+
+int mpc_last_hip_error(void) { return g_last_hip_error; }
+
+mpc_status mpc_encode(const double* x, size_t n, int frac_bits, int64_t* out) {
+  if (n && (!x || !out)) return MPC_E_INVAL;
+  if (frac_bits < 0 || frac_bits > 62) return MPC_E_INVAL;
+  const double scale = std::ldexp(1.0, frac_bits);
+  for (size_t i = 0; i < n; ++i) {
+    const double r = std::nearbyint(x[i] * scale);  // ties to even in the default mode
+    if (!(r >= -9223372036854775808.0 && r < 9223372036854775808.0)) return MPC_E_RANGE;
+    out[i] = (int64_t)r;
+  }
+  return MPC_OK;
+}
+
+mpc_status mpc_decode(const int64_t* v, size_t n, int frac_bits, double* out) {
+  if (n && (!v || !out)) return MPC_E_INVAL;
+  if (frac_bits < 0 || frac_bits > 62) return MPC_E_INVAL;
+  const double inv = std::ldexp(1.0, -frac_bits);
+  for (size_t i = 0; i < n; ++i) out[i] = (double)v[i] * inv;
+  return MPC_OK;
+}
+
+mpc_status mpc_ctx_create(int device, void* stream0, void* stream1, uint64_t seed, mpc_ctx** out) {
+  if (!out) return MPC_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return MPC_E_INVAL;
+  mpc_ctx* c = new (std::nothrow) mpc_ctx();
+  if (!c) return MPC_E_NOMEM;
+  c->device = device;
+  c->seed = seed;
+  auto fail = [&](hipError_t e) {
+    g_last_hip_error = (int)e;
+    mpc_ctx_destroy(c);
+    return MPC_E_HIP;
+  };
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(e);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(e);
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // party 0: the given stream (NULL is the device's null stream); party 1: the
+  // given stream, or a stream the library creates and owns when NULL
+  c->s[0] = (hipStream_t)stream0;
+  if (stream1) {
+    c->s[1] = (hipStream_t)stream1;
+  } else {
+    e = hipStreamCreateWithFlags(&c->s[1], hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(e);
+    c->own[1] = true;
+  }
+  for (int p = 0; p < 2; ++p) {
+    e = hipEventCreateWithFlags(&c->ev[p], hipEventDisableTiming);
+    if (e != hipSuccess) return fail(e);
+  }
+  e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(e);
+  for (int i = 0; i < kSlots; ++i) {
+    e = hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(e);
+  }
+  *out = c;
+  return MPC_OK;
+}
+
+mpc_status mpc_ctx_destroy(mpc_ctx* c) {
+  if (!c) return MPC_OK;
+  (void)hipSetDevice(c->device);
+  for (int p = 0; p < 2; ++p)
+    if (c->s[p]) (void)hipStreamSynchronize(c->s[p]);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  for (int i = 0; i < kSlots; ++i) {
+    UploadSlot& sl = c->slots[i];
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+  for (void* p : c->capture_allocs) (void)hipFree(p);
+  for (auto& t : c->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->ws) (void)hipFree(c->ws);
+  for (int p = 0; p < 2; ++p) {
+    if (c->ev[p]) (void)hipEventDestroy(c->ev[p]);
+    if (c->own[p] && c->s[p]) (void)hipStreamDestroy(c->s[p]);
+  }
+  if (c->side) (void)hipStreamDestroy(c->side);
+  delete c;
+  return MPC_OK;
+}
+
+mpc_status mpc_sync(mpc_ctx* c) {
+  if (!c) return MPC_E_INVAL;
+  CHK(set_device(c));
+  return sync_all(c);
+}
+
+mpc_status mpc_ctx_stats(const mpc_ctx* c, mpc_stats* out) {
+  if (!c || !out) return MPC_E_INVAL;
+  *out = c->stats;
+  return MPC_OK;
+}
+
+mpc_status mpc_reserve(mpc_ctx* c, size_t bytes) {
+  if (!c) return MPC_E_INVAL;
+  CHK(set_device(c));
+  return ensure_ws(c, bytes);
+}
+
+// ------------------------------------------------------------------ sharing
+mpc_status mpc_share(mpc_ctx* c, const uint64_t* x, size_t n, int src, uint64_t tag, uint64_t* s0,
+                     uint64_t* s1) {
+  if (!c || (src != 0 && src != 1)) return MPC_E_INVAL;
+  CHK(check_ptr(x, n));
+  CHK(check_ptr(s0, n));
+  CHK(check_ptr(s1, n));
+  if (overlap(s0, n, x, n) || overlap(s1, n, x, n) || overlap(s0, n, s1, n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_share(c->s[0], x, n, src, stream_key(c->seed, tag, kSlotShare), s0, s1)));
+  c->stats.launches++;
+  return end_call(c);
+}
+
+mpc_status mpc_reveal(mpc_ctx* c, const uint64_t* s0, const uint64_t* s1, size_t n, uint64_t* out) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_ptr(s0, n));
+  CHK(check_ptr(s1, n));
+  CHK(check_ptr(out, n));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_reveal(c->s[0], s0, s1, n, out)));
+  c->stats.launches++;
+  return end_call(c);
+}
+
+mpc_status mpc_truncate(mpc_ctx* c, uint64_t* s0, uint64_t* s1, size_t n, int bits) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_trunc(bits));
+  CHK(check_ptr(s0, n));
+  CHK(check_ptr(s1, n));
+  if (overlap(s0, n, s1, n)) return MPC_E_ALIAS;
+  if (!n || !bits) return MPC_OK;
+  CHK(set_device(c));
+  // each party truncates its own share on its own stream: no communication
+  CHK(fork(c));
+  CHK(hip_status(launch_truncate(c->s[0], s0, n, bits)));
+  CHK(hip_status(launch_truncate(c->s[1], s1, n, bits)));
+  CHK(join(c));
+  c->stats.launches += 2;
+  c->stats.truncations++;
+  return end_call(c);
+}
+
+// ------------------------------------------------------------------ dealer
+mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, uint64_t tag,
+                              const int64_t* dims, const mpc_triple* t) {
+  if (!c || !dims || !t) return MPC_E_INVAL;
+  u64 key[6];
+  for (int sl = 0; sl < 6; ++sl) key[sl] = stream_key(dseed, tag, (u64)sl);
+  CHK(set_device(c));
+  hipStream_t st = c->s[0];
+  if (kind == MPC_TRIPLE_MUL || kind == MPC_TRIPLE_SQUARE) {
+    if (dims[0] < 0) return MPC_E_SHAPE;
+    const size_t n = (size_t)dims[0];
+    const bool sq = kind == MPC_TRIPLE_SQUARE;
+    uint64_t* bufs[6] = {t->a0, t->a1, t->b0, t->b1, t->c0, t->c1};
+    const int nb = sq ? 4 : 6;
+    for (int i = 0; i < nb; ++i) {
+      CHK(check_ptr(bufs[i], n));
+      for (int j = 0; j < i; ++j)
+        if (overlap(bufs[i], n, bufs[j], n)) return MPC_E_ALIAS;
+    }
+    if (!n) return MPC_OK;
+    if (sq) CHK(hip_status(launch_dealer_square(st, key, n, t->a0, t->a1, t->b0, t->b1)));
+    else CHK(hip_status(launch_dealer_mul(st, key, n, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1)));
+    c->stats.launches++;
+    return end_call(c);
+  }
+  if (kind != MPC_TRIPLE_MATMUL && kind != MPC_TRIPLE_CONV1D) return MPC_E_INVAL;
+
+  size_t na, nb, nc;
+  GemmReq r{};
+  mpc_conv1d_shape cs{};
+  if (kind == MPC_TRIPLE_MATMUL) {
+    const i64 M = dims[0], N = dims[1], K = dims[2];
+    if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+    na = (size_t)(M * K);
+    nb = (size_t)(K * N);
+    nc = (size_t)(M * N);
+    // c = (a0 + a1) @ (b0 + b1); c1 = c - c0
+    r.M = M;
+    r.N = N;
+    r.K0 = K;
+    r.K1 = 0;
+    r.A0 = left_rowmajor(t->a0, K, t->a1);
+    r.B0 = right_rowmajor(t->b0, N, t->b1);
+    r.ep = make_ep(t->c0, -1, 0, t->c1, rowmajor_view(N));
+  } else {
+    cs = {dims[0], dims[1], dims[2], dims[3], dims[4], dims[5]};
+    CHK(check_conv(&cs));
+    const i64 lout = conv_lout(cs);
+    na = (size_t)(cs.batch * cs.cin * cs.length);
+    nb = (size_t)(cs.cout * cs.cin * cs.ksize);
+    nc = (size_t)(cs.batch * cs.cout * lout);
+    // c = conv(a, b) = Wm(b0 + b1) @ im2col(a0 + a1) in the transposed orientation
+    r.M = cs.cout;
+    r.N = cs.batch * lout;
+    r.K0 = cs.cin * cs.ksize;
+    r.K1 = 0;
+    r.A0 = left_rowmajor(t->b0, r.K0, t->b1);
+    r.B0 = right_im2col(t->a0, t->a1, cs, lout);
+    r.ep = make_ep(t->c0, -1, 0, t->c1, OutView{lout, std::max<i64>(lout, 1), cs.cout * lout});
+  }
+  CHK(check_ptr(t->a0, na));
+  CHK(check_ptr(t->a1, na));
+  CHK(check_ptr(t->b0, nb));
+  CHK(check_ptr(t->b1, nb));
+  CHK(check_ptr(t->c0, nc));
+  CHK(check_ptr(t->c1, nc));
+  const void* bufs[6] = {t->a0, t->a1, t->b0, t->b1, t->c0, t->c1};
+  const size_t ns[6] = {na, na, nb, nb, nc, nc};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < i; ++j)
+      if (overlap(bufs[i], ns[i], bufs[j], ns[j])) return MPC_E_ALIAS;
+
+  const mpc_form form = resolve_form(MPC_FORM_AUTO, r.M, r.N, r.K0);
+  std::vector<GemmReq> reqs{r};
+  CHK(ensure_ws(c, gemm_ws_bytes(reqs, form) + kAlign));
+  CHK(hip_status(launch_prg_fill(st, key[kSlotA0], t->a0, na)));
+  CHK(hip_status(launch_prg_fill(st, key[kSlotA1], t->a1, na)));
+  CHK(hip_status(launch_prg_fill(st, key[kSlotB0], t->b0, nb)));
+  CHK(hip_status(launch_prg_fill(st, key[kSlotB1], t->b1, nb)));
+  CHK(hip_status(launch_prg_fill(st, key[kSlotC0], t->c0, nc)));
+  c->stats.launches += 5;
+  if (nc) {
+    Carve cv(c->ws);
+    Blob blob;
+    CHK(issue_gemms(c, reqs, form, cv, blob));
+  }
+  return end_call(c);
+}
+
+// ------------------------------------------------------------------ Beaver
+mpc_status mpc_beaver_mul(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64_t* x1,
+                          const uint64_t* y0, const uint64_t* y1, const mpc_triple* t, int trunc_bits,
+                          uint64_t* z0, uint64_t* z1) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  const bool sq = (y0 == nullptr && y1 == nullptr);
+  if (!sq && (y0 == nullptr || y1 == nullptr)) return MPC_E_INVAL;
+  const void* ins[10] = {x0, x1, y0, y1, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1};
+  const int nin = sq ? 8 : 10;
+  for (int i = 0; i < nin; ++i) {
+    if (sq && (i == 2 || i == 3)) continue;
+    CHK(check_ptr(ins[i], n));
+  }
+  CHK(check_ptr(z0, n));
+  CHK(check_ptr(z1, n));
+  if (overlap(z0, n, z1, n)) return MPC_E_ALIAS;
+  for (int i = 0; i < nin; ++i)
+    if (overlap(z0, n, ins[i], n) || overlap(z1, n, ins[i], n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  if (sq)
+    CHK(hip_status(launch_beaver_square(c->s[0], n, x0, x1, t->a0, t->a1, t->b0, t->b1, trunc_bits, z0, z1)));
+  else
+    CHK(hip_status(launch_beaver_mul(c->s[0], n, x0, x1, y0, y1, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1,
+                                     trunc_bits, z0, z1)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += (sq ? 1 : 2) * 8 * (uint64_t)n;
+  if (trunc_bits) c->stats.truncations++;
+  return end_call(c);
+}
+
+namespace {
+
+// Builds the open jobs and both parties' GEMM requests of one Beaver matmul.
+// Workspace: eps (MxK), g = a0 + eps (MxK), delta (KxN).
+struct MatmulPlan {
+  i64 M, N, K;
+  const u64 *x0, *x1, *y0, *y1;
+  mpc_triple t;
+  u64 *z0, *z1;
+};
+
+size_t matmul_open_bytes(const MatmulPlan& m) {
+  return 2 * align_up((size_t)(m.M * m.K) * 8) + align_up((size_t)(m.K * m.N) * 8);
+}
+
+void matmul_build(const MatmulPlan& m, Carve& cv, int trunc, std::vector<OpenJob>& opens,
+                  std::vector<GemmReq>& reqs) {
+  u64* eps = cv.take<u64>((size_t)(m.M * m.K));
+  u64* g = cv.take<u64>((size_t)(m.M * m.K));
+  u64* del = cv.take<u64>((size_t)(m.K * m.N));
+  opens.push_back(OpenJob{kOpenLeft, m.M * m.K, m.x0, m.x1, m.t.a0, m.t.a1, eps, g});
+  opens.push_back(OpenJob{kOpenRight, m.K * m.N, m.y0, m.y1, m.t.b0, m.t.b1, del, nullptr});
+  for (int p = 0; p < 2; ++p) {
+    GemmReq r{};
+    r.M = m.M;
+    r.N = m.N;
+    r.K0 = m.K;
+    r.K1 = m.K;
+    r.A0 = left_rowmajor(eps, m.K);
+    r.A1 = left_rowmajor(p == 0 ? g : m.t.a1, m.K);
+    r.B0 = right_rowmajor(p == 0 ? m.t.b0 : m.t.b1, m.N);
+    r.B1 = right_rowmajor(del, m.N);
+    r.ep = make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1, rowmajor_view(m.N));
+    reqs.push_back(r);
+  }
+}
+
+mpc_status validate_matmul(const MatmulPlan& m) {
+  if (m.M < 0 || m.N < 0 || m.K < 0) return MPC_E_SHAPE;
+  const size_t na = (size_t)(m.M * m.K), nb = (size_t)(m.K * m.N), nc = (size_t)(m.M * m.N);
+  const void* in[10] = {m.x0, m.x1, m.y0, m.y1, m.t.a0, m.t.a1, m.t.b0, m.t.b1, m.t.c0, m.t.c1};
+  const size_t ns[10] = {na, na, nb, nb, na, na, nb, nb, nc, nc};
+  for (int i = 0; i < 10; ++i) CHK(check_ptr(in[i], ns[i]));
+  CHK(check_ptr(m.z0, nc));
+  CHK(check_ptr(m.z1, nc));
+  if (overlap(m.z0, nc, m.z1, nc)) return MPC_E_ALIAS;
+  for (int i = 0; i < 10; ++i)
+    if (overlap(m.z0, nc, in[i], ns[i]) || overlap(m.z1, nc, in[i], ns[i])) return MPC_E_ALIAS;
+  return MPC_OK;
+}
+
+mpc_status run_opens(mpc_ctx* c, const std::vector<OpenJob>& opens, Blob& blob, size_t* ojobs,
+                     size_t* ostart, i64* total) {
+  std::vector<i64> cs(opens.size() + 1, 0);
+  for (size_t i = 0; i < opens.size(); ++i) cs[i + 1] = cs[i] + (opens[i].n + kOpenChunk - 1) / kOpenChunk;
+  *ojobs = blob.add(opens.data(), opens.size());
+  *ostart = blob.add(cs.data(), cs.size());
+  *total = cs.back();
+  (void)c;
+  return MPC_OK;
+}
+
+// Issues opens (one launch) and the GEMMs of all requests.
+mpc_status issue_beaver(mpc_ctx* c, const std::vector<OpenJob>& opens, const std::vector<GemmReq>& reqs,
+                        mpc_form form, Carve& cv) {
+  // The opens need their own small blob uploaded before the GEMMs' blob.
+  Blob ob;
+  size_t ojobs, ostart;
+  i64 total;
+  CHK(run_opens(c, opens, ob, &ojobs, &ostart, &total));
+  uint8_t* dev = nullptr;
+  CHK(upload(c, ob, &dev));
+  // keep this slot busy until the end of the call as well
+  const int open_slot = c->cur_slot;
+  CHK(hip_status(launch_open(c->s[0], (const OpenJob*)(dev + ojobs), (const i64*)(dev + ostart),
+                             (int)opens.size(), total)));
+  c->stats.launches++;
+  if (open_slot >= 0 && !c->capturing) {
+    HIPCHK(hipEventRecord(c->slots[open_slot].done, c->s[0]));
+    c->slots[open_slot].pending = true;
+  }
+  Blob gb;
+  return issue_gemms(c, reqs, form, cv, gb);
+}
+
+}  // namespace
+
+mpc_status mpc_beaver_matmul(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint64_t* x0,
+                             const uint64_t* x1, const uint64_t* y0, const uint64_t* y1,
+                             const mpc_triple* t, int trunc_bits, mpc_form form, uint64_t* z0,
+                             uint64_t* z1) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  CHK(check_form(form));
+  MatmulPlan m{M, N, K, x0, x1, y0, y1, *t, z0, z1};
+  CHK(validate_matmul(m));
+  if (M == 0 || N == 0) return MPC_OK;
+  CHK(set_device(c));
+  form = resolve_form(form, M, N, 2 * K);
+  // size the workspace: open outputs + GEMM operands
+  std::vector<OpenJob> opens;
+  std::vector<GemmReq> reqs;
+  {
+    Carve probe(nullptr);
+    matmul_build(m, probe, trunc_bits, opens, reqs);
+  }
+  const size_t need = matmul_open_bytes(m) + gemm_ws_bytes(reqs, form) + kAlign;
+  CHK(ensure_ws(c, need));
+  opens.clear();
+  reqs.clear();
+  Carve cv(c->ws);
+  matmul_build(m, cv, trunc_bits, opens, reqs);
+  CHK(issue_beaver(c, opens, reqs, form, cv));
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)(M * K + K * N);
+  if (trunc_bits) c->stats.truncations++;
+  return end_call(c);
+}
+
+mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const uint64_t* x0,
+                             const uint64_t* x1, const uint64_t* w0, const uint64_t* w1,
+                             const mpc_triple* t, int trunc_bits, mpc_form form, uint64_t* z0,
+                             uint64_t* z1) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_conv(shape));
+  CHK(check_trunc(trunc_bits));
+  CHK(check_form(form));
+  const mpc_conv1d_shape s = *shape;
+  const i64 lout = conv_lout(s);
+  const size_t nx = (size_t)(s.batch * s.cin * s.length), nw = (size_t)(s.cout * s.cin * s.ksize);
+  const size_t ny = (size_t)(s.batch * s.cout * lout);
+  const void* in[10] = {x0, x1, w0, w1, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1};
+  const size_t ns[10] = {nx, nx, nw, nw, nx, nx, nw, nw, ny, ny};
+  for (int i = 0; i < 10; ++i) CHK(check_ptr(in[i], ns[i]));
+  CHK(check_ptr(z0, ny));
+  CHK(check_ptr(z1, ny));
+  if (overlap(z0, ny, z1, ny)) return MPC_E_ALIAS;
+  for (int i = 0; i < 10; ++i)
+    if (overlap(z0, ny, in[i], ns[i]) || overlap(z1, ny, in[i], ns[i])) return MPC_E_ALIAS;
+  if (ny == 0) return MPC_OK;
+  CHK(set_device(c));
+  const i64 M = s.cout, N = s.batch * lout, K = s.cin * s.ksize;
+  form = resolve_form(form, M, N, 2 * K);
+
+  auto build = [&](Carve& cv, std::vector<OpenJob>& opens, std::vector<GemmReq>& reqs) {
+    // activation side: eps and g0 = a0 + eps;  weight side: delta
+    u64* eps = cv.take<u64>(nx);
+    u64* g = cv.take<u64>(nx);
+    u64* del = cv.take<u64>(nw);
+    opens.push_back(OpenJob{kOpenLeft, (i64)nx, x0, x1, t->a0, t->a1, eps, g});
+    opens.push_back(OpenJob{kOpenRight, (i64)nw, w0, w1, t->b0, t->b1, del, nullptr});
+    // z_p = c_p + Wm(b_p) @ col(eps) + Wm(delta) @ col(g_p)
+    for (int p = 0; p < 2; ++p) {
+      GemmReq r{};
+      r.M = M;
+      r.N = N;
+      r.K0 = K;
+      r.K1 = K;
+      r.A0 = left_rowmajor(p == 0 ? t->b0 : t->b1, K);
+      r.A1 = left_rowmajor(del, K);
+      r.B0 = right_im2col(eps, nullptr, s, lout);
+      r.B1 = right_im2col(p == 0 ? g : t->a1, nullptr, s, lout);
+      r.ep = make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1,
+                     OutView{lout, std::max<i64>(lout, 1), s.cout * lout});
+      reqs.push_back(r);
+    }
+  };
+  std::vector<OpenJob> opens;
+  std::vector<GemmReq> reqs;
+  {
+    Carve probe(nullptr);
+    build(probe, opens, reqs);
+  }
+  const size_t need = 2 * align_up(nx * 8) + align_up(nw * 8) + gemm_ws_bytes(reqs, form) + kAlign;
+  CHK(ensure_ws(c, need));
+  opens.clear();
+  reqs.clear();
+  Carve cv(c->ws);
+  build(cv, opens, reqs);
+  CHK(issue_beaver(c, opens, reqs, form, cv));
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)(nx + nw);
+  if (trunc_bits) c->stats.truncations++;
+  return end_call(c);
+}
+
+mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint64_t* A,
+                         const uint64_t* B, uint64_t* C, mpc_form form) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_form(form));
+  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  CHK(check_ptr(A, (size_t)(M * K)));
+  CHK(check_ptr(B, (size_t)(K * N)));
+  CHK(check_ptr(C, (size_t)(M * N)));
+  if (overlap(C, (size_t)(M * N), A, (size_t)(M * K)) || overlap(C, (size_t)(M * N), B, (size_t)(K * N)))
+    return MPC_E_ALIAS;
+  if (M == 0 || N == 0) return MPC_OK;
+  CHK(set_device(c));
+  form = resolve_form(form, M, N, K);
+  GemmReq r{};
+  r.M = M;
+  r.N = N;
+  r.K0 = K;
+  r.K1 = 0;
+  r.A0 = left_rowmajor(A, K);
+  r.B0 = right_rowmajor(B, N);
+  r.ep = make_ep(nullptr, +1, 0, C, rowmajor_view(N));
+  std::vector<GemmReq> reqs{r};
+  CHK(ensure_ws(c, gemm_ws_bytes(reqs, form) + kAlign));
+  Carve cv(c->ws);
+  Blob blob;
+  CHK(issue_gemms(c, reqs, form, cv, blob));
+  return end_call(c);
+}
+
+mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_desc* descs,
+                                     int trunc_bits, mpc_form form) {
+  if (!c || (count && !descs)) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  CHK(check_form(form));
+  if (form == MPC_FORM_AUTO) form = MPC_FORM_LIMB8;
+  std::vector<MatmulPlan> plans;
+  size_t open_bytes = 0;
+  for (size_t i = 0; i < count; ++i) {
+    const mpc_matmul_desc& d = descs[i];
+    MatmulPlan m{d.M, d.N, d.K, d.x0, d.x1, d.y0, d.y1, d.t, d.z0, d.z1};
+    CHK(validate_matmul(m));
+    if (d.M == 0 || d.N == 0) continue;
+    // outputs of different problems must not overlap either
+    for (const MatmulPlan& o : plans) {
+      const size_t a = (size_t)(m.M * m.N), b = (size_t)(o.M * o.N);
+      if (overlap(m.z0, a, o.z0, b) || overlap(m.z0, a, o.z1, b) || overlap(m.z1, a, o.z0, b) ||
+          overlap(m.z1, a, o.z1, b))
+        return MPC_E_ALIAS;
+    }
+    plans.push_back(m);
+    open_bytes += matmul_open_bytes(m);
+  }
+  if (plans.empty()) return MPC_OK;
+  CHK(set_device(c));
+  // heavy problems first, so the persistent GEMM's static rounds stay balanced
+  std::stable_sort(plans.begin(), plans.end(), [](const MatmulPlan& a, const MatmulPlan& b) {
+    return a.K > b.K;
+  });
+  std::vector<OpenJob> opens;
+  std::vector<GemmReq> reqs;
+  {
+    Carve probe(nullptr);
+    for (const MatmulPlan& m : plans) matmul_build(m, probe, trunc_bits, opens, reqs);
+  }
+  const size_t need = open_bytes + gemm_ws_bytes(reqs, form) + kAlign;
+  CHK(ensure_ws(c, need));
+  opens.clear();
+  reqs.clear();
+  Carve cv(c->ws);
+  for (const MatmulPlan& m : plans) matmul_build(m, cv, trunc_bits, opens, reqs);
+  CHK(issue_beaver(c, opens, reqs, form, cv));
+  for (const MatmulPlan& m : plans) {
+    c->stats.opens++;
+    c->stats.open_bytes_per_party += 8 * (uint64_t)(m.M * m.K + m.K * m.N);
+    if (trunc_bits) c->stats.truncations++;
+  }
+  return end_call(c);
+}
+
+// ------------------------------------------------------------------ measurement
+mpc_status mpc_profile_enable(mpc_ctx* c, int on) {
+  if (!c) return MPC_E_INVAL;
+  c->profiling = on != 0;
+  return MPC_OK;
+}
+
+mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing* plain) {
+  if (!c) return MPC_E_INVAL;
+  CHK(set_device(c));
+  CHK(sync_all(c));
+  mpc_gemm_timing acc[2] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}};  // [0] plain, [1] limb8
+  for (auto& t : c->timed) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t.start, t.stop));
+    mpc_gemm_timing& a = acc[t.form == MPC_FORM_LIMB8 ? 1 : 0];
+    a.launches++;
+    a.total_ms += ms;
+    a.ring_macs += t.ring_macs;
+    c->event_pool.push_back(t.start);
+    c->event_pool.push_back(t.stop);
+  }
+  c->timed.clear();
+  if (limb8) *limb8 = acc[1];
+  if (plain) *plain = acc[0];
+  return MPC_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+mpc_status mpc_graph_begin(mpc_ctx* c) {
+  if (!c || c->capturing) return MPC_E_INVAL;
+  CHK(set_device(c));
+  // finish eager work that still uses the upload slots before capturing
+  CHK(sync_all(c));
+  HIPCHK(hipStreamBeginCapture(c->s[0], hipStreamCaptureModeRelaxed));
+  c->capturing = true;
+  return MPC_OK;
+}
+
+mpc_status mpc_graph_end(mpc_ctx* c, void** graph_exec) {
+  if (!c || !graph_exec || !c->capturing) return MPC_E_INVAL;
+  CHK(set_device(c));
+  hipGraph_t g = nullptr;
+  c->capturing = false;
+  HIPCHK(hipStreamEndCapture(c->s[0], &g));
+  hipGraphExec_t ge = nullptr;
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_status(e);
+  *graph_exec = (void*)ge;
+  return MPC_OK;
+}
+
+mpc_status mpc_graph_launch(mpc_ctx* c, void* graph_exec) {
+  if (!c || !graph_exec) return MPC_E_INVAL;
+  CHK(set_device(c));
+  HIPCHK(hipGraphLaunch((hipGraphExec_t)graph_exec, c->s[0]));
+  return MPC_OK;
+}
+
+mpc_status mpc_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return MPC_OK;
+  HIPCHK(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+  return MPC_OK;
+}
+
+}  // extern "C"

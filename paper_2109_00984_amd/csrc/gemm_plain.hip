@@ -1,0 +1,156 @@
+// gemm_plain.hip -- ring GEMM over Z/2^64 on the vector ALUs (the "plain" form).
+//
+// C = [A0 (+A0add) | A1] @ [B0 (+B0add) ; B1] mod 2^64 for a list of problems
+// in one launch.  A 256-thread workgroup computes a 128x64 tile; each thread
+// owns an 8x4 register block.  Operand tiles of 16 k are staged through LDS
+// (the left tile stored k-major) with the next tile prefetched into registers.
+//
+// One ring multiply-accumulate a*b on 32-bit halves a = aL + 2^32 aH,
+// b = bL + 2^32 bH:  a*b = aL*bL + 2^32 (aL*bH + aH*bL)  (mod 2^64).  The full
+// aL*bL goes into a 64-bit accumulator (v_mad_u64_u32); the cross terms only
+// matter modulo 2^32 and go into a 32-bit accumulator that is shifted in once
+// at the end.
+#include "internal.h"
+
+namespace mpc {
+namespace {
+
+constexpr int BM = 128, BN = 64, BK = 16;
+constexpr int TM = 8, TN = 4;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int find_problem(const int* __restrict__ start, int nprob, int t) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ u64 load_a(const PlainProblem& p, i64 m, i64 k) {
+  if (m >= p.M) return 0;
+  if (k < p.K0) {
+    u64 v = p.A0[m * p.lda0 + k];
+    if (p.A0add) v += p.A0add[m * p.lda0 + k];
+    return v;
+  }
+  if (k < p.K0 + p.K1) return p.A1[m * p.lda1 + (k - p.K0)];
+  return 0;
+}
+
+__device__ __forceinline__ u64 load_b(const PlainProblem& p, i64 k, i64 n) {
+  if (n >= p.N) return 0;
+  if (k < p.K0) {
+    u64 v = p.B0[k * p.ldb0 + n];
+    if (p.B0add) v += p.B0add[k * p.ldb0 + n];
+    return v;
+  }
+  if (k < p.K0 + p.K1) return p.B1[(k - p.K0) * p.ldb1 + n];
+  return 0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_plain_gemm(const PlainProblem* __restrict__ probs, TileMap map) {
+  __shared__ u64 As[BK][BM];
+  __shared__ u64 Bs[BK][BN];
+
+  const int t = blockIdx.x;
+  const int pi = find_problem(map.tile_start, map.nprob, t);
+  const PlainProblem p = probs[pi];
+  const int local = t - map.tile_start[pi];
+  const int ntn = (int)((p.N + BN - 1) / BN);
+  const i64 m0 = (i64)(local / ntn) * BM, n0 = (i64)(local % ntn) * BN;
+  const i64 Ktot = p.K0 + p.K1;
+
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  // loader coordinates
+  const int la_row = tid >> 1, la_k = (tid & 1) * 8;  // 8 consecutive k of one row
+  const int lb_k = tid >> 4, lb_n = (tid & 15) * 4;   // 4 consecutive n of one k
+
+  u64 ra[8], rb[4];
+  auto fetch = [&](i64 k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = load_a(p, m0 + la_row, k0 + la_k + q);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = load_b(p, k0 + lb_k, n0 + lb_n + q);
+  };
+
+  u64 lo[TM][TN];
+  u32 cr[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      lo[i][j] = 0;
+      cr[i][j] = 0;
+    }
+
+  if (Ktot > 0) fetch(0);
+  for (i64 k0 = 0; k0 < Ktot; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[la_k + q][la_row] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[lb_k][lb_n + q] = rb[q];
+    __syncthreads();
+    if (k0 + BK < Ktot) fetch(k0 + BK);
+#pragma unroll 4
+    for (int kk = 0; kk < BK; ++kk) {
+      u64 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const u32 al = (u32)a[i], ah = (u32)(a[i] >> 32);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const u32 bl = (u32)b[j], bh = (u32)(b[j] >> 32);
+          lo[i][j] += (u64)al * (u64)bl;
+          cr[i][j] += al * bh + ah * bl;
+        }
+      }
+    }
+  }
+
+  const Epilogue& ep = p.ep;
+  i64 coff[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const i64 n = n0 + tx + 16 * j;
+    coff[j] = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const i64 m = m0 + ty + 16 * i;
+    if (m >= p.M) continue;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const i64 n = n0 + tx + 16 * j;
+      if (n >= p.N) continue;
+      const i64 off = m * ep.view.ld_m + coff[j];
+      u64 v = lo[i][j] + ((u64)cr[i][j] << 32);
+      if (ep.accumulate) v += ep.Out[off];
+      if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
+      if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
+      ep.Out[off] = v;
+    }
+  }
+}
+
+}  // namespace
+
+int plain_tiles(i64 M, i64 N) { return (int)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)); }
+
+hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
+                             int total_tiles) {
+  if (total_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plain_gemm, dim3(total_tiles), dim3(kThreads), 0, s, probs, map);
+  return hipGetLastError();
+}
+
+}  // namespace mpc

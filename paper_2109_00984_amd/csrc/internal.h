@@ -1,0 +1,186 @@
+// internal.h -- shared declarations of libmpc's HIP sources (not installed).
+//
+// Ring elements are uint64; every kernel is integer-only.  The launchers
+// declared here are defined in the .hip files and called by api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mpc {
+
+using u64 = uint64_t;
+using i64 = int64_t;
+using u32 = uint32_t;
+
+// ---------------------------------------------------------------- PRG
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014).  A stream with state s
+// returns mix(s + (i+1)*gamma) as its i-th output.  Domains nest: the key of
+// (seed, tag, slot) is out_slot(out_tag(seed)) and element i is out_i(key).
+constexpr u64 kGamma = 0x9e3779b97f4a7c15ULL;
+
+__host__ __device__ __forceinline__ u64 sm_mix(u64 z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ u64 sm_out(u64 s, u64 i) { return sm_mix(s + (i + 1) * kGamma); }
+inline u64 stream_key(u64 seed, u64 tag, u64 slot) { return sm_out(sm_out(seed, tag), slot); }
+
+enum Slot : u64 { kSlotShare = 0, kSlotA0 = 1, kSlotA1 = 2, kSlotB0 = 3, kSlotB1 = 4, kSlotC0 = 5 };
+
+// ---------------------------------------------------------------- views
+// Element (m, n) of a GEMM output (and of its additive term) lives at
+//   m * ld_m + (n / n_div) * ld_q + (n % n_div).
+// A row-major MxN matrix is {N, N, 0} (or any ld); the transposed conv1d output
+// [B][Cout][Lout] with m = cout and n = b*Lout + l is {Lout, Lout, Cout*Lout}.
+struct OutView {
+  i64 ld_m, n_div, ld_q;
+};
+
+// Epilogue shared by both GEMM forms:
+//   v = acc (+ Out if accumulate) (+ csign * Cadd);  if (trunc) v = s64(v) >> trunc
+struct Epilogue {
+  const u64* Cadd;  // may be null
+  int csign;        // +1 or -1
+  int trunc_bits;   // 0 = none
+  int accumulate;   // add the current contents of Out (continuation of a K chunk)
+  u64* Out;
+  OutView view;
+};
+
+// Plain-form problem: C = [A0 (+A0add) | A1] @ [B0 (+B0add) ; B1], row-major
+// segments.  K1 may be 0 (then A1/B1 are unused).
+struct PlainProblem {
+  i64 M, N, K0, K1;
+  const u64* A0;
+  const u64* A0add;
+  i64 lda0;
+  const u64* A1;
+  i64 lda1;
+  const u64* B0;
+  const u64* B0add;
+  i64 ldb0;
+  const u64* B1;
+  i64 ldb1;
+  Epilogue ep;
+};
+
+// ---------------------------------------------------------------- limb packing
+// A packed operand holds, for every 32x32 block of a matrix (32 rows x 32 k
+// for a left operand, 32 k x 32 cols for a right operand), eight 1 KiB planes
+// of signed 8-bit limbs.  Inside a plane the 64 lanes of a wavefront each own
+// 16 bytes: lane l covers row (or col) l % 32 and k = (l / 32) * 16 + [0, 16).
+// Block (rb, kb) starts at byte ((rb * kblocks + kb) << 13).  Rows, cols and k
+// are padded with zeros (the limbs of 0 are all 0) to whole blocks; row and
+// col block counts are further padded to a multiple of kLimbRowPad blocks.
+constexpr int kLimbBlockBytes = 8192;
+constexpr int kLimbRowPad = 4;
+
+// Source of a pack job: element (r, k) of the logical operand.
+//   kind ROW: left operand MxK at src[r*ld + k] (+ add[...])
+//   kind COL: right operand KxN at src[k*ld + n] (+ add[...]); r is the column
+//   kind IM2COL: right operand, k = c*ksz + j, n = b*Lout + l, element
+//                x[b][c][l*stride + j] of a [B][Cin][L] activation (+ add)
+enum PackKind : int { kPackRow = 0, kPackCol = 1, kPackIm2col = 2 };
+
+struct PackJob {
+  int kind;
+  i64 rows;  // M for ROW, N for COL/IM2COL (the non-k dimension)
+  i64 K;
+  const u64* src;
+  const u64* add;
+  i64 ld;
+  // im2col geometry
+  i64 cin, len, ksz, stride, lout;
+  uint8_t* dst;
+  i64 rblocks;  // padded block counts
+  i64 kblocks;
+};
+
+// Limb-form problem over packed segments; k-blocks [kb_begin, kb_end) of the
+// concatenation [segment 0 | segment 1] are processed (K chunking).
+struct LimbProblem {
+  i64 M, N;
+  int kb0, kb1;  // k-blocks of segment 0 and 1
+  int kb_begin, kb_end;
+  const uint8_t* PA0;
+  const uint8_t* PA1;
+  const uint8_t* PB0;
+  const uint8_t* PB1;
+  i64 mblocks;  // padded row blocks of the left operand
+  i64 nblocks;  // padded col blocks of the right operand
+  Epilogue ep;
+};
+
+// Largest number of concatenated k values one limb launch may cover: with all
+// limbs -128 a diagonal of 8 pairs adds 8 * 2^14 per k, so 16320 * 2^17 < 2^31.
+constexpr int kLimbMaxKBlocks = 510;  // 510 * 32 = 16320
+
+// Tile-to-problem table for grouped launches.
+struct TileMap {
+  int nprob;
+  const int* tile_start;  // device, nprob+1 entries
+};
+
+// ---------------------------------------------------------------- launchers
+// Element-wise kernels (elementwise.hip).  All take the stream to launch on.
+hipError_t launch_prg_fill(hipStream_t s, u64 key, u64* out, size_t n);
+hipError_t launch_share(hipStream_t s, const u64* x, size_t n, int src, u64 key, u64* s0, u64* s1);
+hipError_t launch_reveal(hipStream_t s, const u64* s0, const u64* s1, size_t n, u64* out);
+hipError_t launch_truncate(hipStream_t s, u64* v, size_t n, int bits);
+hipError_t launch_dealer_mul(hipStream_t s, const u64 key[6], size_t n, u64* a0, u64* a1, u64* b0,
+                             u64* b1, u64* c0, u64* c1);
+hipError_t launch_dealer_square(hipStream_t s, const u64 key[6], size_t n, u64* a0, u64* a1,
+                                u64* b0, u64* b1);
+hipError_t launch_beaver_mul(hipStream_t s, size_t n, const u64* x0, const u64* x1, const u64* y0,
+                             const u64* y1, const u64* a0, const u64* a1, const u64* b0,
+                             const u64* b1, const u64* c0, const u64* c1, int trunc, u64* z0,
+                             u64* z1);
+hipError_t launch_beaver_square(hipStream_t s, size_t n, const u64* x0, const u64* x1,
+                                const u64* a0, const u64* a1, const u64* b0, const u64* b1,
+                                int trunc, u64* z0, u64* z1);
+// Open step of Beaver bilinear products, many operands per launch.  A job of
+// kind kOpenLeft writes eps = (x0-a0)+(x1-a1) to out0 and g = a0 + eps to
+// out1; kind kOpenRight writes delta = (x0-a0)+(x1-a1) to out0 only.  Jobs
+// are split into chunks of kOpenChunk elements; chunk_start (njobs+1 prefix
+// sums of per-job chunk counts) and jobs are device arrays.
+enum OpenKind : int { kOpenLeft = 0, kOpenRight = 1 };
+struct OpenJob {
+  int kind;
+  i64 n;
+  const u64* x0;
+  const u64* x1;
+  const u64* a0;
+  const u64* a1;
+  u64* out0;
+  u64* out1;
+};
+constexpr i64 kOpenChunk = 4096;
+hipError_t launch_open(hipStream_t s, const OpenJob* jobs, const i64* chunk_start, int njobs,
+                       i64 total_chunks);
+// col[k][n] = x[b][c][l*stride + j] (+ add) with k = c*ksz + j, n = b*Lout + l
+hipError_t launch_im2col(hipStream_t s, const u64* x, const u64* add, i64 B, i64 cin, i64 len,
+                         i64 ksz, i64 stride, i64 lout, u64* col);
+// out = x + y
+hipError_t launch_add(hipStream_t s, const u64* x, const u64* y, size_t n, u64* out);
+
+// Plain ring GEMM (gemm_plain.hip): one launch over all problems of `probs`
+// (a device array), tiles listed by `map`.
+hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
+                             int total_tiles);
+int plain_tiles(i64 M, i64 N);
+
+// Limb form (gemm_limb.hip).
+// jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device arrays.
+hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
+                       i64 total_blocks);
+hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
+                            int grid);
+int limb_tiles(i64 M, i64 N);
+i64 limb_rblocks(i64 rows);  // padded 32-row block count
+i64 limb_kblocks(i64 K);
+
+}  // namespace mpc

@@ -1,0 +1,293 @@
+"""GPU parity: every library call against the CPU oracle on identical seeded
+inputs, bit for bit (ring results are exact, so the tolerance is zero)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_util import dev, host, pair, say
+
+pytestmark = pytest.mark.gpu
+
+SEED = 2024
+EDGE = np.array([0, 1, 2, (1 << 63) - 1, 1 << 63, (1 << 64) - 1, 0x7F7F7F7F7F7F7F80,
+                 0x7F7F7F7F7F7F7F7F, 0x8080808080808080], dtype=np.uint64)
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2109_00984_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(m):
+    c = m.Context(device=0, seed=SEED)
+    yield c
+    c.close()
+
+
+def rnd(seed, shape):
+    return workloads.uniform_u64(seed, shape)
+
+
+def shares_dev(m, sh):
+    return m.SharedPair(dev(sh[0]), dev(sh[1]))
+
+
+def triple_dev(m, t):
+    return m.TripleShares(dev(t.a[0]), dev(t.a[1]), dev(t.b[0]), dev(t.b[1]),
+                          dev(t.c[0]) if t.c is not None else None,
+                          dev(t.c[1]) if t.c is not None else None)
+
+
+def assert_pair(ctx, got, want, what):
+    g0, g1 = pair(ctx, got)
+    assert np.array_equal(g0, want[0]), f"{what}: party 0 differs"
+    assert np.array_equal(g1, want[1]), f"{what}: party 1 differs"
+
+
+# ------------------------------------------------------------------ share / reveal / truncate
+@pytest.mark.parametrize("n", [1, 9, 4096, 100003])
+@pytest.mark.parametrize("src", [0, 1])
+def test_share_reveal(m, ctx, n, src):
+    say(f"share n={n} src={src}")
+    x = np.concatenate([EDGE, rnd(n, n)])[:n]
+    s = ctx.share(dev(x), src, tag=n + src)
+    want = oracle.share(x, src, SEED, n + src)
+    assert_pair(ctx, s, want, "share")
+    r = ctx.reveal(s)
+    assert np.array_equal(host(ctx, r), x)
+
+
+@pytest.mark.parametrize("bits", [1, 16, 63])
+def test_truncate(m, ctx, bits):
+    say(f"truncate bits={bits}")
+    a, b = np.concatenate([EDGE, rnd(1, 5000)]), np.concatenate([EDGE[::-1], rnd(2, 5000)])
+    p = m.SharedPair(dev(a), dev(b))
+    ctx.truncate(p, bits)
+    assert_pair(ctx, p, (oracle.truncate(a, bits), oracle.truncate(b, bits)), "truncate")
+
+
+def test_empty_inputs(m, ctx):
+    say("empty")
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    s = ctx.share(e, 0, 1)
+    assert s.s0.numel() == 0
+    assert ctx.reveal(s).numel() == 0
+    ctx.truncate(s, 16)
+    t = ctx.dealer(m.TRIPLE_MUL, 1, 1, (0,))
+    z = ctx.beaver_mul(s, s, t, 16)
+    assert z.s0.numel() == 0
+    zt = ctx.dealer(m.TRIPLE_MATMUL, 1, 2, (0, 5, 3))
+    x = m.SharedPair(ctx.empty((0, 3)), ctx.empty((0, 3)))
+    y = m.SharedPair(ctx.empty((3, 5)), ctx.empty((3, 5)))
+    y = ctx.share(dev(rnd(3, (3, 5))), 0, 3)
+    assert ctx.beaver_matmul(x, y, zt, 16).s0.shape == (0, 5)
+    ctx.sync()
+
+
+def test_argument_errors(m, ctx):
+    say("errors")
+    x = ctx.share(dev(rnd(1, 16)), 0, 1)
+    with pytest.raises(m.MPCError):
+        ctx.truncate(x, 64)
+    with pytest.raises(m.MPCError):
+        ctx.share(dev(rnd(1, 16)), 2, 1)
+    t = ctx.dealer(m.TRIPLE_MUL, 1, 1, (16,))
+    # output aliasing an input is refused
+    with pytest.raises(m.MPCError):
+        ctx.beaver_mul(x, x, t, 16, out=m.SharedPair(x.s0, t.c1.clone()))
+    ctx.sync()
+
+
+# ------------------------------------------------------------------ dealer
+@pytest.mark.parametrize("n", [1, 4096, 65537])
+def test_dealer_elementwise(m, ctx, n):
+    say(f"dealer mul/square n={n}")
+    t = ctx.dealer(m.TRIPLE_MUL, 77, 5, (n,))
+    w = oracle.dealer_mul(77, 5, n)
+    for g, e in [(t.a0, w.a[0]), (t.a1, w.a[1]), (t.b0, w.b[0]), (t.b1, w.b[1]), (t.c0, w.c[0]),
+                 (t.c1, w.c[1])]:
+        assert np.array_equal(host(ctx, g), e)
+    s = ctx.dealer(m.TRIPLE_SQUARE, 78, 6, (n,))
+    w = oracle.dealer_square(78, 6, n)
+    for g, e in [(s.a0, w.a[0]), (s.a1, w.a[1]), (s.b0, w.b[0]), (s.b1, w.b[1])]:
+        assert np.array_equal(host(ctx, g), e)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 32, 128), (37, 53, 70), (130, 70, 300)])
+def test_dealer_matmul(m, ctx, M, N, K):
+    say(f"dealer matmul {M}x{N}x{K}")
+    t = ctx.dealer(m.TRIPLE_MATMUL, 3001, 7, (M, N, K))
+    w = oracle.dealer_matmul(3001, 7, M, N, K)
+    for g, e in [(t.a0, w.a[0]), (t.a1, w.a[1]), (t.b0, w.b[0]), (t.b1, w.b[1]), (t.c0, w.c[0]),
+                 (t.c1, w.c[1])]:
+        assert np.array_equal(host(ctx, g), e)
+
+
+# ------------------------------------------------------------------ Beaver element-wise
+@pytest.mark.parametrize("n", [1, 4096, 4099, 1 << 20])
+@pytest.mark.parametrize("trunc", [0, 16])
+def test_beaver_mul(m, ctx, n, trunc):
+    say(f"beaver mul n={n} trunc={trunc}")
+    x = oracle.encode(workloads.uniform(1001, n, -4, 4))
+    y = oracle.encode(workloads.uniform(1002, n, -4, 4))
+    xs, ys = oracle.share(x, 0, SEED, 1), oracle.share(y, 1, SEED, 2)
+    gx = ctx.share(dev(x), 0, 1)
+    gy = ctx.share(dev(y), 1, 2)
+    assert_pair(ctx, gx, xs, "share x")
+    t = ctx.dealer(m.TRIPLE_MUL, 3001, 9, (n,))
+    z = ctx.beaver_mul(gx, gy, t, trunc)
+    want = oracle.beaver_mul(xs, ys, oracle.dealer_mul(3001, 9, n), trunc)
+    assert_pair(ctx, z, want, "beaver mul")
+
+
+@pytest.mark.parametrize("n", [1, 4096, 70001])
+def test_beaver_square(m, ctx, n):
+    say(f"beaver square n={n}")
+    x = np.concatenate([EDGE, rnd(5, n)])[:n]
+    xs = oracle.share(x, 0, SEED, 3)
+    t = ctx.dealer(m.TRIPLE_SQUARE, 11, 1, (n,))
+    z = ctx.beaver_mul(ctx.share(dev(x), 0, 3), None, t, 16)
+    want = oracle.beaver_square(xs, oracle.dealer_square(11, 1, n), 16)
+    assert_pair(ctx, z, want, "beaver square")
+
+
+# ------------------------------------------------------------------ ring GEMM and Beaver matmul
+GEMM_SHAPES = [(1, 1, 1), (64, 32, 128), (37, 53, 70), (129, 65, 33), (256, 192, 160),
+               (5, 300, 17)]
+
+
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+def test_ring_gemm(m, ctx, form, M, N, K):
+    say(f"ring gemm {form} {M}x{N}x{K}")
+    A, B = rnd(M * 7 + K, (M, K)), rnd(N * 11 + K, (K, N))
+    A.ravel()[0] = 0x7F7F7F7F7F7F7F80
+    B.ravel()[0] = 0x7F7F7F7F7F7F7F80
+    C = ctx.ring_gemm(dev(A), dev(B), form=form)
+    assert np.array_equal(host(ctx, C), oracle.ring_gemm(A, B))
+
+
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+def test_ring_gemm_worst_case_limbs(m, ctx, form):
+    # every limb -128: each int8 product is 2^14, the largest the bound allows
+    say(f"ring gemm all -128 limbs {form}")
+    M, N, K = 64, 64, 8192
+    A = np.full((M, K), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    B = np.full((K, N), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    C = ctx.ring_gemm(dev(A), dev(B), form=form)
+    assert np.array_equal(host(ctx, C), oracle.ring_gemm(A, B))
+
+
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+@pytest.mark.parametrize("trunc", [0, 16])
+def test_beaver_matmul(m, ctx, form, M, N, K, trunc):
+    say(f"beaver matmul {form} {M}x{N}x{K} trunc={trunc}")
+    X = oracle.encode(workloads.uniform(M + 1, (M, K), -4, 4))
+    Y = oracle.encode(workloads.uniform(N + 2, (K, N), -4, 4))
+    xs, ys = oracle.share(X, 0, SEED, 21), oracle.share(Y, 1, SEED, 22)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 3001, 40, (M, N, K))
+    z = ctx.beaver_matmul(ctx.share(dev(X), 0, 21), ctx.share(dev(Y), 1, 22), t, trunc, form)
+    want = oracle.beaver_matmul(xs, ys, oracle.dealer_matmul(3001, 40, M, N, K), trunc)
+    assert_pair(ctx, z, want, "beaver matmul")
+
+
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+def test_beaver_matmul_k_chunked(m, ctx, form):
+    # 2K = 20000 concatenated k exceeds one limb launch's int32-safe range
+    M, N, K = 40, 24, 10000
+    say(f"beaver matmul k-chunked {form} {M}x{N}x{K}")
+    X, Y = rnd(1, (M, K)), rnd(2, (K, N))
+    xs, ys = oracle.share(X, 0, SEED, 31), oracle.share(Y, 0, SEED, 32)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 5, 41, (M, N, K))
+    z = ctx.beaver_matmul(ctx.share(dev(X), 0, 31), ctx.share(dev(Y), 0, 32), t, 16, form)
+    want = oracle.beaver_matmul(xs, ys, oracle.dealer_matmul(5, 41, M, N, K), 16)
+    assert_pair(ctx, z, want, "beaver matmul chunked")
+
+
+def test_forms_agree_and_reveal_is_product(m, ctx):
+    say("forms agree")
+    M, N, K = 96, 80, 200
+    X = oracle.encode(workloads.uniform(7, (M, K), -4, 4))
+    Y = oracle.encode(workloads.uniform(8, (K, N), -4, 4))
+    gx, gy = ctx.share(dev(X), 0, 51), ctx.share(dev(Y), 0, 52)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 9, 50, (M, N, K))
+    zp = ctx.beaver_matmul(gx, gy, t, 0, "plain")
+    zl = ctx.beaver_matmul(gx, gy, t, 0, "limb8")
+    assert_pair(ctx, zl, pair(ctx, zp), "limb vs plain")
+    r = host(ctx, ctx.reveal(zl))
+    assert np.array_equal(r, oracle.as_ring(X) @ oracle.as_ring(Y))
+
+
+def test_round_counters(m, ctx):
+    say("round counters")
+    before = ctx.stats()
+    x = ctx.share(dev(rnd(1, (8, 8))), 0, 61)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 1, 60, (8, 8, 8))
+    ctx.beaver_matmul(x, x, t, 16)
+    ctx.truncate(x, 16)
+    after = ctx.stats()
+    assert after["opens"] - before["opens"] == 1
+    assert after["open_bytes_per_party"] - before["open_bytes_per_party"] == 8 * (64 + 64)
+    assert after["truncations"] - before["truncations"] == 2
+
+
+# ------------------------------------------------------------------ conv1d
+CONV_SMALL = [(2, 3, 17, 4, 5, 2), (1, 40, 100, 16, 48, 2), (2, 8, 30, 8, 7, 1),
+              (1, 16, 40, 32, 1, 1)]
+
+
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("Bt,Cin,L,Cout,k,s", CONV_SMALL)
+def test_beaver_conv1d(m, ctx, form, Bt, Cin, L, Cout, k, s):
+    say(f"beaver conv1d {form} {(Bt, Cin, L, Cout, k, s)}")
+    X = oracle.encode(workloads.uniform(L, (Bt, Cin, L), -2, 2))
+    W = oracle.encode(workloads.uniform(k, (Cout, Cin, k), -2, 2))
+    xs, ws = oracle.share(X, 0, SEED, 71), oracle.share(W, 1, SEED, 72)
+    dims = (Bt, Cin, L, Cout, k, s)
+    t = ctx.dealer(m.TRIPLE_CONV1D, 3004, 70, dims)
+    wt = oracle.dealer_conv1d(3004, 70, *dims)
+    for g, e in [(t.a0, wt.a[0]), (t.b1, wt.b[1]), (t.c0, wt.c[0]), (t.c1, wt.c[1])]:
+        assert np.array_equal(host(ctx, g), e)
+    z = ctx.beaver_conv1d(ctx.share(dev(X), 0, 71), ctx.share(dev(W), 1, 72), t, s, 16, form)
+    want = oracle.beaver_conv1d(xs, ws, wt, s, 16)
+    assert_pair(ctx, z, want, "beaver conv1d")
+
+
+# ------------------------------------------------------------------ graph capture
+def test_graph_replay_matches_eager(m):
+    # capture needs a non-null stream for party 0: run this test on its own stream
+    say("graph replay")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = m.Context(device=0, seed=SEED)
+        M, N, K = 96, 64, 160
+        X, Y = rnd(3, (M, K)), rnd(4, (K, N))
+        gx, gy = c.share(dev(X), 0, 81), c.share(dev(Y), 0, 82)
+        t = c.dealer(m.TRIPLE_MATMUL, 2, 80, (M, N, K))
+        eager = pair(c, c.beaver_matmul(gx, gy, t, 16, "limb8"))
+        out = m.SharedPair(c.empty((M, N)), c.empty((M, N)))
+        c.beaver_matmul(gx, gy, t, 16, "limb8", out=out)  # sizes the workspace
+        c.sync()
+        c.graph_begin()
+        c.beaver_matmul(gx, gy, t, 16, "limb8", out=out)
+        c.truncate(gx, 0)  # a no-op call inside the capture
+        g = c.graph_end()
+        try:
+            for rep in range(4):
+                out.s0.zero_()
+                out.s1.zero_()
+                c.graph_launch(g)
+                got = pair(c, out)
+                assert np.array_equal(got[0], eager[0]), rep
+                assert np.array_equal(got[1], eager[1]), rep
+                # eager work between replays
+                c.reveal(gx)
+                c.sync()
+        finally:
+            m.Context.graph_destroy(g)
+            c.close()
