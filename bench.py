@@ -122,10 +122,8 @@ def main():
                     "kernel": "k_plain_gemm", "launches": g["launches"],
                     "avg_launch_ms": round(avg_ms, 4)}
 
-    # sample of the final step's output for the CPU-oracle leg
-    rows_needed = 256
-    z_rows = (z.s0[:rows_needed].cpu().numpy().view(np.uint64),
-              z.s1[:rows_needed].cpu().numpy().view(np.uint64))
+    # the final step's output, for the CPU-oracle leg to compare against
+    z_rows = (z.s0.cpu().numpy().view(np.uint64), z.s1.cpu().numpy().view(np.uint64))
 
     extras = {}
     if not args.no_extras:
@@ -195,20 +193,22 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     ex["ring_gemm_forms_bit_identical"] = bool(torch.equal(C0, C1))
     del C, C0, C1
 
-    # Beaver element-wise product (fused mask/open/finish/truncate), HBM-bound
-    n = 1 << 26
-    x = ctx.share(X.view(-1)[:n].contiguous(), 0, 11)
-    y = ctx.share(Y.view(-1)[:n].contiguous(), 1, 12)
+    # Beaver element-wise product (fused mask/open/finish/truncate), HBM-bound:
+    # 2^24 elements = 128 MiB per share buffer, 1.5 GiB moved per call
+    n = M * K
+    x = ctx.share(X.view(-1), 0, 11)
+    y = ctx.share(Y.view(-1), 1, 12)
     tm = ctx.dealer(mpc.TRIPLE_MUL, 5, 13, (n,))
     zz = mpc.SharedPair(ctx.empty((n,)), ctx.empty((n,)))
     ctx.beaver_mul(x, y, tm, 16, out=zz)
     ctx.sync()
     ms = _event_time(torch, ctx.streams[0], lambda: ctx.beaver_mul(x, y, tm, 16, out=zz), 10)
     ex["beaver_mul_n"] = n
+    ex["beaver_mul_ms"] = round(ms, 4)
     ex["beaver_mul_elem_per_s"] = round(n / (ms * 1e-3), 1)
     ex["beaver_mul_hbm_GBps_algorithmic"] = round(96.0 * n / (ms * 1e-3) / 1e9, 1)
     ex["beaver_mul_hbm_frac"] = round(ex["beaver_mul_hbm_GBps_algorithmic"] / HBM_PEAK_GBS, 4)
-    log(f"bench: Beaver mul n=2^26: {ms:.3f} ms")
+    log(f"bench: Beaver mul n=2^24: {ms:.3f} ms")
     del x, y, tm, zz
 
     # secure MLP 784-1024-1024-10, batch 128, square activations
@@ -262,12 +262,14 @@ def cpu_baseline(Xh, Yh, party_seed, dealer_seed, z_rows):
         oracle.reveal(*zz)
         return time.perf_counter() - t0, zz
 
-    rows = 16
+    # calibrate on 64 rows, then run about 15 s of oracle work (at most the
+    # whole 4096-row step)
+    rows = 64
     dt, zz = run(rows)
     log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
-    if dt < 8.0:
-        rows = int(min(256, max(rows, rows * 15.0 / dt)))
-        rows -= rows % 8
+    if dt < 10.0:
+        rows = int(min(M, max(rows, rows * 15.0 / dt)))
+        rows -= rows % 64
         dt, zz = run(rows)
         log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
     match = bool(np.array_equal(zz[0], z_rows[0][:rows]) and np.array_equal(zz[1], z_rows[1][:rows]))

@@ -65,6 +65,10 @@ def lib():
             "orc_beaver_matmul_at": (None, [I64, I64, I64] + [u64p] * 10
                                      + [INT, I64, i64p, i64p, u64p, u64p]),
             "orc_beaver_conv1d": (None, [I64] * 6 + [u64p] * 10 + [INT, u64p, u64p]),
+            "orc_dealer_conv1d_c_at": (None, [U64, U64] + [I64] * 6 + [u64p] * 4
+                                       + [I64, i64p, i64p, i64p, u64p, u64p]),
+            "orc_beaver_conv1d_at": (None, [I64] * 6 + [u64p] * 10
+                                     + [INT, I64, i64p, i64p, i64p, u64p, u64p]),
             "orc_limbs": (None, [u64p, SZ, i8p]),
             "orc_limb_gemm": (INT, [I64, I64, I64, u64p, u64p, I64, u64p]),
         }
@@ -336,6 +340,42 @@ def beaver_conv1d(x, w, t, stride, trunc_bits):
     z1, p1 = _out((Bt, Cout, Lout))
     lib().orc_beaver_conv1d(Bt, Cin, L, Cout, ksz, stride, *[p for _, p in args], trunc_bits,
                             p0, p1)
+    return z0, z1
+
+
+def dealer_conv1d_ab(dseed, tag, Bt, Cin, L, Cout, ksz):
+    """a_p (activation shape) and b_p (weight shape) of a conv triple (PRG fills)."""
+    nx, nw = Bt * Cin * L, Cout * Cin * ksz
+    a = tuple(prg_fill(dseed, tag, s, nx).reshape(Bt, Cin, L) for s in (SLOT_A0, SLOT_A1))
+    b = tuple(prg_fill(dseed, tag, s, nw).reshape(Cout, Cin, ksz) for s in (SLOT_B0, SLOT_B1))
+    return a, b
+
+
+def dealer_conv1d_c_at(dseed, tag, shape, a, b, bs, os_, ls):
+    Bt, Cin, L, Cout, ksz, stride = shape
+    (a0, pa0), (a1, pa1) = _u(a[0]), _u(a[1])
+    (b0, pb0), (b1, pb1) = _u(b[0]), _u(b[1])
+    bs, pb = _i(bs)
+    os_, po_ = _i(os_)
+    ls, pl = _i(ls)
+    c0, pc0 = _out(bs.size)
+    c1, pc1 = _out(bs.size)
+    lib().orc_dealer_conv1d_c_at(dseed, tag, Bt, Cin, L, Cout, ksz, stride, pa0, pa1, pb0, pb1,
+                                 bs.size, pb, po_, pl, pc0, pc1)
+    return c0, c1
+
+
+def beaver_conv1d_at(x, w, a, b, c_at, stride, trunc_bits, bs, os_, ls):
+    Bt, Cin, L = x[0].shape
+    Cout, _, ksz = w[0].shape
+    args = [_u(v) for v in (x[0], x[1], w[0], w[1], a[0], a[1], b[0], b[1], c_at[0], c_at[1])]
+    bs, pb = _i(bs)
+    os_, po_ = _i(os_)
+    ls, pl = _i(ls)
+    z0, p0 = _out(bs.size)
+    z1, p1 = _out(bs.size)
+    lib().orc_beaver_conv1d_at(Bt, Cin, L, Cout, ksz, stride, *[p for _, p in args], trunc_bits,
+                               bs.size, pb, po_, pl, p0, p1)
     return z0, z1
 
 

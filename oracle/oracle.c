@@ -440,6 +440,60 @@ void orc_beaver_conv1d(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, co
   free(t);
 }
 
+/* Convolution triple's c shares at listed output positions (b, o, l):
+ * c = conv1d(a_0 + a_1, b_0 + b_1) there, c_0 from the PRG at the flat output
+ * index, c_1 = c - c_0. */
+void orc_dealer_conv1d_c_at(u64 dseed, u64 tag, i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz,
+                            i64 stride, const u64 *a0, const u64 *a1, const u64 *b0,
+                            const u64 *b1, i64 npts, const i64 *bs, const i64 *os,
+                            const i64 *ls, u64 *c0, u64 *c1) {
+  (void)Bt;
+  const i64 Lout = orc_conv1d_lout(L, ksz, stride);
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    u64 c = 0;
+    for (i64 ci = 0; ci < Cin; ++ci)
+      for (i64 j = 0; j < ksz; ++j) {
+        const i64 xi = (bs[t] * Cin + ci) * L + ls[t] * stride + j;
+        const i64 wi = (os[t] * Cin + ci) * ksz + j;
+        c += (a0[xi] + a1[xi]) * (b0[wi] + b1[wi]);
+      }
+    c0[t] = orc_prg(dseed, tag, SLOT_C0, (u64)((bs[t] * Cout + os[t]) * Lout + ls[t]));
+    c1[t] = c - c0[t];
+  }
+}
+
+/* Beaver convolution at listed output positions; c0_at/c1_at are the
+ * triple's c shares at those positions. */
+void orc_beaver_conv1d_at(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, const u64 *x0,
+                          const u64 *x1, const u64 *y0, const u64 *y1, const u64 *a0,
+                          const u64 *a1, const u64 *b0, const u64 *b1, const u64 *c0_at,
+                          const u64 *c1_at, int trunc_bits, i64 npts, const i64 *bs,
+                          const i64 *os, const i64 *ls, u64 *z0, u64 *z1) {
+  (void)Bt;
+  (void)Cout;
+#pragma omp parallel for schedule(static)
+  for (i64 t = 0; t < npts; ++t) {
+    u64 s_eb0 = 0, s_eb1 = 0, s_ad0 = 0, s_ad1 = 0, s_ed = 0;
+    for (i64 ci = 0; ci < Cin; ++ci)
+      for (i64 j = 0; j < ksz; ++j) {
+        const i64 xi = (bs[t] * Cin + ci) * L + ls[t] * stride + j;
+        const i64 wi = (os[t] * Cin + ci) * ksz + j;
+        const u64 eps = (x0[xi] - a0[xi]) + (x1[xi] - a1[xi]);
+        const u64 delta = (y0[wi] - b0[wi]) + (y1[wi] - b1[wi]);
+        s_eb0 += eps * b0[wi];
+        s_eb1 += eps * b1[wi];
+        s_ad0 += a0[xi] * delta;
+        s_ad1 += a1[xi] * delta;
+        s_ed += eps * delta;
+      }
+    z0[t] = c0_at[t] + s_eb0 + s_ad0 + s_ed;
+    z1[t] = c1_at[t] + s_eb1 + s_ad1;
+  }
+  orc_truncate(z0, (size_t)npts, trunc_bits);
+  orc_truncate(z1, (size_t)npts, trunc_bits);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Signed 8-bit limb decomposition (a test helper for the limb GEMM form;     */
 /* not a step of the protocol).  For v in Z/2^64:                            */

@@ -267,226 +267,175 @@ mpc_form resolve_form(mpc_form f, i64 M, i64 N, i64 K) {
   return work >= (double)(1 << 22) ? MPC_FORM_LIMB8 : MPC_FORM_PLAIN;
 }
 
-// ------------------------------------------------------------------ GEMM issue
-// A ring GEMM request in terms of uint64 operands; both forms are built from it.
-struct Operand {
-  int kind;  // kPackRow (left, row-major), kPackCol (right, row-major KxN), kPackIm2col
-  const u64* src;
-  const u64* add;
-  i64 ld;
-  i64 cin, len, ksz, stride, lout;  // im2col geometry
+// ------------------------------------------------------------------ plain form
+size_t packed_bytes(i64 rows, i64 K) {
+  return (size_t)limb_rblocks(rows) * (size_t)limb_kblocks(K) * kLimbBlockBytes;
+}
+
+// One launch of the plain GEMM over `probs` (party 0's stream).
+mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs) {
+  const size_t n = probs.size();
+  if (!n) return MPC_OK;
+  std::vector<int> tstart(n + 1, 0);
+  double macs = 0;
+  for (size_t q = 0; q < n; ++q) {
+    tstart[q + 1] = tstart[q] + plain_tiles(probs[q].M, probs[q].N);
+    macs += (double)probs[q].M * (double)probs[q].N * (double)(probs[q].K0 + probs[q].K1);
+  }
+  Blob blob;
+  const size_t oprob = blob.add(probs.data(), n);
+  const size_t otile = blob.add(tstart.data(), n + 1);
+  uint8_t* dev = nullptr;
+  CHK(upload(c, blob, &dev));
+  TileMap map{(int)n, (const int*)(dev + otile)};
+  LaunchTimer tm(c, MPC_FORM_PLAIN, macs);
+  CHK(tm.start());
+  CHK(hip_status(launch_plain_gemm(c->s[0], (const PlainProblem*)(dev + oprob), map, tstart[n])));
+  CHK(tm.stop());
+  c->stats.launches++;
+  c->stats.gemm_problems += n;
+  return MPC_OK;
+}
+
+PlainProblem plain_problem(i64 M, i64 N, i64 K0, i64 K1, const u64* A0, const u64* A0add, i64 lda0,
+                           const u64* A1, i64 lda1, const u64* B0, const u64* B0add, i64 ldb0,
+                           const u64* B1, i64 ldb1, const Epilogue& ep) {
+  PlainProblem p{};
+  p.M = M;
+  p.N = N;
+  p.K0 = K0;
+  p.K1 = K1;
+  p.A0 = A0;
+  p.A0add = A0add;
+  p.lda0 = lda0;
+  p.A1 = A1;
+  p.lda1 = lda1;
+  p.B0 = B0;
+  p.B0add = B0add;
+  p.ldb0 = ldb0;
+  p.B1 = B1;
+  p.ldb1 = ldb1;
+  p.ep = ep;
+  return p;
+}
+
+// ------------------------------------------------------------------ limb form
+// A pack job before its outputs are placed in the workspace.
+struct JobSpec {
+  int kind = kPackRow;
+  i64 rows = 0, K = 0, ld = 0;
+  i64 cin = 0, len = 0, ksz = 1, stride = 1, lout = 1;
+  int nin = 0, nout = 0;
+  const u64* in[kPackMaxIn] = {nullptr, nullptr, nullptr, nullptr};
+  int8_t coef[kPackMaxOut][kPackMaxIn] = {};
 };
 
-struct GemmReq {
+size_t job_bytes(const JobSpec& j) { return (size_t)j.nout * align_up(packed_bytes(j.rows, j.K)); }
+
+PackJob place_job(const JobSpec& j, Carve& cv) {
+  PackJob p{};
+  p.kind = j.kind;
+  p.nin = j.nin;
+  p.nout = j.nout;
+  p.rows = j.rows;
+  p.K = j.K;
+  p.ld = j.ld;
+  p.cin = j.cin;
+  p.len = j.len;
+  p.ksz = j.ksz;
+  p.stride = j.stride;
+  p.lout = j.lout;
+  for (int i = 0; i < kPackMaxIn; ++i) p.in[i] = j.in[i];
+  for (int o = 0; o < kPackMaxOut; ++o)
+    for (int i = 0; i < kPackMaxIn; ++i) p.coef[o][i] = j.coef[o][i];
+  p.rblocks = limb_rblocks(j.rows);
+  p.kblocks = limb_kblocks(j.K);
+  for (int o = 0; o < kPackMaxOut; ++o)
+    p.dst[o] = o < j.nout ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
+  return p;
+}
+
+// Left operand MxK (row-major, leading dimension ld) from `nin` inputs.
+JobSpec left_job(i64 M, i64 K, i64 ld) {
+  JobSpec j;
+  j.kind = kPackRow;
+  j.rows = M;
+  j.K = K;
+  j.ld = ld;
+  return j;
+}
+// Right operand KxN (row-major, leading dimension ld).
+JobSpec right_job(i64 K, i64 N, i64 ld) {
+  JobSpec j;
+  j.kind = kPackCol;
+  j.rows = N;
+  j.K = K;
+  j.ld = ld;
+  return j;
+}
+// Right operand im2col(x) of a [B][Cin][L] activation: K = Cin*k, N = B*Lout.
+JobSpec im2col_job(const mpc_conv1d_shape& s, i64 lout) {
+  JobSpec j;
+  j.kind = kPackIm2col;
+  j.rows = s.batch * lout;
+  j.K = s.cin * s.ksize;
+  j.cin = s.cin;
+  j.len = s.length;
+  j.ksz = s.ksize;
+  j.stride = s.stride;
+  j.lout = lout;
+  return j;
+}
+// Output coefficient rows used by the jobs.
+void set_inputs(JobSpec& j, std::initializer_list<const u64*> ins) {
+  j.nin = 0;
+  for (const u64* p : ins) j.in[j.nin++] = p;
+}
+void add_output(JobSpec& j, std::initializer_list<int> coef) {
+  int i = 0;
+  for (int c : coef) j.coef[j.nout][i++] = (int8_t)c;
+  j.nout++;
+}
+// The fused open of a Beaver operand pair (x, a): outputs eps = x0+x1-a0-a1,
+// g0 = a0 + eps = x0+x1-a1 and a1 (left side), or for (y, b): delta, b0, b1.
+void open_left(JobSpec& j, const u64* x0, const u64* x1, const u64* a0, const u64* a1) {
+  set_inputs(j, {x0, x1, a0, a1});
+  add_output(j, {1, 1, -1, -1});  // eps
+  add_output(j, {1, 1, 0, -1});   // g0 = a0 + eps
+  add_output(j, {0, 0, 0, 1});    // a1
+}
+void open_right(JobSpec& j, const u64* y0, const u64* y1, const u64* b0, const u64* b1) {
+  set_inputs(j, {y0, y1, b0, b1});
+  add_output(j, {1, 1, -1, -1});  // delta
+  add_output(j, {0, 0, 1, 0});    // b0
+  add_output(j, {0, 0, 0, 1});    // b1
+}
+
+struct LimbReq {
   i64 M, N, K0, K1;
-  Operand A0, A1, B0, B1;  // A1/B1 unused when K1 == 0
+  const uint8_t *PA0, *PA1, *PB0, *PB1;
   Epilogue ep;
 };
 
-Operand left_rowmajor(const u64* p, i64 ld, const u64* add = nullptr) {
-  Operand o{};
-  o.kind = kPackRow;
-  o.src = p;
-  o.add = add;
-  o.ld = ld;
-  return o;
-}
-Operand right_rowmajor(const u64* p, i64 ld, const u64* add = nullptr) {
-  Operand o{};
-  o.kind = kPackCol;
-  o.src = p;
-  o.add = add;
-  o.ld = ld;
-  return o;
-}
-Operand right_im2col(const u64* p, const u64* add, const mpc_conv1d_shape& s, i64 lout) {
-  Operand o{};
-  o.kind = kPackIm2col;
-  o.src = p;
-  o.add = add;
-  o.cin = s.cin;
-  o.len = s.length;
-  o.ksz = s.ksize;
-  o.stride = s.stride;
-  o.lout = lout;
-  return o;
-}
-
-// Workspace needed to issue `reqs` in the given form (im2col operands of the
-// plain form are materialised; the limb form packs every distinct operand).
-struct Plan {
-  // distinct operands are identified by (kind, src, add) so shared ones (eps,
-  // delta) are packed or lowered once.
-  std::vector<Operand> ops;
-  std::vector<i64> op_rows, op_k;
-  int find_or_add(const Operand& o, i64 rows, i64 K) {
-    for (size_t i = 0; i < ops.size(); ++i)
-      if (ops[i].kind == o.kind && ops[i].src == o.src && ops[i].add == o.add && op_rows[i] == rows &&
-          op_k[i] == K)
-        return (int)i;
-    ops.push_back(o);
-    op_rows.push_back(rows);
-    op_k.push_back(K);
-    return (int)ops.size() - 1;
-  }
-};
-
-size_t packed_bytes(i64 rows, i64 K) { return (size_t)limb_rblocks(rows) * limb_kblocks(K) * kLimbBlockBytes; }
-
-// Issues a list of ring GEMMs (one launch per K chunk) on party 0's stream.
-// The workspace region starting at `cv` must be reserved by the caller with
-// gemm_ws_bytes().
-size_t gemm_ws_bytes(const std::vector<GemmReq>& reqs, mpc_form form) {
-  Plan plan;
-  size_t bytes = 0;
-  for (const GemmReq& r : reqs) {
-    const Operand* A[2] = {&r.A0, &r.A1};
-    const Operand* B[2] = {&r.B0, &r.B1};
-    const i64 Ks[2] = {r.K0, r.K1};
-    for (int sgm = 0; sgm < 2; ++sgm) {
-      if (sgm == 1 && r.K1 == 0) break;
-      const int na = (int)plan.ops.size();
-      int ia = plan.find_or_add(*A[sgm], r.M, Ks[sgm]);
-      if (ia == na) bytes += form == MPC_FORM_LIMB8 ? align_up(packed_bytes(r.M, Ks[sgm])) : 0;
-      const int nb = (int)plan.ops.size();
-      int ib = plan.find_or_add(*B[sgm], r.N, Ks[sgm]);
-      if (ib == nb) {
-        if (form == MPC_FORM_LIMB8) bytes += align_up(packed_bytes(r.N, Ks[sgm]));
-        else if (B[sgm]->kind == kPackIm2col) bytes += align_up((size_t)(Ks[sgm] * r.N) * 8);
-      }
-    }
-  }
-  return bytes;
-}
-
-mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form form, Carve& cv,
-                       Blob& blob, std::vector<std::pair<int, size_t>>* /*unused*/ = nullptr) {
+// One pack launch over all jobs, then one GEMM launch per K chunk (a problem
+// whose concatenated K exceeds the int32-safe range continues in the next
+// launch, adding into its output; truncation is applied by its last chunk).
+mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs, const std::vector<LimbReq>& reqs) {
   hipStream_t st = c->s[0];
-  const size_t nreq = reqs.size();
-  if (!nreq) return MPC_OK;
-  Plan plan;
-  std::vector<int> ia[2], ib[2];
-  for (int s = 0; s < 2; ++s) {
-    ia[s].assign(nreq, -1);
-    ib[s].assign(nreq, -1);
-  }
-  for (size_t q = 0; q < nreq; ++q) {
-    const GemmReq& r = reqs[q];
-    ia[0][q] = plan.find_or_add(r.A0, r.M, r.K0);
-    ib[0][q] = plan.find_or_add(r.B0, r.N, r.K0);
-    if (r.K1) {
-      ia[1][q] = plan.find_or_add(r.A1, r.M, r.K1);
-      ib[1][q] = plan.find_or_add(r.B1, r.N, r.K1);
-    }
-  }
-  const size_t nops = plan.ops.size();
+  const size_t nj = jobs.size(), nreq = reqs.size();
+  Blob blob;
+  std::vector<i64> bstart(nj + 1, 0);
+  for (size_t i = 0; i < nj; ++i) bstart[i + 1] = bstart[i] + jobs[i].rblocks * jobs[i].kblocks;
+  const size_t ojobs = blob.add(jobs.data(), nj);
+  const size_t obstart = blob.add(bstart.data(), nj + 1);
 
-  if (form == MPC_FORM_PLAIN) {
-    // materialise im2col operands, then one plain launch
-    std::vector<const u64*> mat(nops, nullptr);
-    for (size_t i = 0; i < nops; ++i) {
-      const Operand& o = plan.ops[i];
-      if (o.kind == kPackIm2col) {
-        const i64 K = plan.op_k[i], N = plan.op_rows[i];
-        u64* col = cv.take<u64>((size_t)(K * N));
-        const i64 B = o.lout ? N / o.lout : 0;
-        CHK(hip_status(launch_im2col(st, o.src, o.add, B, o.cin, o.len, o.ksz, o.stride, o.lout, col)));
-        c->stats.launches++;
-        mat[i] = col;
-      }
-    }
-    std::vector<PlainProblem> probs(nreq);
-    std::vector<int> tstart(nreq + 1, 0);
-    for (size_t q = 0; q < nreq; ++q) {
-      const GemmReq& r = reqs[q];
-      PlainProblem& p = probs[q];
-      p.M = r.M;
-      p.N = r.N;
-      p.K0 = r.K0;
-      p.K1 = r.K1;
-      auto seg_a = [&](int s, const u64** ptr, const u64** add, i64* ld) {
-        const Operand& o = plan.ops[ia[s][q]];
-        *ptr = o.src;
-        *add = o.add;
-        *ld = o.ld;
-      };
-      auto seg_b = [&](int s, const u64** ptr, const u64** add, i64* ld) {
-        const int i = ib[s][q];
-        const Operand& o = plan.ops[i];
-        if (o.kind == kPackIm2col) {
-          *ptr = mat[i];
-          *add = nullptr;
-          *ld = r.N;
-        } else {
-          *ptr = o.src;
-          *add = o.add;
-          *ld = o.ld;
-        }
-      };
-      seg_a(0, &p.A0, &p.A0add, &p.lda0);
-      seg_b(0, &p.B0, &p.B0add, &p.ldb0);
-      if (r.K1) {
-        const u64* dummy;
-        seg_a(1, &p.A1, &dummy, &p.lda1);
-        seg_b(1, &p.B1, &dummy, &p.ldb1);
-        if (plan.ops[ia[1][q]].add || (plan.ops[ib[1][q]].add && plan.ops[ib[1][q]].kind != kPackIm2col))
-          return MPC_E_UNSUPPORTED;  // second segments never carry an addend
-      } else {
-        p.A1 = nullptr;
-        p.B1 = nullptr;
-        p.lda1 = p.ldb1 = 0;
-      }
-      p.ep = r.ep;
-      tstart[q + 1] = tstart[q] + plain_tiles(r.M, r.N);
-    }
-    const size_t oprob = blob.add(probs.data(), nreq);
-    const size_t otile = blob.add(tstart.data(), nreq + 1);
-    uint8_t* dev = nullptr;
-    CHK(upload(c, blob, &dev));
-    TileMap map{(int)nreq, (const int*)(dev + otile)};
-    double macs = 0;
-    for (const GemmReq& r : reqs) macs += (double)r.M * (double)r.N * (double)(r.K0 + r.K1);
-    LaunchTimer tm(c, MPC_FORM_PLAIN, macs);
-    CHK(tm.start());
-    CHK(hip_status(launch_plain_gemm(st, (const PlainProblem*)(dev + oprob), map, tstart[nreq])));
-    CHK(tm.stop());
-    c->stats.launches++;
-    c->stats.gemm_problems += nreq;
-    return MPC_OK;
-  }
-
-  // ---- limb form: pack every distinct operand, then chunked GEMM launches
-  std::vector<PackJob> jobs(nops);
-  std::vector<i64> bstart(nops + 1, 0);
-  for (size_t i = 0; i < nops; ++i) {
-    const Operand& o = plan.ops[i];
-    PackJob& j = jobs[i];
-    j.kind = o.kind;
-    j.rows = plan.op_rows[i];
-    j.K = plan.op_k[i];
-    j.src = o.src;
-    j.add = o.add;
-    j.ld = o.ld;
-    j.cin = o.cin;
-    j.len = o.len;
-    j.ksz = o.ksz;
-    j.stride = o.stride;
-    j.lout = o.lout;
-    j.rblocks = limb_rblocks(j.rows);
-    j.kblocks = limb_kblocks(j.K);
-    j.dst = cv.take<uint8_t>((size_t)(j.rblocks * j.kblocks) * kLimbBlockBytes);
-    bstart[i + 1] = bstart[i] + j.rblocks * j.kblocks;
-  }
-  // chunk plan
-  int max_chunks = 1;
+  int max_chunks = 0;
   std::vector<int> nchunks(nreq);
   for (size_t q = 0; q < nreq; ++q) {
-    const int kbt = (int)(limb_kblocks(reqs[q].K0) + (reqs[q].K1 ? limb_kblocks(reqs[q].K1) : 0));
+    const int kbt = (int)(limb_kblocks(reqs[q].K0) + limb_kblocks(reqs[q].K1));
     nchunks[q] = std::max(1, (kbt + kLimbMaxKBlocks - 1) / kLimbMaxKBlocks);
     max_chunks = std::max(max_chunks, nchunks[q]);
   }
-  const size_t ojobs = blob.add(jobs.data(), nops);
-  const size_t obstart = blob.add(bstart.data(), nops + 1);
   std::vector<size_t> oprob(max_chunks), otile(max_chunks);
   std::vector<int> ttotal(max_chunks, 0), tcount(max_chunks, 0);
   std::vector<double> cmacs(max_chunks, 0.0);
@@ -495,20 +444,19 @@ mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form fo
     std::vector<int> tstart(1, 0);
     for (size_t q = 0; q < nreq; ++q) {
       if (ch >= nchunks[q]) continue;
-      const GemmReq& r = reqs[q];
+      const LimbReq& r = reqs[q];
       LimbProblem p{};
       p.M = r.M;
       p.N = r.N;
       p.kb0 = (int)limb_kblocks(r.K0);
-      p.kb1 = r.K1 ? (int)limb_kblocks(r.K1) : 0;
+      p.kb1 = (int)limb_kblocks(r.K1);
       const int kbt = p.kb0 + p.kb1;
-      p.kb_begin = ch * kLimbMaxKBlocks;
+      p.kb_begin = std::min(kbt, ch * kLimbMaxKBlocks);
       p.kb_end = std::min(kbt, (ch + 1) * kLimbMaxKBlocks);
-      if (p.kb_begin > p.kb_end) p.kb_begin = p.kb_end;
-      p.PA0 = jobs[ia[0][q]].dst;
-      p.PB0 = jobs[ib[0][q]].dst;
-      p.PA1 = r.K1 ? jobs[ia[1][q]].dst : nullptr;
-      p.PB1 = r.K1 ? jobs[ib[1][q]].dst : nullptr;
+      p.PA0 = r.PA0;
+      p.PA1 = r.PA1;
+      p.PB0 = r.PB0;
+      p.PB1 = r.PB1;
       p.mblocks = limb_rblocks(r.M);
       p.nblocks = limb_rblocks(r.N);
       p.ep = r.ep;
@@ -519,14 +467,11 @@ mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form fo
       if (ch + 1 < nchunks[q]) p.ep.trunc_bits = 0;
       probs.push_back(p);
       tstart.push_back(tstart.back() + limb_tiles(r.M, r.N));
-      // true (unpadded) k values covered by this chunk
-      const i64 Kt = r.K0 + r.K1;
-      auto true_k = [&](i64 kb) {  // true k values before concatenated k-block kb
-        const i64 kb0 = p.kb0;
-        return kb <= kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - kb0) * 32, r.K1);
+      // true (unpadded) k values this chunk covers, for the timing record
+      auto true_k = [&](i64 kb) {
+        return kb <= p.kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - p.kb0) * 32, r.K1);
       };
-      const i64 kspan = std::min(Kt, true_k(p.kb_end)) - std::min(Kt, true_k(p.kb_begin));
-      cmacs[ch] += (double)r.M * (double)r.N * (double)kspan;
+      cmacs[ch] += (double)r.M * (double)r.N * (double)(true_k(p.kb_end) - true_k(p.kb_begin));
     }
     oprob[ch] = blob.add(probs.data(), probs.size());
     otile[ch] = blob.add(tstart.data(), tstart.size());
@@ -535,9 +480,11 @@ mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form fo
   }
   uint8_t* dev = nullptr;
   CHK(upload(c, blob, &dev));
-  CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs), (const i64*)(dev + obstart), (int)nops,
-                             bstart[nops])));
-  c->stats.launches++;
+  if (nj) {
+    CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs), (const i64*)(dev + obstart), (int)nj,
+                               bstart[nj])));
+    c->stats.launches++;
+  }
   for (int ch = 0; ch < max_chunks; ++ch) {
     TileMap map{tcount[ch], (const int*)(dev + otile[ch])};
     LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[ch]);
@@ -548,6 +495,11 @@ mpc_status issue_gemms(mpc_ctx* c, const std::vector<GemmReq>& reqs, mpc_form fo
   }
   c->stats.gemm_problems += nreq;
   return MPC_OK;
+}
+
+LimbReq limb_req(i64 M, i64 N, i64 K0, i64 K1, const uint8_t* PA0, const uint8_t* PA1,
+                 const uint8_t* PB0, const uint8_t* PB1, const Epilogue& ep) {
+  return LimbReq{M, N, K0, K1, PA0, PA1, PB0, PB1, ep};
 }
 
 mpc_status check_trunc(int bits) { return (bits < 0 || bits > 63) ? MPC_E_INVAL : MPC_OK; }
@@ -781,38 +733,33 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
   }
   if (kind != MPC_TRIPLE_MATMUL && kind != MPC_TRIPLE_CONV1D) return MPC_E_INVAL;
 
+  // c = f(a0 + a1, b0 + b1), c1 = c - c0, as one ring GEMM whose operands are
+  // formed while they are loaded (plain) or packed (limb).
   size_t na, nb, nc;
-  GemmReq r{};
+  i64 M, N, K, lout = 0;
   mpc_conv1d_shape cs{};
+  OutView view;
   if (kind == MPC_TRIPLE_MATMUL) {
-    const i64 M = dims[0], N = dims[1], K = dims[2];
+    M = dims[0];
+    N = dims[1];
+    K = dims[2];
     if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
     na = (size_t)(M * K);
     nb = (size_t)(K * N);
     nc = (size_t)(M * N);
-    // c = (a0 + a1) @ (b0 + b1); c1 = c - c0
-    r.M = M;
-    r.N = N;
-    r.K0 = K;
-    r.K1 = 0;
-    r.A0 = left_rowmajor(t->a0, K, t->a1);
-    r.B0 = right_rowmajor(t->b0, N, t->b1);
-    r.ep = make_ep(t->c0, -1, 0, t->c1, rowmajor_view(N));
+    view = rowmajor_view(N);
   } else {
     cs = {dims[0], dims[1], dims[2], dims[3], dims[4], dims[5]};
     CHK(check_conv(&cs));
-    const i64 lout = conv_lout(cs);
+    lout = conv_lout(cs);
     na = (size_t)(cs.batch * cs.cin * cs.length);
     nb = (size_t)(cs.cout * cs.cin * cs.ksize);
     nc = (size_t)(cs.batch * cs.cout * lout);
-    // c = conv(a, b) = Wm(b0 + b1) @ im2col(a0 + a1) in the transposed orientation
-    r.M = cs.cout;
-    r.N = cs.batch * lout;
-    r.K0 = cs.cin * cs.ksize;
-    r.K1 = 0;
-    r.A0 = left_rowmajor(t->b0, r.K0, t->b1);
-    r.B0 = right_im2col(t->a0, t->a1, cs, lout);
-    r.ep = make_ep(t->c0, -1, 0, t->c1, OutView{lout, std::max<i64>(lout, 1), cs.cout * lout});
+    // transposed orientation: c[b][o][l] = (Wm(b) @ im2col(a))[o][b*Lout + l]
+    M = cs.cout;
+    N = cs.batch * lout;
+    K = cs.cin * cs.ksize;
+    view = OutView{lout, std::max<i64>(lout, 1), cs.cout * lout};
   }
   CHK(check_ptr(t->a0, na));
   CHK(check_ptr(t->a1, na));
@@ -826,9 +773,20 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
     for (int j = 0; j < i; ++j)
       if (overlap(bufs[i], ns[i], bufs[j], ns[j])) return MPC_E_ALIAS;
 
-  const mpc_form form = resolve_form(MPC_FORM_AUTO, r.M, r.N, r.K0);
-  std::vector<GemmReq> reqs{r};
-  CHK(ensure_ws(c, gemm_ws_bytes(reqs, form) + kAlign));
+  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K);
+  const Epilogue ep = make_ep(t->c0, -1, 0, t->c1, view);
+  // the left factor is a (matmul) or the weight b (conv); the right one b or im2col(a)
+  const u64 *L0 = kind == MPC_TRIPLE_MATMUL ? t->a0 : t->b0, *L1 = kind == MPC_TRIPLE_MATMUL ? t->a1 : t->b1;
+  const u64 *R0 = kind == MPC_TRIPLE_MATMUL ? t->b0 : t->a0, *R1 = kind == MPC_TRIPLE_MATMUL ? t->b1 : t->a1;
+  JobSpec jl = left_job(M, K, K), jr = kind == MPC_TRIPLE_MATMUL ? right_job(K, N, N) : im2col_job(cs, lout);
+  set_inputs(jl, {L0, L1});
+  add_output(jl, {1, 1});
+  set_inputs(jr, {R0, R1});
+  add_output(jr, {1, 1});
+  size_t need = kAlign;
+  if (form == MPC_FORM_LIMB8) need += job_bytes(jl) + job_bytes(jr);
+  else if (kind == MPC_TRIPLE_CONV1D) need += align_up((size_t)(K * N) * 8);
+  CHK(ensure_ws(c, need));
   CHK(hip_status(launch_prg_fill(st, key[kSlotA0], t->a0, na)));
   CHK(hip_status(launch_prg_fill(st, key[kSlotA1], t->a1, na)));
   CHK(hip_status(launch_prg_fill(st, key[kSlotB0], t->b0, nb)));
@@ -837,8 +795,17 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
   c->stats.launches += 5;
   if (nc) {
     Carve cv(c->ws);
-    Blob blob;
-    CHK(issue_gemms(c, reqs, form, cv, blob));
+    if (form == MPC_FORM_LIMB8) {
+      std::vector<PackJob> jobs{place_job(jl, cv), place_job(jr, cv)};
+      CHK(issue_limb(c, jobs, {limb_req(M, N, K, 0, jobs[0].dst[0], nullptr, jobs[1].dst[0], nullptr, ep)}));
+    } else if (kind == MPC_TRIPLE_MATMUL) {
+      CHK(issue_plain(c, {plain_problem(M, N, K, 0, L0, L1, K, nullptr, 0, R0, R1, N, nullptr, 0, ep)}));
+    } else {
+      u64* col = cv.take<u64>((size_t)(K * N));
+      CHK(hip_status(launch_im2col(st, R0, R1, cs.batch, cs.cin, cs.length, cs.ksize, cs.stride, lout, col)));
+      c->stats.launches++;
+      CHK(issue_plain(c, {plain_problem(M, N, K, 0, L0, L1, K, nullptr, 0, col, nullptr, N, nullptr, 0, ep)}));
+    }
   }
   return end_call(c);
 }
@@ -878,40 +845,13 @@ mpc_status mpc_beaver_mul(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64
 
 namespace {
 
-// Builds the open jobs and both parties' GEMM requests of one Beaver matmul.
-// Workspace: eps (MxK), g = a0 + eps (MxK), delta (KxN).
+// One Beaver matmul of the call (a grouped call holds many).
 struct MatmulPlan {
   i64 M, N, K;
   const u64 *x0, *x1, *y0, *y1;
   mpc_triple t;
   u64 *z0, *z1;
 };
-
-size_t matmul_open_bytes(const MatmulPlan& m) {
-  return 2 * align_up((size_t)(m.M * m.K) * 8) + align_up((size_t)(m.K * m.N) * 8);
-}
-
-void matmul_build(const MatmulPlan& m, Carve& cv, int trunc, std::vector<OpenJob>& opens,
-                  std::vector<GemmReq>& reqs) {
-  u64* eps = cv.take<u64>((size_t)(m.M * m.K));
-  u64* g = cv.take<u64>((size_t)(m.M * m.K));
-  u64* del = cv.take<u64>((size_t)(m.K * m.N));
-  opens.push_back(OpenJob{kOpenLeft, m.M * m.K, m.x0, m.x1, m.t.a0, m.t.a1, eps, g});
-  opens.push_back(OpenJob{kOpenRight, m.K * m.N, m.y0, m.y1, m.t.b0, m.t.b1, del, nullptr});
-  for (int p = 0; p < 2; ++p) {
-    GemmReq r{};
-    r.M = m.M;
-    r.N = m.N;
-    r.K0 = m.K;
-    r.K1 = m.K;
-    r.A0 = left_rowmajor(eps, m.K);
-    r.A1 = left_rowmajor(p == 0 ? g : m.t.a1, m.K);
-    r.B0 = right_rowmajor(p == 0 ? m.t.b0 : m.t.b1, m.N);
-    r.B1 = right_rowmajor(del, m.N);
-    r.ep = make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1, rowmajor_view(m.N));
-    reqs.push_back(r);
-  }
-}
 
 mpc_status validate_matmul(const MatmulPlan& m) {
   if (m.M < 0 || m.N < 0 || m.K < 0) return MPC_E_SHAPE;
@@ -927,38 +867,95 @@ mpc_status validate_matmul(const MatmulPlan& m) {
   return MPC_OK;
 }
 
-mpc_status run_opens(mpc_ctx* c, const std::vector<OpenJob>& opens, Blob& blob, size_t* ojobs,
-                     size_t* ostart, i64* total) {
+// Open step of the plain form: one launch over all jobs (device job table).
+mpc_status issue_opens(mpc_ctx* c, const std::vector<OpenJob>& opens) {
+  if (opens.empty()) return MPC_OK;
   std::vector<i64> cs(opens.size() + 1, 0);
   for (size_t i = 0; i < opens.size(); ++i) cs[i + 1] = cs[i] + (opens[i].n + kOpenChunk - 1) / kOpenChunk;
-  *ojobs = blob.add(opens.data(), opens.size());
-  *ostart = blob.add(cs.data(), cs.size());
-  *total = cs.back();
-  (void)c;
+  Blob blob;
+  const size_t ojobs = blob.add(opens.data(), opens.size());
+  const size_t ostart = blob.add(cs.data(), cs.size());
+  uint8_t* dev = nullptr;
+  CHK(upload(c, blob, &dev));
+  // this slot is read only by the open launch
+  if (c->cur_slot >= 0 && !c->capturing) {
+    const int slot = c->cur_slot;
+    CHK(hip_status(launch_open(c->s[0], (const OpenJob*)(dev + ojobs), (const i64*)(dev + ostart),
+                               (int)opens.size(), cs.back())));
+    HIPCHK(hipEventRecord(c->slots[slot].done, c->s[0]));
+    c->slots[slot].pending = true;
+  } else {
+    CHK(hip_status(launch_open(c->s[0], (const OpenJob*)(dev + ojobs), (const i64*)(dev + ostart),
+                               (int)opens.size(), cs.back())));
+  }
+  c->stats.launches++;
   return MPC_OK;
 }
 
-// Issues opens (one launch) and the GEMMs of all requests.
-mpc_status issue_beaver(mpc_ctx* c, const std::vector<OpenJob>& opens, const std::vector<GemmReq>& reqs,
-                        mpc_form form, Carve& cv) {
-  // The opens need their own small blob uploaded before the GEMMs' blob.
-  Blob ob;
-  size_t ojobs, ostart;
-  i64 total;
-  CHK(run_opens(c, opens, ob, &ojobs, &ostart, &total));
-  uint8_t* dev = nullptr;
-  CHK(upload(c, ob, &dev));
-  // keep this slot busy until the end of the call as well
-  const int open_slot = c->cur_slot;
-  CHK(hip_status(launch_open(c->s[0], (const OpenJob*)(dev + ojobs), (const i64*)(dev + ostart),
-                             (int)opens.size(), total)));
-  c->stats.launches++;
-  if (open_slot >= 0 && !c->capturing) {
-    HIPCHK(hipEventRecord(c->slots[open_slot].done, c->s[0]));
-    c->slots[open_slot].pending = true;
+// Workspace of one Beaver matmul in a form.
+size_t matmul_ws(const MatmulPlan& m, mpc_form form) {
+  if (form == MPC_FORM_LIMB8)
+    return 3 * align_up(packed_bytes(m.M, m.K)) + 3 * align_up(packed_bytes(m.N, m.K));
+  return 2 * align_up((size_t)(m.M * m.K) * 8) + align_up((size_t)(m.K * m.N) * 8);
+}
+
+// Plain form: eps, g0 = a0 + eps and delta row-major; party p's finish is
+// z_p = c_p + [eps | g_p] @ [b_p ; delta] with g_1 = a_1.
+void matmul_plain(const MatmulPlan& m, Carve& cv, int trunc, std::vector<OpenJob>& opens,
+                  std::vector<PlainProblem>& probs) {
+  u64* eps = cv.take<u64>((size_t)(m.M * m.K));
+  u64* g = cv.take<u64>((size_t)(m.M * m.K));
+  u64* del = cv.take<u64>((size_t)(m.K * m.N));
+  opens.push_back(OpenJob{kOpenLeft, m.M * m.K, m.x0, m.x1, m.t.a0, m.t.a1, eps, g});
+  opens.push_back(OpenJob{kOpenRight, m.K * m.N, m.y0, m.y1, m.t.b0, m.t.b1, del, nullptr});
+  for (int p = 0; p < 2; ++p)
+    probs.push_back(plain_problem(m.M, m.N, m.K, m.K, eps, nullptr, m.K, p == 0 ? g : m.t.a1, m.K,
+                                  p == 0 ? m.t.b0 : m.t.b1, nullptr, m.N, del, m.N,
+                                  make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1,
+                                          rowmajor_view(m.N))));
+}
+
+// Limb form: one fused open+pack job per operand side, then the same finish
+// over packed operands.
+void matmul_limb(const MatmulPlan& m, Carve& cv, int trunc, std::vector<PackJob>& jobs,
+                 std::vector<LimbReq>& reqs) {
+  JobSpec jl = left_job(m.M, m.K, m.K), jr = right_job(m.K, m.N, m.N);
+  open_left(jl, m.x0, m.x1, m.t.a0, m.t.a1);
+  open_right(jr, m.y0, m.y1, m.t.b0, m.t.b1);
+  const PackJob L = place_job(jl, cv), R = place_job(jr, cv);
+  jobs.push_back(L);
+  jobs.push_back(R);
+  // L.dst: eps, g0, a1;  R.dst: delta, b0, b1
+  for (int p = 0; p < 2; ++p)
+    reqs.push_back(limb_req(m.M, m.N, m.K, m.K, L.dst[0], L.dst[p == 0 ? 1 : 2], R.dst[p == 0 ? 1 : 2],
+                            R.dst[0],
+                            make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1,
+                                    rowmajor_view(m.N))));
+}
+
+mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int trunc, mpc_form form) {
+  size_t need = kAlign;
+  for (const MatmulPlan& m : plans) need += matmul_ws(m, form);
+  CHK(ensure_ws(c, need));
+  Carve cv(c->ws);
+  if (form == MPC_FORM_LIMB8) {
+    std::vector<PackJob> jobs;
+    std::vector<LimbReq> reqs;
+    for (const MatmulPlan& m : plans) matmul_limb(m, cv, trunc, jobs, reqs);
+    CHK(issue_limb(c, jobs, reqs));
+  } else {
+    std::vector<OpenJob> opens;
+    std::vector<PlainProblem> probs;
+    for (const MatmulPlan& m : plans) matmul_plain(m, cv, trunc, opens, probs);
+    CHK(issue_opens(c, opens));
+    CHK(issue_plain(c, probs));
   }
-  Blob gb;
-  return issue_gemms(c, reqs, form, cv, gb);
+  for (const MatmulPlan& m : plans) {
+    c->stats.opens++;
+    c->stats.open_bytes_per_party += 8 * (uint64_t)(m.M * m.K + m.K * m.N);
+    if (trunc) c->stats.truncations++;
+  }
+  return MPC_OK;
 }
 
 }  // namespace
@@ -974,24 +971,7 @@ mpc_status mpc_beaver_matmul(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const 
   CHK(validate_matmul(m));
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
-  form = resolve_form(form, M, N, 2 * K);
-  // size the workspace: open outputs + GEMM operands
-  std::vector<OpenJob> opens;
-  std::vector<GemmReq> reqs;
-  {
-    Carve probe(nullptr);
-    matmul_build(m, probe, trunc_bits, opens, reqs);
-  }
-  const size_t need = matmul_open_bytes(m) + gemm_ws_bytes(reqs, form) + kAlign;
-  CHK(ensure_ws(c, need));
-  opens.clear();
-  reqs.clear();
-  Carve cv(c->ws);
-  matmul_build(m, cv, trunc_bits, opens, reqs);
-  CHK(issue_beaver(c, opens, reqs, form, cv));
-  c->stats.opens++;
-  c->stats.open_bytes_per_party += 8 * (uint64_t)(M * K + K * N);
-  if (trunc_bits) c->stats.truncations++;
+  CHK(run_matmuls(c, {m}, trunc_bits, resolve_form(form, M, N, 2 * K)));
   return end_call(c);
 }
 
@@ -1017,45 +997,47 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
     if (overlap(z0, ny, in[i], ns[i]) || overlap(z1, ny, in[i], ns[i])) return MPC_E_ALIAS;
   if (ny == 0) return MPC_OK;
   CHK(set_device(c));
+  // transposed orientation: z_p[b][o][l] is element (o, b*Lout + l) of
+  //   c_p + Wm(b_p) @ im2col(eps) + Wm(delta) @ im2col(g_p),  g_0 = a_0 + eps, g_1 = a_1
   const i64 M = s.cout, N = s.batch * lout, K = s.cin * s.ksize;
   form = resolve_form(form, M, N, 2 * K);
-
-  auto build = [&](Carve& cv, std::vector<OpenJob>& opens, std::vector<GemmReq>& reqs) {
-    // activation side: eps and g0 = a0 + eps;  weight side: delta
+  const OutView view{lout, std::max<i64>(lout, 1), s.cout * lout};
+  if (form == MPC_FORM_LIMB8) {
+    JobSpec jw = left_job(M, K, K), jx = im2col_job(s, lout);
+    open_right(jw, w0, w1, t->b0, t->b1);  // delta, b0, b1 (weights)
+    open_left(jx, x0, x1, t->a0, t->a1);   // im2col of eps, g0, a1 (activations)
+    CHK(ensure_ws(c, kAlign + job_bytes(jw) + job_bytes(jx)));
+    Carve cv(c->ws);
+    const PackJob W = place_job(jw, cv), X = place_job(jx, cv);
+    std::vector<LimbReq> reqs;
+    for (int p = 0; p < 2; ++p)
+      reqs.push_back(limb_req(M, N, K, K, W.dst[p == 0 ? 1 : 2], W.dst[0], X.dst[0], X.dst[p == 0 ? 1 : 2],
+                              make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
+    CHK(issue_limb(c, {W, X}, reqs));
+  } else {
+    const size_t kn = (size_t)(K * N);
+    CHK(ensure_ws(c, kAlign + 2 * align_up(nx * 8) + align_up(nw * 8) + 3 * align_up(kn * 8)));
+    Carve cv(c->ws);
     u64* eps = cv.take<u64>(nx);
     u64* g = cv.take<u64>(nx);
     u64* del = cv.take<u64>(nw);
-    opens.push_back(OpenJob{kOpenLeft, (i64)nx, x0, x1, t->a0, t->a1, eps, g});
-    opens.push_back(OpenJob{kOpenRight, (i64)nw, w0, w1, t->b0, t->b1, del, nullptr});
-    // z_p = c_p + Wm(b_p) @ col(eps) + Wm(delta) @ col(g_p)
-    for (int p = 0; p < 2; ++p) {
-      GemmReq r{};
-      r.M = M;
-      r.N = N;
-      r.K0 = K;
-      r.K1 = K;
-      r.A0 = left_rowmajor(p == 0 ? t->b0 : t->b1, K);
-      r.A1 = left_rowmajor(del, K);
-      r.B0 = right_im2col(eps, nullptr, s, lout);
-      r.B1 = right_im2col(p == 0 ? g : t->a1, nullptr, s, lout);
-      r.ep = make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1,
-                     OutView{lout, std::max<i64>(lout, 1), s.cout * lout});
-      reqs.push_back(r);
-    }
-  };
-  std::vector<OpenJob> opens;
-  std::vector<GemmReq> reqs;
-  {
-    Carve probe(nullptr);
-    build(probe, opens, reqs);
+    u64* col_e = cv.take<u64>(kn);
+    u64* col_g = cv.take<u64>(kn);
+    u64* col_a1 = cv.take<u64>(kn);
+    CHK(issue_opens(c, {OpenJob{kOpenLeft, (i64)nx, x0, x1, t->a0, t->a1, eps, g},
+                        OpenJob{kOpenRight, (i64)nw, w0, w1, t->b0, t->b1, del, nullptr}}));
+    hipStream_t st = c->s[0];
+    CHK(hip_status(launch_im2col(st, eps, nullptr, s.batch, s.cin, s.length, s.ksize, s.stride, lout, col_e)));
+    CHK(hip_status(launch_im2col(st, g, nullptr, s.batch, s.cin, s.length, s.ksize, s.stride, lout, col_g)));
+    CHK(hip_status(launch_im2col(st, t->a1, nullptr, s.batch, s.cin, s.length, s.ksize, s.stride, lout, col_a1)));
+    c->stats.launches += 3;
+    std::vector<PlainProblem> probs;
+    for (int p = 0; p < 2; ++p)
+      probs.push_back(plain_problem(M, N, K, K, p == 0 ? t->b0 : t->b1, nullptr, K, del, K, col_e, nullptr, N,
+                                    p == 0 ? col_g : col_a1, N,
+                                    make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
+    CHK(issue_plain(c, probs));
   }
-  const size_t need = 2 * align_up(nx * 8) + align_up(nw * 8) + gemm_ws_bytes(reqs, form) + kAlign;
-  CHK(ensure_ws(c, need));
-  opens.clear();
-  reqs.clear();
-  Carve cv(c->ws);
-  build(cv, opens, reqs);
-  CHK(issue_beaver(c, opens, reqs, form, cv));
   c->stats.opens++;
   c->stats.open_bytes_per_party += 8 * (uint64_t)(nx + nw);
   if (trunc_bits) c->stats.truncations++;
@@ -1075,19 +1057,20 @@ mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
   form = resolve_form(form, M, N, K);
-  GemmReq r{};
-  r.M = M;
-  r.N = N;
-  r.K0 = K;
-  r.K1 = 0;
-  r.A0 = left_rowmajor(A, K);
-  r.B0 = right_rowmajor(B, N);
-  r.ep = make_ep(nullptr, +1, 0, C, rowmajor_view(N));
-  std::vector<GemmReq> reqs{r};
-  CHK(ensure_ws(c, gemm_ws_bytes(reqs, form) + kAlign));
-  Carve cv(c->ws);
-  Blob blob;
-  CHK(issue_gemms(c, reqs, form, cv, blob));
+  const Epilogue ep = make_ep(nullptr, +1, 0, C, rowmajor_view(N));
+  if (form == MPC_FORM_LIMB8) {
+    JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
+    set_inputs(ja, {A});
+    add_output(ja, {1});
+    set_inputs(jb, {B});
+    add_output(jb, {1});
+    CHK(ensure_ws(c, kAlign + job_bytes(ja) + job_bytes(jb)));
+    Carve cv(c->ws);
+    const PackJob PA = place_job(ja, cv), PB = place_job(jb, cv);
+    CHK(issue_limb(c, {PA, PB}, {limb_req(M, N, K, 0, PA.dst[0], nullptr, PB.dst[0], nullptr, ep)}));
+  } else {
+    CHK(issue_plain(c, {plain_problem(M, N, K, 0, A, nullptr, K, nullptr, 0, B, nullptr, N, nullptr, 0, ep)}));
+  }
   return end_call(c);
 }
 
@@ -1098,7 +1081,6 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
   CHK(check_form(form));
   if (form == MPC_FORM_AUTO) form = MPC_FORM_LIMB8;
   std::vector<MatmulPlan> plans;
-  size_t open_bytes = 0;
   for (size_t i = 0; i < count; ++i) {
     const mpc_matmul_desc& d = descs[i];
     MatmulPlan m{d.M, d.N, d.K, d.x0, d.x1, d.y0, d.y1, d.t, d.z0, d.z1};
@@ -1112,32 +1094,14 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
         return MPC_E_ALIAS;
     }
     plans.push_back(m);
-    open_bytes += matmul_open_bytes(m);
   }
   if (plans.empty()) return MPC_OK;
   CHK(set_device(c));
-  // heavy problems first, so the persistent GEMM's static rounds stay balanced
+  // heavy problems first, so the GEMM's tile list front-loads the long tiles
   std::stable_sort(plans.begin(), plans.end(), [](const MatmulPlan& a, const MatmulPlan& b) {
     return a.K > b.K;
   });
-  std::vector<OpenJob> opens;
-  std::vector<GemmReq> reqs;
-  {
-    Carve probe(nullptr);
-    for (const MatmulPlan& m : plans) matmul_build(m, probe, trunc_bits, opens, reqs);
-  }
-  const size_t need = open_bytes + gemm_ws_bytes(reqs, form) + kAlign;
-  CHK(ensure_ws(c, need));
-  opens.clear();
-  reqs.clear();
-  Carve cv(c->ws);
-  for (const MatmulPlan& m : plans) matmul_build(m, cv, trunc_bits, opens, reqs);
-  CHK(issue_beaver(c, opens, reqs, form, cv));
-  for (const MatmulPlan& m : plans) {
-    c->stats.opens++;
-    c->stats.open_bytes_per_party += 8 * (uint64_t)(m.M * m.K + m.K * m.N);
-    if (trunc_bits) c->stats.truncations++;
-  }
+  CHK(run_matmuls(c, plans, trunc_bits, form));
   return end_call(c);
 }
 

@@ -20,11 +20,12 @@
 //
 // GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a 128x64
 // output tile; each wave a 64x32 sub-tile held as 2 (row halves) x 8
-// (diagonals) 32x32 int32 accumulators (256 accumulation registers).  Per
-// 32-wide k step the workgroup stages 4 left and 2 right blocks (48 KiB)
-// through a double-buffered LDS ring with one barrier per step, and each wave
-// issues 72 MFMAs.  The launch is persistent (one workgroup per CU) and maps
-// consecutive tiles of a round to the same XCD so they share its L2.
+// (diagonals) 32x32 int32 accumulators (256 accumulation registers).  Each
+// wave streams its own fragments from global memory through buffer loads
+// (every wave load is one contiguous KiB), with one k step of loads in flight
+// behind the 72 MFMAs of the current step: no LDS and no barrier.  One
+// workgroup per tile; tiles are remapped so each XCD works on a contiguous
+// run of them and shares operand blocks in its L2.
 #include "internal.h"
 
 namespace mpc {
@@ -35,14 +36,10 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr u64 kLimbBias = 0x8080808080808080ULL;
 
-typedef __attribute__((address_space(1))) const v4i gv4i;
-
-// 16-byte load through the global (not flat) address space, so the wait
-// counters of LDS traffic and global traffic stay separate.
-__device__ __forceinline__ v4i ld_global16(const uint8_t* p) { return *(gv4i*)p; }
 
 // ------------------------------------------------------------------ packing
 constexpr int kPackThreads = 256;  // 4 waves, one 32x32 block each
+constexpr int kTPad = 33;          // LDS row stride (elements) of the transpose tile
 
 __device__ __forceinline__ int find_job(const i64* __restrict__ start, int njobs, i64 blk) {
   int lo = 0, hi = njobs - 1;
@@ -54,40 +51,23 @@ __device__ __forceinline__ int find_job(const i64* __restrict__ start, int njobs
   return lo;
 }
 
-__device__ __forceinline__ u64 pack_fetch(const PackJob& jb, i64 r, i64 k) {
-  if (r >= jb.rows || k >= jb.K) return 0;
-  size_t off;
-  if (jb.kind == kPackRow) {
-    off = (size_t)(r * jb.ld + k);
-  } else if (jb.kind == kPackCol) {
-    off = (size_t)(k * jb.ld + r);
-  } else {
-    const i64 b = r / jb.lout, l = r % jb.lout;
-    const i64 c = k / jb.ksz, j = k % jb.ksz;
-    off = (size_t)((b * jb.cin + c) * jb.len + l * jb.stride + j);
+// acc[o][q] += coef[o][i] * v
+__device__ __forceinline__ void accumulate(u64 (&acc)[kPackMaxOut][16], const PackJob& jb, int i,
+                                           int q, u64 v) {
+#pragma unroll
+  for (int o = 0; o < kPackMaxOut; ++o) {
+    const int c = jb.coef[o][i];
+    acc[o][q] += c > 0 ? v : (c < 0 ? (u64)0 - v : (u64)0);
   }
-  u64 v = jb.src[off];
-  if (jb.add) v += jb.add[off];
-  return v;
 }
 
-__global__ void __launch_bounds__(kPackThreads)
-    k_pack(const PackJob* __restrict__ jobs, const i64* __restrict__ block_start, int njobs) {
-  const i64 blk = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blk >= block_start[njobs]) return;
-  const int lane = threadIdx.x & 63;
-  const int ji = find_job(block_start, njobs, blk);
-  const PackJob jb = jobs[ji];
-  const i64 local = blk - block_start[ji];
-  const i64 rb = local / jb.kblocks, kb = local % jb.kblocks;
-  const i64 r = rb * 32 + (lane & 31);
-  const i64 k0 = kb * 32 + (lane >> 5) * 16;
-
+// Writes one lane's 16 elements (row or col l % 32, k = (l / 32) * 16 + q) of a
+// block as signed 8-bit limbs: plane i gets byte i of (v + 0x80..80) ^ 0x80..80.
+__device__ __forceinline__ void write_limbs(uint8_t* blockp, int lane, const u64 (&v)[16]) {
   u64 d[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) d[q] = (pack_fetch(jb, r, k0 + q) + kLimbBias) ^ kLimbBias;
-
-  uint8_t* out = jb.dst + ((size_t)local << 13) + lane * 16;
+  for (int q = 0; q < 16; ++q) d[q] = (v[q] + kLimbBias) ^ kLimbBias;
+  uint8_t* out = blockp + lane * 16;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     v4i w;
@@ -102,12 +82,84 @@ __global__ void __launch_bounds__(kPackThreads)
   }
 }
 
+// One wave packs one 32x32 block of every output of a job.  Right operands
+// (COL, IM2COL) are read in the packed lane order directly: for each k the
+// 32 lanes of a half-wave read 32 consecutive columns.  Left operands (ROW)
+// are read with 32 lanes along a row (coalesced) and transposed through a
+// padded LDS tile.
+__global__ void __launch_bounds__(kPackThreads)
+    k_pack(const PackJob* __restrict__ jobs, const i64* __restrict__ block_start, int njobs) {
+  __shared__ u64 tile[4][32 * kTPad];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const i64 blk = (i64)blockIdx.x * 4 + wave;
+  if (blk >= block_start[njobs]) return;  // whole wave leaves; only wave-level sync below
+  const PackJob& jb = jobs[find_job(block_start, njobs, blk)];
+  const i64 local = blk - block_start[find_job(block_start, njobs, blk)];
+  const i64 rb = local / jb.kblocks, kb = local % jb.kblocks;
+  const size_t boff = (size_t)local << 13;
+
+  u64 acc[kPackMaxOut][16];
+#pragma unroll
+  for (int o = 0; o < kPackMaxOut; ++o)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[o][q] = 0;
+
+  if (jb.kind == kPackRow) {
+    // load layout: step q covers rows 2q and 2q+1 of the block, k = lane % 32
+    const i64 k = kb * 32 + (lane & 31);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const i64 r = rb * 32 + 2 * q + (lane >> 5);
+      const bool ok = r < jb.rows && k < jb.K;
+      for (int i = 0; i < jb.nin; ++i) {
+        const u64 v = ok ? jb.in[i][r * jb.ld + k] : 0;
+        accumulate(acc, jb, i, q, v);
+      }
+    }
+    u64* t = tile[wave];
+#pragma unroll
+    for (int o = 0; o < kPackMaxOut; ++o) {
+      if (o >= jb.nout) break;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) t[(2 * q + (lane >> 5)) * kTPad + (lane & 31)] = acc[o][q];
+      __builtin_amdgcn_wave_barrier();
+      u64 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = t[(lane & 31) * kTPad + (lane >> 5) * 16 + q];
+      __builtin_amdgcn_wave_barrier();
+      write_limbs(jb.dst[o] + boff, lane, v);
+    }
+    return;
+  }
+
+  // right operands: lane covers column n = rb*32 + lane%32, k = kb*32 + (lane/32)*16 + q
+  const i64 n = rb * 32 + (lane & 31);
+  const i64 k0 = kb * 32 + (lane >> 5) * 16;
+  i64 col_base = 0;
+  if (jb.kind == kPackIm2col && n < jb.rows) {
+    const i64 b = n / jb.lout, l = n % jb.lout;
+    col_base = b * jb.cin * jb.len + l * jb.stride;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const i64 k = k0 + q;
+    const bool ok = n < jb.rows && k < jb.K;
+    i64 off = 0;
+    if (ok) off = jb.kind == kPackCol ? k * jb.ld + n : col_base + (k / jb.ksz) * jb.len + k % jb.ksz;
+    for (int i = 0; i < jb.nin; ++i) {
+      const u64 v = ok ? jb.in[i][off] : 0;
+      accumulate(acc, jb, i, q, v);
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kPackMaxOut; ++o)
+    if (o < jb.nout) write_limbs(jb.dst[o] + boff, lane, acc[o]);
+}
+
 // ------------------------------------------------------------------ GEMM
 constexpr int kThreads = 256;
-constexpr int LBM = 128, LBN = 64;  // output tile
+constexpr int LBM = 128, LBN = 64;  // output tile of a workgroup
 constexpr int kABlocks = LBM / 32, kBBlocks = LBN / 32;
-constexpr int kStageBytes = (kABlocks + kBBlocks) * kLimbBlockBytes;  // 48 KiB
-constexpr int kLoadsPerThread = kStageBytes / (kThreads * 16);       // 12
 constexpr int kGroupM = 8;
 
 __device__ __forceinline__ int find_problem(const int* __restrict__ start, int nprob, int t) {
@@ -120,40 +172,110 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ start, int n
   return lo;
 }
 
-// Address of the 16 bytes thread `tid` copies for load q of k-block kg.
-__device__ __forceinline__ const uint8_t* stage_src(const LimbProblem& p, i64 tm, i64 tn, int kg,
-                                                    int q, int tid) {
-  const int bi = q >> 1;                         // block within the stage
-  const int within = ((q & 1) << 12) + tid * 16;  // byte within the block
-  const bool seg0 = kg < p.kb0;
-  const i64 kb = seg0 ? kg : kg - p.kb0;
-  const i64 kbs = seg0 ? p.kb0 : p.kb1;
-  if (bi < kABlocks) {
-    const i64 mb = tm * kABlocks + bi;
-    const uint8_t* base = seg0 ? p.PA0 : p.PA1;
-    return base + ((size_t)(mb * kbs + kb) << 13) + within;
-  }
-  const i64 nb = tn * kBBlocks + (bi - kABlocks);
-  const uint8_t* base = seg0 ? p.PB0 : p.PB1;
-  return base + ((size_t)(nb * kbs + kb) << 13) + within;
+// Buffer resource over `bytes` bytes at `base` (raw, no stride).  Loads go
+// through the scalar descriptor with a per-lane byte offset in one VGPR, a
+// per-step scalar offset and the plane offset in the instruction's immediate.
+constexpr int kBufferWord3 = 0x00020000;  // 32-bit raw data format, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const uint8_t* base, i64 bytes) {
+  const int n = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, n, kBufferWord3);
 }
 
+__device__ __forceinline__ v4i ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0);
+}
+
+// The blocks one wave reads in one problem segment: the strip of its two
+// 32-row left blocks (consecutive row blocks, so one descriptor covers both)
+// and the strip of its 32-col right block, each kbs blocks of 8 KiB long.
+struct SegSrc {
+  __amdgpu_buffer_rsrc_t a, b;
+  int kbs;
+};
+
+__device__ __forceinline__ SegSrc seg_src(const uint8_t* PA, const uint8_t* PB, int kbs, i64 mb0,
+                                          i64 nb) {
+  SegSrc q;
+  const i64 strip = (i64)kbs << 13;
+  q.a = make_rsrc(PA + mb0 * strip, 2 * strip);
+  q.b = make_rsrc(PB + nb * strip, strip);
+  q.kbs = kbs;
+  return q;
+}
+
+// Scalar offsets of one k step: block kb of the left strip (row half r at
+// +r*kbs blocks) and of the right strip.
+struct StepOff {
+  __amdgpu_buffer_rsrc_t a, b;
+  int a0, a1, bo;
+};
+
+__device__ __forceinline__ StepOff step_off(const SegSrc& s0, const SegSrc& s1, int kb0, int kg) {
+  const bool seg0 = kg < kb0;
+  const SegSrc& q = seg0 ? s0 : s1;
+  const int kb = seg0 ? kg : kg - kb0;
+  StepOff o;
+  o.a = q.a;
+  o.b = q.b;
+  o.a0 = kb << 13;
+  o.a1 = (kb + q.kbs) << 13;
+  o.bo = kb << 13;
+  return o;
+}
+
+__device__ __forceinline__ void load_b(v4i (&b)[8], const StepOff& o, unsigned lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) b[i] = ld_buf(o.b, lo + i * 1024, o.bo);
+}
+
+// One 32-wide k step: 72 MFMAs.  Level l multiplies left plane l with right
+// planes 0..7-l into diagonals l..7 (for both 32-row halves); consecutive
+// MFMAs write different accumulators.  Left plane l is dead after level l, so
+// it is reloaded in place for the next step right away (a whole step of
+// latency to hide); right plane 0 is used by every level, so the right planes
+// are double-buffered by the caller.
+__device__ __forceinline__ void mfma_step(v16i (&acc)[2][8], v4i (&a)[2][8], const v4i (&b)[8],
+                                          const StepOff& next, unsigned lo) {
+#pragma unroll
+  for (int l = 0; l < 8; ++l) {
+#pragma unroll
+    for (int s = l; s < 8; ++s)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        acc[r][s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[r][l], b[s - l], acc[r][s], 0, 0, 0);
+    a[0][l] = ld_buf(next.a, lo + l * 1024, next.a0);
+    a[1][l] = ld_buf(next.a, lo + l * 1024, next.a1);
+    // keep this order: reordering across levels lengthens the fragments'
+    // live ranges past the register file
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// GEMM over a tile list.  A 256-thread workgroup (one wave per
+// SIMD) owns a 128x64 output tile and each wave a 64x32 quarter of it, held
+// as 2 (row halves) x 8 (diagonals) 32x32 int32 accumulators.  Each wave
+// streams its fragments straight from global memory into two register sets:
+// while the MFMAs consume one k step, the loads of the step two ahead are in
+// flight, so no LDS traffic and no barrier sit between MFMAs.  The four waves
+// of a workgroup read overlapping blocks at about the same time, which the
+// CU's L1 and the XCD's L2 serve.
 __global__ void __launch_bounds__(kThreads, 1)
-    k_limb_gemm(const LimbProblem* __restrict__ probs, TileMap map, int total_tiles) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];  // 2 stages
+    k_limb_gemm(const LimbProblem* __restrict__ probs, TileMap map) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  // the wave index is uniform across the wave: keep it (and every address
+  // derived from it) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const int G = gridDim.x;
-
-  for (int it = 0;; ++it) {
-    const int t0 = it * G + blockIdx.x;
-    if (t0 >= total_tiles) break;
-    // Consecutive tiles of a full round go to the same XCD (blocks are
-    // dispatched to XCDs round-robin), so they share that XCD's L2.
-    int t = t0;
-    if ((it + 1) * G <= total_tiles && (G & 7) == 0) t = it * G + (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-
+  // One workgroup per tile.  Workgroups are dispatched to the 8 XCDs
+  // round-robin in index order, so index b runs on XCD b % 8; remapping
+  // b -> (b % 8) * (G / 8) + b / 8 gives each XCD a contiguous run of tiles,
+  // which then share that XCD's L2.
+  const int G = gridDim.x, b = blockIdx.x;
+  const int G8 = G & ~7;
+  {
+    const int t = b < G8 ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
     const int pi = find_problem(map.tile_start, map.nprob, t);
     const LimbProblem& p = probs[pi];
     const int local = t - map.tile_start[pi];
@@ -164,6 +286,8 @@ __global__ void __launch_bounds__(kThreads, 1)
     const int gsize = min(ntm - first_m, kGroupM);
     const int in_group = local % per_group;
     const i64 tm = first_m + in_group % gsize, tn = in_group / gsize;
+    const i64 mb0 = tm * kABlocks + 2 * wr;  // this wave's first left block
+    const i64 nb = tn * kBBlocks + wc;       // this wave's right block
 
     v16i acc[2][8];
 #pragma unroll
@@ -174,53 +298,32 @@ __global__ void __launch_bounds__(kThreads, 1)
         for (int e = 0; e < 16; ++e) acc[r][s][e] = 0;
 
     const int kbeg = p.kb_begin, nk = p.kb_end - p.kb_begin;
-    v4i pre[kLoadsPerThread];
+    const unsigned lo = (unsigned)lane * 16u;
+    const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mb0, nb);
+    const SegSrc s1 = seg_src(p.PA1 ? p.PA1 : p.PA0, p.PB1 ? p.PB1 : p.PB0, p.kb1, mb0, nb);
+    v4i a[2][8], b0[8], b1[8];
     if (nk > 0) {
+      const StepOff o = step_off(s0, s1, p.kb0, kbeg);
 #pragma unroll
-      for (int q = 0; q < kLoadsPerThread; ++q)
-        pre[q] = ld_global16(stage_src(p, tm, tn, kbeg, q, tid));
-#pragma unroll
-      for (int q = 0; q < kLoadsPerThread; ++q) *(v4i*)(lds + q * 4096 + tid * 16) = pre[q];
-      if (nk > 1) {
-#pragma unroll
-        for (int q = 0; q < kLoadsPerThread; ++q)
-          pre[q] = ld_global16(stage_src(p, tm, tn, kbeg + 1, q, tid));
+      for (int i = 0; i < 8; ++i) {
+        a[0][i] = ld_buf(o.a, lo + i * 1024, o.a0);
+        a[1][i] = ld_buf(o.a, lo + i * 1024, o.a1);
       }
+      load_b(b0, o, lo);
+      load_b(b1, step_off(s0, s1, p.kb0, kbeg + min(1, nk - 1)), lo);
     }
-    __syncthreads();
-
-    for (int kk = 0; kk < nk; ++kk) {
-      const uint8_t* st = lds + (kk & 1) * kStageBytes;
-      v4i bf[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        bf[i] = *(const v4i*)(st + (kABlocks + wc) * kLimbBlockBytes + i * 1024 + lane * 16);
-      // level l: pairs (i = l, j = s - l) for every diagonal s >= l
-#pragma unroll
-      for (int l = 0; l < 8; ++l) {
-        v4i af[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-          af[r] = *(const v4i*)(st + (2 * wr + r) * kLimbBlockBytes + l * 1024 + lane * 16);
-#pragma unroll
-        for (int s = l; s < 8; ++s)
-#pragma unroll
-          for (int r = 0; r < 2; ++r)
-            acc[r][s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bf[s - l], acc[r][s], 0, 0, 0);
-      }
-
-      if (kk + 1 < nk) {
-        uint8_t* nx = lds + ((kk + 1) & 1) * kStageBytes;
-#pragma unroll
-        for (int q = 0; q < kLoadsPerThread; ++q) *(v4i*)(nx + q * 4096 + tid * 16) = pre[q];
-        if (kk + 2 < nk) {
-#pragma unroll
-          for (int q = 0; q < kLoadsPerThread; ++q)
-            pre[q] = ld_global16(stage_src(p, tm, tn, kbeg + kk + 2, q, tid));
-        }
-      }
-      __syncthreads();
+    // Steps alternate between the two right-operand buffers; an odd last step
+    // runs after the loop so the loop body has no branch.  Loads past the last
+    // step re-read the last step's blocks (valid memory, results unused).
+    const int klast = kbeg + nk - 1;
+    int kk = 0;
+    for (; kk + 1 < nk; kk += 2) {
+      mfma_step(acc, a, b0, step_off(s0, s1, p.kb0, min(kbeg + kk + 1, klast)), lo);
+      load_b(b0, step_off(s0, s1, p.kb0, min(kbeg + kk + 2, klast)), lo);
+      mfma_step(acc, a, b1, step_off(s0, s1, p.kb0, min(kbeg + kk + 2, klast)), lo);
+      load_b(b1, step_off(s0, s1, p.kb0, min(kbeg + kk + 3, klast)), lo);
     }
+    if (kk < nk) mfma_step(acc, a, b0, step_off(s0, s1, p.kb0, klast), lo);
 
     // Epilogue: C = sum_s 2^(8s) X_s (mod 2^64), then the shared epilogue.
     // 32x32 accumulator layout: lane l, register e holds row
@@ -249,8 +352,6 @@ __global__ void __launch_bounds__(kThreads, 1)
   }
 }
 
-bool g_attr_set = false;
-
 }  // namespace
 
 i64 limb_rblocks(i64 rows) {
@@ -270,17 +371,9 @@ hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_star
 }
 
 hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
-                            int grid) {
+                            int /*num_cu*/) {
   if (total_tiles <= 0) return hipSuccess;
-  if (!g_attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_limb_gemm,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kStageBytes);
-    if (e != hipSuccess) return e;
-    g_attr_set = true;
-  }
-  if (grid > total_tiles) grid = total_tiles;
-  hipLaunchKernelGGL(k_limb_gemm, dim3(grid), dim3(kThreads), 2 * kStageBytes, s, probs, map,
-                     total_tiles);
+  hipLaunchKernelGGL(k_limb_gemm, dim3(total_tiles), dim3(kThreads), 0, s, probs, map);
   return hipGetLastError();
 }
 

@@ -79,24 +79,30 @@ struct PlainProblem {
 constexpr int kLimbBlockBytes = 8192;
 constexpr int kLimbRowPad = 4;
 
-// Source of a pack job: element (r, k) of the logical operand.
-//   kind ROW: left operand MxK at src[r*ld + k] (+ add[...])
-//   kind COL: right operand KxN at src[k*ld + n] (+ add[...]); r is the column
+// A pack job reads up to four uint64 operands of one shape, elementwise, and
+// writes up to three packed outputs, each a signed sum of the inputs:
+//   out_o(r, k) = sum_i coef[o][i] * in_i(r, k)   (coef in {-1, 0, +1})
+// so one pass can open a masked value and pack it with the triple's shares:
+// eps = x0 + x1 - a0 - a1, g0 = a0 + eps = x0 + x1 - a1, and a1 itself.
+// Element (r, k) of the logical operand (zero outside rows x K) is
+//   kind ROW:    left operand MxK, in[r*ld + k]
+//   kind COL:    right operand KxN, in[k*ld + r]  (r is the column)
 //   kind IM2COL: right operand, k = c*ksz + j, n = b*Lout + l, element
-//                x[b][c][l*stride + j] of a [B][Cin][L] activation (+ add)
+//                in[b][c][l*stride + j] of a [B][Cin][L] activation
 enum PackKind : int { kPackRow = 0, kPackCol = 1, kPackIm2col = 2 };
+constexpr int kPackMaxIn = 4, kPackMaxOut = 3;
 
 struct PackJob {
   int kind;
+  int nin, nout;
   i64 rows;  // M for ROW, N for COL/IM2COL (the non-k dimension)
   i64 K;
-  const u64* src;
-  const u64* add;
+  const u64* in[kPackMaxIn];
   i64 ld;
-  // im2col geometry
-  i64 cin, len, ksz, stride, lout;
-  uint8_t* dst;
-  i64 rblocks;  // padded block counts
+  i64 cin, len, ksz, stride, lout;  // im2col geometry
+  int8_t coef[kPackMaxOut][kPackMaxIn];
+  uint8_t* dst[kPackMaxOut];
+  i64 rblocks;  // padded block counts of every output
   i64 kblocks;
 };
 

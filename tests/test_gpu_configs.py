@@ -1,0 +1,289 @@
+"""GPU parity at the workloads' real sizes, in the launch configuration the
+benchmark uses: full comparison with the oracle where it finishes in seconds,
+sampled outputs (computed one by one by the oracle) otherwise, plus
+plaintext checks where the fixed-point values stay in range."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import bigint
+from tests.gpu_util import dev, host, pair, say
+
+pytestmark = pytest.mark.gpu
+FRAC = 16
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2109_00984_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(m):
+    c = m.Context(device=0, seed=workloads.seeds(0)[1])
+    yield c
+    c.close()
+
+
+def assert_pair(got, want, what):
+    assert np.array_equal(got[0], want[0]), f"{what}: party 0 differs"
+    assert np.array_equal(got[1], want[1]), f"{what}: party 1 differs"
+
+
+def sample_positions(seed, shape, count):
+    g = workloads.rng(seed)
+    idx = [g.integers(0, n, size=count) for n in shape]
+    # always include the corners
+    for i, n in enumerate(shape):
+        idx[i][:2] = [0, n - 1]
+    return idx
+
+
+# ------------------------------------------------------------------ small workload
+def test_small_workload_plaintext(m, ctx):
+    """X[64x128] @ W[128x32] and an element-wise product over 4096, both forms:
+    bit-exact to the oracle and within one unit of the exact fixed-point product."""
+    c = workloads.SMALL
+    dseed, pseed = workloads.seeds(1)[2], workloads.seeds(0)[1]
+    X = oracle.encode(workloads.uniform(1001, (c["M"], c["K"]), c["lo"], c["hi"]))
+    W = oracle.encode(workloads.uniform(1002, (c["K"], c["N"]), c["lo"], c["hi"]))
+    xs, ws = oracle.share(X, 0, pseed, 1), oracle.share(W, 1, pseed, 2)
+    want = oracle.beaver_matmul(xs, ws, oracle.dealer_matmul(dseed, 3, c["M"], c["N"], c["K"]), FRAC)
+    for form in ("plain", "limb8"):
+        say(f"small workload matmul {form}")
+        t = ctx.dealer(m.TRIPLE_MATMUL, dseed, 3, (c["M"], c["N"], c["K"]))
+        z = ctx.beaver_matmul(ctx.share(dev(X), 0, 1), ctx.share(dev(W), 1, 2), t, FRAC, form)
+        assert_pair(pair(ctx, z), want, f"small matmul {form}")
+    exact = bigint.matmul(oracle.as_ring(X).tolist(), oracle.as_ring(W).tolist())
+    got = oracle.reveal(*want)
+    for i in range(c["M"]):
+        for j in range(c["N"]):
+            assert bigint.s64(int(got[i, j])) - (bigint.s64(exact[i][j]) >> FRAC) in (-1, 0)
+    n = c["n_elem"]
+    x = oracle.encode(workloads.uniform(1003, n, c["lo"], c["hi"]))
+    y = oracle.encode(workloads.uniform(1004, n, c["lo"], c["hi"]))
+    t = ctx.dealer(m.TRIPLE_MUL, dseed, 4, (n,))
+    z = ctx.beaver_mul(ctx.share(dev(x), 0, 5), ctx.share(dev(y), 1, 6), t, FRAC)
+    want = oracle.beaver_mul(oracle.share(x, 0, pseed, 5), oracle.share(y, 1, pseed, 6),
+                             oracle.dealer_mul(dseed, 4, n), FRAC)
+    assert_pair(pair(ctx, z), want, "small element-wise")
+
+
+# ------------------------------------------------------------------ MLP
+def run_mlp_gpu(m, ctx, X, Ws, dseed, form):
+    B, dims = workloads.MLP["batch"], workloads.MLP["dims"]
+    h = ctx.share(dev(X), 0, 100)
+    outs = []
+    for i in range(3):
+        w = ctx.share(dev(Ws[i]), 1, 101 + i)
+        t = ctx.dealer(m.TRIPLE_MATMUL, dseed, 200 + i, (B, dims[i + 1], dims[i]))
+        h = ctx.beaver_matmul(h, w, t, FRAC, form)
+        outs.append(pair(ctx, h))
+        if i < 2:
+            p = ctx.dealer(m.TRIPLE_SQUARE, dseed, 300 + i, (B * dims[i + 1],))
+            flat = m.SharedPair(h.s0.view(-1), h.s1.view(-1))
+            sq = ctx.beaver_mul(flat, None, p, FRAC)
+            h = m.SharedPair(sq.s0.view(B, dims[i + 1]), sq.s1.view(B, dims[i + 1]))
+            outs.append(pair(ctx, h))
+    return outs
+
+
+def run_mlp_oracle(X, Ws, pseed, dseed):
+    B, dims = workloads.MLP["batch"], workloads.MLP["dims"]
+    h = oracle.share(X, 0, pseed, 100)
+    outs = []
+    for i in range(3):
+        w = oracle.share(Ws[i], 1, pseed, 101 + i)
+        h = oracle.beaver_matmul(h, w, oracle.dealer_matmul(dseed, 200 + i, B, dims[i + 1], dims[i]), FRAC)
+        outs.append(h)
+        if i < 2:
+            sq = oracle.beaver_square((h[0].ravel(), h[1].ravel()),
+                                      oracle.dealer_square(dseed, 300 + i, B * dims[i + 1]), FRAC)
+            h = (sq[0].reshape(B, dims[i + 1]), sq[1].reshape(B, dims[i + 1]))
+            outs.append(h)
+    return outs
+
+
+def test_mlp_784_1024_1024_10(m, ctx):
+    """Secure 3-layer MLP with square activations, batch 128, both forms: every
+    intermediate share bit-exact; the in-range layers close to float64."""
+    cfg = workloads.MLP
+    dseed, pseed = workloads.seeds(2)[2], workloads.seeds(0)[1]
+    dims = cfg["dims"]
+    Xf = workloads.uniform(1002, (cfg["batch"], dims[0]), cfg["lo"], cfg["hi"])
+    Wf = [workloads.uniform(1102 + i, (dims[i], dims[i + 1]), cfg["lo"], cfg["hi"]) for i in range(3)]
+    X = oracle.encode(Xf)
+    Ws = [oracle.encode(w) for w in Wf]
+    say("mlp oracle")
+    want = run_mlp_oracle(X, Ws, pseed, dseed)
+    for form in ("plain", "limb8"):
+        say(f"mlp gpu {form}")
+        got = run_mlp_gpu(m, ctx, X, Ws, dseed, form)
+        for li, (g, w) in enumerate(zip(got, want)):
+            assert_pair(g, w, f"mlp {form} stage {li}")
+    # layer 1 and its square stay far inside the int64 range: compare with float64
+    h1 = oracle.decode(oracle.reveal(*want[0]))
+    ref1 = oracle.decode(oracle.as_ring(X)) @ oracle.decode(oracle.as_ring(Ws[0]))
+    nmse = np.mean((h1 - ref1) ** 2) / np.mean(ref1 ** 2)
+    assert nmse < 4e-4
+    h1sq = oracle.decode(oracle.reveal(*want[1]))
+    nmse = np.mean((h1sq - h1 ** 2) ** 2) / np.mean(h1 ** 4)
+    assert nmse < 4e-4
+
+
+# ------------------------------------------------------------------ 4096^3
+def test_gemm4k_beaver_matmul_sampled(m, ctx):
+    """The benchmark's step at M = N = K = 4096 on uniform uint64 operands (limb
+    form), checked at sampled outputs; the plain form must agree everywhere."""
+    M = N = K = 4096
+    data_seed, pseed, dseed = workloads.seeds(3)
+    c = m.Context(device=0, seed=pseed)
+    Xh = workloads.uniform_u64(data_seed, (M, K))
+    Yh = workloads.uniform_u64(data_seed + 1, (K, N))
+    say("gemm4k gpu limb")
+    x, y = c.share(dev(Xh), 0, 1), c.share(dev(Yh), 1, 2)
+    t = c.dealer(m.TRIPLE_MATMUL, dseed, 3, (M, N, K))
+    zl = c.beaver_matmul(x, y, t, FRAC, "limb8")
+    say("gemm4k gpu plain")
+    zp = c.beaver_matmul(x, y, t, FRAC, "plain")
+    c.sync()
+    assert torch.equal(zl.s0, zp.s0) and torch.equal(zl.s1, zp.s1)
+    rows, cols = sample_positions(7, (M, N), 256)
+    got = (host(c, zl.s0)[rows, cols], host(c, zl.s1)[rows, cols])
+    gc = (host(c, t.c0)[rows, cols], host(c, t.c1)[rows, cols])
+    say("gemm4k oracle samples")
+    xs, ys = oracle.share(Xh, 0, pseed, 1), oracle.share(Yh, 1, pseed, 2)
+    a, b = oracle.dealer_matmul_ab(dseed, 3, M, N, K)
+    assert np.array_equal(host(c, t.a0), a[0]) and np.array_equal(host(c, t.b1), b[1])
+    c_at = oracle.dealer_matmul_c_at(dseed, 3, M, N, K, a, b, rows, cols)
+    assert_pair(gc, c_at, "gemm4k dealer c")
+    want = oracle.beaver_matmul_at(xs, ys, a, b, c_at, FRAC, rows, cols)
+    assert_pair(got, want, "gemm4k beaver matmul")
+    c.close()
+
+
+def test_gemm4k_ring_gemm_forms(m, ctx):
+    M = N = K = 4096
+    say("gemm4k ring gemm forms")
+    A = workloads.uniform_u64(11, (M, K))
+    B = workloads.uniform_u64(12, (K, N))
+    gA, gB = dev(A), dev(B)
+    Cl = ctx.ring_gemm(gA, gB, "limb8")
+    Cp = ctx.ring_gemm(gA, gB, "plain")
+    ctx.sync()
+    assert torch.equal(Cl, Cp)
+    rows, cols = sample_positions(8, (M, N), 512)
+    assert np.array_equal(host(ctx, Cl)[rows, cols], oracle.ring_gemm_at(A, B, rows, cols))
+
+
+# ------------------------------------------------------------------ conv stack
+CONV_LAYERS = workloads.conv_shapes(workloads.CONV["batch"], workloads.CONV["length"])
+
+
+@pytest.mark.parametrize("li", [0, 1, 8, 9])
+def test_conv_layer_full_size_sampled(m, ctx, li):
+    """Beaver conv1d of one layer of the conv workload at full size (limb form),
+    sampled outputs against the oracle; plain form identical everywhere."""
+    Bt, cin, L, cout, k, s, lout = CONV_LAYERS[li]
+    data_seed, pseed, dseed = workloads.seeds(4)
+    say(f"conv layer {li}: {(Bt, cin, L, cout, k, s)}")
+    X = oracle.encode(workloads.uniform(data_seed + li, (Bt, cin, L), -2, 2))
+    W = oracle.encode(workloads.uniform(data_seed + 100 + li, (cout, cin, k), -2, 2))
+    dims = (Bt, cin, L, cout, k, s)
+    x, w = ctx.share(dev(X), 0, 10 + li), ctx.share(dev(W), 1, 30 + li)
+    t = ctx.dealer(m.TRIPLE_CONV1D, dseed, 50 + li, dims)
+    zl = ctx.beaver_conv1d(x, w, t, s, FRAC, "limb8")
+    zp = ctx.beaver_conv1d(x, w, t, s, FRAC, "plain")
+    ctx.sync()
+    assert torch.equal(zl.s0, zp.s0) and torch.equal(zl.s1, zp.s1)
+    bs, os_, ls = sample_positions(li, (Bt, cout, lout), 128)
+    got = (host(ctx, zl.s0)[bs, os_, ls], host(ctx, zl.s1)[bs, os_, ls])
+    xs, ws = oracle.share(X, 0, pseed, 10 + li), oracle.share(W, 1, pseed, 30 + li)
+    a, b = oracle.dealer_conv1d_ab(dseed, 50 + li, Bt, cin, L, cout, k)
+    c_at = oracle.dealer_conv1d_c_at(dseed, 50 + li, dims, a, b, bs, os_, ls)
+    assert_pair((host(ctx, t.c0)[bs, os_, ls], host(ctx, t.c1)[bs, os_, ls]), c_at, "conv dealer c")
+    want = oracle.beaver_conv1d_at(xs, ws, a, b, c_at, s, FRAC, bs, os_, ls)
+    assert_pair(got, want, f"conv layer {li}")
+    if li == 0:
+        # the first layer stays in range: its reveal is the exact conv truncated
+        r = oracle.reveal(*want).view(np.int64)
+        exact = oracle.conv1d_at(oracle.as_ring(X), oracle.as_ring(W), s, bs, os_, ls)
+        d = r - (exact.view(np.int64) >> FRAC)
+        assert set(d.tolist()) <= {-1, 0}
+
+
+def test_conv_stack_small_full(m, ctx):
+    """The whole 10-layer stack (square activations after all but the last) at
+    batch 1 and a short sequence (every layer's output non-empty), every
+    intermediate share bit-exact."""
+    Bt, L = 1, 200
+    layers = workloads.conv_shapes(Bt, L)
+    assert all(lo > 0 for *_, lo in layers)
+    data_seed, pseed, dseed = workloads.seeds(4)
+    X = oracle.encode(workloads.uniform(data_seed, (Bt, 40, L), -2, 2))
+    Ws = [oracle.encode(workloads.uniform(data_seed + 100 + i, (cout, cin, k), -2, 2))
+          for i, (_, cin, _, cout, k, _, _) in enumerate(layers)]
+    for form in ("limb8", "plain"):
+        say(f"conv stack small {form}")
+        hg = ctx.share(dev(X), 0, 1)
+        ho = oracle.share(X, 0, pseed, 1)
+        for i, (b_, cin, Li, cout, k, s, lout) in enumerate(layers):
+            dims = (b_, cin, Li, cout, k, s)
+            wg = ctx.share(dev(Ws[i]), 1, 20 + i)
+            wo = oracle.share(Ws[i], 1, pseed, 20 + i)
+            tg = ctx.dealer(m.TRIPLE_CONV1D, dseed, 40 + i, dims)
+            to = oracle.dealer_conv1d(dseed, 40 + i, *dims)
+            hg = ctx.beaver_conv1d(hg, wg, tg, s, FRAC, form)
+            ho = oracle.beaver_conv1d(ho, wo, to, s, FRAC)
+            assert_pair(pair(ctx, hg), ho, f"{form} conv {i}")
+            if i < len(layers) - 1:
+                n = b_ * cout * lout
+                pg = ctx.dealer(m.TRIPLE_SQUARE, dseed, 60 + i, (n,))
+                sq = ctx.beaver_mul(m.SharedPair(hg.s0.view(-1), hg.s1.view(-1)), None, pg, FRAC)
+                hg = m.SharedPair(sq.s0.view(b_, cout, lout), sq.s1.view(b_, cout, lout))
+                so = oracle.beaver_square((ho[0].ravel(), ho[1].ravel()),
+                                          oracle.dealer_square(dseed, 60 + i, n), FRAC)
+                ho = (so[0].reshape(b_, cout, lout), so[1].reshape(b_, cout, lout))
+                assert_pair(pair(ctx, hg), ho, f"{form} square {i}")
+
+
+# ------------------------------------------------------------------ grouped
+def test_grouped_256_uneven(m, ctx):
+    """256 independent Beaver matmuls of log-uniform shapes in one grouped call:
+    identical to one call per problem, and to the oracle at sampled outputs."""
+    data_seed, pseed, dseed = workloads.seeds(5)
+    shapes = workloads.grouped_shapes(data_seed, **{k: v for k, v in workloads.GROUPED.items()
+                                                    if k != "count"})
+    assert len(shapes) == 256
+    c = m.Context(device=0, seed=pseed)
+    probs, host_in = [], []
+    say("grouped: building 256 problems")
+    for i, (M, N, K) in enumerate(shapes):
+        X = workloads.uniform_u64(data_seed * 1000 + 2 * i, (M, K))
+        Y = workloads.uniform_u64(data_seed * 1000 + 2 * i + 1, (K, N))
+        x, y = c.share(dev(X), 0, 2 * i), c.share(dev(Y), 1, 2 * i + 1)
+        t = c.dealer(m.TRIPLE_MATMUL, dseed, i, (M, N, K))
+        probs.append((x, y, t))
+        host_in.append((X, Y))
+    say("grouped: launch")
+    zs = c.beaver_matmul_grouped(probs, FRAC, "limb8")
+    c.sync()
+    for i, ((x, y, t), (M, N, K)) in enumerate(zip(probs, shapes)):
+        single = c.beaver_matmul(x, y, t, FRAC, "plain")
+        c.sync()
+        assert torch.equal(zs[i].s0, single.s0) and torch.equal(zs[i].s1, single.s1), i
+    say("grouped: oracle samples")
+    for i in range(0, 256, 5):
+        M, N, K = shapes[i]
+        X, Y = host_in[i]
+        rows, cols = sample_positions(i, (M, N), 8)
+        xs, ys = oracle.share(X, 0, pseed, 2 * i), oracle.share(Y, 1, pseed, 2 * i + 1)
+        a, b = oracle.dealer_matmul_ab(dseed, i, M, N, K)
+        c_at = oracle.dealer_matmul_c_at(dseed, i, M, N, K, a, b, rows, cols)
+        want = oracle.beaver_matmul_at(xs, ys, a, b, c_at, FRAC, rows, cols)
+        got = (host(c, zs[i].s0)[rows, cols], host(c, zs[i].s1)[rows, cols])
+        assert_pair(got, want, f"grouped problem {i} {shapes[i]}")
+    c.close()

@@ -327,6 +327,23 @@ def test_beaver_conv_identity():
     assert oracle.reveal(*z).view(np.int64).tolist() == _correlate_reference(xi, wi, s).tolist()
 
 
+def test_beaver_conv_sampled_matches_full():
+    shape = (2, 3, 20, 4, 5, 2)
+    Bt, Cin, L, Cout, k, s = shape
+    X, W = rand_ring(3, (Bt, Cin, L)), rand_ring(4, (Cout, Cin, k))
+    xs, ws = oracle.share(X, 0, 3, 1), oracle.share(W, 1, 3, 2)
+    t = oracle.dealer_conv1d(9, 2, *shape)
+    z = oracle.beaver_conv1d(xs, ws, t, s, 16)
+    a, b = oracle.dealer_conv1d_ab(9, 2, Bt, Cin, L, Cout, k)
+    assert all(np.array_equal(u, v) for u, v in zip(a + b, t.a + t.b))
+    Lout = z[0].shape[2]
+    bs, os_, ls = np.array([0, 1, 1, 0]), np.array([0, 3, 1, 2]), np.array([0, Lout - 1, 3, 5])
+    c_at = oracle.dealer_conv1d_c_at(9, 2, shape, a, b, bs, os_, ls)
+    assert np.array_equal(c_at[0], t.c[0][bs, os_, ls]) and np.array_equal(c_at[1], t.c[1][bs, os_, ls])
+    z_at = oracle.beaver_conv1d_at(xs, ws, a, b, c_at, s, 16, bs, os_, ls)
+    assert np.array_equal(z_at[0], z[0][bs, os_, ls]) and np.array_equal(z_at[1], z[1][bs, os_, ls])
+
+
 # ------------------------------------------------------------------ limbs
 def test_limb_decomposition_identity():
     v = np.concatenate([ring(EDGE), rand_ring(8, 5000)])
