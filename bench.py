@@ -216,7 +216,90 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
         ex[f"mlp_ms_{form}"] = round(mlp_latency(ctx, mpc, torch, workloads, form), 4)
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
     ctx.sync()
+    ex.update(grouped_bench(mpc, torch, workloads))
+    ex.update(conv_bench(mpc, torch, workloads))
     return ex
+
+
+def grouped_bench(mpc, torch, workloads):
+    """256 uneven Beaver matmuls: one open+pack launch and one GEMM launch,
+    captured in a HIP graph and replayed; autotuned schedule vs the default."""
+    data_seed, pseed, dseed = workloads.seeds(5)
+    shapes = workloads.grouped_shapes(data_seed)
+    side = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(side):
+        c = mpc.Context(device=0, seed=pseed)
+        probs = []
+        for i, (m, n, k) in enumerate(shapes):
+            x = c.share(torch.from_numpy(workloads.uniform_u64(data_seed * 1000 + 2 * i, (m, k)).view(np.int64)).to(c.device), 0, 2 * i)
+            y = c.share(torch.from_numpy(workloads.uniform_u64(data_seed * 1000 + 2 * i + 1, (k, n)).view(np.int64)).to(c.device), 1, 2 * i + 1)
+            probs.append((x, y, c.dealer(mpc.TRIPLE_MATMUL, dseed, i, (m, n, k))))
+        outs = [mpc.SharedPair(c.empty((m, n)), c.empty((m, n))) for (m, n, k) in shapes]
+        macs = float(sum(m * n * k for m, n, k in shapes))
+
+        def timed(label):
+            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)  # sizes the workspace
+            c.sync()
+            c.graph_begin()
+            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)
+            g = c.graph_end()
+            c.graph_launch(g)
+            c.sync()
+            ms = _event_time(torch, side, lambda: c.graph_launch(g), 10)
+            mpc.Context.graph_destroy(g)
+            out[f"grouped256_{label}_ms"] = round(ms, 4)
+            out[f"grouped256_{label}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
+            log(f"bench: grouped 256 ({label}) graph replay {ms:.3f} ms")
+
+        timed("default_schedule")
+        best = c.autotune_matmul(shapes)
+        out["grouped256_tuned_schedule"] = best
+        timed("autotuned")
+        out["grouped256_plaintext_macs"] = macs
+        c.close()
+    return out
+
+
+def conv_bench(mpc, torch, workloads):
+    """The Wav2Letter-shaped conv stack (batch 8, 40x1600): 10 Beaver conv1d
+    layers with truncation and 9 Beaver squares, online phase only."""
+    data_seed, pseed, dseed = workloads.seeds(4)
+    cfg = workloads.CONV
+    layers = workloads.conv_shapes(cfg["batch"], cfg["length"])
+    out = {}
+    c = mpc.Context(device=0, seed=pseed)
+    dv = lambda a: torch.from_numpy(a).to(c.device)
+    X = mpc.encode(workloads.uniform(data_seed, (cfg["batch"], cfg["channels"], cfg["length"]), cfg["lo"], cfg["hi"]), FRAC)
+    x0 = c.share(dv(X), 0, 1)
+    ws, ts, ps = [], [], []
+    for i, (b, cin, L, cout, k, s, lout) in enumerate(layers):
+        W = mpc.encode(workloads.uniform(data_seed + 100 + i, (cout, cin, k), cfg["lo"], cfg["hi"]), FRAC)
+        ws.append(c.share(dv(W), 1, 20 + i))
+        ts.append(c.dealer(mpc.TRIPLE_CONV1D, dseed, 40 + i, (b, cin, L, cout, k, s)))
+        if i < len(layers) - 1:
+            ps.append(c.dealer(mpc.TRIPLE_SQUARE, dseed, 60 + i, (b * cout * lout,)))
+    macs = float(sum(cout * b * lout * cin * k for (b, cin, L, cout, k, s, lout) in layers))
+
+    def forward(form):
+        h = x0
+        for i, (b, cin, L, cout, k, s, lout) in enumerate(layers):
+            h = c.beaver_conv1d(h, ws[i], ts[i], s, FRAC, form)
+            if i < len(layers) - 1:
+                sq = c.beaver_mul(mpc.SharedPair(h.s0.view(-1), h.s1.view(-1)), None, ps[i], FRAC)
+                h = mpc.SharedPair(sq.s0.view(b, cout, lout), sq.s1.view(b, cout, lout))
+        return h
+
+    for form, reps in (("limb8", 5), ("plain", 1)):
+        forward(form)
+        c.sync()
+        ms = _event_time(torch, c.streams[0], lambda: forward(form), reps)
+        out[f"conv_stack_{form}_ms"] = round(ms, 3)
+        out[f"conv_stack_{form}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
+        log(f"bench: conv stack {form}: {ms:.3f} ms")
+    out["conv_stack_plaintext_macs"] = macs
+    c.close()
+    return out
 
 
 def mlp_latency(ctx, mpc, torch, workloads, form):

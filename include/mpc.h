@@ -214,6 +214,28 @@ typedef struct {
 mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
                                      int trunc_bits, mpc_form form);
 
+/* ---- autotuning of the limb GEMM ---------------------------------------- */
+/* A tile schedule: the workgroup tile shape (0: 128x64, 1: 64x128, 2: 64x64
+ * outputs), the number of tile rows per raster group, and whether tiles are
+ * remapped so that each XCD works on a contiguous run of them. */
+typedef struct {
+  int variant, group_m, xcd_remap;
+  double ms; /* measured time of the tuned launch(es), filled by the tuner */
+} mpc_tile_config;
+
+/* Times every tile schedule on the exact GEMM problem list that a Beaver
+ * matmul (count = 1) or a grouped call of these `count` shapes issues in the
+ * limb form (dims: HOST array of M, N, K per problem), on random operands,
+ * and remembers the fastest for later calls with the same shapes.  Uses the
+ * context's workspace and party 0's stream; synchronises it.  `best` may be
+ * NULL. */
+mpc_status mpc_autotune_matmul(mpc_ctx *ctx, size_t count, const int64_t *dims, mpc_tile_config *best);
+/* Writes / reads the tuned schedules (a text file, one entry per line). */
+mpc_status mpc_autotune_save(const mpc_ctx *ctx, const char *path);
+mpc_status mpc_autotune_load(mpc_ctx *ctx, const char *path);
+/* Schedule used when no tuned entry matches (default: 128x64, 8, remap on). */
+mpc_status mpc_set_default_tile_config(mpc_ctx *ctx, const mpc_tile_config *cfg);
+
 /* Stream capture of the context's work into a HIP graph: begin, issue calls,
  * end.  Party 0's stream must not be the null stream.  The workspace must
  * already be large enough (issue the same calls once eagerly first, or call

@@ -50,6 +50,13 @@ class GemmTiming(ctypes.Structure):
     _fields_ = [("launches", U64), ("total_ms", ctypes.c_double), ("ring_macs", ctypes.c_double)]
 
 
+class TileConfig(ctypes.Structure):
+    _fields_ = [("variant", INT), ("group_m", INT), ("xcd_remap", INT), ("ms", ctypes.c_double)]
+
+
+TILE_VARIANTS = {0: "128x64", 1: "64x128", 2: "64x64"}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("opens", U64), ("open_bytes_per_party", U64), ("truncations", U64),
                 ("launches", U64), ("gemm_problems", U64)]
@@ -78,6 +85,10 @@ _SIGS = {
     "mpc_beaver_matmul_grouped": (INT, [VP, SZ, ctypes.POINTER(MatmulDesc), INT, INT]),
     "mpc_profile_enable": (INT, [VP, INT]),
     "mpc_profile_read": (INT, [VP, ctypes.POINTER(GemmTiming), ctypes.POINTER(GemmTiming)]),
+    "mpc_autotune_matmul": (INT, [VP, SZ, ctypes.POINTER(I64), ctypes.POINTER(TileConfig)]),
+    "mpc_autotune_save": (INT, [VP, ctypes.c_char_p]),
+    "mpc_autotune_load": (INT, [VP, ctypes.c_char_p]),
+    "mpc_set_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
     "mpc_graph_begin": (INT, [VP]),
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
     "mpc_graph_launch": (INT, [VP, VP]),
@@ -350,6 +361,29 @@ class Context:
         _check(_lib.mpc_beaver_matmul_grouped(self._h, len(problems), descs, trunc_bits,
                                               FORMS[form]), "mpc_beaver_matmul_grouped")
         return results
+
+    # -------------------------------------------------------------- autotuning
+    def autotune_matmul(self, shapes):
+        """Tune the limb GEMM schedule for a Beaver matmul (one shape) or a
+        grouped call of these (M, N, K) shapes; returns the chosen schedule."""
+        flat = [int(v) for s in shapes for v in s]
+        dims = (I64 * max(1, len(flat)))(*flat)
+        best = TileConfig()
+        _check(_lib.mpc_autotune_matmul(self._h, len(shapes), dims, ctypes.byref(best)),
+               "mpc_autotune_matmul")
+        return {"variant": TILE_VARIANTS[best.variant], "group_m": best.group_m,
+                "xcd_remap": bool(best.xcd_remap), "ms": best.ms}
+
+    def autotune_save(self, path):
+        _check(_lib.mpc_autotune_save(self._h, str(path).encode()), "mpc_autotune_save")
+
+    def autotune_load(self, path):
+        _check(_lib.mpc_autotune_load(self._h, str(path).encode()), "mpc_autotune_load")
+
+    def set_default_tile_config(self, variant=0, group_m=8, xcd_remap=True):
+        cfg = TileConfig(variant, group_m, 1 if xcd_remap else 0, 0.0)
+        _check(_lib.mpc_set_default_tile_config(self._h, ctypes.byref(cfg)),
+               "mpc_set_default_tile_config")
 
     # -------------------------------------------------------------- graphs
     def graph_begin(self):

@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <array>
 #include <new>
 #include <vector>
 
@@ -74,6 +77,10 @@ struct mpc_ctx {
   bool profiling = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
+  // limb GEMM tile schedule used when no tuned entry matches, and the tuned
+  // schedules keyed by the hash of a matmul shape list
+  TileSched sched_default{kLimb128x64, 8, 1};
+  std::map<uint64_t, TileSched> tuned;
 };
 
 namespace {
@@ -193,9 +200,9 @@ mpc_status upload(mpc_ctx* c, const Blob& b, uint8_t** dev) {
   return MPC_OK;
 }
 
-// Marks the end of a call: the current upload slot may be reused once party
-// 0's stream passes this point.
-mpc_status end_call(mpc_ctx* c) {
+// The current upload slot may be reused once party 0's stream passes this
+// point (every kernel reading it has been issued before).
+mpc_status mark_slot(mpc_ctx* c) {
   if (c->cur_slot >= 0 && !c->capturing) {
     UploadSlot& sl = c->slots[c->cur_slot];
     HIPCHK(hipEventRecord(sl.done, c->s[0]));
@@ -204,6 +211,9 @@ mpc_status end_call(mpc_ctx* c) {
   c->cur_slot = -1;
   return MPC_OK;
 }
+
+// Marks the end of a call.
+mpc_status end_call(mpc_ctx* c) { return mark_slot(c); }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 
@@ -323,20 +333,18 @@ PlainProblem plain_problem(i64 M, i64 N, i64 K0, i64 K1, const u64* A0, const u6
 // A pack job before its outputs are placed in the workspace.
 struct JobSpec {
   int kind = kPackRow;
+  int mode = kModeCopy;
   i64 rows = 0, K = 0, ld = 0;
   i64 cin = 0, len = 0, ksz = 1, stride = 1, lout = 1;
-  int nin = 0, nout = 0;
   const u64* in[kPackMaxIn] = {nullptr, nullptr, nullptr, nullptr};
-  int8_t coef[kPackMaxOut][kPackMaxIn] = {};
 };
 
-size_t job_bytes(const JobSpec& j) { return (size_t)j.nout * align_up(packed_bytes(j.rows, j.K)); }
+size_t job_bytes(const JobSpec& j) { return (size_t)pack_nout(j.mode) * align_up(packed_bytes(j.rows, j.K)); }
 
 PackJob place_job(const JobSpec& j, Carve& cv) {
   PackJob p{};
   p.kind = j.kind;
-  p.nin = j.nin;
-  p.nout = j.nout;
+  p.mode = j.mode;
   p.rows = j.rows;
   p.K = j.K;
   p.ld = j.ld;
@@ -346,16 +354,14 @@ PackJob place_job(const JobSpec& j, Carve& cv) {
   p.stride = j.stride;
   p.lout = j.lout;
   for (int i = 0; i < kPackMaxIn; ++i) p.in[i] = j.in[i];
-  for (int o = 0; o < kPackMaxOut; ++o)
-    for (int i = 0; i < kPackMaxIn; ++i) p.coef[o][i] = j.coef[o][i];
   p.rblocks = limb_rblocks(j.rows);
   p.kblocks = limb_kblocks(j.K);
   for (int o = 0; o < kPackMaxOut; ++o)
-    p.dst[o] = o < j.nout ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
+    p.dst[o] = o < pack_nout(j.mode) ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
   return p;
 }
 
-// Left operand MxK (row-major, leading dimension ld) from `nin` inputs.
+// Left operand MxK (row-major, leading dimension ld).
 JobSpec left_job(i64 M, i64 K, i64 ld) {
   JobSpec j;
   j.kind = kPackRow;
@@ -386,29 +392,18 @@ JobSpec im2col_job(const mpc_conv1d_shape& s, i64 lout) {
   j.lout = lout;
   return j;
 }
-// Output coefficient rows used by the jobs.
-void set_inputs(JobSpec& j, std::initializer_list<const u64*> ins) {
-  j.nin = 0;
-  for (const u64* p : ins) j.in[j.nin++] = p;
+void set_mode(JobSpec& j, int mode, std::initializer_list<const u64*> ins) {
+  j.mode = mode;
+  int n = 0;
+  for (const u64* p : ins) j.in[n++] = p;
 }
-void add_output(JobSpec& j, std::initializer_list<int> coef) {
-  int i = 0;
-  for (int c : coef) j.coef[j.nout][i++] = (int8_t)c;
-  j.nout++;
-}
-// The fused open of a Beaver operand pair (x, a): outputs eps = x0+x1-a0-a1,
-// g0 = a0 + eps = x0+x1-a1 and a1 (left side), or for (y, b): delta, b0, b1.
+// The fused open of a Beaver operand pair: (x, a) gives eps, g0 = a0 + eps and
+// a1; (y, b) gives delta, b0 and b1.
 void open_left(JobSpec& j, const u64* x0, const u64* x1, const u64* a0, const u64* a1) {
-  set_inputs(j, {x0, x1, a0, a1});
-  add_output(j, {1, 1, -1, -1});  // eps
-  add_output(j, {1, 1, 0, -1});   // g0 = a0 + eps
-  add_output(j, {0, 0, 0, 1});    // a1
+  set_mode(j, kModeOpenLeft, {x0, x1, a0, a1});
 }
 void open_right(JobSpec& j, const u64* y0, const u64* y1, const u64* b0, const u64* b1) {
-  set_inputs(j, {y0, y1, b0, b1});
-  add_output(j, {1, 1, -1, -1});  // delta
-  add_output(j, {0, 0, 1, 0});    // b0
-  add_output(j, {0, 0, 0, 1});    // b1
+  set_mode(j, kModeOpenRight, {y0, y1, b0, b1});
 }
 
 struct LimbReq {
@@ -420,14 +415,40 @@ struct LimbReq {
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
 // whose concatenated K exceeds the int32-safe range continues in the next
 // launch, adding into its output; truncation is applied by its last chunk).
-mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs, const std::vector<LimbReq>& reqs) {
+mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std::vector<LimbReq>& reqs,
+                      TileSched sched) {
   hipStream_t st = c->s[0];
+  // one pack launch per (kind, mode): the kernel is specialised on both
+  std::vector<PackJob> jobs;
+  std::vector<std::pair<int, int>> launch_km;
+  std::vector<size_t> first_job;
+  for (int kind : {kPackRow, kPackCol, kPackIm2col})
+    for (int mode : {kModeCopy, kModeSum2, kModeOpenLeft, kModeOpenRight}) {
+      bool any = false;
+      for (const PackJob& j : jobs_in) {
+        if (j.kind != kind || j.mode != mode) continue;
+        if (!any) {
+          first_job.push_back(jobs.size());
+          launch_km.push_back({kind, mode});
+          any = true;
+        }
+        jobs.push_back(j);
+      }
+    }
+  first_job.push_back(jobs.size());
   const size_t nj = jobs.size(), nreq = reqs.size();
   Blob blob;
-  std::vector<i64> bstart(nj + 1, 0);
-  for (size_t i = 0; i < nj; ++i) bstart[i + 1] = bstart[i] + jobs[i].rblocks * jobs[i].kblocks;
+  // per launch: prefix sums of its jobs' block counts
+  std::vector<size_t> obstart(launch_km.size());
+  std::vector<i64> nblocks(launch_km.size());
+  for (size_t L = 0; L < launch_km.size(); ++L) {
+    std::vector<i64> bstart(1, 0);
+    for (size_t i = first_job[L]; i < first_job[L + 1]; ++i)
+      bstart.push_back(bstart.back() + jobs[i].rblocks * jobs[i].kblocks);
+    obstart[L] = blob.add(bstart.data(), bstart.size());
+    nblocks[L] = bstart.back();
+  }
   const size_t ojobs = blob.add(jobs.data(), nj);
-  const size_t obstart = blob.add(bstart.data(), nj + 1);
 
   int max_chunks = 0;
   std::vector<int> nchunks(nreq);
@@ -466,7 +487,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs, const std::v
       }
       if (ch + 1 < nchunks[q]) p.ep.trunc_bits = 0;
       probs.push_back(p);
-      tstart.push_back(tstart.back() + limb_tiles(r.M, r.N));
+      tstart.push_back(tstart.back() + limb_tiles(r.M, r.N, sched.variant));
       // true (unpadded) k values this chunk covers, for the timing record
       auto true_k = [&](i64 kb) {
         return kb <= p.kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - p.kb0) * 32, r.K1);
@@ -480,16 +501,17 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs, const std::v
   }
   uint8_t* dev = nullptr;
   CHK(upload(c, blob, &dev));
-  if (nj) {
-    CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs), (const i64*)(dev + obstart), (int)nj,
-                               bstart[nj])));
+  for (size_t L = 0; L < launch_km.size(); ++L) {
+    const int njl = (int)(first_job[L + 1] - first_job[L]);
+    CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs) + first_job[L], (const i64*)(dev + obstart[L]),
+                               njl, nblocks[L], launch_km[L].first, launch_km[L].second)));
     c->stats.launches++;
   }
   for (int ch = 0; ch < max_chunks; ++ch) {
     TileMap map{tcount[ch], (const int*)(dev + otile[ch])};
     LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[ch]);
     CHK(tm.start());
-    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[ch]), map, ttotal[ch], c->num_cu)));
+    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[ch]), map, ttotal[ch], sched)));
     CHK(tm.stop());
     c->stats.launches++;
   }
@@ -779,10 +801,8 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
   const u64 *L0 = kind == MPC_TRIPLE_MATMUL ? t->a0 : t->b0, *L1 = kind == MPC_TRIPLE_MATMUL ? t->a1 : t->b1;
   const u64 *R0 = kind == MPC_TRIPLE_MATMUL ? t->b0 : t->a0, *R1 = kind == MPC_TRIPLE_MATMUL ? t->b1 : t->a1;
   JobSpec jl = left_job(M, K, K), jr = kind == MPC_TRIPLE_MATMUL ? right_job(K, N, N) : im2col_job(cs, lout);
-  set_inputs(jl, {L0, L1});
-  add_output(jl, {1, 1});
-  set_inputs(jr, {R0, R1});
-  add_output(jr, {1, 1});
+  set_mode(jl, kModeSum2, {L0, L1});
+  set_mode(jr, kModeSum2, {R0, R1});
   size_t need = kAlign;
   if (form == MPC_FORM_LIMB8) need += job_bytes(jl) + job_bytes(jr);
   else if (kind == MPC_TRIPLE_CONV1D) need += align_up((size_t)(K * N) * 8);
@@ -797,7 +817,7 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
     Carve cv(c->ws);
     if (form == MPC_FORM_LIMB8) {
       std::vector<PackJob> jobs{place_job(jl, cv), place_job(jr, cv)};
-      CHK(issue_limb(c, jobs, {limb_req(M, N, K, 0, jobs[0].dst[0], nullptr, jobs[1].dst[0], nullptr, ep)}));
+      CHK(issue_limb(c, jobs, {limb_req(M, N, K, 0, jobs[0].dst[0], nullptr, jobs[1].dst[0], nullptr, ep)}, c->sched_default));
     } else if (kind == MPC_TRIPLE_MATMUL) {
       CHK(issue_plain(c, {plain_problem(M, N, K, 0, L0, L1, K, nullptr, 0, R0, R1, N, nullptr, 0, ep)}));
     } else {
@@ -842,6 +862,30 @@ mpc_status mpc_beaver_mul(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64
   if (trunc_bits) c->stats.truncations++;
   return end_call(c);
 }
+
+namespace {
+
+// FNV-1a hash of a list of matmul shapes (in the order the GEMM issues them).
+uint64_t shapes_key(const std::vector<std::array<i64, 3>>& shapes) {
+  uint64_t h = 1469598103934665603ULL;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xff;
+      h *= 1099511628211ULL;
+    }
+  };
+  mix(shapes.size());
+  for (const auto& s : shapes)
+    for (i64 v : s) mix((uint64_t)v);
+  return h;
+}
+
+TileSched sched_for(const mpc_ctx* c, const std::vector<std::array<i64, 3>>& shapes) {
+  auto it = c->tuned.find(shapes_key(shapes));
+  return it == c->tuned.end() ? c->sched_default : it->second;
+}
+
+}  // namespace
 
 namespace {
 
@@ -941,8 +985,12 @@ mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int tru
   if (form == MPC_FORM_LIMB8) {
     std::vector<PackJob> jobs;
     std::vector<LimbReq> reqs;
-    for (const MatmulPlan& m : plans) matmul_limb(m, cv, trunc, jobs, reqs);
-    CHK(issue_limb(c, jobs, reqs));
+    std::vector<std::array<i64, 3>> shapes;
+    for (const MatmulPlan& m : plans) {
+      matmul_limb(m, cv, trunc, jobs, reqs);
+      shapes.push_back({m.M, m.N, m.K});
+    }
+    CHK(issue_limb(c, jobs, reqs, sched_for(c, shapes)));
   } else {
     std::vector<OpenJob> opens;
     std::vector<PlainProblem> probs;
@@ -1013,7 +1061,7 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
     for (int p = 0; p < 2; ++p)
       reqs.push_back(limb_req(M, N, K, K, W.dst[p == 0 ? 1 : 2], W.dst[0], X.dst[0], X.dst[p == 0 ? 1 : 2],
                               make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
-    CHK(issue_limb(c, {W, X}, reqs));
+    CHK(issue_limb(c, {W, X}, reqs, c->sched_default));
   } else {
     const size_t kn = (size_t)(K * N);
     CHK(ensure_ws(c, kAlign + 2 * align_up(nx * 8) + align_up(nw * 8) + 3 * align_up(kn * 8)));
@@ -1060,14 +1108,12 @@ mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint
   const Epilogue ep = make_ep(nullptr, +1, 0, C, rowmajor_view(N));
   if (form == MPC_FORM_LIMB8) {
     JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
-    set_inputs(ja, {A});
-    add_output(ja, {1});
-    set_inputs(jb, {B});
-    add_output(jb, {1});
+    set_mode(ja, kModeCopy, {A});
+    set_mode(jb, kModeCopy, {B});
     CHK(ensure_ws(c, kAlign + job_bytes(ja) + job_bytes(jb)));
     Carve cv(c->ws);
     const PackJob PA = place_job(ja, cv), PB = place_job(jb, cv);
-    CHK(issue_limb(c, {PA, PB}, {limb_req(M, N, K, 0, PA.dst[0], nullptr, PB.dst[0], nullptr, ep)}));
+    CHK(issue_limb(c, {PA, PB}, {limb_req(M, N, K, 0, PA.dst[0], nullptr, PB.dst[0], nullptr, ep)}, c->sched_default));
   } else {
     CHK(issue_plain(c, {plain_problem(M, N, K, 0, A, nullptr, K, nullptr, 0, B, nullptr, N, nullptr, 0, ep)}));
   }
@@ -1103,6 +1149,114 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
   });
   CHK(run_matmuls(c, plans, trunc_bits, form));
   return end_call(c);
+}
+
+// ------------------------------------------------------------------ autotuning
+mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mpc_tile_config* best) {
+  if (!c || (count && !dims) || c->capturing) return MPC_E_INVAL;
+  std::vector<std::array<i64, 3>> shapes;
+  for (size_t i = 0; i < count; ++i) {
+    const i64 M = dims[3 * i], N = dims[3 * i + 1], K = dims[3 * i + 2];
+    if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+    if (M && N) shapes.push_back({M, N, K});
+  }
+  if (shapes.empty()) return MPC_OK;
+  CHK(set_device(c));
+  // the order a grouped call issues its problems in
+  if (shapes.size() > 1)
+    std::stable_sort(shapes.begin(), shapes.end(),
+                     [](const std::array<i64, 3>& a, const std::array<i64, 3>& b) { return a[2] > b[2]; });
+  // packed operands of both parties' finish GEMMs, as a Beaver matmul lays
+  // them out: left eps, g0, a1 and right delta, b0, b1 per problem
+  size_t need = kAlign;
+  for (const auto& s : shapes)
+    need += 3 * align_up(packed_bytes(s[0], s[2])) + 3 * align_up(packed_bytes(s[1], s[2]));
+  CHK(ensure_ws(c, need));
+  Carve cv(c->ws);
+  std::vector<LimbReq> reqs;
+  for (const auto& s : shapes) {
+    const i64 M = s[0], N = s[1], K = s[2];
+    uint8_t* L[3];
+    uint8_t* R[3];
+    for (auto& p : L) p = cv.take<uint8_t>(packed_bytes(M, K));
+    for (auto& p : R) p = cv.take<uint8_t>(packed_bytes(N, K));
+    for (int p = 0; p < 2; ++p)
+      reqs.push_back(limb_req(M, N, K, K, L[0], L[p == 0 ? 1 : 2], R[p == 0 ? 1 : 2], R[0],
+                              make_ep(nullptr, +1, 0, nullptr, rowmajor_view(N))));
+  }
+  // random limbs: the matrix cores' power draw, and so their clock, depends
+  // on the data
+  CHK(hip_status(launch_prg_fill(c->s[0], stream_key(c->seed, 0x7475, 0), (u64*)c->ws, cv.off / 8)));
+  // outputs: one scratch buffer per party, the largest problem's size
+  i64 maxmn = 0;
+  for (const auto& s : shapes) maxmn = std::max(maxmn, s[0] * s[1]);
+  u64* out[2] = {nullptr, nullptr};
+  for (int p = 0; p < 2; ++p) HIPCHK(hipMalloc((void**)&out[p], (size_t)maxmn * 8));
+  for (size_t q = 0; q < reqs.size(); ++q) reqs[q].ep.Out = out[q & 1];
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  mpc_tile_config win{c->sched_default.variant, c->sched_default.group_m, c->sched_default.xcd_remap, 1e30};
+  const bool prof = c->profiling;
+  c->profiling = false;
+  mpc_status st = MPC_OK;
+  for (int v = 0; v < kLimbVariants && st == MPC_OK; ++v)
+    for (int gm : {4, 8, 16})
+      for (int remap : {1, 0}) {
+        const TileSched ts{v, gm, remap};
+        st = issue_limb(c, {}, reqs, ts);  // warm-up
+        if (st == MPC_OK) st = mark_slot(c);
+        if (st != MPC_OK) break;
+        const int reps = 3;
+        (void)hipEventRecord(e0, c->s[0]);
+        for (int r = 0; r < reps && st == MPC_OK; ++r) {
+          st = issue_limb(c, {}, reqs, ts);
+          if (st == MPC_OK) st = mark_slot(c);
+        }
+        (void)hipEventRecord(e1, c->s[0]);
+        if (st != MPC_OK || hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms / reps < win.ms) win = mpc_tile_config{v, gm, remap, ms / reps};
+      }
+  c->profiling = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(c->s[0]);
+  for (int p = 0; p < 2; ++p) (void)hipFree(out[p]);
+  CHK(st);
+  c->tuned[shapes_key(shapes)] = TileSched{win.variant, win.group_m, win.xcd_remap};
+  if (best) *best = win;
+  return end_call(c);
+}
+
+mpc_status mpc_autotune_save(const mpc_ctx* c, const char* path) {
+  if (!c || !path) return MPC_E_INVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return MPC_E_INVAL;
+  for (const auto& kv : c->tuned)
+    std::fprintf(f, "%016llx %d %d %d\n", (unsigned long long)kv.first, kv.second.variant, kv.second.group_m,
+                 kv.second.xcd_remap);
+  std::fclose(f);
+  return MPC_OK;
+}
+
+mpc_status mpc_autotune_load(mpc_ctx* c, const char* path) {
+  if (!c || !path) return MPC_E_INVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return MPC_E_INVAL;
+  unsigned long long key;
+  int v, gm, remap;
+  while (std::fscanf(f, "%llx %d %d %d", &key, &v, &gm, &remap) == 4)
+    if (v >= 0 && v < kLimbVariants && gm >= 1) c->tuned[(uint64_t)key] = TileSched{v, gm, remap ? 1 : 0};
+  std::fclose(f);
+  return MPC_OK;
+}
+
+mpc_status mpc_set_default_tile_config(mpc_ctx* c, const mpc_tile_config* cfg) {
+  if (!c || !cfg || cfg->variant < 0 || cfg->variant >= kLimbVariants || cfg->group_m < 1) return MPC_E_INVAL;
+  c->sched_default = TileSched{cfg->variant, cfg->group_m, cfg->xcd_remap ? 1 : 0};
+  return MPC_OK;
 }
 
 // ------------------------------------------------------------------ measurement

@@ -5,6 +5,8 @@
 // Each kernel is a grid-stride loop over 64-bit elements with 256-thread
 // workgroups; consecutive lanes touch consecutive elements, so every wavefront
 // load or store is one contiguous 512-byte access.
+#include <initializer_list>
+
 #include "internal.h"
 
 namespace mpc {
@@ -134,6 +136,57 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// Two-element variants for 16-byte aligned arrays: one 16-byte load per
+// array per lane (half as many memory instructions), streamed with
+// non-temporal hints since no element is touched twice.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u64x2 ld2(const u64* p, size_t i) {
+  return __builtin_nontemporal_load((const u64x2*)p + i);
+}
+__device__ __forceinline__ void st2(u64* p, size_t i, u64x2 v) {
+  __builtin_nontemporal_store(v, (u64x2*)p + i);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_beaver_mul2(size_t n2, const u64* __restrict__ x0, const u64* __restrict__ x1,
+                  const u64* __restrict__ y0, const u64* __restrict__ y1,
+                  const u64* __restrict__ a0, const u64* __restrict__ a1,
+                  const u64* __restrict__ b0, const u64* __restrict__ b1,
+                  const u64* __restrict__ c0, const u64* __restrict__ c1, int trunc,
+                  u64* __restrict__ z0, u64* __restrict__ z1) {
+  GRID_STRIDE(i, n2) {
+    const u64x2 va0 = ld2(a0, i), va1 = ld2(a1, i), vb0 = ld2(b0, i), vb1 = ld2(b1, i);
+    const u64x2 eps = (ld2(x0, i) - va0) + (ld2(x1, i) - va1);
+    const u64x2 del = (ld2(y0, i) - vb0) + (ld2(y1, i) - vb1);
+    const u64x2 r0 = ld2(c0, i) + eps * vb0 + va0 * del + eps * del;
+    const u64x2 r1 = ld2(c1, i) + eps * vb1 + va1 * del;
+    st2(z0, i, u64x2{trunc_share(r0.x, trunc), trunc_share(r0.y, trunc)});
+    st2(z1, i, u64x2{trunc_share(r1.x, trunc), trunc_share(r1.y, trunc)});
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_beaver_square2(size_t n2, const u64* __restrict__ x0, const u64* __restrict__ x1,
+                     const u64* __restrict__ a0, const u64* __restrict__ a1,
+                     const u64* __restrict__ b0, const u64* __restrict__ b1, int trunc,
+                     u64* __restrict__ z0, u64* __restrict__ z1) {
+  GRID_STRIDE(i, n2) {
+    const u64x2 va0 = ld2(a0, i), va1 = ld2(a1, i);
+    const u64x2 eps = (ld2(x0, i) - va0) + (ld2(x1, i) - va1);
+    const u64x2 r0 = ld2(b0, i) + 2 * eps * va0 + eps * eps;
+    const u64x2 r1 = ld2(b1, i) + 2 * eps * va1;
+    st2(z0, i, u64x2{trunc_share(r0.x, trunc), trunc_share(r0.y, trunc)});
+    st2(z1, i, u64x2{trunc_share(r1.x, trunc), trunc_share(r1.y, trunc)});
+  }
+}
+
+bool aligned16(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (((uintptr_t)p & 15) != 0) return false;
+  return true;
+}
+
 // Open step of Beaver bilinear products: one workgroup per chunk of
 // kOpenChunk elements of one job (the job is found once per workgroup).
 __global__ void __launch_bounds__(kThreads)
@@ -228,6 +281,11 @@ hipError_t launch_beaver_mul(hipStream_t s, size_t n, const u64* x0, const u64* 
                              const u64* b1, const u64* c0, const u64* c1, int trunc, u64* z0,
                              u64* z1) {
   if (!n) return hipSuccess;
+  if (n % 2 == 0 && aligned16({x0, x1, y0, y1, a0, a1, b0, b1, c0, c1, z0, z1})) {
+    hipLaunchKernelGGL(k_beaver_mul2, dim3(grid_for(n / 2)), dim3(kThreads), 0, s, n / 2, x0, x1, y0, y1,
+                       a0, a1, b0, b1, c0, c1, trunc, z0, z1);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_beaver_mul, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x0, x1, y0, y1, a0,
                      a1, b0, b1, c0, c1, trunc, z0, z1);
   return hipGetLastError();
@@ -237,6 +295,11 @@ hipError_t launch_beaver_square(hipStream_t s, size_t n, const u64* x0, const u6
                                 const u64* a0, const u64* a1, const u64* b0, const u64* b1,
                                 int trunc, u64* z0, u64* z1) {
   if (!n) return hipSuccess;
+  if (n % 2 == 0 && aligned16({x0, x1, a0, a1, b0, b1, z0, z1})) {
+    hipLaunchKernelGGL(k_beaver_square2, dim3(grid_for(n / 2)), dim3(kThreads), 0, s, n / 2, x0, x1, a0,
+                       a1, b0, b1, trunc, z0, z1);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_beaver_square, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x0, x1, a0, a1,
                      b0, b1, trunc, z0, z1);
   return hipGetLastError();

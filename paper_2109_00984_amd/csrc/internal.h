@@ -79,32 +79,38 @@ struct PlainProblem {
 constexpr int kLimbBlockBytes = 8192;
 constexpr int kLimbRowPad = 4;
 
-// A pack job reads up to four uint64 operands of one shape, elementwise, and
-// writes up to three packed outputs, each a signed sum of the inputs:
-//   out_o(r, k) = sum_i coef[o][i] * in_i(r, k)   (coef in {-1, 0, +1})
-// so one pass can open a masked value and pack it with the triple's shares:
-// eps = x0 + x1 - a0 - a1, g0 = a0 + eps = x0 + x1 - a1, and a1 itself.
+// A pack job reads one to four uint64 operands of one shape, elementwise, and
+// writes one to three packed outputs (mode):
+//   COPY       in0                                  -> out0
+//   SUM2       in0 + in1                            -> out0
+//   OPEN_LEFT  (x0, x1, a0, a1): eps = x0+x1-a0-a1  -> out0,
+//              g0 = a0 + eps = x0+x1-a1 -> out1,  a1 -> out2
+//   OPEN_RIGHT (y0, y1, b0, b1): delta = y0+y1-b0-b1 -> out0,  b0 -> out1,  b1 -> out2
+// so one pass opens a masked value and packs it with the triple's shares.
 // Element (r, k) of the logical operand (zero outside rows x K) is
 //   kind ROW:    left operand MxK, in[r*ld + k]
 //   kind COL:    right operand KxN, in[k*ld + r]  (r is the column)
 //   kind IM2COL: right operand, k = c*ksz + j, n = b*Lout + l, element
 //                in[b][c][l*stride + j] of a [B][Cin][L] activation
 enum PackKind : int { kPackRow = 0, kPackCol = 1, kPackIm2col = 2 };
+enum PackMode : int { kModeCopy = 0, kModeSum2 = 1, kModeOpenLeft = 2, kModeOpenRight = 3 };
 constexpr int kPackMaxIn = 4, kPackMaxOut = 3;
 
 struct PackJob {
   int kind;
-  int nin, nout;
+  int mode;
   i64 rows;  // M for ROW, N for COL/IM2COL (the non-k dimension)
   i64 K;
   const u64* in[kPackMaxIn];
   i64 ld;
   i64 cin, len, ksz, stride, lout;  // im2col geometry
-  int8_t coef[kPackMaxOut][kPackMaxIn];
   uint8_t* dst[kPackMaxOut];
   i64 rblocks;  // padded block counts of every output
   i64 kblocks;
 };
+
+inline int pack_nin(int mode) { return mode == kModeCopy ? 1 : mode == kModeSum2 ? 2 : 4; }
+inline int pack_nout(int mode) { return mode <= kModeSum2 ? 1 : 3; }
 
 // Limb-form problem over packed segments; k-blocks [kb_begin, kb_end) of the
 // concatenation [segment 0 | segment 1] are processed (K chunking).
@@ -180,12 +186,23 @@ hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap m
 int plain_tiles(i64 M, i64 N);
 
 // Limb form (gemm_limb.hip).
-// jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device arrays.
+// jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device
+// arrays; every job of one launch has the given kind and mode.
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
-                       i64 total_blocks);
+                       i64 total_blocks, int kind, int mode);
+// Tile shapes of the limb GEMM (workgroup output tile) and the tile order.
+enum LimbVariant : int { kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2 };
+constexpr int kLimbVariants = 3;
+struct TileSched {
+  int variant;    // LimbVariant
+  int group_m;    // tile rows per raster group
+  int xcd_remap;  // give each XCD a contiguous run of tiles
+};
 hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
-                            int grid);
-int limb_tiles(i64 M, i64 N);
+                            TileSched sched);
+int limb_tiles(i64 M, i64 N, int variant);
+int limb_variant_sa(int variant);
+int limb_variant_sb(int variant);
 i64 limb_rblocks(i64 rows);  // padded 32-row block count
 i64 limb_kblocks(i64 K);
 

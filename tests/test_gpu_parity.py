@@ -291,3 +291,78 @@ def test_graph_replay_matches_eager(m):
         finally:
             m.Context.graph_destroy(g)
             c.close()
+
+
+@pytest.mark.parametrize("n", [4096, 4097])
+def test_beaver_mul_unaligned_views(m, ctx, n):
+    # views starting one element in are only 8-byte aligned: the element-wise
+    # kernels must take their scalar path and still match
+    say(f"beaver mul/square on offset views n={n}")
+    x = np.concatenate([EDGE, rnd(41, n + 1)])[: n + 1]
+    y = rnd(42, n + 1)
+    gx, gy = ctx.share(dev(x), 0, 91), ctx.share(dev(y), 1, 92)
+    t = ctx.dealer(m.TRIPLE_MUL, 17, 93, (n + 1,))
+    ts = m.TripleShares(*(v[1:] for v in (t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)))
+    xv = m.SharedPair(gx.s0[1:], gx.s1[1:])
+    yv = m.SharedPair(gy.s0[1:], gy.s1[1:])
+    out = m.SharedPair(ctx.empty((n + 1,))[1:], ctx.empty((n + 1,))[1:])
+    z = ctx.beaver_mul(xv, yv, ts, 16, out=out)
+    xs, ys = oracle.share(x, 0, SEED, 91), oracle.share(y, 1, SEED, 92)
+    w = oracle.dealer_mul(17, 93, n + 1)
+    sl = lambda p: (p[0][1:], p[1][1:])
+    want = oracle.beaver_mul(sl(xs), sl(ys), oracle.Triple(sl(w.a), sl(w.b), sl(w.c)), 16)
+    assert_pair(ctx, z, want, "beaver mul on views")
+    sq = ctx.beaver_mul(xv, None, ts, 16, out=out)
+    wsq = oracle.beaver_square(sl(xs), oracle.Triple(sl(w.a), sl(w.b)), 16)
+    assert_pair(ctx, sq, wsq, "beaver square on views")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("group_m,remap", [(1, False), (8, True)])
+def test_limb_tile_variants(m, variant, group_m, remap):
+    # every tile shape and schedule of the limb GEMM gives the plain result
+    say(f"limb tile variant {variant} group_m={group_m} remap={remap}")
+    c = m.Context(device=0, seed=SEED)
+    c.set_default_tile_config(variant, group_m, remap)
+    for (M, N, K) in [(200, 136, 70), (64, 64, 64), (1, 300, 33), (513, 65, 260)]:
+        A, B = rnd(M + variant, (M, K)), rnd(N + 7, (K, N))
+        Cl = c.ring_gemm(dev(A), dev(B), "limb8")
+        assert np.array_equal(host(c, Cl), oracle.ring_gemm(A, B)), (M, N, K)
+        X, Y = rnd(M + 1, (M, K)), rnd(N + 2, (K, N))
+        t = c.dealer(m.TRIPLE_MATMUL, 3, 9, (M, N, K))
+        gx, gy = c.share(dev(X), 0, 1), c.share(dev(Y), 1, 2)
+        zl = c.beaver_matmul(gx, gy, t, 16, "limb8")
+        zp = c.beaver_matmul(gx, gy, t, 16, "plain")
+        c.sync()
+        assert torch.equal(zl.s0, zp.s0) and torch.equal(zl.s1, zp.s1), (M, N, K)
+    c.close()
+
+
+def test_autotune_grouped_and_cache(m, tmp_path):
+    say("autotune grouped")
+    c = m.Context(device=0, seed=SEED)
+    shapes = [(300, 120, 500), (40, 600, 64), (128, 128, 128), (17, 33, 2000)]
+    best = c.autotune_matmul(shapes)
+    assert best["variant"] in ("128x64", "64x128", "64x64") and best["ms"] > 0
+    probs, outs_plain = [], []
+    for i, (M, N, K) in enumerate(shapes):
+        x = c.share(dev(rnd(3 * i, (M, K))), 0, 2 * i)
+        y = c.share(dev(rnd(3 * i + 1, (K, N))), 1, 2 * i + 1)
+        t = c.dealer(m.TRIPLE_MATMUL, 5, i, (M, N, K))
+        probs.append((x, y, t))
+        outs_plain.append(c.beaver_matmul(x, y, t, 16, "plain"))
+    zs = c.beaver_matmul_grouped(probs, 16, "limb8")  # uses the tuned schedule
+    c.sync()
+    for z, zp in zip(zs, outs_plain):
+        assert torch.equal(z.s0, zp.s0) and torch.equal(z.s1, zp.s1)
+    path = tmp_path / "tuned.txt"
+    c.autotune_save(path)
+    assert len(open(path).read().split()) == 4
+    c2 = m.Context(device=0, seed=SEED)
+    c2.autotune_load(path)
+    zs2 = c2.beaver_matmul_grouped(probs, 16, "limb8")
+    c2.sync()
+    for z, zp in zip(zs2, outs_plain):
+        assert torch.equal(z.s0, zp.s0) and torch.equal(z.s1, zp.s1)
+    c2.close()
+    c.close()
