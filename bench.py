@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--form", default="limb8", choices=["limb8", "plain"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="after the JSON line, run three device-to-device copies of MIB MiB "
+                         "(a plain copy kernel of known size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -110,7 +113,8 @@ def main():
         per_launch_ops = 72.0 * g["ring_macs"] / max(1, g["launches"])  # 36 int8 MACs per ring MAC
         achieved = per_launch_ops / (avg_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
-                    "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                    "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
+                    "traffic": measured_traffic(),
                     "kernel": "k_limb_gemm", "launches": g["launches"],
                     "avg_launch_ms": round(avg_ms, 4),
                     "work_per_launch": "72 int8 ops per ring multiply-accumulate (36 limb pairs)"}
@@ -156,8 +160,44 @@ def main():
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibrate > 0:
+        n = args.copy_calibrate << 17  # int64 elements
+        src = torch.empty(n, dtype=torch.int64, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration, 3 x {args.copy_calibrate} MiB device-to-device")
     ctx.close()
     return 0
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_limb_gemm_secure_gemm_4096_traffic.md")
+LIMB_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "gemm_limb.hip")
+
+
+def measured_traffic():
+    """HBM bytes per limb-GEMM launch of this workload, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the same counters
+    read on a copy of known size.  None when no summary exists or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        line = line.strip().strip("`")
+        if ":" in line and line.split(":", 1)[0] in ("source_sha256", "hbm_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    if "source_sha256" not in fields or "hbm_bytes_per_launch" not in fields:
+        return None
+    sha = hashlib.sha256(open(LIMB_SOURCE, "rb").read()).hexdigest()
+    if sha != fields["source_sha256"]:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
 
 
 def _event_time(torch, stream, fn, reps):
@@ -345,23 +385,36 @@ def cpu_baseline(Xh, Yh, party_seed, dealer_seed, z_rows):
         oracle.reveal(*zz)
         return time.perf_counter() - t0, zz
 
-    # calibrate on 64 rows, then run about 15 s of oracle work (at most the
-    # whole 4096-row step)
+    # calibrate on 64 rows, then aim at about 15 s of oracle work (at most the
+    # whole 4096-row step); the operand-B share and triple are a fixed cost, so
+    # the row count is re-estimated once more if the first estimate falls short
     rows = 64
     dt, zz = run(rows)
     log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
-    if dt < 10.0:
-        rows = int(min(M, max(rows, rows * 15.0 / dt)))
+    for _ in range(2):
+        if dt >= 10.0 or rows >= M:
+            break
+        rows = int(min(M, max(rows + 64, rows * 15.0 / dt)))
         rows -= rows % 64
         dt, zz = run(rows)
         log(f"bench: cpu oracle {rows} rows: {dt:.2f} s")
     match = bool(np.array_equal(zz[0], z_rows[0][:rows]) and np.array_equal(zz[1], z_rows[1][:rows]))
+    cores = oracle.num_threads()
+    # the paper's CPU setting: one thread, on a smaller slice
+    oracle.set_num_threads(1)
+    rows1 = 16
+    dt1, zz1 = run(rows1)
+    oracle.set_num_threads(cores)
+    log(f"bench: cpu oracle 1 thread, {rows1} rows: {dt1:.2f} s")
+    match = match and bool(np.array_equal(zz1[0], z_rows[0][:rows1]))
     return {"value": round(2.0 * rows * N * K / dt / 1e12, 6), "unit": "Tops/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"rows 0..{rows - 1} of the 4096^3 step (share, dealer, Beaver matmul, "
                       f"truncate, reveal) in the CPU oracle; {dt:.1f} s",
-            "sample_matches_gpu_bit_exact": match}
-
+            "sample_matches_gpu_bit_exact": match,
+            "one_thread": {"value": round(2.0 * rows1 * N * K / dt1 / 1e12, 6),
+                           "unit": "Tops/s", "cores": 1,
+                           "sample": f"rows 0..{rows1 - 1}; {dt1:.1f} s"}}
 
 if __name__ == "__main__":
     sys.exit(main())

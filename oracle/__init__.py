@@ -38,6 +38,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         sig = {
             "orc_num_threads": (INT, []),
+            "orc_set_num_threads": (None, [INT]),
             "orc_sm64_mix": (U64, [U64]),
             "orc_sm64_at": (U64, [U64, U64]),
             "orc_prg": (U64, [U64, U64, U64, U64]),
@@ -97,6 +98,10 @@ def _out(shape):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------- PRG

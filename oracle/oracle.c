@@ -41,6 +41,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Sets the number of threads later calls use (n < 1 is ignored). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Counter-based PRG.                                                        */
 /*                                                                           */

@@ -474,6 +474,8 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       const int kbt = p.kb0 + p.kb1;
       p.kb_begin = std::min(kbt, ch * kLimbMaxKBlocks);
       p.kb_end = std::min(kbt, (ch + 1) * kLimbMaxKBlocks);
+      // the GEMM steps over pairs of k-blocks inside one segment
+      if ((p.kb0 | p.kb1 | p.kb_begin | p.kb_end) & 1) return MPC_E_INVAL;
       p.PA0 = r.PA0;
       p.PA1 = r.PA1;
       p.PB0 = r.PB0;

@@ -6,26 +6,26 @@
 // u ^ 0x8080808080808080 read as int8.  For C = A @ B:
 //   C = sum_{s=0..7} 2^(8s) X_s (mod 2^64),  X_s = sum_{i+j=s} D_i @ E_j,
 // because pairs with i + j >= 8 vanish modulo 2^64: 36 int8 GEMMs per ring
-// GEMM.  Each X_s is accumulated exactly in int32 by v_mfma_i32_32x32x32_i8:
+// GEMM.  Each X_s is accumulated exactly in int32 by v_mfma_i32_16x16x64_i8:
 // a diagonal has at most 8 pairs of products bounded by 2^14, so K <= 16320
 // per launch keeps |X_s| < 2^31 (longer K is split into launches that add
 // into the output).  No floating point is involved anywhere.
 //
 // Packing.  pack kernels turn uint64 operands into the blocked limb layout
 // described in internal.h (one 8 KiB block = eight 1 KiB planes of a 32x32
-// tile, each plane stored as the 64 lanes' 16-byte MFMA fragments in lane
-// order), padding with zeros.  The GEMM then streams whole blocks from global
-// memory into LDS with 16-byte loads and reads fragments with conflict-free
-// 16-byte LDS reads: no conversion work is left in the GEMM's inner loop.
+// tile, each plane stored as 64 lanes' 16-byte runs in lane order), padding
+// with zeros, so no conversion work is left in the GEMM's inner loop.
 //
-// GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a 128x64
-// output tile; each wave a 64x32 sub-tile held as 2 (row halves) x 8
-// (diagonals) 32x32 int32 accumulators (256 accumulation registers).  Each
-// wave streams its own fragments from global memory through buffer loads
-// (every wave load is one contiguous KiB), with one k step of loads in flight
-// behind the 72 MFMAs of the current step: no LDS and no barrier.  One
+// GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a
+// (64*SA) x (64*SB) output tile; each wave a (32*SA) x (32*SB) sub-tile held
+// as 16x16 blocks with 8 diagonal int32 accumulators each (256 accumulation
+// registers for the 128x64 and 64x128 tiles).  Each wave streams its own
+// fragments from global memory through buffer loads, one k step of loads in
+// flight behind the MFMAs of the current step: no LDS and no barrier.  One
 // workgroup per tile; tiles are remapped so each XCD works on a contiguous
-// run of them and shares operand blocks in its L2.
+// run of them and shares operand blocks in its L2.  The 16x16x64 instruction
+// sustains a higher rate than 32x32x32 on this chip, with uniformly random
+// operands as well as constant ones.
 #include "internal.h"
 
 namespace mpc {
@@ -230,20 +230,26 @@ __device__ __forceinline__ v4i ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, i
 
 // Wave tile of SA left x SB right 32-blocks (SA, SB in {1, 2}, SA*SB <= 2);
 // the workgroup's four waves form a 2x2 grid, so its output tile is
-// (64*SA) x (64*SB).  The operand with more blocks per wave ("outer") is
-// iterated by level and reloaded in place; the other ("inner") is
-// double-buffered, because its plane 0 is used by every level.
+// (64*SA) x (64*SB).  The MFMA unit is v_mfma_i32_16x16x64_i8, so a wave
+// holds HA = 2*SA by HB = 2*SB blocks of 16x16 outputs, each with 8 diagonal
+// accumulators of 4 registers.  The operand with more 16-halves per wave
+// ("outer") is iterated by level and each of its planes is reloaded in place
+// right after its last use; the other ("inner") keeps planes 3..7 the same
+// way, while its planes 0..2, used by the last levels of a step, are
+// double-buffered.
 template <int SA, int SB>
 struct Shape {
   static constexpr int BM = 64 * SA, BN = 64 * SB;
+  static constexpr int HA = 2 * SA, HB = 2 * SB;
   static constexpr bool kOuterA = SA >= SB;
-  static constexpr int SO = kOuterA ? SA : SB, SI = kOuterA ? SB : SA;
-  static constexpr int kOcc = SA * SB == 1 ? 2 : 1;  // workgroups per CU the registers allow
+  static constexpr int HO = kOuterA ? HA : HB, HI = kOuterA ? HB : HA;
+  static constexpr int kDbl = 3;  // inner planes 0..kDbl-1 are double-buffered
 };
 
 // The blocks one wave reads in one problem segment: its strips of left and
-// right blocks, each block kbs k-blocks of 8 KiB long; consecutive row (col)
-// blocks are consecutive strips, so one descriptor covers a wave's strips.
+// right 32-blocks, each strip kbs k-blocks of 8 KiB long; consecutive row
+// (col) blocks are consecutive strips, so one descriptor covers a wave's
+// strips.
 struct SegSrc {
   __amdgpu_buffer_rsrc_t a, b;
   int kbs;
@@ -259,12 +265,12 @@ __device__ __forceinline__ SegSrc seg_src(const uint8_t* PA, const uint8_t* PB, 
   return q;
 }
 
-// Descriptors and scalar byte offsets of k-block kg (block r of a strip at
-// +r*kbs blocks).
+// Descriptors and scalar byte offsets of the k step starting at k-block kg
+// (32-block x of a strip sits at +x*kbs blocks).
 struct StepOff {
   __amdgpu_buffer_rsrc_t a, b;
   int kb, kbs;
-  __device__ int off(int r) const { return (kb + r * kbs) << 13; }
+  __device__ int off(int x) const { return (kb + x * kbs) << 13; }
 };
 
 __device__ __forceinline__ StepOff step_off(const SegSrc& s0, const SegSrc& s1, int kb0, int kg) {
@@ -278,40 +284,79 @@ __device__ __forceinline__ StepOff step_off(const SegSrc& s0, const SegSrc& s1, 
   return o;
 }
 
-template <int S>
-__device__ __forceinline__ void load_blocks(v4i (&f)[S][8], __amdgpu_buffer_rsrc_t r, const StepOff& o,
-                                            unsigned lo) {
-#pragma unroll
-  for (int x = 0; x < S; ++x)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) f[x][i] = ld_buf(r, lo + i * 1024, o.off(x));
+// A 16x16x64 fragment is gathered from two consecutive 32x32 planes (k-blocks
+// kb and kb+1): lane l takes rows (or cols) 16*h + l%16 and 16 k values of
+// group g = l/16, i.e. k-block kb + g/2, plane lane 16*h + l%16 + 32*(g%2).
+// The k order inside a step is the same for both operands, which is all the
+// product needs.  lane_off = (g/2)*8192 + (g%2)*512 + (l%16)*16; half h and
+// plane i add h*256 + i*1024.
+struct LaneOff {
+  unsigned lo;
+  __device__ unsigned at(int h, int i) const { return lo + (unsigned)((h & 1) * 256 + i * 1024); }
+};
+
+__device__ __forceinline__ v4i ld_frag(__amdgpu_buffer_rsrc_t r, const LaneOff& lo, const StepOff& o,
+                                       int h, int i) {
+  return ld_buf(r, lo.at(h, i), o.off(h >> 1));
 }
 
-// One 32-wide k step: 36 MFMAs per (left block, right block) pair.  Level l
-// multiplies outer plane l with inner planes 0..7-l into diagonals l..7;
-// consecutive MFMAs write different accumulators.  Outer plane l is dead after
-// level l and is reloaded in place for the next step right away.
-template <int SA, int SB, int SO, int SI>
-__device__ __forceinline__ void mfma_step(v16i (&acc)[SA][SB][8], v4i (&outer)[SO][8],
-                                          const v4i (&inner)[SI][8], const StepOff& next,
-                                          unsigned lo) {
+// acc += A @ B on one 16x16x64 int8 tile, accumulating in place.  Written as
+// inline assembly so that the accumulator stays in the same four AGPRs from
+// one MFMA to the next (the compiler's own form of this instruction takes a
+// fresh destination and then copies it back).  Ordering: the operands come
+// from buffer loads, which the compiler's wait-count pass covers; two MFMAs
+// into the same accumulator are at least HO*HI MFMAs apart in the step below,
+// and the first MFMA of every accumulator takes the literal 0 as its input, so
+// no VALU write precedes an MFMA read.
+__device__ __forceinline__ void mfma16(v4i& acc, const v4i& a, const v4i& b) {
+  asm volatile("v_mfma_i32_16x16x64_i8 %0, %1, %2, %0" : "+a"(acc) : "v"(a), "v"(b));
+}
+__device__ __forceinline__ void mfma16_first(v4i& acc, const v4i& a, const v4i& b) {
+  asm volatile("v_mfma_i32_16x16x64_i8 %0, %1, %2, 0" : "=a"(acc) : "v"(a), "v"(b));
+}
+
+// One 64-wide k step: 36 MFMAs per (left half, right half) pair.  Level l
+// multiplies outer plane l with inner planes 0..7-l into diagonals l..7.
+// (HO, HI, ND repeat Shape<SA, SB>'s HO, HI, kDbl: array bounds in a
+// parameter list cannot depend on the template's own members.)
+template <int SA, int SB, int HO, int HI, int ND, bool FIRST>
+__device__ __forceinline__ void mfma_step(v4i (&acc)[2 * SA][2 * SB][8], v4i (&outer)[HO][8],
+                                          v4i (&inner)[HI][8], const v4i (&dcur)[HI][ND],
+                                          v4i (&dnext)[HI][ND], const StepOff& next,
+                                          const LaneOff& lo) {
   using S = Shape<SA, SB>;
+  static_assert(S::HO == HO && S::HI == HI && S::kDbl == ND, "shape mismatch");
+  const __amdgpu_buffer_rsrc_t ro = S::kOuterA ? next.a : next.b;
+  const __amdgpu_buffer_rsrc_t ri = S::kOuterA ? next.b : next.a;
+  // the next step's double-buffered inner planes: a whole step of latency
+#pragma unroll
+  for (int i = 0; i < S::HI; ++i)
+#pragma unroll
+    for (int j = 0; j < S::kDbl; ++j) dnext[i][j] = ld_frag(ri, lo, next, i, j);
 #pragma unroll
   for (int l = 0; l < 8; ++l) {
 #pragma unroll
     for (int s = l; s < 8; ++s)
 #pragma unroll
-      for (int o = 0; o < S::SO; ++o)
+      for (int o = 0; o < S::HO; ++o)
 #pragma unroll
-        for (int i = 0; i < S::SI; ++i) {
-          if (S::kOuterA)
-            acc[o][i][s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(outer[o][l], inner[i][s - l], acc[o][i][s], 0, 0, 0);
-          else
-            acc[i][o][s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(inner[i][s - l], outer[o][l], acc[i][o][s], 0, 0, 0);
+        for (int i = 0; i < S::HI; ++i) {
+          const v4i& in = (s - l) < S::kDbl ? dcur[i][s - l] : inner[i][s - l];
+          v4i& c = S::kOuterA ? acc[o][i][s] : acc[i][o][s];
+          const v4i& a = S::kOuterA ? outer[o][l] : in;
+          const v4i& b = S::kOuterA ? in : outer[o][l];
+          if (FIRST && l == 0) mfma16_first(c, a, b);
+          else mfma16(c, a, b);
         }
+    // outer plane l and inner plane 7-l are dead for this step; the barrier
+    // keeps their reloads behind the MFMAs that read them
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int o = 0; o < S::SO; ++o)
-      outer[o][l] = ld_buf(S::kOuterA ? next.a : next.b, lo + l * 1024, next.off(o));
+    for (int o = 0; o < S::HO; ++o) outer[o][l] = ld_frag(ro, lo, next, o, l);
+    if (7 - l >= S::kDbl) {
+#pragma unroll
+      for (int i = 0; i < S::HI; ++i) inner[i][7 - l] = ld_frag(ri, lo, next, i, 7 - l);
+    }
     // keep this order: reordering across levels lengthens the fragments'
     // live ranges past the register file
     __builtin_amdgcn_sched_barrier(0);
@@ -319,13 +364,12 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[SA][SB][8], v4i (&outer)[S
 }
 
 // GEMM over a tile list.  Each wave streams its fragments straight from
-// global memory (buffer loads, each wave load one contiguous KiB): the outer
-// planes are reloaded one step ahead right after their last use, the inner
-// planes are double-buffered, so no LDS traffic and no barrier sit between
-// MFMAs.  The four waves of a workgroup read overlapping blocks at about the
-// same time, which the CU's L1 and the XCD's L2 serve.
+// global memory (buffer loads; every wave load reads four contiguous 256-byte
+// runs), one k step ahead of the MFMAs, so no LDS traffic and no barrier sit
+// between MFMAs.  The four waves of a workgroup read overlapping blocks at
+// about the same time, which the CU's L1 and the XCD's L2 serve.
 template <int SA, int SB>
-__global__ void __launch_bounds__(kThreads, (Shape<SA, SB>::kOcc))
+__global__ void __launch_bounds__(kThreads, 1)
     k_limb_gemm(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
   using S = Shape<SA, SB>;
   const int tid = threadIdx.x;
@@ -352,64 +396,84 @@ __global__ void __launch_bounds__(kThreads, (Shape<SA, SB>::kOcc))
   const int gsize = min(ntm - first_m, gm);
   const int in_group = local % per_group;
   const i64 tm = first_m + in_group % gsize, tn = in_group / gsize;
-  const i64 mb0 = tm * 2 * SA + wr * SA;  // this wave's first left block
-  const i64 nb0 = tn * 2 * SB + wc * SB;  // this wave's first right block
+  const i64 mb0 = tm * 2 * SA + wr * SA;  // this wave's first left 32-block
+  const i64 nb0 = tn * 2 * SB + wc * SB;  // this wave's first right 32-block
 
-  v16i acc[SA][SB][8];
-#pragma unroll
-  for (int x = 0; x < SA; ++x)
-#pragma unroll
-    for (int y = 0; y < SB; ++y)
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[x][y][s][e] = 0;
+  v4i acc[S::HA][S::HB][8];
 
-  const int kbeg = p.kb_begin, nk = p.kb_end - p.kb_begin;
-  const unsigned lo = (unsigned)lane * 16u;
+  // k runs in steps of two 32-blocks; every segment holds an even number of
+  // blocks, so a step never straddles two segments
+  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int g = lane >> 4;
+  const LaneOff lo{(unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16)};
   const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mb0, nb0, SA, SB);
   const SegSrc s1 = seg_src(p.PA1 ? p.PA1 : p.PA0, p.PB1 ? p.PB1 : p.PB0, p.kb1, mb0, nb0, SA, SB);
-  v4i outer[S::SO][8], in0[S::SI][8], in1[S::SI][8];
-  if (nk > 0) {
+  v4i outer[S::HO][8], inner[S::HI][8], d0[S::HI][S::kDbl], d1[S::HI][S::kDbl];
+  if (nsteps > 0) {
     const StepOff o = step_off(s0, s1, p.kb0, kbeg);
-    const StepOff o1 = step_off(s0, s1, p.kb0, kbeg + min(1, nk - 1));
-    load_blocks<S::SO>(outer, S::kOuterA ? o.a : o.b, o, lo);
-    load_blocks<S::SI>(in0, S::kOuterA ? o.b : o.a, o, lo);
-    load_blocks<S::SI>(in1, S::kOuterA ? o1.b : o1.a, o1, lo);
-  }
-  // Steps alternate between the two inner buffers; an odd last step runs
-  // after the loop so the loop body has no branch.  Loads past the last step
-  // re-read the last step's blocks (valid memory, results unused).
-  const int klast = kbeg + nk - 1;
-  int kk = 0;
-  for (; kk + 1 < nk; kk += 2) {
-    mfma_step<SA, SB, S::SO, S::SI>(acc, outer, in0, step_off(s0, s1, p.kb0, min(kbeg + kk + 1, klast)), lo);
-    {
-      const StepOff o = step_off(s0, s1, p.kb0, min(kbeg + kk + 2, klast));
-      load_blocks<S::SI>(in0, S::kOuterA ? o.b : o.a, o, lo);
-    }
-    mfma_step<SA, SB, S::SO, S::SI>(acc, outer, in1, step_off(s0, s1, p.kb0, min(kbeg + kk + 2, klast)), lo);
-    {
-      const StepOff o = step_off(s0, s1, p.kb0, min(kbeg + kk + 3, klast));
-      load_blocks<S::SI>(in1, S::kOuterA ? o.b : o.a, o, lo);
+    const __amdgpu_buffer_rsrc_t ro = S::kOuterA ? o.a : o.b, ri = S::kOuterA ? o.b : o.a;
+#pragma unroll
+    for (int h = 0; h < S::HO; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) outer[h][i] = ld_frag(ro, lo, o, h, i);
+#pragma unroll
+    for (int h = 0; h < S::HI; ++h) {
+#pragma unroll
+      for (int i = 0; i < S::kDbl; ++i) d0[h][i] = ld_frag(ri, lo, o, h, i);
+#pragma unroll
+      for (int i = S::kDbl; i < 8; ++i) inner[h][i] = ld_frag(ri, lo, o, h, i);
     }
   }
-  if (kk < nk) mfma_step<SA, SB, S::SO, S::SI>(acc, outer, in0, step_off(s0, s1, p.kb0, klast), lo);
+  // Steps alternate between the two buffers of inner planes 0..kDbl-1; the
+  // first step starts every accumulator, and the loop body holds two steps so
+  // it has no branch.  Loads past the last step re-read the last step's
+  // blocks (valid memory, results unused).
+  const int klast = kbeg + 2 * (nsteps - 1);
+  if (nsteps > 0) {
+    mfma_step<SA, SB, S::HO, S::HI, S::kDbl, true>(acc, outer, inner, d0, d1,
+                                                    step_off(s0, s1, p.kb0, min(kbeg + 2, klast)), lo);
+    int st = 1;
+    for (; st + 1 < nsteps; st += 2) {
+      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(
+          acc, outer, inner, d1, d0, step_off(s0, s1, p.kb0, min(kbeg + 2 * st + 2, klast)), lo);
+      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(
+          acc, outer, inner, d0, d1, step_off(s0, s1, p.kb0, min(kbeg + 2 * st + 4, klast)), lo);
+    }
+    if (st < nsteps)
+      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(acc, outer, inner, d1, d0,
+                                                       step_off(s0, s1, p.kb0, klast), lo);
+  } else {
+#pragma unroll
+    for (int x = 0; x < S::HA; ++x)
+#pragma unroll
+      for (int y = 0; y < S::HB; ++y)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
+  }
+  // Wait states between the last MFMAs and the reads of their results: every
+  // accumulator passes through a short s_nop in diagonal order, and diagonal
+  // s = 7 (written by the last HO*HI MFMAs) comes last.
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int x = 0; x < S::HA; ++x)
+#pragma unroll
+      for (int y = 0; y < S::HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
 
   // Epilogue: C = sum_s 2^(8s) X_s (mod 2^64), then the shared epilogue.
-  // 32x32 accumulator layout: lane l, register e holds row
-  // 8*(e/4) + 4*(l/32) + e%4 and column l%32 of the 32x32 block.
+  // 16x16 accumulator layout: lane l, register e holds row 4*(l/16) + e and
+  // column l%16 of the 16x16 block.
   const Epilogue& ep = p.ep;
 #pragma unroll
-  for (int y = 0; y < SB; ++y) {
-    const i64 n = tn * S::BN + (wc * SB + y) * 32 + (lane & 31);
+  for (int y = 0; y < S::HB; ++y) {
+    const i64 n = tn * S::BN + wc * 32 * SB + y * 16 + (lane & 15);
     const bool n_ok = n < p.N;
     const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
 #pragma unroll
-    for (int x = 0; x < SA; ++x) {
+    for (int x = 0; x < S::HA; ++x) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const i64 m = tm * S::BM + (wr * SA + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      for (int e = 0; e < 4; ++e) {
+        const i64 m = tm * S::BM + wr * 32 * SA + x * 16 + 4 * (lane >> 4) + e;
         u64 v = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
@@ -431,7 +495,7 @@ i64 limb_rblocks(i64 rows) {
   const i64 b = (rows + 31) / 32;
   return (b + kLimbRowPad - 1) / kLimbRowPad * kLimbRowPad;
 }
-i64 limb_kblocks(i64 K) { return (K + 31) / 32; }
+i64 limb_kblocks(i64 K) { return (K + 63) / 64 * 2; }
 int limb_tiles(i64 M, i64 N, int variant) {
   const i64 bm = 64 * limb_variant_sa(variant), bn = 64 * limb_variant_sb(variant);
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));

@@ -75,7 +75,8 @@ struct PlainProblem {
 // 16 bytes: lane l covers row (or col) l % 32 and k = (l / 32) * 16 + [0, 16).
 // Block (rb, kb) starts at byte ((rb * kblocks + kb) << 13).  Rows, cols and k
 // are padded with zeros (the limbs of 0 are all 0) to whole blocks; row and
-// col block counts are further padded to a multiple of kLimbRowPad blocks.
+// col block counts are further padded to a multiple of kLimbRowPad blocks and
+// k block counts to an even number (the GEMM steps over 64 k at a time).
 constexpr int kLimbBlockBytes = 8192;
 constexpr int kLimbRowPad = 4;
 
@@ -129,7 +130,9 @@ struct LimbProblem {
 
 // Largest number of concatenated k values one limb launch may cover: with all
 // limbs -128 a diagonal of 8 pairs adds 8 * 2^14 per k, so 16320 * 2^17 < 2^31.
+// (Even, so chunk boundaries fall between the GEMM's 64-wide k steps.)
 constexpr int kLimbMaxKBlocks = 510;  // 510 * 32 = 16320
+static_assert(kLimbMaxKBlocks % 2 == 0, "chunks must hold whole k steps");
 
 // Tile-to-problem table for grouped launches.
 struct TileMap {
