@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("secure int64-ring GEMM Tops/s (limb-MFMA vs plain, bit-exact); Beaver mul elem/s")
 INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 matrix peak, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 M = N = K = 4096
 FRAC = 16
 
@@ -112,9 +113,11 @@ def main():
     if args.form == "limb8":
         per_launch_ops = 72.0 * g["ring_macs"] / max(1, g["launches"])  # 36 int8 MACs per ring MAC
         achieved = per_launch_ops / (avg_ms * 1e-3) / 1e12
+        traffic, alg_bytes = measured_traffic()
         roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
                     "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-                    "traffic": measured_traffic(),
+                    "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE "
+                    "+ WRITE_SIZE, copy-calibrated)", "algorithmic_bytes_per_launch": alg_bytes,
                     "kernel": "k_limb_gemm", "launches": g["launches"],
                     "avg_launch_ms": round(avg_ms, 4),
                     "work_per_launch": "72 int8 ops per ring multiply-accumulate (36 limb pairs)"}
@@ -174,30 +177,38 @@ def main():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_limb_gemm_secure_gemm_4096_traffic.md")
 LIMB_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "gemm_limb.hip")
+API_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "api.cpp")
+
+
+def kernel_fingerprint():
+    """sha256 over the limb GEMM source and the library's default tile schedule
+    (the two things the GEMM's HBM traffic depends on)."""
+    import hashlib
+    h = hashlib.sha256(open(LIMB_SOURCE, "rb").read())
+    sched = [ln.strip() for ln in open(API_SOURCE).read().splitlines() if "TileSched sched_default" in ln]
+    h.update("\n".join(sched).encode())
+    return h.hexdigest()
 
 
 def measured_traffic():
-    """HBM bytes per limb-GEMM launch of this workload, from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the same counters
-    read on a copy of known size.  None when no summary exists or the kernel
-    source has changed since the counters were taken."""
-    import hashlib
+    """HBM bytes per limb-GEMM launch of this workload (and the algorithmic
+    bytes beside them), from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, each counter scaled by its reading on a copy of known size.
+    (None, None) when no summary exists or the kernel or its default schedule
+    has changed since the counters were taken."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
-        return None
+        return None, None
+    keys = ("kernel_sha256", "hbm_bytes_per_launch", "algorithmic_bytes_per_launch")
     fields = {}
     for line in text.splitlines():
-        line = line.strip().strip("`")
-        if ":" in line and line.split(":", 1)[0] in ("source_sha256", "hbm_bytes_per_launch"):
-            k, v = line.split(":", 1)
-            fields[k] = v.strip()
-    if "source_sha256" not in fields or "hbm_bytes_per_launch" not in fields:
-        return None
-    sha = hashlib.sha256(open(LIMB_SOURCE, "rb").read()).hexdigest()
-    if sha != fields["source_sha256"]:
-        return None
-    return float(fields["hbm_bytes_per_launch"])
+        k, _, v = line.partition(":")
+        if k.strip() in keys:
+            fields[k.strip()] = v.strip()
+    if any(k not in fields for k in keys) or fields["kernel_sha256"] != kernel_fingerprint():
+        return None, None
+    return float(fields["hbm_bytes_per_launch"]), float(fields["algorithmic_bytes_per_launch"])
 
 
 def _event_time(torch, stream, fn, reps):
@@ -213,9 +224,11 @@ def _event_time(torch, stream, fn, reps):
 def secondary(ctx, mpc, torch, workloads, X, Y):
     ex = {}
     # ring GEMM alone, both forms, timed with the library's launch events
+    # (the fp64 limb form is the paper's method: four 16-bit limbs, ten exact
+    # float64 GEMMs of the vendor BLAS; its bracket covers those GEMMs)
     C = ctx.empty((M, N))
     ctx.profile(True)
-    for form, reps in (("limb8", 5), ("plain", 2)):
+    for form, reps in (("limb8", 5), ("plain", 2), ("fp64limb", 2)):
         ctx.ring_gemm(X, Y, form, out=C)  # warm
         ctx.profile_read()
         for _ in range(reps):
@@ -224,14 +237,22 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
         ms = g["total_ms"] / g["launches"]
         ex[f"ring_gemm_4096_{form}_tops"] = round(2.0 * M * N * K / (ms * 1e-3) / 1e12, 3)
         ex[f"ring_gemm_4096_{form}_ms"] = round(ms, 4)
-        log(f"bench: ring GEMM 4096^3 {form}: {ms:.3f} ms")
+        # the whole call: operand packing, the GEMM(s), the combine
+        ex[f"ring_gemm_4096_{form}_call_ms"] = round(
+            _event_time(torch, ctx.streams[0], lambda: ctx.ring_gemm(X, Y, form, out=C), reps), 4)
+        log(f"bench: ring GEMM 4096^3 {form}: {ms:.3f} ms (call {ex[f'ring_gemm_4096_{form}_call_ms']} ms)")
     ctx.profile(False)
     ex["limb_over_plain_speedup"] = round(ex["ring_gemm_4096_plain_ms"] / ex["ring_gemm_4096_limb8_ms"], 2)
+    ex["limb_over_fp64limb_speedup"] = round(ex["ring_gemm_4096_fp64limb_ms"] / ex["ring_gemm_4096_limb8_ms"], 2)
+    # ten float64 multiply-adds per ring multiply-accumulate, against the FP64 matrix peak
+    ex["fp64limb_gemm_fp64_frac"] = round(
+        20.0 * M * N * K / (ex["ring_gemm_4096_fp64limb_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
     C0 = ctx.ring_gemm(X, Y, "limb8")
     C1 = ctx.ring_gemm(X, Y, "plain")
+    C2 = ctx.ring_gemm(X, Y, "fp64limb")
     ctx.sync()
-    ex["ring_gemm_forms_bit_identical"] = bool(torch.equal(C0, C1))
-    del C, C0, C1
+    ex["ring_gemm_forms_bit_identical"] = bool(torch.equal(C0, C1) and torch.equal(C0, C2))
+    del C, C0, C1, C2
 
     # Beaver element-wise product (fused mask/open/finish/truncate), HBM-bound:
     # 2^24 elements = 128 MiB per share buffer, 1.5 GiB moved per call
@@ -253,8 +274,11 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
 
     # secure MLP 784-1024-1024-10, batch 128, square activations
     for form in ("plain", "limb8"):
-        ex[f"mlp_ms_{form}"] = round(mlp_latency(ctx, mpc, torch, workloads, form), 4)
+        total, ops = mlp_latency(ctx, mpc, torch, workloads, form)
+        ex[f"mlp_ms_{form}"] = round(total, 4)
+        ex[f"mlp_ops_ms_{form}"] = ops
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
+    ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
     ctx.sync()
     ex.update(grouped_bench(mpc, torch, workloads))
     ex.update(conv_bench(mpc, torch, workloads))
@@ -290,6 +314,8 @@ def grouped_bench(mpc, torch, workloads):
             mpc.Context.graph_destroy(g)
             out[f"grouped256_{label}_ms"] = round(ms, 4)
             out[f"grouped256_{label}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
+            # int8 work of the finish GEMMs (2 parties x M x N x 2K ring MACs, 72 int8 ops each)
+            out[f"grouped256_{label}_int8_frac"] = round(72.0 * 4.0 * macs / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)
             log(f"bench: grouped 256 ({label}) graph replay {ms:.3f} ms")
 
         timed("default_schedule")
@@ -356,19 +382,63 @@ def mlp_latency(ctx, mpc, torch, workloads, form):
             for i in range(3)]
     pairs = [ctx.dealer(mpc.TRIPLE_SQUARE, dseed, 300 + i, (B * dims[i + 1],)) for i in range(2)]
 
-    def forward():
+    def forward(keep=None):
         h = x
         for i in range(3):
+            if keep is not None:
+                keep.append(("matmul", i, h))
             h = ctx.beaver_matmul(h, ws[i], trip[i], FRAC, form)
             if i < 2:
                 flat = mpc.SharedPair(h.s0.view(-1), h.s1.view(-1))
+                if keep is not None:
+                    keep.append(("square", i, flat))
                 sq = ctx.beaver_mul(flat, None, pairs[i], FRAC)
                 h = mpc.SharedPair(sq.s0.view(B, dims[i + 1]), sq.s1.view(B, dims[i + 1]))
         return h
 
-    forward()
+    inputs = []
+    forward(inputs)
     ctx.sync()
-    return _event_time(torch, ctx.streams[0], forward, 20)
+    total = _event_time(torch, ctx.streams[0], forward, 20)
+    # per-operation breakdown: each op replayed alone on its recorded input
+    ops = {}
+    for kind, i, h in inputs:
+        if kind == "matmul":
+            fn = lambda h=h, i=i: ctx.beaver_matmul(h, ws[i], trip[i], FRAC, form)
+            label = f"layer{i + 1}_matmul_{dims[i]}x{dims[i + 1]}"
+        else:
+            fn = lambda h=h, i=i: ctx.beaver_mul(h, None, pairs[i], FRAC)
+            label = f"square{i + 1}_{B}x{dims[i + 1]}"
+        ops[label] = round(_event_time(torch, ctx.streams[0], fn, 20), 4)
+    return total, ops
+
+
+def beaver_mul_sweep(ctx, mpc, torch):
+    """Beaver element-wise product (mask, open, finish, 2^16 truncation in one
+    pass) from 2^12 to 2^28 elements: algorithmic GB/s at 96 B per element."""
+    out = {}
+    dev = ctx.device
+    for lg in range(12, 29, 2):
+        n = 1 << lg
+        g = torch.Generator(device=dev)
+        g.manual_seed(lg)
+        X = torch.randint(-(1 << 62), 1 << 62, (n,), device=dev, generator=g, dtype=torch.int64)
+        Y = torch.randint(-(1 << 62), 1 << 62, (n,), device=dev, generator=g, dtype=torch.int64)
+        x = ctx.share(X, 0, 70 + lg)
+        y = ctx.share(Y, 1, 71 + lg)
+        del X, Y
+        t = ctx.dealer(mpc.TRIPLE_MUL, 9, 72 + lg, (n,))
+        z = mpc.SharedPair(ctx.empty((n,)), ctx.empty((n,)))
+        ctx.beaver_mul(x, y, t, FRAC, out=z)
+        ctx.sync()
+        reps = max(3, min(200, (1 << 26) // n))
+        ms = _event_time(torch, ctx.streams[0], lambda: ctx.beaver_mul(x, y, t, FRAC, out=z), reps)
+        out[f"2^{lg}"] = {"us": round(ms * 1e3, 2), "elem_per_s": round(n / (ms * 1e-3), 1),
+                          "GBps": round(96.0 * n / (ms * 1e-3) / 1e9, 1)}
+        del x, y, t, z
+        torch.cuda.empty_cache()
+    log("bench: Beaver mul sweep " + ", ".join(f"{k}: {v['GBps']} GB/s" for k, v in out.items()))
+    return out
 
 
 def cpu_baseline(Xh, Yh, party_seed, dealer_seed, z_rows):

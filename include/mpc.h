@@ -63,8 +63,21 @@ typedef enum {
  *          pairs (i, j) with i + j <= 7 are multiplied on INT8 matrix cores
  *          with exact int32 accumulation (K split so no sum can overflow) and
  *          combined as sum 2^(8(i+j)) D_i E_j mod 2^64.  Bit-identical to PLAIN.
- *   AUTO:  the library's choice (LIMB8 unless the problem is tiny). */
-typedef enum { MPC_FORM_PLAIN = 0, MPC_FORM_LIMB8 = 1, MPC_FORM_AUTO = 2 } mpc_form;
+ *   AUTO:  the library's choice (LIMB8 unless the problem is tiny).
+ *   FP64LIMB: the paper's own GPU method (Section 5.3, off-loading to the
+ *          GPU): operands split into four 16-bit limbs (ten pairwise products)
+ *          or, when the summed k is below 1024, three 22-bit limbs (six), each
+ *          pairwise product an exact float64 GEMM of the vendor BLAS, combined
+ *          mod 2^64.  Bit-identical to PLAIN; kept for comparison.  Supported
+ *          by mpc_ring_gemm, mpc_beaver_matmul and mpc_beaver_matmul_grouped
+ *          for summed k below 2^21 and outside graph capture; otherwise
+ *          MPC_E_UNSUPPORTED (also from mpc_beaver_conv1d). */
+typedef enum {
+  MPC_FORM_PLAIN = 0,
+  MPC_FORM_LIMB8 = 1,
+  MPC_FORM_AUTO = 2,
+  MPC_FORM_FP64LIMB = 3
+} mpc_form;
 
 typedef enum {
   MPC_TRIPLE_MUL = 0,    /* element-wise: a, b, c = a*b, all of length n          */
@@ -179,7 +192,7 @@ mpc_status mpc_beaver_conv1d(mpc_ctx *ctx, const mpc_conv1d_shape *shape, const 
                              uint64_t *z1);
 
 /* Public ring GEMM C = A @ B mod 2^64 (A: MxK, B: KxN, C: MxN), on party 0's
- * stream: the kernel both Beaver forms use, exposed for comparison. */
+ * stream: the kernel the Beaver forms use, exposed for comparison. */
 mpc_status mpc_ring_gemm(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const uint64_t *A,
                          const uint64_t *B, uint64_t *C, mpc_form form);
 
@@ -190,14 +203,17 @@ mpc_status mpc_ring_gemm(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const ui
  * launches since the last read, their summed event-measured duration and
  * their algorithmic work (ring multiply-accumulates M*N*K over true, unpadded
  * sizes; the limb form also performs 36 int8 multiply-accumulates per ring
- * one), and clears the record.  Either output pointer may be NULL. */
+ * one, the fp64 limb form 6 or 10 float64 ones), and clears the record.  In
+ * the fp64 limb form the bracket covers its vendor-BLAS GEMM calls (one per
+ * limb diagonal) as one launch.  Any output pointer may be NULL. */
 typedef struct {
   uint64_t launches;
   double total_ms;
   double ring_macs;
 } mpc_gemm_timing;
 mpc_status mpc_profile_enable(mpc_ctx *ctx, int on);
-mpc_status mpc_profile_read(mpc_ctx *ctx, mpc_gemm_timing *limb8, mpc_gemm_timing *plain);
+mpc_status mpc_profile_read(mpc_ctx *ctx, mpc_gemm_timing *limb8, mpc_gemm_timing *plain,
+                            mpc_gemm_timing *fp64limb);
 
 /* ---- batching form ------------------------------------------------------ */
 /* One Beaver matmul of a group (all pointers device, as in mpc_beaver_matmul). */
@@ -208,9 +224,12 @@ typedef struct {
   uint64_t *z0, *z1;
 } mpc_matmul_desc;
 
-/* Many independent Beaver matmuls of uneven shapes: one open launch and one
- * persistent GEMM launch for all problems and both parties.  `descs` is a
- * HOST array of `count` descriptors. */
+/* Many independent Beaver matmuls of uneven shapes (batching amortises the
+ * rounds, Section 6.1): in the limb form one fused open+pack launch per
+ * operand kind and one grouped GEMM launch over the tiles of all problems and
+ * both parties (a tile-to-problem table; one workgroup per tile, handed out
+ * by the hardware dispatcher); the plain form likewise with one open launch.
+ * `descs` is a HOST array of `count` descriptors. */
 mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
                                      int trunc_bits, mpc_form form);
 
@@ -233,14 +252,18 @@ mpc_status mpc_autotune_matmul(mpc_ctx *ctx, size_t count, const int64_t *dims, 
 /* Writes / reads the tuned schedules (a text file, one entry per line). */
 mpc_status mpc_autotune_save(const mpc_ctx *ctx, const char *path);
 mpc_status mpc_autotune_load(mpc_ctx *ctx, const char *path);
-/* Schedule used when no tuned entry matches (default: 128x64, 8, remap on). */
+/* Schedule used when no tuned entry matches (default: 64x128, 8, remap on). */
 mpc_status mpc_set_default_tile_config(mpc_ctx *ctx, const mpc_tile_config *cfg);
 
 /* Stream capture of the context's work into a HIP graph: begin, issue calls,
  * end.  Party 0's stream must not be the null stream.  The workspace must
  * already be large enough (issue the same calls once eagerly first, or call
- * mpc_reserve).  mpc_graph_launch replays the graph on party 0's stream;
- * mpc_graph_destroy frees it. */
+ * mpc_reserve).  mpc_graph_launch replays the graph on party 0's stream of
+ * the context that captured it (MPC_E_INVAL for another context);
+ * mpc_graph_destroy frees it.  A graph refers to the context's workspace by
+ * address, so while any graph of a context exists the workspace cannot move:
+ * a call that would need a larger one returns MPC_E_NOMEM (reserve enough
+ * before capturing).  Destroy a context's graphs before the context. */
 mpc_status mpc_graph_begin(mpc_ctx *ctx);
 mpc_status mpc_graph_end(mpc_ctx *ctx, void **graph_exec);
 mpc_status mpc_graph_launch(mpc_ctx *ctx, void *graph_exec);

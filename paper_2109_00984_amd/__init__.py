@@ -16,9 +16,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpc.so")
 
-FORM_PLAIN, FORM_LIMB8, FORM_AUTO = 0, 1, 2
+FORM_PLAIN, FORM_LIMB8, FORM_AUTO, FORM_FP64LIMB = 0, 1, 2, 3
 TRIPLE_MUL, TRIPLE_SQUARE, TRIPLE_MATMUL, TRIPLE_CONV1D = 0, 1, 2, 3
-FORMS = {"plain": FORM_PLAIN, "limb8": FORM_LIMB8, "auto": FORM_AUTO}
+FORMS = {"plain": FORM_PLAIN, "limb8": FORM_LIMB8, "auto": FORM_AUTO, "fp64limb": FORM_FP64LIMB}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2109_00984_amd/build.py "
@@ -84,7 +84,8 @@ _SIGS = {
     "mpc_ring_gemm": (INT, [VP, I64, I64, I64, VP, VP, VP, INT]),
     "mpc_beaver_matmul_grouped": (INT, [VP, SZ, ctypes.POINTER(MatmulDesc), INT, INT]),
     "mpc_profile_enable": (INT, [VP, INT]),
-    "mpc_profile_read": (INT, [VP, ctypes.POINTER(GemmTiming), ctypes.POINTER(GemmTiming)]),
+    "mpc_profile_read": (INT, [VP, ctypes.POINTER(GemmTiming), ctypes.POINTER(GemmTiming),
+                             ctypes.POINTER(GemmTiming)]),
     "mpc_autotune_matmul": (INT, [VP, SZ, ctypes.POINTER(I64), ctypes.POINTER(TileConfig)]),
     "mpc_autotune_save": (INT, [VP, ctypes.c_char_p]),
     "mpc_autotune_load": (INT, [VP, ctypes.c_char_p]),
@@ -231,12 +232,12 @@ class Context:
         _check(_lib.mpc_profile_enable(self._h, 1 if on else 0), "mpc_profile_enable")
 
     def profile_read(self):
-        lm, pl = GemmTiming(), GemmTiming()
-        _check(_lib.mpc_profile_read(self._h, ctypes.byref(lm), ctypes.byref(pl)),
+        lm, pl, fp = GemmTiming(), GemmTiming(), GemmTiming()
+        _check(_lib.mpc_profile_read(self._h, ctypes.byref(lm), ctypes.byref(pl), ctypes.byref(fp)),
                "mpc_profile_read")
         as_dict = lambda g: {"launches": int(g.launches), "total_ms": float(g.total_ms),
                              "ring_macs": float(g.ring_macs)}
-        return {"limb8": as_dict(lm), "plain": as_dict(pl)}
+        return {"limb8": as_dict(lm), "plain": as_dict(pl), "fp64limb": as_dict(fp)}
 
     def reserve(self, nbytes):
         _check(_lib.mpc_reserve(self._h, int(nbytes)), "mpc_reserve")

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpc.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.cpp", "elementwise.hip", "gemm_plain.hip", "gemm_limb.hip"]
+SOURCES = ["api.cpp", "elementwise.hip", "gemm_plain.hip", "gemm_limb.hip", "gemm_fp64.hip"]
 ARCH = os.environ.get("MPC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from forming packed fp32 instructions
@@ -32,7 +32,10 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    # the vendor BLAS serves only the fp64 limb comparison form
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
+           "-L", rocm_lib, "-lrocblas", f"-Wl,-rpath,{rocm_lib}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of libmpc (declared in include/mpc.h): context and
 // workspace management, argument validation and the orchestration of the
 // kernels for each protocol step.
+#include <rocblas/rocblas.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,8 +80,21 @@ struct mpc_ctx {
   std::vector<hipEvent_t> event_pool;
   // limb GEMM tile schedule used when no tuned entry matches, and the tuned
   // schedules keyed by the hash of a matmul shape list
-  TileSched sched_default{kLimb128x64, 8, 1};
+  TileSched sched_default{kLimb64x128, 8, 1};
   std::map<uint64_t, TileSched> tuned;
+  // vendor BLAS handle of the fp64 limb form (created on first use)
+  rocblas_handle blas = nullptr;
+  // partial sums of split-K plain GEMMs (grown on demand)
+  uint8_t* splitk = nullptr;
+  size_t splitk_cap = 0;
+  // instantiated graphs not yet destroyed: they hold workspace addresses, so
+  // no buffer may move while any exists
+  int live_graphs = 0;
+};
+// An instantiated graph and the context whose buffers it references.
+struct mpc_graph {
+  hipGraphExec_t exec;
+  mpc_ctx* ctx;
 };
 
 namespace {
@@ -122,7 +136,8 @@ mpc_status sync_all(mpc_ctx* c) {
 // first waits for both streams; it is refused while a graph is being captured.
 mpc_status ensure_ws(mpc_ctx* c, size_t bytes) {
   if (bytes <= c->ws_cap) return MPC_OK;
-  if (c->capturing) return MPC_E_NOMEM;
+  // a live graph (or one being captured) holds the current workspace address
+  if (c->capturing || c->live_graphs > 0) return MPC_E_NOMEM;
   CHK(sync_all(c));
   if (c->ws) HIPCHK(hipFree(c->ws));
   c->ws = nullptr;
@@ -282,14 +297,69 @@ size_t packed_bytes(i64 rows, i64 K) {
   return (size_t)limb_rblocks(rows) * (size_t)limb_kblocks(K) * kLimbBlockBytes;
 }
 
-// One launch of the plain GEMM over `probs` (party 0's stream).
-mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs) {
-  const size_t n = probs.size();
+// Split-K plan of a plain launch: when the launch has fewer output tiles than
+// compute units, long k ranges are cut into slices (at least kPlainMinSlice
+// k each) so that about two workgroups per compute unit run; the slices'
+// partial sums live in the context's split buffer.  Never grows that buffer
+// during capture (the launch then runs unsplit).
+constexpr i64 kPlainMinSlice = 128;
+
+mpc_status plan_splitk(mpc_ctx* c, std::vector<PlainProblem>& probs) {
+  i64 tiles = 0;
+  for (const PlainProblem& p : probs) tiles += plain_tiles(p.M, p.N);
+  std::vector<int> ks(probs.size(), 1);
+  size_t need = 0;
+  if (tiles > 0 && tiles < c->num_cu) {
+    const i64 want = (2 * (i64)c->num_cu + tiles - 1) / tiles;
+    for (size_t q = 0; q < probs.size(); ++q) {
+      const i64 Kt = probs[q].K0 + probs[q].K1;
+      ks[q] = (int)std::max<i64>(1, std::min<i64>(want, Kt / kPlainMinSlice));
+      if (ks[q] > 1) need += align_up((size_t)(ks[q] * probs[q].M * probs[q].N) * 8);
+    }
+  }
+  if (need > c->splitk_cap) {
+    if (c->capturing || c->live_graphs > 0) {
+      need = 0;
+      std::fill(ks.begin(), ks.end(), 1);
+    } else {
+      CHK(sync_all(c));
+      if (c->splitk) HIPCHK(hipFree(c->splitk));
+      c->splitk = nullptr;
+      c->splitk_cap = 0;
+      HIPCHK(hipMalloc(&c->splitk, need));
+      c->splitk_cap = need;
+    }
+  }
+  size_t off = 0;
+  for (size_t q = 0; q < probs.size(); ++q) {
+    PlainProblem& p = probs[q];
+    const i64 Kt = p.K0 + p.K1;
+    if (ks[q] > 1) {
+      const i64 per = (Kt + ks[q] - 1) / ks[q];
+      p.kslice = (per + kPlainBK - 1) / kPlainBK * kPlainBK;
+      p.ksplit = (int)((Kt + p.kslice - 1) / p.kslice);
+      p.partial = (u64*)(c->splitk + off);
+      off += align_up((size_t)(ks[q] * p.M * p.N) * 8);
+    } else {
+      p.ksplit = 1;
+      p.kslice = std::max<i64>(Kt, 1);
+      p.partial = nullptr;
+    }
+  }
+  return MPC_OK;
+}
+
+// One launch of the plain GEMM over `probs` (party 0's stream), plus one
+// reduction per split problem.
+mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs_in) {
+  const size_t n = probs_in.size();
   if (!n) return MPC_OK;
+  std::vector<PlainProblem> probs = probs_in;
+  CHK(plan_splitk(c, probs));
   std::vector<int> tstart(n + 1, 0);
   double macs = 0;
   for (size_t q = 0; q < n; ++q) {
-    tstart[q + 1] = tstart[q] + plain_tiles(probs[q].M, probs[q].N);
+    tstart[q + 1] = tstart[q] + plain_tiles(probs[q].M, probs[q].N) * probs[q].ksplit;
     macs += (double)probs[q].M * (double)probs[q].N * (double)(probs[q].K0 + probs[q].K1);
   }
   Blob blob;
@@ -301,6 +371,11 @@ mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs) {
   LaunchTimer tm(c, MPC_FORM_PLAIN, macs);
   CHK(tm.start());
   CHK(hip_status(launch_plain_gemm(c->s[0], (const PlainProblem*)(dev + oprob), map, tstart[n])));
+  for (size_t q = 0; q < n; ++q) {
+    if (probs[q].ksplit <= 1) continue;
+    CHK(hip_status(launch_plain_reduce(c->s[0], (const PlainProblem*)(dev + oprob) + q, probs[q].M, probs[q].N)));
+    c->stats.launches++;
+  }
   CHK(tm.stop());
   c->stats.launches++;
   c->stats.gemm_problems += n;
@@ -327,6 +402,61 @@ PlainProblem plain_problem(i64 M, i64 N, i64 K0, i64 K1, const u64* A0, const u6
   p.ldb1 = ldb1;
   p.ep = ep;
   return p;
+}
+
+// ------------------------------------------------------------------ fp64 limb form
+// Workspace of one fp64-form ring GEMM of M x N over Kt concatenated k.
+size_t fp64_ws(i64 M, i64 N, i64 Kt) {
+  const i64 L = fp64_limbs(Kt);
+  return align_up((size_t)(M * L * Kt) * 8) + align_up((size_t)(L * Kt * N) * 8) +
+         align_up((size_t)(L * M * N) * 8);
+}
+
+// C = [A0 | A1] @ [B0 ; B1] (mod 2^64) through fp64 limb planes and one vendor
+// fp64 GEMM per diagonal, on party 0's stream; `cv` provides fp64_ws bytes.
+mpc_status issue_fp64(mpc_ctx* c, Carve& cv, i64 M, i64 N, i64 K0, i64 K1, const u64* A0, i64 lda0,
+                      const u64* A1, i64 lda1, const u64* B0, i64 ldb0, const u64* B1, i64 ldb1,
+                      const Epilogue& ep) {
+  const i64 Kt = K0 + K1;
+  if (Kt >= kFp64MaxK) return MPC_E_UNSUPPORTED;
+  if (c->capturing) return MPC_E_UNSUPPORTED;  // vendor BLAS calls are not captured
+  if (!c->blas) {
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) return MPC_E_HIP;
+  }
+  if (rocblas_set_stream(c->blas, c->s[0]) != rocblas_status_success) return MPC_E_HIP;
+  const int L = fp64_limbs(Kt);
+  double* LA = cv.take<double>((size_t)(M * L * Kt));
+  double* RB = cv.take<double>((size_t)(L * Kt * N));
+  double* X = cv.take<double>((size_t)(L * M * N));
+  const hipStream_t st = c->s[0];
+  if (Kt > 0) {
+    CHK(hip_status(launch_fp64_pack_left(st, M, K0, K1, A0, lda0, A1, lda1, L, LA)));
+    CHK(hip_status(launch_fp64_pack_right(st, N, K0, K1, B0, ldb0, B1, ldb1, L, RB)));
+    c->stats.launches += 2;
+  }
+  // diagonal s: X_s = LA[:, 0:(s+1)Kt] @ RB[(L-1-s)Kt : L Kt, :]; row-major
+  // products are issued as column-major X_s^T = RB_sub^T LA_sub^T
+  const double one = 1.0, zero = 0.0;
+  LaunchTimer tm(c, MPC_FORM_FP64LIMB, (double)M * (double)N * (double)Kt);
+  CHK(tm.start());
+  for (int sd = 0; sd < L; ++sd) {
+    double* Xs = X + (size_t)sd * (size_t)(M * N);
+    if (Kt == 0) {
+      HIPCHK(hipMemsetAsync(Xs, 0, (size_t)(M * N) * 8, st));
+      continue;
+    }
+    const rocblas_status bs = rocblas_dgemm(
+        c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
+        (rocblas_int)((sd + 1) * Kt), &one, RB + (size_t)(L - 1 - sd) * (size_t)Kt * (size_t)N,
+        (rocblas_int)N, LA, (rocblas_int)(L * Kt), &zero, Xs, (rocblas_int)N);
+    if (bs != rocblas_status_success) return MPC_E_HIP;
+    c->stats.launches++;
+  }
+  CHK(tm.stop());
+  CHK(hip_status(launch_fp64_combine(st, M, N, L, X, ep)));
+  c->stats.launches++;
+  c->stats.gemm_problems++;
+  return MPC_OK;
 }
 
 // ------------------------------------------------------------------ limb form
@@ -528,7 +658,9 @@ LimbReq limb_req(i64 M, i64 N, i64 K0, i64 K1, const uint8_t* PA0, const uint8_t
 
 mpc_status check_trunc(int bits) { return (bits < 0 || bits > 63) ? MPC_E_INVAL : MPC_OK; }
 mpc_status check_form(mpc_form f) {
-  return (f == MPC_FORM_PLAIN || f == MPC_FORM_LIMB8 || f == MPC_FORM_AUTO) ? MPC_OK : MPC_E_INVAL;
+  return (f == MPC_FORM_PLAIN || f == MPC_FORM_LIMB8 || f == MPC_FORM_AUTO || f == MPC_FORM_FP64LIMB)
+             ? MPC_OK
+             : MPC_E_INVAL;
 }
 
 Epilogue make_ep(const u64* cadd, int csign, int trunc, u64* out, OutView v) {
@@ -657,6 +789,8 @@ mpc_status mpc_ctx_destroy(mpc_ctx* c) {
     (void)hipEventDestroy(t.stop);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
+  if (c->splitk) (void)hipFree(c->splitk);
   if (c->ws) (void)hipFree(c->ws);
   for (int p = 0; p < 2; ++p) {
     if (c->ev[p]) (void)hipEventDestroy(c->ev[p]);
@@ -945,6 +1079,42 @@ size_t matmul_ws(const MatmulPlan& m, mpc_form form) {
   return 2 * align_up((size_t)(m.M * m.K) * 8) + align_up((size_t)(m.K * m.N) * 8);
 }
 
+// Plain-form opens, then each party's finish z_p = c_p + [eps | g_p] @ [b_p ; delta]
+// in the fp64 limb form, one party after the other through one shared
+// fp64 workspace (all on party 0's stream).
+mpc_status run_matmuls_fp64(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int trunc) {
+  size_t need = kAlign, fp = 0;
+  for (const MatmulPlan& m : plans) {
+    if (2 * m.K >= kFp64MaxK) return MPC_E_UNSUPPORTED;
+    need += matmul_ws(m, MPC_FORM_PLAIN);
+    fp = std::max(fp, fp64_ws(m.M, m.N, 2 * m.K));
+  }
+  CHK(ensure_ws(c, need + fp));
+  Carve cv(c->ws);
+  std::vector<OpenJob> opens;
+  struct Opened { u64 *eps, *g, *del; };
+  std::vector<Opened> op;
+  for (const MatmulPlan& m : plans) {
+    u64* eps = cv.take<u64>((size_t)(m.M * m.K));
+    u64* g = cv.take<u64>((size_t)(m.M * m.K));
+    u64* del = cv.take<u64>((size_t)(m.K * m.N));
+    opens.push_back(OpenJob{kOpenLeft, m.M * m.K, m.x0, m.x1, m.t.a0, m.t.a1, eps, g});
+    opens.push_back(OpenJob{kOpenRight, m.K * m.N, m.y0, m.y1, m.t.b0, m.t.b1, del, nullptr});
+    op.push_back(Opened{eps, g, del});
+  }
+  CHK(issue_opens(c, opens));
+  for (size_t q = 0; q < plans.size(); ++q) {
+    const MatmulPlan& m = plans[q];
+    for (int p = 0; p < 2; ++p) {
+      Carve fcv = cv;  // the same fp64 workspace for every product, in stream order
+      CHK(issue_fp64(c, fcv, m.M, m.N, m.K, m.K, op[q].eps, m.K, p == 0 ? op[q].g : m.t.a1, m.K,
+                     p == 0 ? m.t.b0 : m.t.b1, m.N, op[q].del, m.N,
+                     make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1, rowmajor_view(m.N))));
+    }
+  }
+  return MPC_OK;
+}
+
 // Plain form: eps, g0 = a0 + eps and delta row-major; party p's finish is
 // z_p = c_p + [eps | g_p] @ [b_p ; delta] with g_1 = a_1.
 void matmul_plain(const MatmulPlan& m, Carve& cv, int trunc, std::vector<OpenJob>& opens,
@@ -980,11 +1150,13 @@ void matmul_limb(const MatmulPlan& m, Carve& cv, int trunc, std::vector<PackJob>
 }
 
 mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int trunc, mpc_form form) {
-  size_t need = kAlign;
-  for (const MatmulPlan& m : plans) need += matmul_ws(m, form);
-  CHK(ensure_ws(c, need));
-  Carve cv(c->ws);
-  if (form == MPC_FORM_LIMB8) {
+  if (form == MPC_FORM_FP64LIMB) {
+    CHK(run_matmuls_fp64(c, plans, trunc));
+  } else if (form == MPC_FORM_LIMB8) {
+    size_t need = kAlign;
+    for (const MatmulPlan& m : plans) need += matmul_ws(m, form);
+    CHK(ensure_ws(c, need));
+    Carve cv(c->ws);
     std::vector<PackJob> jobs;
     std::vector<LimbReq> reqs;
     std::vector<std::array<i64, 3>> shapes;
@@ -994,6 +1166,10 @@ mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int tru
     }
     CHK(issue_limb(c, jobs, reqs, sched_for(c, shapes)));
   } else {
+    size_t need = kAlign;
+    for (const MatmulPlan& m : plans) need += matmul_ws(m, form);
+    CHK(ensure_ws(c, need));
+    Carve cv(c->ws);
     std::vector<OpenJob> opens;
     std::vector<PlainProblem> probs;
     for (const MatmulPlan& m : plans) matmul_plain(m, cv, trunc, opens, probs);
@@ -1033,6 +1209,7 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
   CHK(check_conv(shape));
   CHK(check_trunc(trunc_bits));
   CHK(check_form(form));
+  if (form == MPC_FORM_FP64LIMB) return MPC_E_UNSUPPORTED;
   const mpc_conv1d_shape s = *shape;
   const i64 lout = conv_lout(s);
   const size_t nx = (size_t)(s.batch * s.cin * s.length), nw = (size_t)(s.cout * s.cin * s.ksize);
@@ -1116,6 +1293,11 @@ mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint
     Carve cv(c->ws);
     const PackJob PA = place_job(ja, cv), PB = place_job(jb, cv);
     CHK(issue_limb(c, {PA, PB}, {limb_req(M, N, K, 0, PA.dst[0], nullptr, PB.dst[0], nullptr, ep)}, c->sched_default));
+  } else if (form == MPC_FORM_FP64LIMB) {
+    if (K >= kFp64MaxK) return MPC_E_UNSUPPORTED;
+    CHK(ensure_ws(c, kAlign + fp64_ws(M, N, K)));
+    Carve cv(c->ws);
+    CHK(issue_fp64(c, cv, M, N, K, 0, A, K, nullptr, 0, B, N, nullptr, 0, ep));
   } else {
     CHK(issue_plain(c, {plain_problem(M, N, K, 0, A, nullptr, K, nullptr, 0, B, nullptr, N, nullptr, 0, ep)}));
   }
@@ -1268,15 +1450,17 @@ mpc_status mpc_profile_enable(mpc_ctx* c, int on) {
   return MPC_OK;
 }
 
-mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing* plain) {
+mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing* plain,
+                            mpc_gemm_timing* fp64limb) {
   if (!c) return MPC_E_INVAL;
   CHK(set_device(c));
   CHK(sync_all(c));
-  mpc_gemm_timing acc[2] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}};  // [0] plain, [1] limb8
+  // [0] plain, [1] limb8, [2] fp64 limb
+  mpc_gemm_timing acc[3] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}};
   for (auto& t : c->timed) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, t.start, t.stop));
-    mpc_gemm_timing& a = acc[t.form == MPC_FORM_LIMB8 ? 1 : 0];
+    mpc_gemm_timing& a = acc[t.form == MPC_FORM_LIMB8 ? 1 : t.form == MPC_FORM_FP64LIMB ? 2 : 0];
     a.launches++;
     a.total_ms += ms;
     a.ring_macs += t.ring_macs;
@@ -1286,6 +1470,7 @@ mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing*
   c->timed.clear();
   if (limb8) *limb8 = acc[1];
   if (plain) *plain = acc[0];
+  if (fp64limb) *fp64limb = acc[2];
   return MPC_OK;
 }
 
@@ -1310,20 +1495,27 @@ mpc_status mpc_graph_end(mpc_ctx* c, void** graph_exec) {
   hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return hip_status(e);
-  *graph_exec = (void*)ge;
+  *graph_exec = (void*)new mpc_graph{ge, c};
+  c->live_graphs++;
   return MPC_OK;
 }
 
 mpc_status mpc_graph_launch(mpc_ctx* c, void* graph_exec) {
   if (!c || !graph_exec) return MPC_E_INVAL;
+  mpc_graph* g = (mpc_graph*)graph_exec;
+  if (g->ctx != c) return MPC_E_INVAL;
   CHK(set_device(c));
-  HIPCHK(hipGraphLaunch((hipGraphExec_t)graph_exec, c->s[0]));
+  HIPCHK(hipGraphLaunch(g->exec, c->s[0]));
   return MPC_OK;
 }
 
 mpc_status mpc_graph_destroy(void* graph_exec) {
   if (!graph_exec) return MPC_OK;
-  HIPCHK(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+  mpc_graph* g = (mpc_graph*)graph_exec;
+  const hipError_t e = hipGraphExecDestroy(g->exec);
+  g->ctx->live_graphs--;
+  delete g;
+  HIPCHK(e);
   return MPC_OK;
 }
 

@@ -15,7 +15,7 @@
 namespace mpc {
 namespace {
 
-constexpr int BM = 128, BN = 64, BK = 16;
+constexpr int BM = 128, BN = 64, BK = kPlainBK;
 constexpr int TM = 8, TN = 4;
 constexpr int kThreads = 256;
 
@@ -61,8 +61,12 @@ __global__ void __launch_bounds__(kThreads)
   const PlainProblem p = probs[pi];
   const int local = t - map.tile_start[pi];
   const int ntn = (int)((p.N + BN - 1) / BN);
-  const i64 m0 = (i64)(local / ntn) * BM, n0 = (i64)(local % ntn) * BN;
-  const i64 Ktot = p.K0 + p.K1;
+  const int tiles_mn = (int)((p.M + BM - 1) / BM) * ntn;
+  const int slice = local / tiles_mn, lt = local % tiles_mn;
+  const i64 m0 = (i64)(lt / ntn) * BM, n0 = (i64)(lt % ntn) * BN;
+  // this workgroup's k range: one slice of a split problem, else all of k
+  const i64 kbeg = (i64)slice * p.kslice;
+  const i64 Ktot = min(p.K0 + p.K1, kbeg + p.kslice);
 
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
@@ -88,8 +92,8 @@ __global__ void __launch_bounds__(kThreads)
       cr[i][j] = 0;
     }
 
-  if (Ktot > 0) fetch(0);
-  for (i64 k0 = 0; k0 < Ktot; k0 += BK) {
+  if (kbeg < Ktot) fetch(kbeg);
+  for (i64 k0 = kbeg; k0 < Ktot; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) As[la_k + q][la_row] = ra[q];
@@ -117,6 +121,21 @@ __global__ void __launch_bounds__(kThreads)
     }
   }
 
+  if (p.ksplit > 1) {
+    // raw slice sum; the reduction adds the slices and applies the epilogue
+    u64* part = p.partial + (i64)slice * p.M * p.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const i64 m = m0 + ty + 16 * i;
+      if (m >= p.M) continue;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const i64 n = n0 + tx + 16 * j;
+        if (n < p.N) part[m * p.N + n] = lo[i][j] + ((u64)cr[i][j] << 32);
+      }
+    }
+    return;
+  }
   const Epilogue& ep = p.ep;
   i64 coff[TN];
 #pragma unroll
@@ -142,7 +161,32 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+__global__ void __launch_bounds__(kThreads)
+    k_plain_reduce(const PlainProblem* __restrict__ prob) {
+  const PlainProblem& p = *prob;
+  const i64 total = p.M * p.N;
+  const Epilogue& ep = p.ep;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
+    u64 v = 0;
+    for (int s = 0; s < p.ksplit; ++s) v += p.partial[s * total + e];
+    const i64 m = e / p.N, n = e % p.N;
+    const i64 off = m * ep.view.ld_m + (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
+    if (ep.accumulate) v += ep.Out[off];
+    if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
+    if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
+    ep.Out[off] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_plain_reduce(hipStream_t s, const PlainProblem* prob_dev, i64 M, i64 N) {
+  const i64 total = M * N;
+  if (total <= 0) return hipSuccess;
+  const i64 b = (total + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_plain_reduce, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(kThreads), 0, s, prob_dev);
+  return hipGetLastError();
+}
 
 int plain_tiles(i64 M, i64 N) { return (int)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)); }
 

@@ -66,6 +66,12 @@ struct PlainProblem {
   const u64* B1;
   i64 ldb1;
   Epilogue ep;
+  // Split-K: the k range is cut into ksplit slices of kslice values (a
+  // multiple of the kernel's k tile); with ksplit > 1 each slice writes its raw
+  // sum to partial[slice][M][N] and a reduction applies the epilogue.
+  int ksplit;
+  i64 kslice;
+  u64* partial;
 };
 
 // ---------------------------------------------------------------- limb packing
@@ -187,6 +193,9 @@ hipError_t launch_add(hipStream_t s, const u64* x, const u64* y, size_t n, u64* 
 hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
                              int total_tiles);
 int plain_tiles(i64 M, i64 N);
+constexpr int kPlainBK = 16;  // k tile of the plain GEMM (split-K slices are multiples)
+// sum of the ksplit partial results of one split problem, then its epilogue
+hipError_t launch_plain_reduce(hipStream_t s, const PlainProblem* prob_dev, i64 M, i64 N);
 
 // Limb form (gemm_limb.hip).
 // jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device
@@ -201,6 +210,24 @@ struct TileSched {
   int group_m;    // tile rows per raster group
   int xcd_remap;  // give each XCD a contiguous run of tiles
 };
+// ---------------------------------------------------------------- fp64 limb form
+// The paper's GPU form of the ring GEMM: L fp64 limb planes per operand (L = 3
+// of 22 bits when the concatenated k is below kFp64Limb22MaxK, else L = 4 of
+// 16 bits), one fp64 GEMM per diagonal, exact combine.  Per-k diagonal sums
+// are bounded by 2^43 (L = 3) and 2^32 (L = 4), so every partial sum of up to
+// kFp64Limb22MaxK (resp. kFp64MaxK) terms stays an integer below 2^53.
+constexpr i64 kFp64Limb22MaxK = 1024;     // L = 3 needs Kt < 2^10
+constexpr i64 kFp64MaxK = (i64)1 << 21;   // L = 4 needs Kt < 2^21
+int fp64_limbs(i64 Kt);
+// LA: M x (L*Kt) row-major, limb i in columns [i*Kt, (i+1)*Kt)
+hipError_t launch_fp64_pack_left(hipStream_t s, i64 M, i64 K0, i64 K1, const u64* A0, i64 lda0,
+                                 const u64* A1, i64 lda1, int L, double* LA);
+// RB: (L*Kt) x N row-major, limb j in rows [(L-1-j)*Kt, (L-j)*Kt)
+hipError_t launch_fp64_pack_right(hipStream_t s, i64 N, i64 K0, i64 K1, const u64* B0, i64 ldb0,
+                                  const u64* B1, i64 ldb1, int L, double* RB);
+// X: L x M x N row-major diagonal sums -> epilogue
+hipError_t launch_fp64_combine(hipStream_t s, i64 M, i64 N, int L, const double* X, const Epilogue& ep);
+
 hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
                             TileSched sched);
 int limb_tiles(i64 M, i64 N, int variant);

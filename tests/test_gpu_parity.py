@@ -366,3 +366,63 @@ def test_autotune_grouped_and_cache(m, tmp_path):
         assert torch.equal(z.s0, zp.s0) and torch.equal(z.s1, zp.s1)
     c2.close()
     c.close()
+
+
+# ------------------------------------------------------------------ plain split-K
+@pytest.mark.parametrize("M,N,K", [(5, 7, 5000), (128, 10, 2048), (1, 1, 3000), (130, 70, 777)])
+def test_ring_gemm_plain_split_k(m, ctx, M, N, K):
+    # few output tiles and a long k: the plain launch splits k into slices
+    say(f"ring gemm plain split-k {M}x{N}x{K}")
+    A, B = rnd(M + 3 * K, (M, K)), rnd(N + 5 * K, (K, N))
+    C = ctx.ring_gemm(dev(A), dev(B), form="plain")
+    assert np.array_equal(host(ctx, C), oracle.ring_gemm(A, B))
+
+
+@pytest.mark.parametrize("trunc", [0, 16])
+def test_beaver_matmul_plain_split_k(m, ctx, trunc):
+    # the MLP's last layer shape: 128 x 10 outputs over 2 x 1024 concatenated k
+    M, N, K = 128, 10, 1024
+    say(f"beaver matmul plain split-k trunc={trunc}")
+    X = oracle.encode(workloads.uniform(91, (M, K), -1, 1))
+    Y = oracle.encode(workloads.uniform(92, (K, N), -1, 1))
+    xs, ys = oracle.share(X, 0, SEED, 93), oracle.share(Y, 1, SEED, 94)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 3002, 95, (M, N, K))
+    z = ctx.beaver_matmul(ctx.share(dev(X), 0, 93), ctx.share(dev(Y), 1, 94), t, trunc, "plain")
+    want = oracle.beaver_matmul(xs, ys, oracle.dealer_matmul(3002, 95, M, N, K), trunc)
+    assert_pair(ctx, z, want, "beaver matmul plain split-k")
+
+
+def test_live_graph_pins_workspace(m):
+    # while a captured graph exists the workspace cannot move: a call needing a
+    # larger one is refused, and works again once the graph is destroyed
+    say("graph pins workspace")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = m.Context(device=0, seed=SEED)
+        try:
+            M, N, K = 64, 64, 64
+            gx = c.share(dev(rnd(5, (M, K))), 0, 1)
+            gy = c.share(dev(rnd(6, (K, N))), 1, 2)
+            t = c.dealer(m.TRIPLE_MATMUL, 2, 3, (M, N, K))
+            out = m.SharedPair(c.empty((M, N)), c.empty((M, N)))
+            # a large product's inputs (its dealer call grows the workspace a
+            # little, less than the product itself will need)
+            big = 1024
+            bx = c.share(dev(rnd(7, (big, big))), 0, 4)
+            by = c.share(dev(rnd(8, (big, big))), 1, 5)
+            bt = c.dealer(m.TRIPLE_MATMUL, 2, 6, (big, big, big))
+            c.beaver_matmul(gx, gy, t, 16, "limb8", out=out)
+            c.sync()
+            c.graph_begin()
+            c.beaver_matmul(gx, gy, t, 16, "limb8", out=out)
+            g = c.graph_end()
+            with pytest.raises(m.MPCError) as e:
+                c.beaver_matmul(bx, by, bt, 16, "limb8")
+            assert e.value.status == -4
+            c.graph_launch(g)
+            m.Context.graph_destroy(g)
+            z = c.beaver_matmul(bx, by, bt, 16, "limb8")
+            c.sync()
+            assert z.s0.shape == (big, big)
+        finally:
+            c.close()
