@@ -21,6 +21,7 @@ u64p = ctypes.POINTER(ctypes.c_uint64)
 i64p = ctypes.POINTER(ctypes.c_int64)
 i8p = ctypes.POINTER(ctypes.c_int8)
 dblp = ctypes.POINTER(ctypes.c_double)
+u64pp = ctypes.POINTER(u64p)
 U64 = ctypes.c_uint64
 I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
@@ -72,6 +73,14 @@ def lib():
                                      + [INT, I64, i64p, i64p, i64p, u64p, u64p]),
             "orc_limbs": (None, [u64p, SZ, i8p]),
             "orc_limb_gemm": (INT, [I64, I64, I64, u64p, u64p, I64, u64p]),
+            "orc_mp_share": (None, [u64p, SZ, INT, INT, U64, U64, u64pp]),
+            "orc_mp_reveal": (None, [INT, u64pp, SZ, u64p]),
+            "orc_mp_dealer_mul": (None, [U64, U64, INT, SZ, INT, u64pp, u64pp, u64pp]),
+            "orc_mp_dealer_matmul": (None, [U64, U64, INT, I64, I64, I64, u64pp, u64pp, u64pp]),
+            "orc_mp_beaver_mul": (None, [INT, SZ, u64pp, u64pp, u64pp, u64pp, u64pp, u64pp]),
+            "orc_mp_beaver_matmul": (None, [INT, I64, I64, I64] + [u64pp] * 6),
+            "orc_mp_dealer_trunc": (None, [U64, U64, INT, SZ, u64pp, u64pp]),
+            "orc_mp_truncate": (None, [INT, SZ, INT, u64pp, u64pp, u64pp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -402,3 +411,83 @@ def limb_gemm(A, B, kchunk):
     if rc != 0:
         raise OverflowError("an int32 chunk sum overflowed")
     return C
+
+
+# ----------------------------------------------------------------- more than two parties
+# A sharing among P parties is a list of P numpy uint64 arrays of one shape.
+def _pp(arrs):
+    """C array of P pointers to contiguous uint64 arrays (kept alive by the caller)."""
+    return (u64p * len(arrs))(*[a.ctypes.data_as(u64p) for a in arrs])
+
+
+def _outs(P, shape):
+    return [np.zeros(shape, dtype=np.uint64) for _ in range(P)]
+
+
+def mp_share(x, P, src, seed, tag):
+    x = np.ascontiguousarray(x).view(np.uint64) if np.asarray(x).dtype == np.int64 else np.ascontiguousarray(x, dtype=np.uint64)
+    s = _outs(P, x.shape)
+    lib().orc_mp_share(x.ctypes.data_as(u64p), x.size, P, src, seed, tag, _pp(s))
+    return s
+
+
+def mp_reveal(s):
+    s = [np.ascontiguousarray(v, dtype=np.uint64) for v in s]
+    out = np.zeros(s[0].shape, dtype=np.uint64)
+    lib().orc_mp_reveal(len(s), _pp(s), s[0].size, out.ctypes.data_as(u64p))
+    return out
+
+
+def mp_dealer_mul(dseed, tag, P, n, square=False):
+    a, b, c = _outs(P, n), _outs(P, n), _outs(P, n)
+    lib().orc_mp_dealer_mul(dseed, tag, P, n, int(square), _pp(a), _pp(b), _pp(c))
+    return Triple(a, b, None if square else c)
+
+
+def mp_dealer_matmul(dseed, tag, P, M, N, K):
+    a, b, c = _outs(P, (M, K)), _outs(P, (K, N)), _outs(P, (M, N))
+    lib().orc_mp_dealer_matmul(dseed, tag, P, M, N, K, _pp(a), _pp(b), _pp(c))
+    return Triple(a, b, c)
+
+
+def mp_beaver_mul(x, y, t):
+    """P-party Beaver product (y None: square with the pair t = (a, b = a^2))."""
+    P = len(x)
+    x = [np.ascontiguousarray(v, dtype=np.uint64) for v in x]
+    a = [np.ascontiguousarray(v, dtype=np.uint64) for v in t.a]
+    b = [np.ascontiguousarray(v, dtype=np.uint64) for v in t.b]
+    z = _outs(P, x[0].shape)
+    if y is None:
+        lib().orc_mp_beaver_mul(P, x[0].size, _pp(x), None, _pp(a), _pp(b), None, _pp(z))
+    else:
+        y = [np.ascontiguousarray(v, dtype=np.uint64) for v in y]
+        c = [np.ascontiguousarray(v, dtype=np.uint64) for v in t.c]
+        lib().orc_mp_beaver_mul(P, x[0].size, _pp(x), _pp(y), _pp(a), _pp(b), _pp(c), _pp(z))
+    return z
+
+
+def mp_beaver_matmul(x, y, t):
+    P = len(x)
+    M, K = x[0].shape
+    N = y[0].shape[1]
+    arrs = [[np.ascontiguousarray(v, dtype=np.uint64) for v in g] for g in (x, y, t.a, t.b, t.c)]
+    z = _outs(P, (M, N))
+    lib().orc_mp_beaver_matmul(P, M, N, K, *[_pp(g) for g in arrs], _pp(z))
+    return z
+
+
+def mp_dealer_trunc(dseed, tag, P, n):
+    """Algorithm 1's dealer inputs: shares of a uniform r and of its wrap count."""
+    r, t = _outs(P, n), _outs(P, n)
+    lib().orc_mp_dealer_trunc(dseed, tag, P, n, _pp(r), _pp(t))
+    return r, t
+
+
+def mp_truncate(x, bits, r, t):
+    """Algorithm 1 truncation (eta = 0) of a P-party sharing; returns new shares."""
+    P = len(x)
+    out = [np.array(v, dtype=np.uint64, copy=True).ravel() for v in x]
+    r = [np.ascontiguousarray(v, dtype=np.uint64).ravel() for v in r]
+    t = [np.ascontiguousarray(v, dtype=np.uint64).ravel() for v in t]
+    lib().orc_mp_truncate(P, out[0].size, bits, _pp(out), _pp(r), _pp(t))
+    return [o.reshape(np.shape(x[0])) for o in out]

@@ -544,3 +544,182 @@ int orc_limb_gemm(i64 M, i64 N, i64 K, const u64 *A, const u64 *B, i64 kchunk, u
   free(dB);
   return bad ? -1 : 0;
 }
+
+/* ======================================================================== */
+/* More than two parties (App. C.1.1, arithmetic secret sharing for any      */
+/* number of parties |P|; Algorithm 1 for the truncation).  A sharing among  */
+/* P parties is an array of P share buffers.  PRG domains of these functions */
+/* are separate slots: 0x100+p share, 0x200+p a, 0x300+p b, 0x400+p c,       */
+/* 0x500+p r, 0x600+p theta_r, for party p.                                  */
+/* ======================================================================== */
+enum { MP_SHARE = 0x100, MP_A = 0x200, MP_B = 0x300, MP_C = 0x400, MP_R = 0x500, MP_T = 0x600 };
+
+/* signed view and exact integer helpers */
+static inline i64 s64(u64 v) { return (i64)v; }
+
+/* Sharing (section 5.1): a pseudorandom zero-share of P numbers summing to 0,
+ * z_p = m_p - m_{(p+1) mod P} with m_p = G(seed, tag, 0x100+p, i); the source
+ * party adds its value. */
+void orc_mp_share(const u64 *x, size_t n, int P, int src, u64 seed, u64 tag, u64 *const *s) {
+  for (size_t i = 0; i < n; ++i)
+    for (int p = 0; p < P; ++p) {
+      const u64 mp = orc_prg(seed, tag, MP_SHARE + (u64)p, (u64)i);
+      const u64 mq = orc_prg(seed, tag, MP_SHARE + (u64)((p + 1) % P), (u64)i);
+      s[p][i] = (mp - mq) + (p == src ? x[i] : 0);
+    }
+}
+
+/* x = sum_p [x]_p mod Q */
+void orc_mp_reveal(int P, const u64 *const *s, size_t n, u64 *out) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 acc = 0;
+    for (int p = 0; p < P; ++p) acc += s[p][i];
+    out[i] = acc;
+  }
+}
+
+/* The last party's share of a value v whose other P-1 shares are drawn from
+ * the PRG: v - sum_{p<P-1} G(slot+p). */
+static void mp_split(u64 dseed, u64 tag, u64 slot, int P, size_t n, const u64 *v, u64 *const *out) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 rest = v[i];
+    for (int p = 0; p < P - 1; ++p) {
+      out[p][i] = orc_prg(dseed, tag, slot + (u64)p, (u64)i);
+      rest -= out[p][i];
+    }
+    out[P - 1][i] = rest;
+  }
+}
+
+/* Dealer (the TTP), element-wise: a_p, b_p uniform from the PRG; c = a*b
+ * shared as c_p = G(0x400+p) for p < P-1 and the rest for the last party.
+ * square != 0: the Beaver pair (a, b = a^2), b shared the same way, c unused. */
+void orc_mp_dealer_mul(u64 dseed, u64 tag, int P, size_t n, int square, u64 *const *a, u64 *const *b,
+                       u64 *const *c) {
+  u64 *prod = (u64 *)malloc((n ? n : 1) * sizeof(u64));
+  for (int p = 0; p < P; ++p) orc_prg_fill(dseed, tag, MP_A + (u64)p, n, a[p]);
+  if (!square)
+    for (int p = 0; p < P; ++p) orc_prg_fill(dseed, tag, MP_B + (u64)p, n, b[p]);
+  for (size_t i = 0; i < n; ++i) {
+    u64 av = 0, bv = 0;
+    for (int p = 0; p < P; ++p) av += a[p][i];
+    if (!square)
+      for (int p = 0; p < P; ++p) bv += b[p][i];
+    prod[i] = square ? av * av : av * bv;
+  }
+  if (square) mp_split(dseed, tag, MP_B, P, n, prod, b);
+  else mp_split(dseed, tag, MP_C, P, n, prod, c);
+  free(prod);
+}
+
+/* Dealer, matrix triple: a_p (MxK), b_p (KxN) uniform; c = a @ b (MxN). */
+void orc_mp_dealer_matmul(u64 dseed, u64 tag, int P, i64 M, i64 N, i64 K, u64 *const *a, u64 *const *b,
+                          u64 *const *c) {
+  const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
+  u64 *as = (u64 *)calloc(na ? na : 1, sizeof(u64));
+  u64 *bs = (u64 *)calloc(nb ? nb : 1, sizeof(u64));
+  u64 *cs = (u64 *)malloc((nc ? nc : 1) * sizeof(u64));
+  for (int p = 0; p < P; ++p) {
+    orc_prg_fill(dseed, tag, MP_A + (u64)p, na, a[p]);
+    orc_prg_fill(dseed, tag, MP_B + (u64)p, nb, b[p]);
+    for (size_t i = 0; i < na; ++i) as[i] += a[p][i];
+    for (size_t i = 0; i < nb; ++i) bs[i] += b[p][i];
+  }
+  orc_ring_gemm(M, N, K, as, bs, cs);
+  mp_split(dseed, tag, MP_C, P, nc, cs, c);
+  free(as);
+  free(bs);
+  free(cs);
+}
+
+/* Beaver product among P parties (App. C.1.1, Multiplication and Square):
+ * eps = sum_p ([x]_p - [a]_p), delta = sum_p ([y]_p - [b]_p) are opened, and
+ * [z]_p = [c]_p + eps [b]_p + [a]_p delta (+ eps delta for party 0).
+ * y == NULL: the square with the pair (a, b = a^2):
+ * [z]_p = [b]_p + 2 eps [a]_p (+ eps^2 for party 0). */
+void orc_mp_beaver_mul(int P, size_t n, const u64 *const *x, const u64 *const *y, const u64 *const *a,
+                       const u64 *const *b, const u64 *const *c, u64 *const *z) {
+  for (size_t i = 0; i < n; ++i) {
+    u64 eps = 0, delta = 0;
+    for (int p = 0; p < P; ++p) eps += x[p][i] - a[p][i];
+    if (y)
+      for (int p = 0; p < P; ++p) delta += y[p][i] - b[p][i];
+    for (int p = 0; p < P; ++p) {
+      if (y) z[p][i] = c[p][i] + eps * b[p][i] + a[p][i] * delta + (p == 0 ? eps * delta : 0);
+      else z[p][i] = b[p][i] + 2 * eps * a[p][i] + (p == 0 ? eps * eps : 0);
+    }
+  }
+}
+
+/* Beaver matmul among P parties, the three products kept separate and in
+ * order: [z]_p = [c]_p + eps @ [b]_p + [a]_p @ delta (+ eps @ delta, party 0). */
+void orc_mp_beaver_matmul(int P, i64 M, i64 N, i64 K, const u64 *const *x, const u64 *const *y,
+                          const u64 *const *a, const u64 *const *b, const u64 *const *c, u64 *const *z) {
+  const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
+  u64 *eps = (u64 *)calloc(na ? na : 1, sizeof(u64));
+  u64 *del = (u64 *)calloc(nb ? nb : 1, sizeof(u64));
+  u64 *t1 = (u64 *)malloc((nc ? nc : 1) * sizeof(u64));
+  u64 *t2 = (u64 *)malloc((nc ? nc : 1) * sizeof(u64));
+  u64 *t3 = (u64 *)malloc((nc ? nc : 1) * sizeof(u64));
+  for (int p = 0; p < P; ++p) {
+    for (size_t i = 0; i < na; ++i) eps[i] += x[p][i] - a[p][i];
+    for (size_t i = 0; i < nb; ++i) del[i] += y[p][i] - b[p][i];
+  }
+  orc_ring_gemm(M, N, K, eps, del, t3);
+  for (int p = 0; p < P; ++p) {
+    orc_ring_gemm(M, N, K, eps, b[p], t1);
+    orc_ring_gemm(M, N, K, a[p], del, t2);
+    for (size_t i = 0; i < nc; ++i) z[p][i] = c[p][i] + t1[i] + t2[i] + (p == 0 ? t3[i] : 0);
+  }
+  free(eps);
+  free(del);
+  free(t1);
+  free(t2);
+  free(t3);
+}
+
+/* The wrap count theta_v of shares v_0..v_{P-1} (App. C.1.1, Truncation): the
+ * integer with sum_p s64(v_p) = s64(v) + theta_v Q, v = sum_p v_p mod Q. */
+static i64 mp_wraps(int P, const u64 *const *v, size_t i) {
+  __int128 sum = 0;
+  u64 ring = 0;
+  for (int p = 0; p < P; ++p) {
+    sum += (__int128)s64(v[p][i]);
+    ring += v[p][i];
+  }
+  return (i64)((sum - (__int128)s64(ring)) / ((__int128)1 << 64));
+}
+
+/* Dealer of the truncation randomness (Algorithm 1's inputs): r_p uniform
+ * from the PRG, and a sharing of the wrap count theta_r of r's shares
+ * (t_p = G(0x600+p) for p < P-1, the last share the rest). */
+void orc_mp_dealer_trunc(u64 dseed, u64 tag, int P, size_t n, u64 *const *r, u64 *const *t) {
+  u64 *th = (u64 *)malloc((n ? n : 1) * sizeof(u64));
+  for (int p = 0; p < P; ++p) orc_prg_fill(dseed, tag, MP_R + (u64)p, n, r[p]);
+  for (size_t i = 0; i < n; ++i) th[i] = (u64)mp_wraps(P, (const u64 *const *)r, i);
+  mp_split(dseed, tag, MP_T, P, n, th, t);
+  free(th);
+}
+
+/* Truncation by 2^bits among P parties (App. C.1.1, Truncation, Algorithm 1
+ * with eta set to 0 as the paper does), in place:
+ *   [z] = [x] + [r];  beta_p = (s64(x_p) + s64(r_p) - s64(z_p)) / Q;
+ *   z = reveal([z]), theta_z = the wrap count of z's shares;
+ *   [theta_x] = theta_z (added by party 0) + [beta] - [theta_r];
+ *   [x / 2^bits]_p = floor(s64(x_p) / 2^bits) - [theta_x]_p * 2^(64 - bits). */
+void orc_mp_truncate(int P, size_t n, int bits, u64 *const *x, const u64 *const *r, const u64 *const *t) {
+  if (bits <= 0 || P < 1 || P > 64) return; /* nothing to divide by / out of this oracle's range */
+  u64 *zs[64];
+  for (int p = 0; p < P; ++p) zs[p] = (u64 *)malloc((n ? n : 1) * sizeof(u64));
+  for (size_t i = 0; i < n; ++i)
+    for (int p = 0; p < P; ++p) zs[p][i] = x[p][i] + r[p][i];
+  for (size_t i = 0; i < n; ++i) {
+    const i64 theta_z = mp_wraps(P, (const u64 *const *)zs, i);
+    for (int p = 0; p < P; ++p) {
+      const __int128 beta = ((__int128)s64(x[p][i]) + s64(r[p][i]) - s64(zs[p][i])) / ((__int128)1 << 64);
+      const u64 theta_x = (p == 0 ? (u64)theta_z : 0) + (u64)(i64)beta - t[p][i];
+      x[p][i] = (u64)floor_div_pow2(s64(x[p][i]), bits) - theta_x * ((u64)1 << (64 - bits));
+    }
+  }
+  for (int p = 0; p < P; ++p) free(zs[p]);
+}
