@@ -279,6 +279,7 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
         ex[f"mlp_ops_ms_{form}"] = ops
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
     ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
+    ex.update(multiparty_bench(ctx, mpc, torch, X, Y))
     ctx.sync()
     ex.update(grouped_bench(mpc, torch, workloads))
     ex.update(conv_bench(mpc, torch, workloads))
@@ -411,6 +412,46 @@ def mlp_latency(ctx, mpc, torch, workloads, form):
             label = f"square{i + 1}_{B}x{dims[i + 1]}"
         ops[label] = round(_event_time(torch, ctx.streams[0], fn, 20), 4)
     return total, ops
+
+
+def multiparty_bench(ctx, mpc, torch, X, Y):
+    """Three parties: the fused Beaver product and the wrap-count truncation
+    (Algorithm 1) at 2^24 elements against HBM, and the Beaver matmul at
+    4096^3 in the limb form (three per-party ring GEMMs of 4096x4096x8192)."""
+    out = {}
+    P, n = 3, 1 << 24
+    x = ctx.mp_share(X.view(-1), P, 0, 90)
+    y = ctx.mp_share(Y.view(-1), P, 1, 91)
+    t = ctx.mp_dealer(P, mpc.TRIPLE_MUL, 17, 92, (n,))
+    z = mpc.Shared([ctx.empty((n,)) for _ in range(P)])
+    ctx.mp_beaver_mul(x, y, t, out=z)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.mp_beaver_mul(x, y, t, out=z), 10)
+    out["mp3_beaver_mul_ms"] = round(ms, 4)
+    # 5 inputs and 1 output per party, 8 bytes each
+    out["mp3_beaver_mul_GBps_algorithmic"] = round(48.0 * P * n / (ms * 1e-3) / 1e9, 1)
+    r, th = ctx.mp_dealer_trunc(P, 17, 93, n)
+    ctx.mp_truncate(z, 16, r, th)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.mp_truncate(z, 16, r, th), 10)
+    out["mp3_truncate_ms"] = round(ms, 4)
+    # x, r, theta_r in and x out per party
+    out["mp3_truncate_GBps_algorithmic"] = round(32.0 * P * n / (ms * 1e-3) / 1e9, 1)
+    del t, z, r, th
+    xm = mpc.Shared([v.view(M, K) for v in x])
+    ym = mpc.Shared([v.view(K, N) for v in y])
+    tm = ctx.mp_dealer(P, mpc.TRIPLE_MATMUL, 17, 94, (M, N, K))
+    zm = mpc.Shared([ctx.empty((M, N)) for _ in range(P)])
+    ctx.mp_beaver_matmul(xm, ym, tm, "limb8", out=zm)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.mp_beaver_matmul(xm, ym, tm, "limb8", out=zm), 3)
+    out["mp3_beaver_matmul_4096_ms"] = round(ms, 3)
+    out["mp3_beaver_matmul_4096_tops"] = round(2.0 * M * N * K / (ms * 1e-3) / 1e12, 3)
+    log(f"bench: 3 parties: Beaver mul {out['mp3_beaver_mul_GBps_algorithmic']} GB/s, truncate "
+        f"{out['mp3_truncate_GBps_algorithmic']} GB/s, matmul 4096^3 {out['mp3_beaver_matmul_4096_ms']} ms")
+    del x, y, tm, zm
+    torch.cuda.empty_cache()
+    return out
 
 
 def beaver_mul_sweep(ctx, mpc, torch):

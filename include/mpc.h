@@ -269,6 +269,60 @@ mpc_status mpc_graph_end(mpc_ctx *ctx, void **graph_exec);
 mpc_status mpc_graph_launch(mpc_ctx *ctx, void *graph_exec);
 mpc_status mpc_graph_destroy(void *graph_exec);
 
+/* ---- more than two parties (App. C.1.1; Algorithm 1) --------------------
+ * A sharing among P parties (2 <= P <= MPC_MAX_PARTIES) is a HOST array of P
+ * device pointers, one buffer per party, all of the same length.  Every call
+ * runs all parties' work on party 0's stream, as one pass per step (the
+ * opening of a masked value is a device-local sum over the P buffers); each
+ * Beaver product and each truncation counts one opening.  Outputs must not
+ * alias inputs (MPC_E_ALIAS), except mpc_mp_truncate, which works in place.
+ * PRG domains: party p's zero-share stream is slot 0x100+p of (seed, tag);
+ * the dealer's a, b, c, r, theta_r streams are slots 0x200+p ... 0x600+p of
+ * (dseed, tag). */
+#define MPC_MAX_PARTIES 16
+
+/* Sharing (section 5.1): a pseudorandom zero-share of P numbers summing to 0,
+ * z_p = m_p - m_{(p+1) mod P} with m_p party p's stream; party src adds x. */
+mpc_status mpc_mp_share(mpc_ctx *ctx, int P, const uint64_t *x, size_t n, int src, uint64_t tag,
+                        uint64_t *const *s);
+/* x = sum_p s_p (mod 2^64). */
+mpc_status mpc_mp_reveal(mpc_ctx *ctx, int P, const uint64_t *const *s, size_t n, uint64_t *out);
+
+/* Shares of a triple among P parties (arrays indexed by party). */
+typedef struct {
+  uint64_t *a[MPC_MAX_PARTIES], *b[MPC_MAX_PARTIES], *c[MPC_MAX_PARTIES];
+} mpc_mp_triple;
+/* The dealer (TTP): a_p, b_p uniform; c = a*b (MUL), b = a*a (SQUARE, c
+ * unused) or c = a@b (MATMUL) split as c_p = G(p) for p < P-1 and the rest
+ * for the last party.  dims: {n} for MUL/SQUARE, {M, N, K} for MATMUL. */
+mpc_status mpc_mp_dealer_triples(mpc_ctx *ctx, int P, mpc_triple_kind kind, uint64_t dseed, uint64_t tag,
+                                 const int64_t *dims, const mpc_mp_triple *out);
+/* The dealer of Algorithm 1's inputs: shares r_p of a uniform r and shares
+ * t_p of r's wrap count theta_r (sum_p s64(r_p) = s64(r) + theta_r 2^64). */
+mpc_status mpc_mp_dealer_trunc(mpc_ctx *ctx, int P, uint64_t dseed, uint64_t tag, size_t n,
+                               uint64_t *const *r, uint64_t *const *theta_r);
+
+/* Beaver product among P parties: eps = sum_p (x_p - a_p), delta likewise;
+ * z_p = c_p + eps b_p + a_p delta (+ eps delta for party 0).  y == NULL: the
+ * square with the pair (a, b = a^2), z_p = b_p + 2 eps a_p (+ eps^2). */
+mpc_status mpc_mp_beaver_mul(mpc_ctx *ctx, int P, size_t n, const uint64_t *const *x,
+                             const uint64_t *const *y, const mpc_mp_triple *t, uint64_t *const *z);
+/* Beaver matmul among P parties (X: MxK, Y: KxN, z_p: MxN):
+ * z_p = c_p + (a_p + [p=0] eps) @ delta + eps @ b_p, one ring GEMM of
+ * M x N x 2K per party, all P in one launch (PLAIN, LIMB8 or AUTO). */
+mpc_status mpc_mp_beaver_matmul(mpc_ctx *ctx, int P, int64_t M, int64_t N, int64_t K,
+                                const uint64_t *const *x, const uint64_t *const *y, const mpc_mp_triple *t,
+                                mpc_form form, uint64_t *const *z);
+/* Truncation by 2^bits (1 <= bits <= 63) of a P-party sharing, in place, by
+ * Algorithm 1 with eta = 0: z = x + r is opened with its wrap count, each
+ * party's share of theta_x = theta_z + beta - theta_r is formed locally, and
+ * x_p <- floor(s64(x_p) / 2^bits) - [theta_x]_p 2^(64 - bits).  The result is
+ * within P-1 below floor(x / 2^bits) unless x + r leaves the signed range
+ * (probability about |x| / 2^64).  r, theta_r from mpc_mp_dealer_trunc, one
+ * fresh pair per truncation. */
+mpc_status mpc_mp_truncate(mpc_ctx *ctx, int P, size_t n, int bits, uint64_t *const *x,
+                           const uint64_t *const *r, const uint64_t *const *theta_r);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,13 @@ class MatmulDesc(ctypes.Structure):
                 ("y1", VP), ("t", Triple), ("z0", VP), ("z1", VP)]
 
 
+MAX_PARTIES = 16
+
+
+class MpTriple(ctypes.Structure):
+    _fields_ = [("a", VP * MAX_PARTIES), ("b", VP * MAX_PARTIES), ("c", VP * MAX_PARTIES)]
+
+
 class GemmTiming(ctypes.Structure):
     _fields_ = [("launches", U64), ("total_ms", ctypes.c_double), ("ring_macs", ctypes.c_double)]
 
@@ -94,6 +101,17 @@ _SIGS = {
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
     "mpc_graph_launch": (INT, [VP, VP]),
     "mpc_graph_destroy": (INT, [VP]),
+    "mpc_mp_share": (INT, [VP, INT, VP, SZ, INT, U64, ctypes.POINTER(VP)]),
+    "mpc_mp_reveal": (INT, [VP, INT, ctypes.POINTER(VP), SZ, VP]),
+    "mpc_mp_dealer_triples": (INT, [VP, INT, INT, U64, U64, ctypes.POINTER(I64),
+                                    ctypes.POINTER(MpTriple)]),
+    "mpc_mp_dealer_trunc": (INT, [VP, INT, U64, U64, SZ, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
+    "mpc_mp_beaver_mul": (INT, [VP, INT, SZ, ctypes.POINTER(VP), ctypes.POINTER(VP),
+                                ctypes.POINTER(MpTriple), ctypes.POINTER(VP)]),
+    "mpc_mp_beaver_matmul": (INT, [VP, INT, I64, I64, I64, ctypes.POINTER(VP), ctypes.POINTER(VP),
+                                   ctypes.POINTER(MpTriple), INT, ctypes.POINTER(VP)]),
+    "mpc_mp_truncate": (INT, [VP, INT, SZ, INT, ctypes.POINTER(VP), ctypes.POINTER(VP),
+                              ctypes.POINTER(VP)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -154,6 +172,49 @@ class SharedPair:
 
     def __iter__(self):
         return iter((self.s0, self.s1))
+
+
+class Shared:
+    """The P parties' shares of one secret tensor (P >= 2)."""
+
+    def __init__(self, shares):
+        self.shares = list(shares)
+
+    @property
+    def P(self):
+        return len(self.shares)
+
+    @property
+    def shape(self):
+        return self.shares[0].shape
+
+    def __iter__(self):
+        return iter(self.shares)
+
+    def __getitem__(self, p):
+        return self.shares[p]
+
+
+class MpTripleShares:
+    """Device buffers of a triple shared among P parties: lists a, b, c."""
+
+    def __init__(self, a, b, c=None):
+        self.a, self.b, self.c = list(a), list(b), (list(c) if c is not None else None)
+
+    def struct(self):
+        t = MpTriple()
+        for p, v in enumerate(self.a):
+            t.a[p] = v.data_ptr()
+        for p, v in enumerate(self.b):
+            t.b[p] = v.data_ptr()
+        if self.c is not None:
+            for p, v in enumerate(self.c):
+                t.c[p] = v.data_ptr()
+        return t
+
+
+def _pptr(ts):
+    return (VP * len(ts))(*[t.data_ptr() for t in ts])
 
 
 class TripleShares:
@@ -289,6 +350,78 @@ class Context:
         _check(_lib.mpc_dealer_triples(self._h, kind, dseed, tag, d, ctypes.byref(st)),
                "mpc_dealer_triples")
         return t
+
+    # -------------------------------------------------------------- more than two parties
+    def mp_share(self, x, P, src, tag, out=None):
+        """Shares x among P parties (pseudorandom zero-share; party src adds x)."""
+        self._check_t(x)
+        s = out if out is not None else Shared([self.empty(x.shape) for _ in range(P)])
+        self._check_t(*s.shares)
+        _check(_lib.mpc_mp_share(self._h, P, _ptr(x), x.numel(), src, tag, _pptr(s.shares)),
+               "mpc_mp_share")
+        return s
+
+    def mp_reveal(self, s, out=None):
+        self._check_t(*s.shares)
+        out = out if out is not None else self.empty(s.shape)
+        _check(_lib.mpc_mp_reveal(self._h, s.P, _pptr(s.shares), out.numel(), _ptr(out)),
+               "mpc_mp_reveal")
+        return out
+
+    def mp_dealer(self, P, kind, dseed, tag, dims):
+        if kind in (TRIPLE_MUL, TRIPLE_SQUARE):
+            (n,) = dims
+            sa = sb = sc = (n,)
+        elif kind == TRIPLE_MATMUL:
+            M, N, K = dims
+            sa, sb, sc = (M, K), (K, N), (M, N)
+        else:
+            raise ValueError("multi-party triples: MUL, SQUARE or MATMUL")
+        t = MpTripleShares([self.empty(sa) for _ in range(P)], [self.empty(sb) for _ in range(P)],
+                           None if kind == TRIPLE_SQUARE else [self.empty(sc) for _ in range(P)])
+        d = (I64 * 3)(*(list(dims) + [0] * (3 - len(dims))))
+        st = t.struct()
+        _check(_lib.mpc_mp_dealer_triples(self._h, P, kind, dseed, tag, d, ctypes.byref(st)),
+               "mpc_mp_dealer_triples")
+        return t
+
+    def mp_dealer_trunc(self, P, dseed, tag, n):
+        """Algorithm 1's dealer inputs: (shares of r, shares of r's wrap count)."""
+        r = Shared([self.empty((n,)) for _ in range(P)])
+        th = Shared([self.empty((n,)) for _ in range(P)])
+        _check(_lib.mpc_mp_dealer_trunc(self._h, P, dseed, tag, n, _pptr(r.shares), _pptr(th.shares)),
+               "mpc_mp_dealer_trunc")
+        return r, th
+
+    def mp_beaver_mul(self, x, y, t, out=None):
+        """P-party Beaver product; y=None selects the square with the pair t."""
+        P = x.P
+        self._check_t(*x.shares, *(y.shares if y is not None else []), *t.a, *t.b, *(t.c or []))
+        z = out if out is not None else Shared([self.empty(x.shape) for _ in range(P)])
+        st = t.struct()
+        _check(_lib.mpc_mp_beaver_mul(self._h, P, x.shares[0].numel(), _pptr(x.shares),
+                                      _pptr(y.shares) if y is not None else None, ctypes.byref(st),
+                                      _pptr(z.shares)), "mpc_mp_beaver_mul")
+        return z
+
+    def mp_beaver_matmul(self, x, y, t, form="auto", out=None):
+        P = x.P
+        M, K = x.shape
+        N = y.shape[1]
+        self._check_t(*x.shares, *y.shares, *t.a, *t.b, *t.c)
+        z = out if out is not None else Shared([self.empty((M, N)) for _ in range(P)])
+        st = t.struct()
+        _check(_lib.mpc_mp_beaver_matmul(self._h, P, M, N, K, _pptr(x.shares), _pptr(y.shares),
+                                         ctypes.byref(st), FORMS[form], _pptr(z.shares)),
+               "mpc_mp_beaver_matmul")
+        return z
+
+    def mp_truncate(self, x, bits, r, theta_r):
+        """In-place truncation by 2^bits (Algorithm 1, eta = 0)."""
+        self._check_t(*x.shares, *r.shares, *theta_r.shares)
+        _check(_lib.mpc_mp_truncate(self._h, x.P, x.shares[0].numel(), bits, _pptr(x.shares),
+                                    _pptr(r.shares), _pptr(theta_r.shares)), "mpc_mp_truncate")
+        return x
 
     # -------------------------------------------------------------- Beaver
     def beaver_mul(self, x, y, t, trunc_bits=0, out=None):

@@ -1474,6 +1474,294 @@ mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing*
   return MPC_OK;
 }
 
+// ------------------------------------------------------------------ more than two parties
+}  // extern "C"
+
+namespace {
+
+mpc_status check_parties(int P) { return (P < 2 || P > kMaxParties) ? MPC_E_INVAL : MPC_OK; }
+
+MpKeys mp_keys(u64 seed, u64 tag, u64 base, int P) {
+  MpKeys k{};
+  for (int p = 0; p < P; ++p) k.k[p] = stream_key(seed, tag, base + (u64)p);
+  return k;
+}
+
+// Gathers a host array of P device pointers, each checked for n elements.
+mpc_status mp_out(uint64_t* const* v, int P, size_t n, MpOut* o) {
+  if (!v) return MPC_E_INVAL;
+  *o = MpOut{};
+  for (int p = 0; p < P; ++p) {
+    CHK(check_ptr(v[p], n));
+    o->p[p] = v[p];
+  }
+  return MPC_OK;
+}
+mpc_status mp_in(const uint64_t* const* v, int P, size_t n, MpIn* o) {
+  if (!v) return MPC_E_INVAL;
+  *o = MpIn{};
+  for (int p = 0; p < P; ++p) {
+    CHK(check_ptr(v[p], n));
+    o->p[p] = v[p];
+  }
+  return MPC_OK;
+}
+
+// outputs (P buffers of no) against each other and against every input set
+mpc_status mp_alias(const MpOut& out, int P, size_t no, std::initializer_list<std::pair<const MpIn*, size_t>> ins) {
+  for (int p = 0; p < P; ++p) {
+    for (int q = p + 1; q < P; ++q)
+      if (overlap(out.p[p], no, out.p[q], no)) return MPC_E_ALIAS;
+    for (const auto& in : ins) {
+      if (!in.first) continue;
+      for (int q = 0; q < P; ++q)
+        if (in.first->p[q] && overlap(out.p[p], no, in.first->p[q], in.second)) return MPC_E_ALIAS;
+    }
+  }
+  return MPC_OK;
+}
+
+MpIn as_in(const MpOut& o) {
+  MpIn i{};
+  for (int p = 0; p < kMaxParties; ++p) i.p[p] = o.p[p];
+  return i;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpc_status mpc_mp_share(mpc_ctx* c, int P, const uint64_t* x, size_t n, int src, uint64_t tag,
+                        uint64_t* const* s) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  if (src < 0 || src >= P) return MPC_E_INVAL;
+  CHK(check_ptr(x, n));
+  MpOut o;
+  CHK(mp_out(s, P, n, &o));
+  MpIn xi{};
+  xi.p[0] = x;
+  CHK(mp_alias(o, P, n, {{&xi, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_mp_share(c->s[0], x, n, P, src, mp_keys(c->seed, tag, kMpShare, P), o)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
+mpc_status mpc_mp_reveal(mpc_ctx* c, int P, const uint64_t* const* s, size_t n, uint64_t* out) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  MpIn in;
+  CHK(mp_in(s, P, n, &in));
+  CHK(check_ptr(out, n));
+  for (int p = 0; p < P; ++p)
+    if (overlap(out, n, in.p[p], n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_mp_reveal(c->s[0], in, P, n, out)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n;
+  return MPC_OK;
+}
+
+mpc_status mpc_mp_dealer_triples(mpc_ctx* c, int P, mpc_triple_kind kind, uint64_t dseed, uint64_t tag,
+                                 const int64_t* dims, const mpc_mp_triple* t) {
+  if (!c || !dims || !t) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  CHK(set_device(c));
+  const hipStream_t st = c->s[0];
+  const MpKeys ka = mp_keys(dseed, tag, kMpA, P), kb = mp_keys(dseed, tag, kMpB, P),
+               kc = mp_keys(dseed, tag, kMpC, P);
+  if (kind == MPC_TRIPLE_MUL || kind == MPC_TRIPLE_SQUARE) {
+    if (dims[0] < 0) return MPC_E_SHAPE;
+    const size_t n = (size_t)dims[0];
+    const bool sq = kind == MPC_TRIPLE_SQUARE;
+    MpOut a, b, cc{};
+    CHK(mp_out(t->a, P, n, &a));
+    CHK(mp_out(t->b, P, n, &b));
+    if (!sq) CHK(mp_out(t->c, P, n, &cc));
+    const MpIn bi = as_in(b), ci = as_in(cc);
+    CHK(mp_alias(a, P, n, {{&bi, n}, {sq ? nullptr : &ci, n}}));
+    if (!sq) CHK(mp_alias(b, P, n, {{&ci, n}}));
+    if (!n) return MPC_OK;
+    CHK(hip_status(launch_mp_dealer_mul(st, ka, kb, sq ? kb : kc, P, n, sq ? 1 : 0, a, b, cc)));
+    c->stats.launches++;
+    return end_call(c);
+  }
+  if (kind != MPC_TRIPLE_MATMUL) return MPC_E_UNSUPPORTED;
+  const i64 M = dims[0], N = dims[1], K = dims[2];
+  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
+  MpOut a, b, cc;
+  CHK(mp_out(t->a, P, na, &a));
+  CHK(mp_out(t->b, P, nb, &b));
+  CHK(mp_out(t->c, P, nc, &cc));
+  const MpIn bi = as_in(b), ci = as_in(cc);
+  CHK(mp_alias(a, P, na, {{&bi, nb}, {&ci, nc}}));
+  CHK(mp_alias(b, P, nb, {{&ci, nc}}));
+  if (!na && !nb && !nc) return MPC_OK;
+  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K);
+  // workspace: a = sum a_p, b = sum b_p, S = sum_{p<P-1} c_p, then the GEMM's packs
+  JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
+  size_t need = kAlign + align_up(na * 8) + align_up(nb * 8) + align_up(nc * 8);
+  if (form == MPC_FORM_LIMB8) need += job_bytes(ja) + job_bytes(jb);
+  CHK(ensure_ws(c, need));
+  Carve cv(c->ws);
+  u64* as = cv.take<u64>(na);
+  u64* bs = cv.take<u64>(nb);
+  u64* S = cv.take<u64>(nc);
+  CHK(hip_status(launch_mp_fill_sum(st, ka, P, na, a, as)));
+  CHK(hip_status(launch_mp_fill_sum(st, kb, P, nb, b, bs)));
+  CHK(hip_status(launch_mp_fill_sum(st, kc, P - 1, nc, cc, S)));
+  c->stats.launches += 3;
+  if (!nc) return end_call(c);
+  // c_{P-1} = a @ b - S
+  const Epilogue ep = make_ep(S, -1, 0, cc.p[P - 1], rowmajor_view(N));
+  if (form == MPC_FORM_LIMB8) {
+    set_mode(ja, kModeCopy, {as});
+    set_mode(jb, kModeCopy, {bs});
+    const PackJob PA = place_job(ja, cv), PB = place_job(jb, cv);
+    CHK(issue_limb(c, {PA, PB}, {limb_req(M, N, K, 0, PA.dst[0], nullptr, PB.dst[0], nullptr, ep)},
+                   c->sched_default));
+  } else {
+    CHK(issue_plain(c, {plain_problem(M, N, K, 0, as, nullptr, K, nullptr, 0, bs, nullptr, N, nullptr, 0, ep)}));
+  }
+  return end_call(c);
+}
+
+mpc_status mpc_mp_dealer_trunc(mpc_ctx* c, int P, uint64_t dseed, uint64_t tag, size_t n, uint64_t* const* r,
+                               uint64_t* const* theta_r) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  MpOut ro, to;
+  CHK(mp_out(r, P, n, &ro));
+  CHK(mp_out(theta_r, P, n, &to));
+  const MpIn ti = as_in(to);
+  CHK(mp_alias(ro, P, n, {{&ti, n}}));
+  CHK(mp_alias(to, P, n, {}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_mp_dealer_trunc(c->s[0], mp_keys(dseed, tag, kMpR, P), mp_keys(dseed, tag, kMpT, P), P,
+                                        n, ro, to)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
+mpc_status mpc_mp_beaver_mul(mpc_ctx* c, int P, size_t n, const uint64_t* const* x, const uint64_t* const* y,
+                             const mpc_mp_triple* t, uint64_t* const* z) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  const bool sq = y == nullptr;
+  MpIn xi, yi{}, ai, bi, ci{};
+  CHK(mp_in(x, P, n, &xi));
+  if (!sq) CHK(mp_in(y, P, n, &yi));
+  CHK(mp_in(t->a, P, n, &ai));
+  CHK(mp_in(t->b, P, n, &bi));
+  if (!sq) CHK(mp_in(t->c, P, n, &ci));
+  MpOut zo;
+  CHK(mp_out(z, P, n, &zo));
+  CHK(mp_alias(zo, P, n, {{&xi, n}, {sq ? nullptr : &yi, n}, {&ai, n}, {&bi, n}, {sq ? nullptr : &ci, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_mp_beaver_mul(c->s[0], xi, yi, ai, bi, ci, P, n, sq ? 1 : 0, zo)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n * (sq ? 1 : 2);
+  return MPC_OK;
+}
+
+mpc_status mpc_mp_beaver_matmul(mpc_ctx* c, int P, int64_t M, int64_t N, int64_t K, const uint64_t* const* x,
+                                const uint64_t* const* y, const mpc_mp_triple* t, mpc_form form,
+                                uint64_t* const* z) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  CHK(check_form(form));
+  if (form == MPC_FORM_FP64LIMB) return MPC_E_UNSUPPORTED;
+  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
+  MpIn xi, yi, ai, bi, ci;
+  CHK(mp_in(x, P, na, &xi));
+  CHK(mp_in(y, P, nb, &yi));
+  CHK(mp_in(t->a, P, na, &ai));
+  CHK(mp_in(t->b, P, nb, &bi));
+  CHK(mp_in(t->c, P, nc, &ci));
+  MpOut zo;
+  CHK(mp_out(z, P, nc, &zo));
+  CHK(mp_alias(zo, P, nc, {{&xi, na}, {&yi, nb}, {&ai, na}, {&bi, nb}, {&ci, nc}}));
+  if (!nc) return MPC_OK;
+  CHK(set_device(c));
+  form = resolve_form(form, M, N, 2 * K);
+  const hipStream_t st = c->s[0];
+  // open eps (MxK) and delta (KxN) into the workspace, then party p's finish
+  // z_p = c_p + [a_p + [p=0] eps | eps] @ [delta ; b_p]
+  size_t need = kAlign + align_up(na * 8) + align_up(nb * 8);
+  if (form == MPC_FORM_LIMB8)
+    need += (size_t)(P + 1) * align_up(packed_bytes(M, K)) + (size_t)(P + 1) * align_up(packed_bytes(N, K));
+  CHK(ensure_ws(c, need));
+  Carve cv(c->ws);
+  u64* eps = cv.take<u64>(na);
+  u64* del = cv.take<u64>(nb);
+  CHK(hip_status(launch_mp_open(st, xi, ai, P, na, eps)));
+  CHK(hip_status(launch_mp_open(st, yi, bi, P, nb, del)));
+  c->stats.launches += 2;
+  if (form == MPC_FORM_LIMB8) {
+    std::vector<PackJob> jobs;
+    JobSpec je = left_job(M, K, K), jd = right_job(K, N, N);
+    set_mode(je, kModeCopy, {eps});
+    set_mode(jd, kModeCopy, {del});
+    jobs.push_back(place_job(je, cv));
+    jobs.push_back(place_job(jd, cv));
+    std::vector<const uint8_t*> pa(P), pb(P);
+    for (int p = 0; p < P; ++p) {
+      JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
+      if (p == 0) set_mode(ja, kModeSum2, {ai.p[0], eps});
+      else set_mode(ja, kModeCopy, {ai.p[p]});
+      set_mode(jb, kModeCopy, {bi.p[p]});
+      jobs.push_back(place_job(ja, cv));
+      pa[p] = jobs.back().dst[0];
+      jobs.push_back(place_job(jb, cv));
+      pb[p] = jobs.back().dst[0];
+    }
+    std::vector<LimbReq> reqs;
+    for (int p = 0; p < P; ++p)
+      reqs.push_back(limb_req(M, N, K, K, pa[p], jobs[0].dst[0], jobs[1].dst[0], pb[p],
+                              make_ep(ci.p[p], +1, 0, zo.p[p], rowmajor_view(N))));
+    CHK(issue_limb(c, jobs, reqs, c->sched_default));
+  } else {
+    std::vector<PlainProblem> probs;
+    for (int p = 0; p < P; ++p)
+      probs.push_back(plain_problem(M, N, K, K, ai.p[p], p == 0 ? eps : nullptr, K, eps, K, del, nullptr, N,
+                                    bi.p[p], N, make_ep(ci.p[p], +1, 0, zo.p[p], rowmajor_view(N))));
+    CHK(issue_plain(c, probs));
+  }
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)(na + nb);
+  return end_call(c);
+}
+
+mpc_status mpc_mp_truncate(mpc_ctx* c, int P, size_t n, int bits, uint64_t* const* x, const uint64_t* const* r,
+                           const uint64_t* const* theta_r) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_parties(P));
+  if (bits < 1 || bits > 63) return MPC_E_INVAL;
+  MpOut xo;
+  MpIn ri, ti;
+  CHK(mp_out(x, P, n, &xo));
+  CHK(mp_in(r, P, n, &ri));
+  CHK(mp_in(theta_r, P, n, &ti));
+  CHK(mp_alias(xo, P, n, {{&ri, n}, {&ti, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_mp_truncate(c->s[0], xo, ri, ti, P, n, bits)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.truncations++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n;
+  return MPC_OK;
+}
+
 // ------------------------------------------------------------------ graphs
 mpc_status mpc_graph_begin(mpc_ctx* c) {
   if (!c || c->capturing) return MPC_E_INVAL;

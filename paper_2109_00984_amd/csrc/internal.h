@@ -30,6 +30,8 @@ __host__ __device__ __forceinline__ u64 sm_out(u64 s, u64 i) { return sm_mix(s +
 inline u64 stream_key(u64 seed, u64 tag, u64 slot) { return sm_out(sm_out(seed, tag), slot); }
 
 enum Slot : u64 { kSlotShare = 0, kSlotA0 = 1, kSlotA1 = 2, kSlotB0 = 3, kSlotB1 = 4, kSlotC0 = 5 };
+// Slots of sharings among P > 2 parties: base + party index.
+enum MpSlot : u64 { kMpShare = 0x100, kMpA = 0x200, kMpB = 0x300, kMpC = 0x400, kMpR = 0x500, kMpT = 0x600 };
 
 // ---------------------------------------------------------------- views
 // Element (m, n) of a GEMM output (and of its additive term) lives at
@@ -210,6 +212,32 @@ struct TileSched {
   int group_m;    // tile rows per raster group
   int xcd_remap;  // give each XCD a contiguous run of tiles
 };
+// ---------------------------------------------------------------- more than two parties
+constexpr int kMaxParties = 16;
+struct MpOut {
+  u64* p[kMaxParties];
+};
+struct MpIn {
+  const u64* p[kMaxParties];
+};
+struct MpKeys {
+  u64 k[kMaxParties];
+};
+hipError_t launch_mp_share(hipStream_t s, const u64* x, size_t n, int P, int src, const MpKeys& keys,
+                           const MpOut& out);
+hipError_t launch_mp_reveal(hipStream_t s, const MpIn& in, int P, size_t n, u64* out);
+hipError_t launch_mp_fill_sum(hipStream_t s, const MpKeys& keys, int cnt, size_t n, const MpOut& out,
+                              u64* sum);
+hipError_t launch_mp_dealer_mul(hipStream_t s, const MpKeys& ka, const MpKeys& kb, const MpKeys& ks, int P,
+                                size_t n, int square, const MpOut& a, const MpOut& b, const MpOut& c);
+hipError_t launch_mp_open(hipStream_t s, const MpIn& x, const MpIn& a, int P, size_t n, u64* eps);
+hipError_t launch_mp_beaver_mul(hipStream_t s, const MpIn& x, const MpIn& y, const MpIn& a, const MpIn& b,
+                                const MpIn& c, int P, size_t n, int square, const MpOut& z);
+hipError_t launch_mp_dealer_trunc(hipStream_t s, const MpKeys& kr, const MpKeys& kt, int P, size_t n,
+                                  const MpOut& r, const MpOut& t);
+hipError_t launch_mp_truncate(hipStream_t s, const MpOut& x, const MpIn& r, const MpIn& t, int P, size_t n,
+                              int bits);
+
 // ---------------------------------------------------------------- fp64 limb form
 // The paper's GPU form of the ring GEMM: L fp64 limb planes per operand (L = 3
 // of 22 bits when the concatenated k is below kFp64Limb22MaxK, else L = 4 of
