@@ -286,6 +286,17 @@ struct LaunchTimer {
 
 OutView rowmajor_view(i64 N) { return OutView{N, std::max<i64>(N, 1), 0}; }
 
+Epilogue make_ep(const u64* cadd, int csign, int trunc, u64* out, OutView v) {
+  Epilogue e{};
+  e.Cadd = cadd;
+  e.csign = csign;
+  e.trunc_bits = trunc;
+  e.accumulate = 0;
+  e.Out = out;
+  e.view = v;
+  return e;
+}
+
 mpc_form resolve_form(mpc_form f, i64 M, i64 N, i64 K) {
   if (f != MPC_FORM_AUTO) return f;
   const double work = (double)M * (double)N * (double)K;
@@ -304,6 +315,24 @@ size_t packed_bytes(i64 rows, i64 K) {
 // during capture (the launch then runs unsplit).
 constexpr i64 kPlainMinSlice = 128;
 
+// Makes the split-K partial buffer at least `bytes` large; false when it
+// would have to move while a graph is being captured or still refers to it
+// (the caller then runs unsplit).
+bool ensure_splitk(mpc_ctx* c, size_t bytes) {
+  if (bytes <= c->splitk_cap) return true;
+  if (c->capturing || c->live_graphs > 0) return false;
+  if (sync_all(c) != MPC_OK) return false;
+  if (c->splitk) (void)hipFree(c->splitk);
+  c->splitk = nullptr;
+  c->splitk_cap = 0;
+  if (hipMalloc(&c->splitk, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  c->splitk_cap = bytes;
+  return true;
+}
+
 mpc_status plan_splitk(mpc_ctx* c, std::vector<PlainProblem>& probs) {
   i64 tiles = 0;
   for (const PlainProblem& p : probs) tiles += plain_tiles(p.M, p.N);
@@ -317,18 +346,9 @@ mpc_status plan_splitk(mpc_ctx* c, std::vector<PlainProblem>& probs) {
       if (ks[q] > 1) need += align_up((size_t)(ks[q] * probs[q].M * probs[q].N) * 8);
     }
   }
-  if (need > c->splitk_cap) {
-    if (c->capturing || c->live_graphs > 0) {
-      need = 0;
-      std::fill(ks.begin(), ks.end(), 1);
-    } else {
-      CHK(sync_all(c));
-      if (c->splitk) HIPCHK(hipFree(c->splitk));
-      c->splitk = nullptr;
-      c->splitk_cap = 0;
-      HIPCHK(hipMalloc(&c->splitk, need));
-      c->splitk_cap = need;
-    }
+  if (need && !ensure_splitk(c, need)) {
+    need = 0;
+    std::fill(ks.begin(), ks.end(), 1);
   }
   size_t off = 0;
   for (size_t q = 0; q < probs.size(); ++q) {
@@ -373,7 +393,8 @@ mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs_in) {
   CHK(hip_status(launch_plain_gemm(c->s[0], (const PlainProblem*)(dev + oprob), map, tstart[n])));
   for (size_t q = 0; q < n; ++q) {
     if (probs[q].ksplit <= 1) continue;
-    CHK(hip_status(launch_plain_reduce(c->s[0], (const PlainProblem*)(dev + oprob) + q, probs[q].M, probs[q].N)));
+    CHK(hip_status(launch_splitk_reduce(c->s[0], probs[q].partial, probs[q].ksplit, probs[q].M, probs[q].N,
+                                        probs[q].ep)));
     c->stats.launches++;
   }
   CHK(tm.stop());
@@ -580,30 +601,64 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   }
   const size_t ojobs = blob.add(jobs.data(), nj);
 
-  int max_chunks = 0;
-  std::vector<int> nchunks(nreq);
+  // K pieces per request.  The int32 bound needs kbt / kLimbMaxKBlocks chunks,
+  // run as consecutive launches that add into the output.  When the whole
+  // launch has fewer tiles than compute units, k is instead cut into slices
+  // (at least that many) that run side by side in one launch, each writing
+  // its raw sum to a partial buffer; a reduction adds them and applies the
+  // epilogue (split-K).
+  std::vector<int> nchunks(nreq), nslices(nreq, 1);
+  i64 tiles_all = 0;
   for (size_t q = 0; q < nreq; ++q) {
     const int kbt = (int)(limb_kblocks(reqs[q].K0) + limb_kblocks(reqs[q].K1));
     nchunks[q] = std::max(1, (kbt + kLimbMaxKBlocks - 1) / kLimbMaxKBlocks);
-    max_chunks = std::max(max_chunks, nchunks[q]);
+    tiles_all += limb_tiles(reqs[q].M, reqs[q].N, sched.variant);
   }
-  std::vector<size_t> oprob(max_chunks), otile(max_chunks);
-  std::vector<int> ttotal(max_chunks, 0), tcount(max_chunks, 0);
-  std::vector<double> cmacs(max_chunks, 0.0);
-  for (int ch = 0; ch < max_chunks; ++ch) {
-    std::vector<LimbProblem> probs;
-    std::vector<int> tstart(1, 0);
+  size_t part_bytes = 0;
+  if (tiles_all > 0 && tiles_all < c->num_cu) {
+    const i64 want = (2 * (i64)c->num_cu + tiles_all - 1) / tiles_all;
     for (size_t q = 0; q < nreq; ++q) {
-      if (ch >= nchunks[q]) continue;
-      const LimbReq& r = reqs[q];
+      const i64 steps = (limb_kblocks(reqs[q].K0) + limb_kblocks(reqs[q].K1)) / 2;
+      const i64 sl = std::max<i64>(nchunks[q], std::min<i64>(want, steps / kLimbMinSliceSteps));
+      if (sl > 1) {
+        nslices[q] = (int)sl;
+        part_bytes += align_up((size_t)(sl * reqs[q].M * reqs[q].N) * 8);
+      }
+    }
+    if (part_bytes && !ensure_splitk(c, part_bytes)) {
+      part_bytes = 0;
+      std::fill(nslices.begin(), nslices.end(), 1);
+    }
+  }
+  // piece lists per launch
+  int nlaunch = 1;
+  for (size_t q = 0; q < nreq; ++q)
+    if (nslices[q] == 1) nlaunch = std::max(nlaunch, nchunks[q]);
+  std::vector<std::vector<LimbProblem>> pieces(nlaunch);
+  std::vector<std::vector<int>> tstarts(nlaunch, std::vector<int>(1, 0));
+  std::vector<double> cmacs(nlaunch, 0.0);
+  struct Reduce {
+    const u64* partial;
+    int ks;
+    i64 M, N;
+    Epilogue ep;
+  };
+  std::vector<Reduce> reduces;
+  size_t part_off = 0;
+  for (size_t q = 0; q < nreq; ++q) {
+    const LimbReq& r = reqs[q];
+    const int kb0 = (int)limb_kblocks(r.K0), kb1 = (int)limb_kblocks(r.K1), kbt = kb0 + kb1;
+    auto true_k = [&](i64 kb) {
+      return kb <= kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - kb0) * 32, r.K1);
+    };
+    auto piece = [&](int launch, int kb_begin, int kb_end, const Epilogue& ep) -> mpc_status {
       LimbProblem p{};
       p.M = r.M;
       p.N = r.N;
-      p.kb0 = (int)limb_kblocks(r.K0);
-      p.kb1 = (int)limb_kblocks(r.K1);
-      const int kbt = p.kb0 + p.kb1;
-      p.kb_begin = std::min(kbt, ch * kLimbMaxKBlocks);
-      p.kb_end = std::min(kbt, (ch + 1) * kLimbMaxKBlocks);
+      p.kb0 = kb0;
+      p.kb1 = kb1;
+      p.kb_begin = kb_begin;
+      p.kb_end = kb_end;
       // the GEMM steps over pairs of k-blocks inside one segment
       if ((p.kb0 | p.kb1 | p.kb_begin | p.kb_end) & 1) return MPC_E_INVAL;
       p.PA0 = r.PA0;
@@ -612,24 +667,38 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       p.PB1 = r.PB1;
       p.mblocks = limb_rblocks(r.M);
       p.nblocks = limb_rblocks(r.N);
-      p.ep = r.ep;
-      if (ch > 0) {
-        p.ep.accumulate = 1;
-        p.ep.Cadd = nullptr;
+      p.ep = ep;
+      pieces[launch].push_back(p);
+      tstarts[launch].push_back(tstarts[launch].back() + limb_tiles(r.M, r.N, sched.variant));
+      cmacs[launch] += (double)r.M * (double)r.N * (double)(true_k(kb_end) - true_k(kb_begin));
+      return MPC_OK;
+    };
+    if (nslices[q] > 1) {
+      const int ks = nslices[q];
+      const i64 steps = kbt / 2;
+      u64* part = (u64*)(c->splitk + part_off);
+      part_off += align_up((size_t)(ks * r.M * r.N) * 8);
+      for (int sl = 0; sl < ks; ++sl) {
+        const int b0 = (int)(2 * (steps * sl / ks)), b1 = (int)(2 * (steps * (sl + 1) / ks));
+        CHK(piece(0, b0, b1, make_ep(nullptr, +1, 0, part + (size_t)sl * (size_t)(r.M * r.N), rowmajor_view(r.N))));
       }
-      if (ch + 1 < nchunks[q]) p.ep.trunc_bits = 0;
-      probs.push_back(p);
-      tstart.push_back(tstart.back() + limb_tiles(r.M, r.N, sched.variant));
-      // true (unpadded) k values this chunk covers, for the timing record
-      auto true_k = [&](i64 kb) {
-        return kb <= p.kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - p.kb0) * 32, r.K1);
-      };
-      cmacs[ch] += (double)r.M * (double)r.N * (double)(true_k(p.kb_end) - true_k(p.kb_begin));
+      reduces.push_back(Reduce{part, ks, r.M, r.N, r.ep});
+    } else {
+      for (int ch = 0; ch < nchunks[q]; ++ch) {
+        Epilogue ep = r.ep;
+        if (ch > 0) {
+          ep.accumulate = 1;
+          ep.Cadd = nullptr;
+        }
+        if (ch + 1 < nchunks[q]) ep.trunc_bits = 0;
+        CHK(piece(ch, std::min(kbt, ch * kLimbMaxKBlocks), std::min(kbt, (ch + 1) * kLimbMaxKBlocks), ep));
+      }
     }
-    oprob[ch] = blob.add(probs.data(), probs.size());
-    otile[ch] = blob.add(tstart.data(), tstart.size());
-    ttotal[ch] = tstart.back();
-    tcount[ch] = (int)probs.size();
+  }
+  std::vector<size_t> oprob(nlaunch), otile(nlaunch);
+  for (int L = 0; L < nlaunch; ++L) {
+    oprob[L] = blob.add(pieces[L].data(), pieces[L].size());
+    otile[L] = blob.add(tstarts[L].data(), tstarts[L].size());
   }
   uint8_t* dev = nullptr;
   CHK(upload(c, blob, &dev));
@@ -639,12 +708,17 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
                                njl, nblocks[L], launch_km[L].first, launch_km[L].second)));
     c->stats.launches++;
   }
-  for (int ch = 0; ch < max_chunks; ++ch) {
-    TileMap map{tcount[ch], (const int*)(dev + otile[ch])};
-    LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[ch]);
+  for (int L = 0; L < nlaunch; ++L) {
+    if (pieces[L].empty()) continue;
+    TileMap map{(int)pieces[L].size(), (const int*)(dev + otile[L])};
+    LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[L]);
     CHK(tm.start());
-    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[ch]), map, ttotal[ch], sched)));
+    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[L]), map, tstarts[L].back(), sched)));
     CHK(tm.stop());
+    c->stats.launches++;
+  }
+  for (const Reduce& rd : reduces) {
+    CHK(hip_status(launch_splitk_reduce(st, rd.partial, rd.ks, rd.M, rd.N, rd.ep)));
     c->stats.launches++;
   }
   c->stats.gemm_problems += nreq;
@@ -663,16 +737,6 @@ mpc_status check_form(mpc_form f) {
              : MPC_E_INVAL;
 }
 
-Epilogue make_ep(const u64* cadd, int csign, int trunc, u64* out, OutView v) {
-  Epilogue e{};
-  e.Cadd = cadd;
-  e.csign = csign;
-  e.trunc_bits = trunc;
-  e.accumulate = 0;
-  e.Out = out;
-  e.view = v;
-  return e;
-}
 
 i64 conv_lout(const mpc_conv1d_shape& s) {
   return s.length < s.ksize ? 0 : (s.length - s.ksize) / s.stride + 1;

@@ -162,14 +162,12 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 __global__ void __launch_bounds__(kThreads)
-    k_plain_reduce(const PlainProblem* __restrict__ prob) {
-  const PlainProblem& p = *prob;
-  const i64 total = p.M * p.N;
-  const Epilogue& ep = p.ep;
+    k_splitk_reduce(const u64* __restrict__ partial, int ks, i64 M, i64 N, Epilogue ep) {
+  const i64 total = M * N;
   for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
     u64 v = 0;
-    for (int s = 0; s < p.ksplit; ++s) v += p.partial[s * total + e];
-    const i64 m = e / p.N, n = e % p.N;
+    for (int s = 0; s < ks; ++s) v += partial[s * total + e];
+    const i64 m = e / N, n = e % N;
     const i64 off = m * ep.view.ld_m + (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
     if (ep.accumulate) v += ep.Out[off];
     if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
@@ -180,11 +178,12 @@ __global__ void __launch_bounds__(kThreads)
 
 }  // namespace
 
-hipError_t launch_plain_reduce(hipStream_t s, const PlainProblem* prob_dev, i64 M, i64 N) {
+hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M, i64 N, const Epilogue& ep) {
   const i64 total = M * N;
   if (total <= 0) return hipSuccess;
   const i64 b = (total + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_plain_reduce, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(kThreads), 0, s, prob_dev);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(kThreads), 0, s, partial, ks, M,
+                     N, ep);
   return hipGetLastError();
 }
 

@@ -140,6 +140,8 @@ struct LimbProblem {
 // limbs -128 a diagonal of 8 pairs adds 8 * 2^14 per k, so 16320 * 2^17 < 2^31.
 // (Even, so chunk boundaries fall between the GEMM's 64-wide k steps.)
 constexpr int kLimbMaxKBlocks = 510;  // 510 * 32 = 16320
+// Smallest split-K slice of the limb GEMM, in 64-wide k steps.
+constexpr int kLimbMinSliceSteps = 4;
 static_assert(kLimbMaxKBlocks % 2 == 0, "chunks must hold whole k steps");
 
 // Tile-to-problem table for grouped launches.
@@ -196,8 +198,9 @@ hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap m
                              int total_tiles);
 int plain_tiles(i64 M, i64 N);
 constexpr int kPlainBK = 16;  // k tile of the plain GEMM (split-K slices are multiples)
-// sum of the ksplit partial results of one split problem, then its epilogue
-hipError_t launch_plain_reduce(hipStream_t s, const PlainProblem* prob_dev, i64 M, i64 N);
+// Split-K reduction shared by both GEMM forms: v = sum of the ks partial
+// M x N results (partial[slice][M][N]), then the epilogue.
+hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M, i64 N, const Epilogue& ep);
 
 // Limb form (gemm_limb.hip).
 // jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kMpThreads)
 
 unsigned grid_for(size_t n) {
   const size_t b = (n + kMpThreads - 1) / kMpThreads;
-  return (unsigned)(b < 1 ? 1 : b > 8192 ? 8192 : b);
+  return (unsigned)(b < 1 ? 1 : b > 65536 ? 65536 : b);
 }
 
 }  // namespace

@@ -259,13 +259,14 @@ def test_beaver_conv1d(m, ctx, form, Bt, Cin, L, Cout, k, s):
 
 
 # ------------------------------------------------------------------ graph capture
-def test_graph_replay_matches_eager(m):
-    # capture needs a non-null stream for party 0: run this test on its own stream
-    say("graph replay")
+@pytest.mark.parametrize("M,N,K", [(96, 64, 160), (128, 64, 2048)])
+def test_graph_replay_matches_eager(m, M, N, K):
+    # capture needs a non-null stream for party 0: run this test on its own
+    # stream.  The second shape has few tiles and a long k (split-K inside).
+    say(f"graph replay {M}x{N}x{K}")
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         c = m.Context(device=0, seed=SEED)
-        M, N, K = 96, 64, 160
         X, Y = rnd(3, (M, K)), rnd(4, (K, N))
         gx, gy = c.share(dev(X), 0, 81), c.share(dev(Y), 0, 82)
         t = c.dealer(m.TRIPLE_MATMUL, 2, 80, (M, N, K))
@@ -369,27 +370,30 @@ def test_autotune_grouped_and_cache(m, tmp_path):
 
 
 # ------------------------------------------------------------------ plain split-K
-@pytest.mark.parametrize("M,N,K", [(5, 7, 5000), (128, 10, 2048), (1, 1, 3000), (130, 70, 777)])
-def test_ring_gemm_plain_split_k(m, ctx, M, N, K):
-    # few output tiles and a long k: the plain launch splits k into slices
-    say(f"ring gemm plain split-k {M}x{N}x{K}")
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("M,N,K", [(5, 7, 5000), (128, 10, 2048), (1, 1, 3000), (130, 70, 777),
+                                   (128, 1024, 1568), (40, 24, 20000)])
+def test_ring_gemm_split_k(m, ctx, form, M, N, K):
+    # few output tiles and a long k: the launch splits k into slices
+    say(f"ring gemm {form} split-k {M}x{N}x{K}")
     A, B = rnd(M + 3 * K, (M, K)), rnd(N + 5 * K, (K, N))
-    C = ctx.ring_gemm(dev(A), dev(B), form="plain")
+    C = ctx.ring_gemm(dev(A), dev(B), form=form)
     assert np.array_equal(host(ctx, C), oracle.ring_gemm(A, B))
 
 
+@pytest.mark.parametrize("form", ["plain", "limb8"])
 @pytest.mark.parametrize("trunc", [0, 16])
-def test_beaver_matmul_plain_split_k(m, ctx, trunc):
+def test_beaver_matmul_split_k(m, ctx, form, trunc):
     # the MLP's last layer shape: 128 x 10 outputs over 2 x 1024 concatenated k
     M, N, K = 128, 10, 1024
-    say(f"beaver matmul plain split-k trunc={trunc}")
+    say(f"beaver matmul {form} split-k trunc={trunc}")
     X = oracle.encode(workloads.uniform(91, (M, K), -1, 1))
     Y = oracle.encode(workloads.uniform(92, (K, N), -1, 1))
     xs, ys = oracle.share(X, 0, SEED, 93), oracle.share(Y, 1, SEED, 94)
     t = ctx.dealer(m.TRIPLE_MATMUL, 3002, 95, (M, N, K))
-    z = ctx.beaver_matmul(ctx.share(dev(X), 0, 93), ctx.share(dev(Y), 1, 94), t, trunc, "plain")
+    z = ctx.beaver_matmul(ctx.share(dev(X), 0, 93), ctx.share(dev(Y), 1, 94), t, trunc, form)
     want = oracle.beaver_matmul(xs, ys, oracle.dealer_matmul(3002, 95, M, N, K), trunc)
-    assert_pair(ctx, z, want, "beaver matmul plain split-k")
+    assert_pair(ctx, z, want, f"beaver matmul {form} split-k")
 
 
 def test_live_graph_pins_workspace(m):
