@@ -73,6 +73,14 @@ def lib():
                                      + [INT, I64, i64p, i64p, i64p, u64p, u64p]),
             "orc_limbs": (None, [u64p, SZ, i8p]),
             "orc_limb_gemm": (INT, [I64, I64, I64, u64p, u64p, I64, u64p]),
+            "orc_bin_share": (None, [u64p, SZ, INT, U64, U64, u64p, u64p]),
+            "orc_bin_reveal": (None, [u64p, u64p, SZ, u64p]),
+            "orc_dealer_and": (None, [U64, U64, SZ] + [u64p] * 6),
+            "orc_bin_and": (None, [SZ] + [u64p] * 12),
+            "orc_a2b": (None, [SZ, u64p, u64p, U64, U64, u64pp, u64p, u64p]),
+            "orc_dealer_b2a": (None, [U64, U64, SZ] + [u64p] * 4),
+            "orc_b2a_bit": (None, [SZ, INT] + [u64p] * 8),
+            "orc_relu": (None, [SZ, u64p, u64p, U64, U64, u64pp] + [u64p] * 12),
             "orc_mp_share": (None, [u64p, SZ, INT, INT, U64, U64, u64pp]),
             "orc_mp_reveal": (None, [INT, u64pp, SZ, u64p]),
             "orc_mp_dealer_mul": (None, [U64, U64, INT, SZ, INT, u64pp, u64pp, u64pp]),
@@ -491,3 +499,79 @@ def mp_truncate(x, bits, r, t):
     t = [np.ascontiguousarray(v, dtype=np.uint64).ravel() for v in t]
     lib().orc_mp_truncate(P, out[0].size, bits, _pp(out), _pp(r), _pp(t))
     return [o.reshape(np.shape(x[0])) for o in out]
+
+
+# ----------------------------------------------------------------- binary sharing (two parties)
+A2B_TRIPLES = 12
+
+
+def bin_share(x, src, seed, tag):
+    x, px = _u(x)
+    s0, p0 = _out(x.shape)
+    s1, p1 = _out(x.shape)
+    lib().orc_bin_share(px, x.size, src, seed, tag, p0, p1)
+    return s0, s1
+
+
+def bin_reveal(s0, s1):
+    (a, pa), (b, pb) = _u(s0), _u(s1)
+    out, po = _out(a.shape)
+    lib().orc_bin_reveal(pa, pb, a.size, po)
+    return out
+
+
+def dealer_and(dseed, tag, n):
+    """n bitwise AND triples (a, b, c = a & b), XOR-shared."""
+    bufs = [_out(n) for _ in range(6)]
+    lib().orc_dealer_and(dseed, tag, n, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
+
+
+def bin_and(x, y, t):
+    args = [_u(v) for v in (x[0], x[1], y[0], y[1], t.a[0], t.a[1], t.b[0], t.b[1], t.c[0], t.c[1])]
+    z0, p0 = _out(args[0][0].shape)
+    z1, p1 = _out(args[0][0].shape)
+    lib().orc_bin_and(args[0][0].size, *[p for _, p in args], p0, p1)
+    return z0, z1
+
+
+def _tr6(t):
+    arrs = [np.ascontiguousarray(v, dtype=np.uint64) for v in (t.a[0], t.a[1], t.b[0], t.b[1], t.c[0], t.c[1])]
+    return arrs, _pp(arrs)
+
+
+def a2b(x, seed, tag, t):
+    """Arithmetic to binary sharing; t holds A2B_TRIPLES * n AND triples ([12][n] layout)."""
+    (x0, px0), (x1, px1) = _u(x[0]), _u(x[1])
+    arrs, pp = _tr6(t)
+    z0, p0 = _out(x0.shape)
+    z1, p1 = _out(x0.shape)
+    lib().orc_a2b(x0.size, px0, px1, seed, tag, pp, p0, p1)
+    return z0, z1
+
+
+def dealer_b2a(dseed, tag, n):
+    """Algorithm 2's random bits: (<r>_0, <r>_1), ([r]_0, [r]_1)."""
+    bufs = [_out(n) for _ in range(4)]
+    lib().orc_dealer_b2a(dseed, tag, n, *[p for _, p in bufs])
+    rb0, rb1, ra0, ra1 = [b for b, _ in bufs]
+    return (rb0, rb1), (ra0, ra1)
+
+
+def b2a_bit(b, bit, rb, ra):
+    args = [_u(v) for v in (b[0], b[1], rb[0], rb[1], ra[0], ra[1])]
+    z0, p0 = _out(args[0][0].shape)
+    z1, p1 = _out(args[0][0].shape)
+    lib().orc_b2a_bit(args[0][0].size, bit, *[p for _, p in args], p0, p1)
+    return z0, z1
+
+
+def relu(x, seed, tag, t, rb, ra, tm):
+    (x0, px0), (x1, px1) = _u(x[0]), _u(x[1])
+    arrs, pp = _tr6(t)
+    rest = [_u(v) for v in (rb[0], rb[1], ra[0], ra[1], tm.a[0], tm.a[1], tm.b[0], tm.b[1], tm.c[0], tm.c[1])]
+    z0, p0 = _out(x0.shape)
+    z1, p1 = _out(x0.shape)
+    lib().orc_relu(x0.size, px0, px1, seed, tag, pp, *[p for _, p in rest], p0, p1)
+    return z0, z1

@@ -723,3 +723,165 @@ void orc_mp_truncate(int P, size_t n, int bits, u64 *const *x, const u64 *const 
   }
   for (int p = 0; p < P; ++p) free(zs[p]);
 }
+
+/* ======================================================================== */
+/* Binary sharing (App. C.1.1, Binary Secret Sharing; Converting Between     */
+/* Secret-Sharing Types; Logic-based Operations), two parties.  A binary     */
+/* sharing holds 64 independent bits per word: x = <x>_0 XOR <x>_1.          */
+/* PRG slots: 0x700 share, 0x701-0x705 AND triple (a0, a1, b0, b1, c0),      */
+/* 0x706/0x707 the parties' re-sharing in A2B, 0x708-0x70a the B2A bit.      */
+/* ======================================================================== */
+enum {
+  BIN_SHARE = 0x700, BIN_A0 = 0x701, BIN_A1 = 0x702, BIN_B0 = 0x703, BIN_B1 = 0x704, BIN_C0 = 0x705,
+  A2B_Y0 = 0x706, A2B_Y1 = 0x707, B2A_R = 0x708, B2A_RB0 = 0x709, B2A_RA0 = 0x70a
+};
+#define A2B_TRIPLES 12
+
+/* Sharing: XOR zero-share (m, m); the source party XORs its value in. */
+void orc_bin_share(const u64 *x, size_t n, int src, u64 seed, u64 tag, u64 *s0, u64 *s1) {
+  for (size_t i = 0; i < n; ++i) {
+    const u64 m = orc_prg(seed, tag, BIN_SHARE, (u64)i);
+    s0[i] = src == 0 ? x[i] ^ m : m;
+    s1[i] = src == 1 ? x[i] ^ m : m;
+  }
+}
+
+void orc_bin_reveal(const u64 *s0, const u64 *s1, size_t n, u64 *out) {
+  for (size_t i = 0; i < n; ++i) out[i] = s0[i] ^ s1[i];
+}
+
+/* Dealer of bitwise AND triples: a_p, b_p random words, c = a AND b shared as
+ * c0 = G, c1 = c XOR c0. */
+void orc_dealer_and(u64 dseed, u64 tag, size_t n, u64 *a0, u64 *a1, u64 *b0, u64 *b1, u64 *c0, u64 *c1) {
+  for (size_t i = 0; i < n; ++i) {
+    a0[i] = orc_prg(dseed, tag, BIN_A0, (u64)i);
+    a1[i] = orc_prg(dseed, tag, BIN_A1, (u64)i);
+    b0[i] = orc_prg(dseed, tag, BIN_B0, (u64)i);
+    b1[i] = orc_prg(dseed, tag, BIN_B1, (u64)i);
+    c0[i] = orc_prg(dseed, tag, BIN_C0, (u64)i);
+    c1[i] = ((a0[i] ^ a1[i]) & (b0[i] ^ b1[i])) ^ c0[i];
+  }
+}
+
+/* Bitwise AND (App. C.1.1, Bitwise AND): eps = x XOR a, delta = y XOR b are
+ * opened; <z>_p = <c>_p ^ (eps & <b>_p) ^ (<a>_p & delta) (^ eps & delta for
+ * party 0). */
+void orc_bin_and(size_t n, const u64 *x0, const u64 *x1, const u64 *y0, const u64 *y1, const u64 *a0,
+                 const u64 *a1, const u64 *b0, const u64 *b1, const u64 *c0, const u64 *c1, u64 *z0,
+                 u64 *z1) {
+  for (size_t i = 0; i < n; ++i) {
+    const u64 eps = (x0[i] ^ a0[i]) ^ (x1[i] ^ a1[i]);
+    const u64 del = (y0[i] ^ b0[i]) ^ (y1[i] ^ b1[i]);
+    z0[i] = c0[i] ^ (eps & b0[i]) ^ (a0[i] & del) ^ (eps & del);
+    z1[i] = c1[i] ^ (eps & b1[i]) ^ (a1[i] & del);
+  }
+}
+
+/* One AND of two binary sharings held in local arrays, with triple t of a
+ * [A2B_TRIPLES][n] triple buffer. */
+static void a2b_and(size_t n, size_t t, const u64 *x0, const u64 *x1, const u64 *y0, const u64 *y1,
+                    const u64 *const *tr, u64 *z0, u64 *z1) {
+  const size_t o = t * n;
+  orc_bin_and(n, x0, x1, y0, y1, tr[0] + o, tr[1] + o, tr[2] + o, tr[3] + o, tr[4] + o, tr[5] + o, z0, z1);
+}
+
+/* Arithmetic to binary (App. C.1.1, From [x] to <x>): each party binary-shares
+ * its arithmetic share (party p is the source of <y_p>), and the parties add
+ * <y_0> + <y_1> with a carry-lookahead (Kogge-Stone) adder over binary shares:
+ *   G = y0 AND y1, P = y0 XOR y1 (the per-bit generate and propagate);
+ *   for k = 1, 2, 4, ..., 32:  G <- G XOR (P AND (G << k)),  P <- P AND (P << k)
+ *   (the two terms of the group-generate OR never both hold, so XOR is OR;
+ *   the last level's P is not needed), then x = (y0 XOR y1) XOR (G << 1).
+ * tr: six pointers (a0, a1, b0, b1, c0, c1), each [A2B_TRIPLES][n] words. */
+void orc_a2b(size_t n, const u64 *x0, const u64 *x1, u64 seed, u64 tag, const u64 *const *tr, u64 *z0, u64 *z1) {
+  const size_t cnt = n ? n : 1;
+  u64 *y00 = calloc(cnt, sizeof(u64)), *y01 = calloc(cnt, sizeof(u64)), *y10 = calloc(cnt, sizeof(u64)), *y11 = calloc(cnt, sizeof(u64));
+  u64 *g0 = calloc(cnt, sizeof(u64)), *g1 = calloc(cnt, sizeof(u64)), *p0 = calloc(cnt, sizeof(u64)), *p1 = calloc(cnt, sizeof(u64));
+  u64 *s0 = calloc(cnt, sizeof(u64)), *s1 = calloc(cnt, sizeof(u64)), *t0 = calloc(cnt, sizeof(u64)), *t1 = calloc(cnt, sizeof(u64));
+  u64 *q0 = calloc(cnt, sizeof(u64)), *q1 = calloc(cnt, sizeof(u64));
+  /* <y_0> = (x0 ^ m0, m0), <y_1> = (m1, x1 ^ m1) */
+  for (size_t i = 0; i < n; ++i) {
+    const u64 m0 = orc_prg(seed, tag, A2B_Y0, (u64)i), m1 = orc_prg(seed, tag, A2B_Y1, (u64)i);
+    y00[i] = x0[i] ^ m0;
+    y01[i] = m0;
+    y10[i] = m1;
+    y11[i] = x1[i] ^ m1;
+  }
+  size_t t = 0;
+  a2b_and(n, t++, y00, y01, y10, y11, tr, g0, g1);
+  for (size_t i = 0; i < n; ++i) {
+    p0[i] = y00[i] ^ y10[i];
+    p1[i] = y01[i] ^ y11[i];
+  }
+  for (int k = 1; k < 64; k <<= 1) {
+    for (size_t i = 0; i < n; ++i) {
+      s0[i] = g0[i] << k;
+      s1[i] = g1[i] << k;
+    }
+    a2b_and(n, t++, p0, p1, s0, s1, tr, t0, t1); /* P AND (G << k) */
+    if (k < 32) {
+      for (size_t i = 0; i < n; ++i) {
+        s0[i] = p0[i] << k;
+        s1[i] = p1[i] << k;
+      }
+      a2b_and(n, t++, p0, p1, s0, s1, tr, q0, q1); /* P AND (P << k) */
+    }
+    for (size_t i = 0; i < n; ++i) {
+      g0[i] ^= t0[i];
+      g1[i] ^= t1[i];
+      if (k < 32) {
+        p0[i] = q0[i];
+        p1[i] = q1[i];
+      }
+    }
+  }
+  for (size_t i = 0; i < n; ++i) {
+    z0[i] = (y00[i] ^ y10[i]) ^ (g0[i] << 1);
+    z1[i] = (y01[i] ^ y11[i]) ^ (g1[i] << 1);
+  }
+  free(y00); free(y01); free(y10); free(y11); free(g0); free(g1); free(p0); free(p1);
+  free(s0); free(s1); free(t0); free(t1); free(q0); free(q1);
+}
+
+/* Dealer of Algorithm 2's random bit: r in {0, 1} shared both ways,
+ * <r> = (w, w XOR r) and [r] = (v, r - v). */
+void orc_dealer_b2a(u64 dseed, u64 tag, size_t n, u64 *rb0, u64 *rb1, u64 *ra0, u64 *ra1) {
+  for (size_t i = 0; i < n; ++i) {
+    const u64 r = orc_prg(dseed, tag, B2A_R, (u64)i) & 1;
+    rb0[i] = orc_prg(dseed, tag, B2A_RB0, (u64)i);
+    rb1[i] = rb0[i] ^ r;
+    ra0[i] = orc_prg(dseed, tag, B2A_RA0, (u64)i);
+    ra1[i] = r - ra0[i];
+  }
+}
+
+/* Binary to arithmetic for bit `bit` of <b> (Algorithm 2): <z> = <b> XOR <r>
+ * on that bit, z = reveal(<z>), [b] = [r] + z - 2 [r] z (z added by party 0). */
+void orc_b2a_bit(size_t n, int bit, const u64 *b0, const u64 *b1, const u64 *rb0, const u64 *rb1,
+                 const u64 *ra0, const u64 *ra1, u64 *z0, u64 *z1) {
+  for (size_t i = 0; i < n; ++i) {
+    const u64 zb = ((((b0[i] >> bit) ^ rb0[i]) ^ ((b1[i] >> bit) ^ rb1[i])) & 1);
+    z0[i] = ra0[i] + zb - 2 * ra0[i] * zb;
+    z1[i] = ra1[i] - 2 * ra1[i] * zb;
+  }
+}
+
+/* ReLU (App. C.1.1, Sign, absolute value, and ReLU): [x < 0] is the sign bit
+ * of <x> = A2B([x]) converted by Algorithm 2; ReLU([x]) = [x] * (1 - [x < 0])
+ * with one Beaver product (no truncation: the factor is an integer 0/1).
+ * tr: the A2B triples; (rb, ra): the B2A bit; (ma..mc): a MUL triple. */
+void orc_relu(size_t n, const u64 *x0, const u64 *x1, u64 seed, u64 tag, const u64 *const *tr,
+              const u64 *rb0, const u64 *rb1, const u64 *ra0, const u64 *ra1, const u64 *ma0,
+              const u64 *ma1, const u64 *mb0, const u64 *mb1, const u64 *mc0, const u64 *mc1, u64 *z0,
+              u64 *z1) {
+  const size_t cnt = n ? n : 1;
+  u64 *w0 = calloc(cnt, sizeof(u64)), *w1 = calloc(cnt, sizeof(u64)), *l0 = calloc(cnt, sizeof(u64)), *l1 = calloc(cnt, sizeof(u64));
+  orc_a2b(n, x0, x1, seed, tag, tr, w0, w1);
+  orc_b2a_bit(n, 63, w0, w1, rb0, rb1, ra0, ra1, l0, l1); /* [x < 0] */
+  for (size_t i = 0; i < n; ++i) {                        /* [x >= 0] = 1 - [x < 0] */
+    l0[i] = 1 - l0[i];
+    l1[i] = (u64)0 - l1[i];
+  }
+  orc_beaver_mul(n, x0, x1, l0, l1, ma0, ma1, mb0, mb1, mc0, mc1, 0, z0, z1);
+  free(w0); free(w1); free(l0); free(l1);
+}
