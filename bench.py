@@ -280,6 +280,7 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
     ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
     ex.update(multiparty_bench(ctx, mpc, torch, X, Y))
+    ex.update(binary_bench(ctx, mpc, torch, X))
     ctx.sync()
     ex.update(grouped_bench(mpc, torch, workloads))
     ex.update(conv_bench(mpc, torch, workloads))
@@ -450,6 +451,35 @@ def multiparty_bench(ctx, mpc, torch, X, Y):
     log(f"bench: 3 parties: Beaver mul {out['mp3_beaver_mul_GBps_algorithmic']} GB/s, truncate "
         f"{out['mp3_truncate_GBps_algorithmic']} GB/s, matmul 4096^3 {out['mp3_beaver_matmul_4096_ms']} ms")
     del x, y, tm, zm
+    torch.cuda.empty_cache()
+    return out
+
+
+def binary_bench(ctx, mpc, torch, X):
+    """Binary sharing at 2^22 words: arithmetic-to-binary conversion (7 rounds,
+    12 AND triples per word) and ReLU (A2B, Algorithm 2 on the sign bit, one
+    Beaver product) against HBM: each reads its shares and every triple word
+    once and writes two words per element."""
+    out = {}
+    n = 1 << 22
+    x = ctx.share(X.view(-1)[:n], 0, 95)
+    t = ctx.dealer_and(19, 96, 12 * n)
+    rb, ra = ctx.dealer_b2a(19, 97, n)
+    tm = ctx.dealer(mpc.TRIPLE_MUL, 19, 98, (n,))
+    z = mpc.SharedPair(ctx.empty((n,)), ctx.empty((n,)))
+    ctx.a2b(x, 99, t, out=z)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.a2b(x, 99, t, out=z), 10)
+    out["a2b_2^22_ms"] = round(ms, 4)
+    out["a2b_GBps_algorithmic"] = round(8.0 * (2 + 72 + 2) * n / (ms * 1e-3) / 1e9, 1)
+    ctx.relu(x, 99, t, rb, ra, tm, out=z)
+    ctx.sync()
+    ms = _event_time(torch, ctx.streams[0], lambda: ctx.relu(x, 99, t, rb, ra, tm, out=z), 10)
+    out["relu_2^22_ms"] = round(ms, 4)
+    out["relu_GBps_algorithmic"] = round(8.0 * (2 + 72 + 4 + 6 + 2) * n / (ms * 1e-3) / 1e9, 1)
+    log(f"bench: binary: A2B 2^22 {out['a2b_2^22_ms']} ms ({out['a2b_GBps_algorithmic']} GB/s), ReLU "
+        f"{out['relu_2^22_ms']} ms ({out['relu_GBps_algorithmic']} GB/s)")
+    del x, t, rb, ra, tm, z
     torch.cuda.empty_cache()
     return out
 

@@ -269,6 +269,49 @@ mpc_status mpc_graph_end(mpc_ctx *ctx, void **graph_exec);
 mpc_status mpc_graph_launch(mpc_ctx *ctx, void *graph_exec);
 mpc_status mpc_graph_destroy(void *graph_exec);
 
+/* ---- binary sharing, two parties (App. C.1.1) -----------------------------
+ * A binary sharing holds 64 independent shared bits per word:
+ * x = <x>_0 XOR <x>_1.  Bitwise AND uses triples (a, b, c = a AND b) from the
+ * dealer, one per word.  All calls run on party 0's stream; every opening is
+ * a device-local XOR, and each counts as one opening (one round) in the
+ * statistics.  Outputs must not alias inputs (MPC_E_ALIAS).  PRG domains:
+ * slot 0x700 of (seed, tag) for sharing, 0x706/0x707 for the parties'
+ * re-sharing inside A2B; slots 0x701-0x705 and 0x708-0x70a of (dseed, tag)
+ * for the dealer. */
+
+/* Binary sharing (XOR zero-share (m, m); party src XORs in x) and reveal. */
+mpc_status mpc_bin_share(mpc_ctx *ctx, const uint64_t *x, size_t n, int src, uint64_t tag, uint64_t *s0,
+                         uint64_t *s1);
+mpc_status mpc_bin_reveal(mpc_ctx *ctx, const uint64_t *s0, const uint64_t *s1, size_t n, uint64_t *out);
+/* n bitwise AND triples (words): a_p, b_p uniform, c = a AND b XOR-shared. */
+mpc_status mpc_dealer_and_triples(mpc_ctx *ctx, uint64_t dseed, uint64_t tag, size_t n, const mpc_triple *out);
+/* Bitwise AND (App. C.1.1, Bitwise AND): eps = x ^ a, delta = y ^ b opened;
+ * z_p = c_p ^ (eps & b_p) ^ (a_p & delta) (^ eps & delta for party 0). */
+mpc_status mpc_bin_and(mpc_ctx *ctx, size_t n, const uint64_t *x0, const uint64_t *x1, const uint64_t *y0,
+                       const uint64_t *y1, const mpc_triple *t, uint64_t *z0, uint64_t *z1);
+/* Arithmetic to binary sharing (App. C.1.1, From [x] to <x>): each party
+ * binary-shares its arithmetic share, and a carry-lookahead adder over binary
+ * shares adds them: 7 rounds, 12 AND triples per word (t holds 12*n triples,
+ * triple j of word i at j*n + i, e.g. from mpc_dealer_and_triples with 12*n). */
+mpc_status mpc_a2b(mpc_ctx *ctx, size_t n, const uint64_t *x0, const uint64_t *x1, uint64_t tag,
+                   const mpc_triple *t, uint64_t *z0, uint64_t *z1);
+/* The dealer of Algorithm 2's random bits: r in {0, 1} per word, shared as
+ * <r> = (rb0, rb1) (bit 0) and [r] = (ra0, ra1). */
+mpc_status mpc_dealer_b2a(mpc_ctx *ctx, uint64_t dseed, uint64_t tag, size_t n, uint64_t *rb0, uint64_t *rb1,
+                          uint64_t *ra0, uint64_t *ra1);
+/* Binary to arithmetic for bit `bit` (0..63) of each word (Algorithm 2):
+ * z = that bit of <b> XOR <r> is opened, [b] = [r] + z - 2 z [r]. */
+mpc_status mpc_b2a_bit(mpc_ctx *ctx, size_t n, int bit, const uint64_t *b0, const uint64_t *b1,
+                       const uint64_t *rb0, const uint64_t *rb1, const uint64_t *ra0, const uint64_t *ra1,
+                       uint64_t *z0, uint64_t *z1);
+/* ReLU (App. C.1.1, Sign, absolute value, and ReLU) of a fixed-point sharing:
+ * [x < 0] is the sign bit of A2B([x]) converted by Algorithm 2, and
+ * z = [x] * (1 - [x < 0]) by one Beaver product with the MUL triple m (no
+ * truncation).  9 rounds; t: 12*n AND triples; (rb, ra): n B2A bits; m: n. */
+mpc_status mpc_relu(mpc_ctx *ctx, size_t n, const uint64_t *x0, const uint64_t *x1, uint64_t tag,
+                    const mpc_triple *t, const uint64_t *rb0, const uint64_t *rb1, const uint64_t *ra0,
+                    const uint64_t *ra1, const mpc_triple *m, uint64_t *z0, uint64_t *z1);
+
 /* ---- more than two parties (App. C.1.1; Algorithm 1) --------------------
  * A sharing among P parties (2 <= P <= MPC_MAX_PARTIES) is a HOST array of P
  * device pointers, one buffer per party, all of the same length.  Every call

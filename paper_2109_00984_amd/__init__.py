@@ -101,6 +101,15 @@ _SIGS = {
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
     "mpc_graph_launch": (INT, [VP, VP]),
     "mpc_graph_destroy": (INT, [VP]),
+    "mpc_bin_share": (INT, [VP, VP, SZ, INT, U64, VP, VP]),
+    "mpc_bin_reveal": (INT, [VP, VP, VP, SZ, VP]),
+    "mpc_dealer_and_triples": (INT, [VP, U64, U64, SZ, ctypes.POINTER(Triple)]),
+    "mpc_bin_and": (INT, [VP, SZ, VP, VP, VP, VP, ctypes.POINTER(Triple), VP, VP]),
+    "mpc_a2b": (INT, [VP, SZ, VP, VP, U64, ctypes.POINTER(Triple), VP, VP]),
+    "mpc_dealer_b2a": (INT, [VP, U64, U64, SZ, VP, VP, VP, VP]),
+    "mpc_b2a_bit": (INT, [VP, SZ, INT, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "mpc_relu": (INT, [VP, SZ, VP, VP, U64, ctypes.POINTER(Triple), VP, VP, VP, VP,
+                       ctypes.POINTER(Triple), VP, VP]),
     "mpc_mp_share": (INT, [VP, INT, VP, SZ, INT, U64, ctypes.POINTER(VP)]),
     "mpc_mp_reveal": (INT, [VP, INT, ctypes.POINTER(VP), SZ, VP]),
     "mpc_mp_dealer_triples": (INT, [VP, INT, INT, U64, U64, ctypes.POINTER(I64),
@@ -350,6 +359,69 @@ class Context:
         _check(_lib.mpc_dealer_triples(self._h, kind, dseed, tag, d, ctypes.byref(st)),
                "mpc_dealer_triples")
         return t
+
+    # -------------------------------------------------------------- binary sharing
+    A2B_TRIPLES = 12
+
+    def bin_share(self, x, src, tag, out=None):
+        self._check_t(x)
+        z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        _check(_lib.mpc_bin_share(self._h, _ptr(x), x.numel(), src, tag, _ptr(z.s0), _ptr(z.s1)),
+               "mpc_bin_share")
+        return z
+
+    def bin_reveal(self, s, out=None):
+        out = out if out is not None else self.empty(s.shape)
+        _check(_lib.mpc_bin_reveal(self._h, _ptr(s.s0), _ptr(s.s1), out.numel(), _ptr(out)),
+               "mpc_bin_reveal")
+        return out
+
+    def dealer_and(self, dseed, tag, n):
+        """n bitwise AND triples (XOR-shared words)."""
+        t = TripleShares(*[self.empty((n,)) for _ in range(6)])
+        st = t.struct()
+        _check(_lib.mpc_dealer_and_triples(self._h, dseed, tag, n, ctypes.byref(st)),
+               "mpc_dealer_and_triples")
+        return t
+
+    def bin_and(self, x, y, t, out=None):
+        z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        st = t.struct()
+        _check(_lib.mpc_bin_and(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), _ptr(y.s0), _ptr(y.s1),
+                                ctypes.byref(st), _ptr(z.s0), _ptr(z.s1)), "mpc_bin_and")
+        return z
+
+    def a2b(self, x, tag, t, out=None):
+        """Arithmetic to binary sharing; t holds 12 * n AND triples."""
+        z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        st = t.struct()
+        _check(_lib.mpc_a2b(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), tag, ctypes.byref(st),
+                            _ptr(z.s0), _ptr(z.s1)), "mpc_a2b")
+        return z
+
+    def dealer_b2a(self, dseed, tag, n):
+        """Algorithm 2's random bits: (<r> shares, [r] shares)."""
+        rb = SharedPair(self.empty((n,)), self.empty((n,)))
+        ra = SharedPair(self.empty((n,)), self.empty((n,)))
+        _check(_lib.mpc_dealer_b2a(self._h, dseed, tag, n, _ptr(rb.s0), _ptr(rb.s1), _ptr(ra.s0),
+                                   _ptr(ra.s1)), "mpc_dealer_b2a")
+        return rb, ra
+
+    def b2a_bit(self, b, bit, rb, ra, out=None):
+        z = out if out is not None else SharedPair(self.empty(b.shape), self.empty(b.shape))
+        _check(_lib.mpc_b2a_bit(self._h, b.s0.numel(), bit, _ptr(b.s0), _ptr(b.s1), _ptr(rb.s0),
+                                _ptr(rb.s1), _ptr(ra.s0), _ptr(ra.s1), _ptr(z.s0), _ptr(z.s1)),
+               "mpc_b2a_bit")
+        return z
+
+    def relu(self, x, tag, t, rb, ra, m, out=None):
+        """ReLU of a fixed-point sharing: t 12*n AND triples, (rb, ra) B2A bits, m MUL triple."""
+        z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        st, sm = t.struct(), m.struct()
+        _check(_lib.mpc_relu(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), tag, ctypes.byref(st),
+                             _ptr(rb.s0), _ptr(rb.s1), _ptr(ra.s0), _ptr(ra.s1), ctypes.byref(sm),
+                             _ptr(z.s0), _ptr(z.s1)), "mpc_relu")
+        return z
 
     # -------------------------------------------------------------- more than two parties
     def mp_share(self, x, P, src, tag, out=None):

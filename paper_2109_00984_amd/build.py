@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpc.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["api.cpp", "elementwise.hip", "gemm_plain.hip", "gemm_limb.hip", "gemm_fp64.hip",
-           "multiparty.hip"]
+           "multiparty.hip", "binary.hip"]
 ARCH = os.environ.get("MPC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from forming packed fp32 instructions

@@ -1538,6 +1538,180 @@ mpc_status mpc_profile_read(mpc_ctx* c, mpc_gemm_timing* limb8, mpc_gemm_timing*
   return MPC_OK;
 }
 
+// ------------------------------------------------------------------ binary sharing
+}  // extern "C"
+
+namespace {
+
+// The six arrays of a triple, each checked for n words.
+mpc_status triple_ptrs(const mpc_triple* t, size_t n, TriplePtrs* out) {
+  if (!t) return MPC_E_INVAL;
+  const u64* v[6] = {t->a0, t->a1, t->b0, t->b1, t->c0, t->c1};
+  for (int i = 0; i < 6; ++i) CHK(check_ptr(v[i], n));
+  *out = TriplePtrs{v[0], v[1], v[2], v[3], v[4], v[5]};
+  return MPC_OK;
+}
+
+// output pair against a list of (pointer, length) inputs
+mpc_status out_alias(const u64* z0, const u64* z1, size_t nz, std::initializer_list<std::pair<const void*, size_t>> ins) {
+  if (overlap(z0, nz, z1, nz)) return MPC_E_ALIAS;
+  for (const auto& in : ins)
+    if (in.first && (overlap(z0, nz, in.first, in.second) || overlap(z1, nz, in.first, in.second)))
+      return MPC_E_ALIAS;
+  return MPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpc_status mpc_bin_share(mpc_ctx* c, const uint64_t* x, size_t n, int src, uint64_t tag, uint64_t* s0,
+                         uint64_t* s1) {
+  if (!c || (src != 0 && src != 1)) return MPC_E_INVAL;
+  CHK(check_ptr(x, n));
+  CHK(check_ptr(s0, n));
+  CHK(check_ptr(s1, n));
+  CHK(out_alias(s0, s1, n, {{x, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_bin_share(c->s[0], x, n, src, stream_key(c->seed, tag, kBinShare), s0, s1)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
+mpc_status mpc_bin_reveal(mpc_ctx* c, const uint64_t* s0, const uint64_t* s1, size_t n, uint64_t* out) {
+  if (!c) return MPC_E_INVAL;
+  CHK(check_ptr(s0, n));
+  CHK(check_ptr(s1, n));
+  CHK(check_ptr(out, n));
+  if (overlap(out, n, s0, n) || overlap(out, n, s1, n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_bin_reveal(c->s[0], s0, s1, n, out)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n;
+  return MPC_OK;
+}
+
+mpc_status mpc_dealer_and_triples(mpc_ctx* c, uint64_t dseed, uint64_t tag, size_t n, const mpc_triple* t) {
+  if (!c || !t) return MPC_E_INVAL;
+  TriplePtrs tp;
+  CHK(triple_ptrs(t, n, &tp));
+  const u64* v[6] = {tp.a0, tp.a1, tp.b0, tp.b1, tp.c0, tp.c1};
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j)
+      if (overlap(v[i], n, v[j], n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  const BinKeys k{stream_key(dseed, tag, kBinA0), stream_key(dseed, tag, kBinA1), stream_key(dseed, tag, kBinB0),
+                  stream_key(dseed, tag, kBinB1), stream_key(dseed, tag, kBinC0)};
+  CHK(hip_status(launch_dealer_and(c->s[0], k, n, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
+mpc_status mpc_bin_and(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64_t* x1, const uint64_t* y0,
+                       const uint64_t* y1, const mpc_triple* t, uint64_t* z0, uint64_t* z1) {
+  if (!c) return MPC_E_INVAL;
+  TriplePtrs tp;
+  CHK(triple_ptrs(t, n, &tp));
+  const u64* in[4] = {x0, x1, y0, y1};
+  for (const u64* p : in) CHK(check_ptr(p, n));
+  CHK(check_ptr(z0, n));
+  CHK(check_ptr(z1, n));
+  CHK(out_alias(z0, z1, n, {{x0, n}, {x1, n}, {y0, n}, {y1, n}, {tp.a0, n}, {tp.a1, n}, {tp.b0, n}, {tp.b1, n},
+                            {tp.c0, n}, {tp.c1, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_bin_and(c->s[0], n, x0, x1, y0, y1, tp, z0, z1)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 16 * (uint64_t)n;
+  return MPC_OK;
+}
+
+mpc_status mpc_a2b(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64_t* x1, uint64_t tag,
+                   const mpc_triple* t, uint64_t* z0, uint64_t* z1) {
+  if (!c) return MPC_E_INVAL;
+  const size_t nt = (size_t)kA2bTriples * n;
+  TriplePtrs tp;
+  CHK(triple_ptrs(t, nt, &tp));
+  CHK(check_ptr(x0, n));
+  CHK(check_ptr(x1, n));
+  CHK(check_ptr(z0, n));
+  CHK(check_ptr(z1, n));
+  CHK(out_alias(z0, z1, n, {{x0, n}, {x1, n}, {tp.a0, nt}, {tp.a1, nt}, {tp.b0, nt}, {tp.b1, nt}, {tp.c0, nt},
+                            {tp.c1, nt}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_a2b(c->s[0], n, x0, x1, stream_key(c->seed, tag, kA2bY0), stream_key(c->seed, tag, kA2bY1),
+                            tp, z0, z1)));
+  c->stats.launches++;
+  c->stats.opens += 7;
+  c->stats.open_bytes_per_party += 16 * (uint64_t)nt;
+  return MPC_OK;
+}
+
+mpc_status mpc_dealer_b2a(mpc_ctx* c, uint64_t dseed, uint64_t tag, size_t n, uint64_t* rb0, uint64_t* rb1,
+                          uint64_t* ra0, uint64_t* ra1) {
+  if (!c) return MPC_E_INVAL;
+  u64* v[4] = {rb0, rb1, ra0, ra1};
+  for (int i = 0; i < 4; ++i) CHK(check_ptr(v[i], n));
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(v[i], n, v[j], n)) return MPC_E_ALIAS;
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_dealer_b2a(c->s[0], n, stream_key(dseed, tag, kB2aR), stream_key(dseed, tag, kB2aRb0),
+                                   stream_key(dseed, tag, kB2aRa0), rb0, rb1, ra0, ra1)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
+mpc_status mpc_b2a_bit(mpc_ctx* c, size_t n, int bit, const uint64_t* b0, const uint64_t* b1,
+                       const uint64_t* rb0, const uint64_t* rb1, const uint64_t* ra0, const uint64_t* ra1,
+                       uint64_t* z0, uint64_t* z1) {
+  if (!c || bit < 0 || bit > 63) return MPC_E_INVAL;
+  const u64* in[6] = {b0, b1, rb0, rb1, ra0, ra1};
+  for (const u64* p : in) CHK(check_ptr(p, n));
+  CHK(check_ptr(z0, n));
+  CHK(check_ptr(z1, n));
+  CHK(out_alias(z0, z1, n, {{b0, n}, {b1, n}, {rb0, n}, {rb1, n}, {ra0, n}, {ra1, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_b2a_bit(c->s[0], n, bit, b0, b1, rb0, rb1, ra0, ra1, z0, z1)));
+  c->stats.launches++;
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n;
+  return MPC_OK;
+}
+
+mpc_status mpc_relu(mpc_ctx* c, size_t n, const uint64_t* x0, const uint64_t* x1, uint64_t tag,
+                    const mpc_triple* t, const uint64_t* rb0, const uint64_t* rb1, const uint64_t* ra0,
+                    const uint64_t* ra1, const mpc_triple* m, uint64_t* z0, uint64_t* z1) {
+  if (!c) return MPC_E_INVAL;
+  const size_t nt = (size_t)kA2bTriples * n;
+  TriplePtrs tp, mp;
+  CHK(triple_ptrs(t, nt, &tp));
+  CHK(triple_ptrs(m, n, &mp));
+  const u64* in[6] = {x0, x1, rb0, rb1, ra0, ra1};
+  for (const u64* p : in) CHK(check_ptr(p, n));
+  CHK(check_ptr(z0, n));
+  CHK(check_ptr(z1, n));
+  CHK(out_alias(z0, z1, n, {{x0, n}, {x1, n}, {rb0, n}, {rb1, n}, {ra0, n}, {ra1, n}, {tp.a0, nt}, {tp.a1, nt},
+                            {tp.b0, nt}, {tp.b1, nt}, {tp.c0, nt}, {tp.c1, nt}, {mp.a0, n}, {mp.a1, n},
+                            {mp.b0, n}, {mp.b1, n}, {mp.c0, n}, {mp.c1, n}}));
+  if (!n) return MPC_OK;
+  CHK(set_device(c));
+  CHK(hip_status(launch_relu(c->s[0], n, x0, x1, stream_key(c->seed, tag, kA2bY0), stream_key(c->seed, tag, kA2bY1),
+                             tp, rb0, rb1, ra0, ra1, mp, z0, z1)));
+  c->stats.launches++;
+  c->stats.opens += 9;
+  c->stats.open_bytes_per_party += 16 * (uint64_t)nt + 8 * (uint64_t)n + 16 * (uint64_t)n;
+  return MPC_OK;
+}
+
 // ------------------------------------------------------------------ more than two parties
 }  // extern "C"
 

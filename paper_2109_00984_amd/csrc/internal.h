@@ -215,6 +215,38 @@ struct TileSched {
   int group_m;    // tile rows per raster group
   int xcd_remap;  // give each XCD a contiguous run of tiles
 };
+// ---------------------------------------------------------------- binary sharing (two parties)
+// Slots: 0x700 share, 0x701..0x705 AND triple a0, a1, b0, b1, c0, 0x706/0x707
+// the parties' re-sharing in A2B, 0x708..0x70a Algorithm 2's bit r, <r>_0, [r]_0.
+enum BinSlot : u64 {
+  kBinShare = 0x700, kBinA0 = 0x701, kBinA1 = 0x702, kBinB0 = 0x703, kBinB1 = 0x704, kBinC0 = 0x705,
+  kA2bY0 = 0x706, kA2bY1 = 0x707, kB2aR = 0x708, kB2aRb0 = 0x709, kB2aRa0 = 0x70a
+};
+constexpr int kA2bTriples = 12;  // AND triples per word of one A2B conversion
+struct TriplePtrs {
+  const u64 *a0, *a1, *b0, *b1, *c0, *c1;
+};
+struct BinKeys {
+  u64 a0, a1, b0, b1, c0;
+};
+hipError_t launch_bin_share(hipStream_t s, const u64* x, size_t n, int src, u64 key, u64* s0, u64* s1);
+hipError_t launch_bin_reveal(hipStream_t s, const u64* s0, const u64* s1, size_t n, u64* out);
+hipError_t launch_dealer_and(hipStream_t s, const BinKeys& k, size_t n, u64* a0, u64* a1, u64* b0, u64* b1,
+                             u64* c0, u64* c1);
+hipError_t launch_bin_and(hipStream_t s, size_t n, const u64* x0, const u64* x1, const u64* y0, const u64* y1,
+                          const TriplePtrs& t, u64* z0, u64* z1);
+// t: kA2bTriples AND triples per element, triple j of element i at j * n + i
+hipError_t launch_a2b(hipStream_t s, size_t n, const u64* x0, const u64* x1, u64 ky0, u64 ky1,
+                      const TriplePtrs& t, u64* z0, u64* z1);
+hipError_t launch_dealer_b2a(hipStream_t s, size_t n, u64 kr, u64 krb, u64 kra, u64* rb0, u64* rb1, u64* ra0,
+                             u64* ra1);
+hipError_t launch_b2a_bit(hipStream_t s, size_t n, int bit, const u64* b0, const u64* b1, const u64* rb0,
+                          const u64* rb1, const u64* ra0, const u64* ra1, u64* z0, u64* z1);
+// m: an arithmetic MUL triple
+hipError_t launch_relu(hipStream_t s, size_t n, const u64* x0, const u64* x1, u64 ky0, u64 ky1,
+                       const TriplePtrs& t, const u64* rb0, const u64* rb1, const u64* ra0, const u64* ra1,
+                       const TriplePtrs& m, u64* z0, u64* z1);
+
 // ---------------------------------------------------------------- more than two parties
 constexpr int kMaxParties = 16;
 struct MpOut {
