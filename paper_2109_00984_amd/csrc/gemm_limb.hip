@@ -317,50 +317,104 @@ __device__ __forceinline__ void mfma16_first(v4i& acc, const v4i& a, const v4i& 
 
 // One 64-wide k step: 36 MFMAs per (left half, right half) pair.  Level l
 // multiplies outer plane l with inner planes 0..7-l into diagonals l..7.
+//
+// Loads are spread evenly over the MFMAs rather than issued in bursts: the
+// four waves of a CU share one vector-memory pipeline, and a burst stalls
+// every wave's in-order issue (MFMAs included) until the pipeline accepts it.
+// Level L reloads the registers freed by level L-1: outer plane L-1 and inner
+// plane 8-L (for the next step); level 0 reloads outer plane 7 for this step
+// (freed by the previous step's level 7) and fills the next step's
+// double-buffered inner planes.
 // (HO, HI, ND repeat Shape<SA, SB>'s HO, HI, kDbl: array bounds in a
 // parameter list cannot depend on the template's own members.)
-template <int SA, int SB, int HO, int HI, int ND, bool FIRST>
-__device__ __forceinline__ void mfma_step(v4i (&acc)[2 * SA][2 * SB][8], v4i (&outer)[HO][8],
-                                          v4i (&inner)[HI][8], const v4i (&dcur)[HI][ND],
-                                          v4i (&dnext)[HI][ND], const StepOff& next,
-                                          const LaneOff& lo) {
+// Registers of one wave's k loop, bundled so the compile-time-indexed helpers
+// below take one reference.
+template <int SA, int SB>
+struct StepRegs {
   using S = Shape<SA, SB>;
-  static_assert(S::HO == HO && S::HI == HI && S::kDbl == ND, "shape mismatch");
-  const __amdgpu_buffer_rsrc_t ro = S::kOuterA ? next.a : next.b;
-  const __amdgpu_buffer_rsrc_t ri = S::kOuterA ? next.b : next.a;
-  // the next step's double-buffered inner planes: a whole step of latency
-#pragma unroll
-  for (int i = 0; i < S::HI; ++i)
-#pragma unroll
-    for (int j = 0; j < S::kDbl; ++j) dnext[i][j] = ld_frag(ri, lo, next, i, j);
-#pragma unroll
-  for (int l = 0; l < 8; ++l) {
-#pragma unroll
-    for (int s = l; s < 8; ++s)
-#pragma unroll
-      for (int o = 0; o < S::HO; ++o)
-#pragma unroll
-        for (int i = 0; i < S::HI; ++i) {
-          const v4i& in = (s - l) < S::kDbl ? dcur[i][s - l] : inner[i][s - l];
-          v4i& c = S::kOuterA ? acc[o][i][s] : acc[i][o][s];
-          const v4i& a = S::kOuterA ? outer[o][l] : in;
-          const v4i& b = S::kOuterA ? in : outer[o][l];
-          if (FIRST && l == 0) mfma16_first(c, a, b);
-          else mfma16(c, a, b);
-        }
-    // outer plane l and inner plane 7-l are dead for this step; the barrier
-    // keeps their reloads behind the MFMAs that read them
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int o = 0; o < S::HO; ++o) outer[o][l] = ld_frag(ro, lo, next, o, l);
-    if (7 - l >= S::kDbl) {
-#pragma unroll
-      for (int i = 0; i < S::HI; ++i) inner[i][7 - l] = ld_frag(ri, lo, next, i, 7 - l);
+  v4i (&acc)[2 * SA][2 * SB][8];
+  v4i (&outer)[S::HO][8];
+  v4i (&inner)[S::HI][8];
+  const v4i (&dcur)[S::HI][S::kDbl];
+  v4i (&dnext)[S::HI][S::kDbl];
+};
+
+// Load number Q of level L (see mfma_step).
+template <int SA, int SB, bool FIRST, int L, int Q>
+__device__ __forceinline__ void level_load(StepRegs<SA, SB>& r, const StepOff& cur, const StepOff& next,
+                                           const LaneOff& lo) {
+  using S = Shape<SA, SB>;
+  constexpr int HO = S::HO, ND = S::kDbl;
+  if constexpr (L == 0) {
+    constexpr int NO = FIRST ? 0 : HO;  // the first step's planes come from the prologue
+    if constexpr (Q < NO) {
+      r.outer[Q][7] = ld_frag(S::kOuterA ? cur.a : cur.b, lo, cur, Q, 7);
+    } else {
+      constexpr int D = Q - NO;
+      r.dnext[D / ND][D % ND] = ld_frag(S::kOuterA ? next.b : next.a, lo, next, D / ND, D % ND);
     }
+  } else if constexpr (Q < HO) {
+    r.outer[Q][L - 1] = ld_frag(S::kOuterA ? next.a : next.b, lo, next, Q, L - 1);
+  } else {
+    r.inner[Q - HO][8 - L] = ld_frag(S::kOuterA ? next.b : next.a, lo, next, Q - HO, 8 - L);
+  }
+}
+
+// MFMA number M (0-based) of level L, then the load that falls after it, then
+// the rest of the level.  MFMA M multiplies outer plane L of half o with inner
+// plane s - L of half i into diagonal s; the level's NL loads sit at the ends
+// of NL + 1 equal fractions of its NM MFMAs (NL < NM: at most one per MFMA).
+template <int SA, int SB, bool FIRST, int L, int M>
+__device__ __forceinline__ void mfma_level(StepRegs<SA, SB>& r, const StepOff& cur, const StepOff& next,
+                                           const LaneOff& lo) {
+  using S = Shape<SA, SB>;
+  constexpr int HO = S::HO, HI = S::HI, ND = S::kDbl;
+  constexpr int NM = (8 - L) * HO * HI;
+  if constexpr (M < NM) {
+    constexpr int s = L + M / (HO * HI), o = (M / HI) % HO, i = M % HI;
+    const v4i& in = (s - L) < ND ? r.dcur[i][(s - L) % ND] : r.inner[i][s - L];
+    v4i& c = S::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
+    const v4i& a = S::kOuterA ? r.outer[o][L] : in;
+    const v4i& b = S::kOuterA ? in : r.outer[o][L];
+    if constexpr (FIRST && L == 0) mfma16_first(c, a, b);
+    else mfma16(c, a, b);
+    constexpr int NL = L == 0 ? (FIRST ? 0 : HO) + HI * ND : HO + (8 - L >= ND ? HI : 0);
+    constexpr int Q = (M + 1) * (NL + 1) / NM - 1, QPREV = M * (NL + 1) / NM - 1;
+    if constexpr (Q >= 0 && Q < NL && Q != QPREV) {
+      __builtin_amdgcn_sched_barrier(0);
+      level_load<SA, SB, FIRST, L, Q>(r, cur, next, lo);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    mfma_level<SA, SB, FIRST, L, M + 1>(r, cur, next, lo);
+  }
+}
+
+template <int SA, int SB, bool FIRST, int L>
+__device__ __forceinline__ void mfma_levels(StepRegs<SA, SB>& r, const StepOff& cur, const StepOff& next,
+                                            const LaneOff& lo) {
+  if constexpr (L < 8) {
+    mfma_level<SA, SB, FIRST, L, 0>(r, cur, next, lo);
     // keep this order: reordering across levels lengthens the fragments'
     // live ranges past the register file
     __builtin_amdgcn_sched_barrier(0);
+    mfma_levels<SA, SB, FIRST, L + 1>(r, cur, next, lo);
   }
+}
+
+// One 64-wide k step: 36 MFMAs per (left half, right half) pair.  Level l
+// multiplies outer plane l with inner planes 0..7-l into diagonals l..7.
+//
+// Loads are spread evenly over the MFMAs rather than issued in bursts: the
+// four waves of a CU share one vector-memory pipeline, and a burst stalls
+// every wave's in-order issue (MFMAs included) until the pipeline accepts it.
+// Level L reloads the registers freed by level L-1: outer plane L-1 and inner
+// plane 8-L (for the next step); level 0 reloads outer plane 7 for this step
+// (freed by the previous step's level 7) and fills the next step's
+// double-buffered inner planes.
+template <int SA, int SB, bool FIRST>
+__device__ __forceinline__ void mfma_step(StepRegs<SA, SB> r, const StepOff& cur, const StepOff& next,
+                                          const LaneOff& lo) {
+  mfma_levels<SA, SB, FIRST, 0>(r, cur, next, lo);
 }
 
 // GEMM over a tile list.  Each wave streams its fragments straight from
@@ -430,18 +484,15 @@ __global__ void __launch_bounds__(kThreads, 1)
   // blocks (valid memory, results unused).
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
-    mfma_step<SA, SB, S::HO, S::HI, S::kDbl, true>(acc, outer, inner, d0, d1,
-                                                    step_off(s0, s1, p.kb0, min(kbeg + 2, klast)), lo);
+    using R = StepRegs<SA, SB>;
+    auto off = [&](int st) { return step_off(s0, s1, p.kb0, min(kbeg + 2 * st, klast)); };
+    mfma_step<SA, SB, true>(R{acc, outer, inner, d0, d1}, off(0), off(1), lo);
     int st = 1;
     for (; st + 1 < nsteps; st += 2) {
-      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(
-          acc, outer, inner, d1, d0, step_off(s0, s1, p.kb0, min(kbeg + 2 * st + 2, klast)), lo);
-      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(
-          acc, outer, inner, d0, d1, step_off(s0, s1, p.kb0, min(kbeg + 2 * st + 4, klast)), lo);
+      mfma_step<SA, SB, false>(R{acc, outer, inner, d1, d0}, off(st), off(st + 1), lo);
+      mfma_step<SA, SB, false>(R{acc, outer, inner, d0, d1}, off(st + 1), off(st + 2), lo);
     }
-    if (st < nsteps)
-      mfma_step<SA, SB, S::HO, S::HI, S::kDbl, false>(acc, outer, inner, d1, d0,
-                                                       step_off(s0, s1, p.kb0, klast), lo);
+    if (st < nsteps) mfma_step<SA, SB, false>(R{acc, outer, inner, d1, d0}, off(st), off(st + 1), lo);
   } else {
 #pragma unroll
     for (int x = 0; x < S::HA; ++x)
