@@ -235,8 +235,11 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmu
 
 /* ---- autotuning of the limb GEMM ---------------------------------------- */
 /* A tile schedule: the workgroup tile shape (0: 128x64, 1: 64x128, 2: 64x64
- * outputs), the number of tile rows per raster group, and whether tiles are
- * remapped so that each XCD works on a contiguous run of them. */
+ * outputs, every wave fetching its operand fragments from global memory;
+ * 3, 4, 5: the same shapes with the operand that has more fragments per wave
+ * copied once per workgroup into LDS and read from there), the number of tile
+ * rows per raster group, and whether tiles are remapped so that each XCD
+ * works on a contiguous run of them. */
 typedef struct {
   int variant, group_m, xcd_remap;
   double ms; /* measured time of the tuned launch(es), filled by the tuner */

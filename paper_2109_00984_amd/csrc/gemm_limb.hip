@@ -417,6 +417,79 @@ __device__ __forceinline__ void mfma_step(StepRegs<SA, SB> r, const StepOff& cur
   mfma_levels<SA, SB, FIRST, 0>(r, cur, next, lo);
 }
 
+// Output tile of this workgroup.  One workgroup per tile.  Workgroups are
+// dispatched to the 8 XCDs round-robin in index order, so index b runs on XCD
+// b % 8; remapping b -> (b % 8) * (G / 8) + b / 8 gives each XCD a contiguous
+// run of tiles, which then share that XCD's L2.  Inside a problem the tiles
+// follow a grouped raster: runs of group_m tile rows, column by column.
+struct TilePos {
+  int pi;
+  i64 tm, tn;
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ probs, const TileMap& map,
+                                            const TileSched& sched) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int G8 = G & ~7;
+  const int t = (sched.xcd_remap && b < G8) ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
+  TilePos q;
+  q.pi = find_problem(map.tile_start, map.nprob, t);
+  const LimbProblem& p = probs[q.pi];
+  const int local = t - map.tile_start[q.pi];
+  const int ntm = (int)((p.M + BM - 1) / BM), ntn = (int)((p.N + BN - 1) / BN);
+  const int gm = sched.group_m;
+  const int per_group = gm * ntn;
+  const int first_m = (local / per_group) * gm;
+  const int gsize = min(ntm - first_m, gm);
+  const int in_group = local % per_group;
+  q.tm = first_m + in_group % gsize;
+  q.tn = in_group / gsize;
+  return q;
+}
+
+// Wait states between the last MFMAs and the reads of their results: every
+// accumulator passes through a short s_nop in diagonal order, and diagonal
+// s = 7 (written by the last MFMAs of a step) comes last.  Then
+// C = sum_s 2^(8s) X_s (mod 2^64) and the shared epilogue.  16x16 accumulator
+// layout: lane l, register e holds row 4*(l/16) + e and column l%16 of the
+// 16x16 block.
+template <int SA, int SB>
+__device__ __forceinline__ void store_tile(v4i (&acc)[2 * SA][2 * SB][8], const LimbProblem& p, i64 tm,
+                                           i64 tn, int wr, int wc, int lane) {
+  using S = Shape<SA, SB>;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int x = 0; x < S::HA; ++x)
+#pragma unroll
+      for (int y = 0; y < S::HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
+  const Epilogue& ep = p.ep;
+#pragma unroll
+  for (int y = 0; y < S::HB; ++y) {
+    const i64 n = tn * S::BN + wc * 32 * SB + y * 16 + (lane & 15);
+    const bool n_ok = n < p.N;
+    const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
+#pragma unroll
+    for (int x = 0; x < S::HA; ++x) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const i64 m = tm * S::BM + wr * 32 * SA + x * 16 + 4 * (lane >> 4) + e;
+        u64 v = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
+        if (n_ok && m < p.M) {
+          const i64 off = m * ep.view.ld_m + coff;
+          if (ep.accumulate) v += ep.Out[off];
+          if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
+          if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
+          ep.Out[off] = v;
+        }
+      }
+    }
+  }
+}
+
 // GEMM over a tile list.  Each wave streams its fragments straight from
 // global memory (buffer loads; every wave load reads four contiguous 256-byte
 // runs), one k step ahead of the MFMAs, so no LDS traffic and no barrier sit
@@ -432,24 +505,9 @@ __global__ void __launch_bounds__(kThreads, 1)
   // derived from it) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  // One workgroup per tile.  Workgroups are dispatched to the 8 XCDs
-  // round-robin in index order, so index b runs on XCD b % 8; remapping
-  // b -> (b % 8) * (G / 8) + b / 8 gives each XCD a contiguous run of tiles,
-  // which then share that XCD's L2.
-  const int G = gridDim.x, b = blockIdx.x;
-  const int G8 = G & ~7;
-  const int t = (sched.xcd_remap && b < G8) ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
-  const int pi = find_problem(map.tile_start, map.nprob, t);
-  const LimbProblem& p = probs[pi];
-  const int local = t - map.tile_start[pi];
-  // grouped raster: runs of group_m tile rows, column by column
-  const int ntm = (int)((p.M + S::BM - 1) / S::BM), ntn = (int)((p.N + S::BN - 1) / S::BN);
-  const int gm = sched.group_m;
-  const int per_group = gm * ntn;
-  const int first_m = (local / per_group) * gm;
-  const int gsize = min(ntm - first_m, gm);
-  const int in_group = local % per_group;
-  const i64 tm = first_m + in_group % gsize, tn = in_group / gsize;
+  const TilePos tp = tile_pos<S::BM, S::BN>(probs, map, sched);
+  const LimbProblem& p = probs[tp.pi];
+  const i64 tm = tp.tm, tn = tp.tn;
   const i64 mb0 = tm * 2 * SA + wr * SA;  // this wave's first left 32-block
   const i64 nb0 = tn * 2 * SB + wc * SB;  // this wave's first right 32-block
 
@@ -501,43 +559,280 @@ __global__ void __launch_bounds__(kThreads, 1)
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  // Wait states between the last MFMAs and the reads of their results: every
-  // accumulator passes through a short s_nop in diagonal order, and diagonal
-  // s = 7 (written by the last HO*HI MFMAs) comes last.
+  store_tile<SA, SB>(acc, p, tm, tn, wr, wc, lane);
+}
+
+
+// ------------------------------------------------------------------ LDS-staged GEMM
+// The same product with the outer operand staged through LDS.  In k_limb_gemm
+// the two waves that share an outer strip both fetch it from global memory,
+// so the workgroup fetches every outer block twice.  Here each k step's outer
+// blocks of the whole workgroup (one 16 KiB run of two k-blocks per strip)
+// are copied once into LDS by buffer loads that write LDS directly, a quarter
+// of them by each wave, and every wave reads its fragments back with 16-byte
+// LDS reads (64 lanes reading four 256-byte runs: no bank conflicts).  The
+// inner operand still goes from global memory straight into registers.  This
+// cuts the vector-memory instructions per wave and k step from
+// 8 * (HO + HI) to 8 * HI + 4 * kStrips.
+//
+// Two LDS buffers alternate between steps: a step computes from one while its
+// copies for the next step land in the other.  One barrier per step hands
+// them over; it sits in level 6, after the last read of the step's buffer
+// (outer limb 7) has returned and after the wave's copies have landed, so
+// that the next step's limb 0 can be read during levels 6 and 7.  Every
+// global load of a step is issued in levels 0..2, the copies first, so the
+// wait for the copies at the barrier normally finds them done.
+
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) v4i lds_v4i;
+
+template <int SA, int SB>
+struct LShape {
+  using S = Shape<SA, SB>;
+  static constexpr int HO = S::HO, HI = S::HI;
+  static constexpr int SO = S::kOuterA ? SA : SB;  // outer strips per wave
+  static constexpr int kStrips = 2 * SO;           // outer strips per workgroup
+  static constexpr int kBufBytes = kStrips << 14;  // two 8 KiB k-blocks per strip
+  static constexpr int kCopies = kStrips * 4;      // 1 KiB copies per wave and step
+  // Every inner plane is double-buffered (the registers the outer operand no
+  // longer needs pay for it), so a step's global loads need not wait for the
+  // last use of anything: all of them go out in levels 0..kLoadLevels-1, the
+  // copies first, leaving a long slack before the hand-over waits for them.
+  static constexpr int kLoadLevels = 3;
+  static constexpr int kLoads = kCopies + HI * 8;
+  static constexpr int mfmas_upto(int L) {
+    int c = 0;
+    for (int l = 0; l <= L; ++l) c += (8 - l) * HO * HI;
+    return c;
+  }
+  // Loads issued in levels 0..L, in proportion to the levels' MFMAs.
+  static constexpr int loads_upto(int L) {
+    if (L < 0) return 0;
+    if (L >= kLoadLevels - 1) return kLoads;
+    const int last = mfmas_upto(kLoadLevels - 1);
+    return (kLoads * mfmas_upto(L) + last / 2) / last;
+  }
+  static constexpr int loads_at(int L) { return loads_upto(L) - loads_upto(L - 1); }
+  static constexpr bool loads_fit() {
+    for (int L = 0; L < 8; ++L)
+      if (loads_at(L) >= (8 - L) * HO * HI) return false;
+    return true;
+  }
+  static_assert(loads_fit(), "at most one load after each MFMA of a level");
+  static_assert(2 * kBufBytes <= 160 * 1024, "two step buffers must fit in LDS");
+  // Vector-memory loads complete in issue order, and a step issues its copies
+  // before its inner loads, so the hand-over need not wait for the last
+  // kPending loads (inner planes for the next step, still in flight); half of
+  // the inner loads keeps a margin.
+  static constexpr int kPending = HI * 8 / 2;
+  static_assert(kPending <= HI * 8 && kPending < 64, "vmcnt holds the pending inner loads");
+};
+
+// Descriptors and offsets of one k step: the wave's inner strips and the
+// workgroup's outer strips (strip x of either at +x*kbs k-blocks).
+struct LStep {
+  __amdgpu_buffer_rsrc_t inner, outer;
+  int kb, kbs;
+  __device__ int off(int x) const { return (kb + x * kbs) << 13; }
+};
+
+template <bool OUTER_A>
+__device__ __forceinline__ LStep lstep(const SegSrc& s0, const SegSrc& s1, const SegSrc& w0,
+                                       const SegSrc& w1, int kb0, int kg) {
+  const bool seg0 = kg < kb0;
+  LStep o;
+  o.inner = OUTER_A ? (seg0 ? s0.b : s1.b) : (seg0 ? s0.a : s1.a);
+  o.outer = OUTER_A ? (seg0 ? w0.a : w1.a) : (seg0 ? w0.b : w1.b);
+  o.kb = seg0 ? kg : kg - kb0;
+  o.kbs = seg0 ? s0.kbs : s1.kbs;
+  return o;
+}
+
+// Per-wave constants of the LDS path.
+struct LCtx {
+  unsigned rd;    // LDS byte offset of this lane's fragment in the wave's first strip
+  unsigned lane;  // lane * 16: a copy's per-lane source offset (LDS takes lane * 16 itself)
+  int cx, cu0;    // strip and first 1 KiB unit of this wave's copies
+};
+
+// Copy j of this wave: 1 KiB of the next step's outer run into LDS.
+__device__ __forceinline__ void copy_unit(const LCtx& c, const LStep& o, lds_u8* buf, int j) {
+  const int u = c.cu0 + j;
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(o.outer, (__attribute__((address_space(3))) void*)(buf + (c.cx << 14) + (u << 10)),
+                                           16, c.lane, o.off(c.cx) + (u << 10), 0, 0);
+}
+
+// Outer fragment (half h, limb i) of this wave from an LDS buffer.
+__device__ __forceinline__ v4i lds_frag(const lds_u8* buf, const LCtx& c, int h, int i) {
+  return *(const lds_v4i*)(buf + c.rd + (h >> 1) * 16384 + (h & 1) * 256 + i * 1024);
+}
+
+// Wait until at most PENDING of this wave's vector-memory loads are in flight
+// and its LDS reads have returned, then for the other waves.
+template <int PENDING>
+__device__ __forceinline__ void lds_handover() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(PENDING) : "memory");
+}
+
+template <int SA, int SB>
+struct LRegs {
+  using Sh = LShape<SA, SB>;
+  v4i (&acc)[2 * SA][2 * SB][8];
+  v4i (&z)[Sh::HO];      // outer limb 0
+  v4i (&ob)[2][Sh::HO];  // outer limbs 1..7: limb l in ob[l & 1]
+  const v4i (&dcur)[Sh::HI][8];  // inner planes of this step
+  v4i (&dnext)[Sh::HI][8];       // and of the next
+
+  const lds_u8* cur;  // this step's outer blocks
+  lds_u8* next;       // the next step's
+};
+
+// Global load number Q of level L: the step's copies come first, then the
+// next step's inner planes.
+template <int SA, int SB, int L, int Q>
+__device__ __forceinline__ void lds_level_load(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
+                                               const LaneOff& lo) {
+  using Sh = LShape<SA, SB>;
+  constexpr int q = Sh::loads_upto(L - 1) + Q;
+  if constexpr (q < Sh::kCopies) {
+    copy_unit(c, next, r.next, q);
+  } else {
+    constexpr int h = (q - Sh::kCopies) / 8, i = (q - Sh::kCopies) % 8;
+    r.dnext[h][i] = ld_buf(next.inner, lo.at(h, i), next.off(h >> 1));
+  }
+}
+
+// MFMA number M of level L and what follows it: at M = 0 the reads of outer
+// limb L + 1 (this step's buffer); in level 6, half way, the hand-over and the
+// reads of the next step's limb 0; and the level's global loads, evenly spread.
+// A tile's odd last step issues no loads, copies or hand-over.
+template <int SA, int SB, bool FIRST, bool LAST, int L, int M>
+__device__ __forceinline__ void lds_level(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
+                                          const LaneOff& lo) {
+  using Sh = LShape<SA, SB>;
+  constexpr int HO = Sh::HO, HI = Sh::HI;
+  constexpr int NM = (8 - L) * HO * HI;
+  if constexpr (M < NM) {
+    constexpr int s = L + M / (HO * HI), o = (M / HI) % HO, i = M % HI;
+    const v4i& in = r.dcur[i][s - L];
+    const v4i& out = L == 0 ? r.z[o] : r.ob[L & 1][o];
+    v4i& acc = Sh::S::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
+    const v4i& a = Sh::S::kOuterA ? out : in;
+    const v4i& b = Sh::S::kOuterA ? in : out;
+    if constexpr (FIRST && L == 0) mfma16_first(acc, a, b);
+    else mfma16(acc, a, b);
+    if constexpr (M == 0 && L < 7) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
+      for (int h = 0; h < HO; ++h) r.ob[(L + 1) & 1][h] = lds_frag(r.cur, c, h, L + 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (!LAST && L == 6 && M == NM / 2 - 1) {
+      __builtin_amdgcn_sched_barrier(0);
+      lds_handover<Sh::kPending>();
+#pragma unroll
+      for (int h = 0; h < HO; ++h) r.z[h] = lds_frag(r.next, c, h, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    constexpr int NL = LAST ? 0 : Sh::loads_at(L);
+    constexpr int Q = (M + 1) * (NL + 1) / NM - 1, QPREV = M * (NL + 1) / NM - 1;
+    if constexpr (Q >= 0 && Q < NL && Q != QPREV) {
+      __builtin_amdgcn_sched_barrier(0);
+      lds_level_load<SA, SB, L, Q>(r, c, next, lo);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    lds_level<SA, SB, FIRST, LAST, L, M + 1>(r, c, next, lo);
+  }
+}
+
+template <int SA, int SB, bool FIRST, bool LAST, int L>
+__device__ __forceinline__ void lds_levels(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
+                                           const LaneOff& lo) {
+  if constexpr (L < 8) {
+    lds_level<SA, SB, FIRST, LAST, L, 0>(r, c, next, lo);
+    __builtin_amdgcn_sched_barrier(0);
+    lds_levels<SA, SB, FIRST, LAST, L + 1>(r, c, next, lo);
+  }
+}
+
+template <int SA, int SB, bool FIRST, bool LAST>
+__device__ __forceinline__ void lds_step(LRegs<SA, SB> r, const LCtx& c, const LStep& next, const LaneOff& lo) {
+  lds_levels<SA, SB, FIRST, LAST, 0>(r, c, next, lo);
+}
+
+template <int SA, int SB>
+__global__ void __launch_bounds__(kThreads, 1)
+    k_limb_gemm_lds(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
+  using S = Shape<SA, SB>;
+  using Sh = LShape<SA, SB>;
+  __shared__ v4i stage[2][Sh::kBufBytes / 16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const TilePos tp = tile_pos<S::BM, S::BN>(probs, map, sched);
+  const LimbProblem& p = probs[tp.pi];
+  const i64 tm = tp.tm, tn = tp.tn;
+  const i64 mw = tm * 2 * SA, nw = tn * 2 * SB;  // the workgroup's first left / right 32-block
+  const i64 mb0 = mw + wr * SA, nb0 = nw + wc * SB;
+
+  v4i acc[S::HA][S::HB][8];
+  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int g = lane >> 4;
+  const unsigned lane_off = (unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16);
+  const LaneOff lo{lane_off};
+  const uint8_t* PA1 = p.PA1 ? p.PA1 : p.PA0;
+  const uint8_t* PB1 = p.PB1 ? p.PB1 : p.PB0;
+  const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mb0, nb0, SA, SB);
+  const SegSrc s1 = seg_src(PA1, PB1, p.kb1, mb0, nb0, SA, SB);
+  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, 2 * SA, 2 * SB);
+  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, 2 * SA, 2 * SB);
+  const int c0 = wave * Sh::kCopies;
+  const LCtx c{(unsigned)(((S::kOuterA ? wr : wc) * Sh::SO) << 14) + lane_off, (unsigned)lane * 16u, c0 >> 4,
+               c0 & 15};
+  lds_u8* b0 = (lds_u8*)&stage[0][0];
+  lds_u8* b1 = (lds_u8*)&stage[1][0];
+
+  v4i z[Sh::HO], ob[2][Sh::HO], d0[Sh::HI][8], d1[Sh::HI][8];
+  const int klast = kbeg + 2 * (nsteps - 1);
+  if (nsteps > 0) {
+    auto off = [&](int st) {
+      return lstep<S::kOuterA>(s0, s1, w0, w1, p.kb0, min(kbeg + 2 * st, klast));
+    };
+    // prologue: step 0's outer run into buffer 0, its inner planes into registers
+    {
+      const LStep o = off(0);
+#pragma unroll
+      for (int j = 0; j < Sh::kCopies; ++j) copy_unit(c, o, b0, j);
+#pragma unroll
+      for (int h = 0; h < Sh::HI; ++h)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d0[h][i] = ld_buf(o.inner, lo.at(h, i), o.off(h >> 1));
+      lds_handover<0>();
+#pragma unroll
+      for (int h = 0; h < Sh::HO; ++h) z[h] = lds_frag(b0, c, h, 0);
+    }
+    // Steps alternate between the two LDS buffers and the two sets of inner
+    // planes; the loop body holds two steps.  An odd last step (the tail)
+    // issues no loads; otherwise loads past the last step re-read its blocks
+    // (valid memory, results unused) and complete at its hand-over.
+    using R = LRegs<SA, SB>;
+    lds_step<SA, SB, true, false>(R{acc, z, ob, d0, d1, b0, b1}, c, off(1), lo);
+    int st = 1;
+    for (; st + 1 < nsteps; st += 2) {
+      lds_step<SA, SB, false, false>(R{acc, z, ob, d1, d0, b1, b0}, c, off(st + 1), lo);
+      lds_step<SA, SB, false, false>(R{acc, z, ob, d0, d1, b0, b1}, c, off(st + 2), lo);
+    }
+    if (st < nsteps) lds_step<SA, SB, false, true>(R{acc, z, ob, d1, d0, b1, b0}, c, off(st + 1), lo);
+  } else {
 #pragma unroll
     for (int x = 0; x < S::HA; ++x)
 #pragma unroll
-      for (int y = 0; y < S::HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
-
-  // Epilogue: C = sum_s 2^(8s) X_s (mod 2^64), then the shared epilogue.
-  // 16x16 accumulator layout: lane l, register e holds row 4*(l/16) + e and
-  // column l%16 of the 16x16 block.
-  const Epilogue& ep = p.ep;
+      for (int y = 0; y < S::HB; ++y)
 #pragma unroll
-  for (int y = 0; y < S::HB; ++y) {
-    const i64 n = tn * S::BN + wc * 32 * SB + y * 16 + (lane & 15);
-    const bool n_ok = n < p.N;
-    const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
-#pragma unroll
-    for (int x = 0; x < S::HA; ++x) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const i64 m = tm * S::BM + wr * 32 * SA + x * 16 + 4 * (lane >> 4) + e;
-        u64 v = 0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
-        if (n_ok && m < p.M) {
-          const i64 off = m * ep.view.ld_m + coff;
-          if (ep.accumulate) v += ep.Out[off];
-          if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
-          if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
-          ep.Out[off] = v;
-        }
-      }
-    }
+        for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
+  store_tile<SA, SB>(acc, p, tm, tn, wr, wc, lane);
 }
 
 }  // namespace
@@ -551,8 +846,8 @@ int limb_tiles(i64 M, i64 N, int variant) {
   const i64 bm = 64 * limb_variant_sa(variant), bn = 64 * limb_variant_sb(variant);
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
-int limb_variant_sa(int variant) { return variant == kLimb128x64 ? 2 : 1; }
-int limb_variant_sb(int variant) { return variant == kLimb64x128 ? 2 : 1; }
+int limb_variant_sa(int variant) { return variant == kLimb128x64 || variant == kLimbLds128x64 ? 2 : 1; }
+int limb_variant_sb(int variant) { return variant == kLimb64x128 || variant == kLimbLds64x128 ? 2 : 1; }
 
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
                        i64 total_blocks, int kind, int mode) {
@@ -585,6 +880,9 @@ hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map
     case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, block, 0, s, probs, map, sched); break;
     case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, block, 0, s, probs, map, sched); break;
     case kLimb64x64: hipLaunchKernelGGL((k_limb_gemm<1, 1>), grid, block, 0, s, probs, map, sched); break;
+    case kLimbLds128x64: hipLaunchKernelGGL((k_limb_gemm_lds<2, 1>), grid, block, 0, s, probs, map, sched); break;
+    case kLimbLds64x128: hipLaunchKernelGGL((k_limb_gemm_lds<1, 2>), grid, block, 0, s, probs, map, sched); break;
+    case kLimbLds64x64: hipLaunchKernelGGL((k_limb_gemm_lds<1, 1>), grid, block, 0, s, probs, map, sched); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
