@@ -238,8 +238,9 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmu
  * outputs, every wave fetching its operand fragments from global memory;
  * 3, 4, 5: the same shapes with the operand that has more fragments per wave
  * copied once per workgroup into LDS and read from there), the number of tile
- * rows per raster group, and whether tiles are remapped so that each XCD
- * works on a contiguous run of them. */
+ * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
+ * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
+ * runs together share operand blocks in its L2) instead of one by one. */
 typedef struct {
   int variant, group_m, xcd_remap;
   double ms; /* measured time of the tuned launch(es), filled by the tuner */

@@ -419,9 +419,22 @@ __device__ __forceinline__ void mfma_step(StepRegs<SA, SB> r, const StepOff& cur
 
 // Output tile of this workgroup.  One workgroup per tile.  Workgroups are
 // dispatched to the 8 XCDs round-robin in index order, so index b runs on XCD
-// b % 8; remapping b -> (b % 8) * (G / 8) + b / 8 gives each XCD a contiguous
-// run of tiles, which then share that XCD's L2.  Inside a problem the tiles
-// follow a grouped raster: runs of group_m tile rows, column by column.
+// b % 8 as that XCD's (b / 8)-th workgroup.  With the remap, each XCD takes
+// runs of kXcdRun consecutive tiles (one per compute unit, the tiles it runs
+// at the same time), the runs going round the XCDs in turn: the tiles an XCD
+// runs together are neighbours that share operand blocks in its L2, and when
+// tiles differ in cost (a grouped launch lists its longest problems first)
+// every XCD gets its share of each kind.  Inside a problem the tiles follow a
+// grouped raster: runs of group_m tile rows, column by column.
+constexpr int kXcds = 8, kXcdRun = 32;
+
+__device__ __forceinline__ int remap_tile(int b, int G) {
+  constexpr int span = kXcds * kXcdRun;
+  if (b >= G / span * span) return b;  // the last partial round keeps dispatch order
+  const int x = b % kXcds, j = b / kXcds;
+  return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
+}
+
 struct TilePos {
   int pi;
   i64 tm, tn;
@@ -430,9 +443,8 @@ struct TilePos {
 template <int BM, int BN>
 __device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ probs, const TileMap& map,
                                             const TileSched& sched) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int G8 = G & ~7;
-  const int t = (sched.xcd_remap && b < G8) ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
+  const int b = blockIdx.x;
+  const int t = sched.xcd_remap ? remap_tile(b, gridDim.x) : b;
   TilePos q;
   q.pi = find_problem(map.tile_start, map.nprob, t);
   const LimbProblem& p = probs[q.pi];

@@ -217,7 +217,7 @@ constexpr int kLimbVariants = 6;
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group
-  int xcd_remap;  // give each XCD a contiguous run of tiles
+  int xcd_remap;  // hand tiles to the XCDs in runs of neighbouring tiles
 };
 // ---------------------------------------------------------------- binary sharing (two parties)
 // Slots: 0x700 share, 0x701..0x705 AND triple a0, a1, b0, b1, c0, 0x706/0x707
