@@ -488,6 +488,8 @@ struct JobSpec {
   i64 rows = 0, K = 0, ld = 0;
   i64 cin = 0, len = 0, ksz = 1, stride = 1, lout = 1;
   const u64* in[kPackMaxIn] = {nullptr, nullptr, nullptr, nullptr};
+  u64 key[2] = {0, 0};
+  u64* share[2] = {nullptr, nullptr};
 };
 
 size_t job_bytes(const JobSpec& j) { return (size_t)pack_nout(j.mode) * align_up(packed_bytes(j.rows, j.K)); }
@@ -505,6 +507,10 @@ PackJob place_job(const JobSpec& j, Carve& cv) {
   p.stride = j.stride;
   p.lout = j.lout;
   for (int i = 0; i < kPackMaxIn; ++i) p.in[i] = j.in[i];
+  for (int i = 0; i < 2; ++i) {
+    p.key[i] = j.key[i];
+    p.share[i] = j.share[i];
+  }
   p.rblocks = limb_rblocks(j.rows);
   p.kblocks = limb_kblocks(j.K);
   for (int o = 0; o < kPackMaxOut; ++o)
@@ -548,6 +554,15 @@ void set_mode(JobSpec& j, int mode, std::initializer_list<const u64*> ins) {
   int n = 0;
   for (const u64* p : ins) j.in[n++] = p;
 }
+// Dealer operand drawn while it is packed: shares G(k0, e), G(k1, e) written
+// to s0, s1, their sum packed.
+void set_prg_sum2(JobSpec& j, u64 k0, u64 k1, u64* s0, u64* s1) {
+  j.mode = kModePrgSum2;
+  j.key[0] = k0;
+  j.key[1] = k1;
+  j.share[0] = s0;
+  j.share[1] = s1;
+}
 // The fused open of a Beaver operand pair: (x, a) gives eps, g0 = a0 + eps and
 // a1; (y, b) gives delta, b0 and b1.
 void open_left(JobSpec& j, const u64* x0, const u64* x1, const u64* a0, const u64* a1) {
@@ -574,7 +589,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   std::vector<std::pair<int, int>> launch_km;
   std::vector<size_t> first_job;
   for (int kind : {kPackRow, kPackCol, kPackIm2col})
-    for (int mode : {kModeCopy, kModeSum2, kModeOpenLeft, kModeOpenRight}) {
+    for (int mode : {kModeCopy, kModeSum2, kModeOpenLeft, kModeOpenRight, kModePrgSum2}) {
       bool any = false;
       for (const PackJob& j : jobs_in) {
         if (j.kind != kind || j.mode != mode) continue;
@@ -1003,16 +1018,35 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
   JobSpec jl = left_job(M, K, K), jr = kind == MPC_TRIPLE_MATMUL ? right_job(K, N, N) : im2col_job(cs, lout);
   set_mode(jl, kModeSum2, {L0, L1});
   set_mode(jr, kModeSum2, {R0, R1});
+  // In the limb form a matrix operand's shares are drawn inside its pack
+  // (each element is packed exactly once), so they are written once and never
+  // read back; an im2col operand (overlapping windows, possibly uncovered
+  // tail elements) and the plain form take the shares from PRG fills.
+  const bool limb = form == MPC_FORM_LIMB8 && nc > 0;
+  const bool a_left = kind == MPC_TRIPLE_MATMUL;  // which triple factor is the left operand
+  u64* Ls[2] = {a_left ? t->a0 : t->b0, a_left ? t->a1 : t->b1};
+  u64* Rs[2] = {a_left ? t->b0 : t->a0, a_left ? t->b1 : t->a1};
+  const int Lslot = a_left ? kSlotA0 : kSlotB0, Rslot = a_left ? kSlotB0 : kSlotA0;
+  const bool fuse_r = limb && kind == MPC_TRIPLE_MATMUL;
+  if (limb) set_prg_sum2(jl, key[Lslot], key[Lslot + 1], Ls[0], Ls[1]);
+  if (fuse_r) set_prg_sum2(jr, key[Rslot], key[Rslot + 1], Rs[0], Rs[1]);
   size_t need = kAlign;
   if (form == MPC_FORM_LIMB8) need += job_bytes(jl) + job_bytes(jr);
   else if (kind == MPC_TRIPLE_CONV1D) need += align_up((size_t)(K * N) * 8);
   CHK(ensure_ws(c, need));
-  CHK(hip_status(launch_prg_fill(st, key[kSlotA0], t->a0, na)));
-  CHK(hip_status(launch_prg_fill(st, key[kSlotA1], t->a1, na)));
-  CHK(hip_status(launch_prg_fill(st, key[kSlotB0], t->b0, nb)));
-  CHK(hip_status(launch_prg_fill(st, key[kSlotB1], t->b1, nb)));
+  const size_t nl = a_left ? na : nb, nr = a_left ? nb : na;
+  if (!limb) {
+    CHK(hip_status(launch_prg_fill(st, key[Lslot], Ls[0], nl)));
+    CHK(hip_status(launch_prg_fill(st, key[Lslot + 1], Ls[1], nl)));
+    c->stats.launches += 2;
+  }
+  if (!fuse_r) {
+    CHK(hip_status(launch_prg_fill(st, key[Rslot], Rs[0], nr)));
+    CHK(hip_status(launch_prg_fill(st, key[Rslot + 1], Rs[1], nr)));
+    c->stats.launches += 2;
+  }
   CHK(hip_status(launch_prg_fill(st, key[kSlotC0], t->c0, nc)));
-  c->stats.launches += 5;
+  c->stats.launches += 1;
   if (nc) {
     Carve cv(c->ws);
     if (form == MPC_FORM_LIMB8) {

@@ -86,6 +86,10 @@ template <> struct Mode<kModeSum2> {
   static constexpr int nin = 2, nout = 1;
   __device__ static u64 out(int, const u64* v) { return v[0] + v[1]; }
 };
+template <> struct Mode<kModePrgSum2> {  // v0, v1 drawn from the PRG -> v0 + v1
+  static constexpr int nin = 2, nout = 1;
+  __device__ static u64 out(int, const u64* v) { return v[0] + v[1]; }
+};
 template <> struct Mode<kModeOpenLeft> {  // x0, x1, a0, a1 -> eps, g0 = a0 + eps, a1
   static constexpr int nin = 4, nout = 3;
   __device__ static u64 out(int o, const u64* v) {
@@ -171,7 +175,17 @@ __global__ void __launch_bounds__(kPackThreads)
   for (int i = 0; i < Md::nin; ++i) in[i] = gptr(jb.in[i]);
   const bool interior = (rb + 1) * 32 <= jb.rows && (kb + 1) * 32 <= jb.K;
   u64 v[16][Md::nin];
-  if (interior) {
+  if constexpr (MODE == kModePrgSum2) {
+    // the shares are the PRG at each element's row-major offset; write them
+    // out in this (coalesced) load layout
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        v[q][i] = ok[q] ? sm_out(jb.key[i], (u64)off[q]) : 0;
+        if (ok[q]) jb.share[i][off[q]] = v[q][i];
+      }
+  } else if (interior) {
 #pragma unroll
     for (int q = 0; q < 16; ++q)
 #pragma unroll
@@ -874,9 +888,11 @@ hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_star
   MPC_PACK_CASE(kPackRow, kModeSum2)
   MPC_PACK_CASE(kPackRow, kModeOpenLeft)
   MPC_PACK_CASE(kPackRow, kModeOpenRight)
+  MPC_PACK_CASE(kPackRow, kModePrgSum2)
   MPC_PACK_CASE(kPackCol, kModeCopy)
   MPC_PACK_CASE(kPackCol, kModeSum2)
   MPC_PACK_CASE(kPackCol, kModeOpenRight)
+  MPC_PACK_CASE(kPackCol, kModePrgSum2)
   MPC_PACK_CASE(kPackIm2col, kModeSum2)
   MPC_PACK_CASE(kPackIm2col, kModeOpenLeft)
 #undef MPC_PACK_CASE

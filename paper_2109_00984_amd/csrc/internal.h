@@ -102,7 +102,11 @@ constexpr int kLimbRowPad = 4;
 //   kind IM2COL: right operand, k = c*ksz + j, n = b*Lout + l, element
 //                in[b][c][l*stride + j] of a [B][Cin][L] activation
 enum PackKind : int { kPackRow = 0, kPackCol = 1, kPackIm2col = 2 };
-enum PackMode : int { kModeCopy = 0, kModeSum2 = 1, kModeOpenLeft = 2, kModeOpenRight = 3 };
+// kModePrgSum2 draws the two inputs from the PRG instead of reading them:
+// element e (its row-major offset) gets v_i = G(key[i], e), which is also
+// written to share[i][e]; the packed output is v_0 + v_1.  Used by the
+// dealer for matrix operands, where every element is visited exactly once.
+enum PackMode : int { kModeCopy = 0, kModeSum2 = 1, kModeOpenLeft = 2, kModeOpenRight = 3, kModePrgSum2 = 4 };
 constexpr int kPackMaxIn = 4, kPackMaxOut = 3;
 
 struct PackJob {
@@ -116,10 +120,14 @@ struct PackJob {
   uint8_t* dst[kPackMaxOut];
   i64 rblocks;  // padded block counts of every output
   i64 kblocks;
+  u64 key[2];    // kModePrgSum2: PRG stream keys of the two shares
+  u64* share[2];  // kModePrgSum2: where the two shares are written
 };
 
-inline int pack_nin(int mode) { return mode == kModeCopy ? 1 : mode == kModeSum2 ? 2 : 4; }
-inline int pack_nout(int mode) { return mode <= kModeSum2 ? 1 : 3; }
+inline int pack_nin(int mode) {
+  return mode == kModeCopy ? 1 : (mode == kModeSum2 || mode == kModePrgSum2) ? 2 : 4;
+}
+inline int pack_nout(int mode) { return (mode <= kModeSum2 || mode == kModePrgSum2) ? 1 : 3; }
 
 // Limb-form problem over packed segments; k-blocks [kb_begin, kb_end) of the
 // concatenation [segment 0 | segment 1] are processed (K chunking).

@@ -117,7 +117,10 @@ def test_dealer_elementwise(m, ctx, n):
         assert np.array_equal(host(ctx, g), e)
 
 
-@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 32, 128), (37, 53, 70), (130, 70, 300)])
+# the first four take the plain form, the rest the limb form (work >= 2^22),
+# whose packs draw a and b from the PRG themselves
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 32, 128), (37, 53, 70), (130, 70, 300),
+                                   (200, 150, 300), (257, 33, 1000), (2048, 2049, 1), (64, 64, 1024)])
 def test_dealer_matmul(m, ctx, M, N, K):
     say(f"dealer matmul {M}x{N}x{K}")
     t = ctx.dealer(m.TRIPLE_MATMUL, 3001, 7, (M, N, K))
@@ -238,7 +241,7 @@ def test_round_counters(m, ctx):
 
 # ------------------------------------------------------------------ conv1d
 CONV_SMALL = [(2, 3, 17, 4, 5, 2), (1, 40, 100, 16, 48, 2), (2, 8, 30, 8, 7, 1),
-              (1, 16, 40, 32, 1, 1)]
+              (1, 16, 40, 32, 1, 1), (4, 16, 300, 64, 7, 1)]
 
 
 @pytest.mark.parametrize("form", ["plain", "limb8"])
@@ -251,7 +254,8 @@ def test_beaver_conv1d(m, ctx, form, Bt, Cin, L, Cout, k, s):
     dims = (Bt, Cin, L, Cout, k, s)
     t = ctx.dealer(m.TRIPLE_CONV1D, 3004, 70, dims)
     wt = oracle.dealer_conv1d(3004, 70, *dims)
-    for g, e in [(t.a0, wt.a[0]), (t.b1, wt.b[1]), (t.c0, wt.c[0]), (t.c1, wt.c[1])]:
+    for g, e in [(t.a0, wt.a[0]), (t.a1, wt.a[1]), (t.b0, wt.b[0]), (t.b1, wt.b[1]), (t.c0, wt.c[0]),
+                 (t.c1, wt.c[1])]:
         assert np.array_equal(host(ctx, g), e)
     z = ctx.beaver_conv1d(ctx.share(dev(X), 0, 71), ctx.share(dev(W), 1, 72), t, s, 16, form)
     want = oracle.beaver_conv1d(xs, ws, wt, s, 16)
