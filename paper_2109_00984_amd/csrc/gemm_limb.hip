@@ -303,15 +303,16 @@ __device__ __forceinline__ StepOff step_off(const SegSrc& s0, const SegSrc& s1, 
 // group g = l/16, i.e. k-block kb + g/2, plane lane 16*h + l%16 + 32*(g%2).
 // The k order inside a step is the same for both operands, which is all the
 // product needs.  lane_off = (g/2)*8192 + (g%2)*512 + (l%16)*16; half h and
-// plane i add h*256 + i*1024.
+// plane i add h*256 + i*1024, which go into the scalar offset so that every
+// load of a wave shares the one lane-offset register.
 struct LaneOff {
   unsigned lo;
-  __device__ unsigned at(int h, int i) const { return lo + (unsigned)((h & 1) * 256 + i * 1024); }
+  __device__ static int sub(int h, int i) { return (h & 1) * 256 + i * 1024; }
 };
 
 __device__ __forceinline__ v4i ld_frag(__amdgpu_buffer_rsrc_t r, const LaneOff& lo, const StepOff& o,
                                        int h, int i) {
-  return ld_buf(r, lo.at(h, i), o.off(h >> 1));
+  return ld_buf(r, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
 }
 
 // acc += A @ B on one 16x16x64 int8 tile, accumulating in place.  Written as
@@ -620,18 +621,28 @@ struct LShape {
   static constexpr int kStrips = 2 * SO;           // outer strips per workgroup
   static constexpr int kBufBytes = kStrips << 14;  // two 8 KiB k-blocks per strip
   static constexpr int kCopies = kStrips * 4;      // 1 KiB copies per wave and step
-  // Every inner plane is double-buffered (the registers the outer operand no
-  // longer needs pay for it), so a step's global loads need not wait for the
-  // last use of anything: all of them go out in levels 0..kLoadLevels-1, the
-  // copies first, leaving a long slack before the hand-over waits for them.
-  static constexpr int kLoadLevels = 3;
-  static constexpr int kLoads = kCopies + HI * 8;
+  // Workgroups per CU.  The 64x64 tile (128 accumulator registers) runs two
+  // per CU, so one's prologue, epilogue and stalls overlap the other's
+  // MFMAs; that leaves 128 other registers per lane.
+  static constexpr int kMinBlocks = SA * SB == 1 ? 2 : 1;
+  // Inner planes 0..kDbl-1 are double-buffered; planes kDbl..7 are reloaded
+  // in place for the next step at level 8 - p, after their last use.  The
+  // large tiles double-buffer all of them (the registers the outer operand no
+  // longer needs pay for it); the 64x64 tile cannot afford that at two
+  // workgroups per CU.
+  static constexpr int kDbl = kMinBlocks == 2 ? 3 : 8;
+  // Levels 0..kLoadLevels-1 issue every global load of a step: the copies
+  // first, then the double-buffered planes, then the in-place planes 7, 6,
+  // ..., kDbl, each load in the level of its position in proportion to the
+  // levels' MFMAs.  The hand-over in level 6 finds them long done.
+  static constexpr int kLoadLevels = kDbl == 8 ? 3 : 9 - kDbl;
+  static constexpr int kInner = HI * 8;
+  static constexpr int kLoads = kCopies + kInner;
   static constexpr int mfmas_upto(int L) {
     int c = 0;
     for (int l = 0; l <= L; ++l) c += (8 - l) * HO * HI;
     return c;
   }
-  // Loads issued in levels 0..L, in proportion to the levels' MFMAs.
   static constexpr int loads_upto(int L) {
     if (L < 0) return 0;
     if (L >= kLoadLevels - 1) return kLoads;
@@ -639,19 +650,27 @@ struct LShape {
     return (kLoads * mfmas_upto(L) + last / 2) / last;
   }
   static constexpr int loads_at(int L) { return loads_upto(L) - loads_upto(L - 1); }
-  static constexpr bool loads_fit() {
+  static constexpr int level_of(int q) {
+    int L = 0;
+    while (loads_upto(L) <= q) ++L;
+    return L;
+  }
+  // Load q >= kCopies + HI*kDbl reloads plane p = 7 - (q - kCopies - HI*kDbl)/HI.
+  static constexpr bool schedule_ok() {
     for (int L = 0; L < 8; ++L)
-      if (loads_at(L) >= (8 - L) * HO * HI) return false;
+      if (loads_at(L) >= (8 - L) * HO * HI) return false;  // at most one load per MFMA
+    for (int q = kCopies + HI * kDbl; q < kLoads; ++q)
+      if (level_of(q) < 8 - (7 - (q - kCopies - HI * kDbl) / HI)) return false;  // after last use
     return true;
   }
-  static_assert(loads_fit(), "at most one load after each MFMA of a level");
-  static_assert(2 * kBufBytes <= 160 * 1024, "two step buffers must fit in LDS");
+  static_assert(schedule_ok(), "load schedule");
+  static_assert(2 * kBufBytes * kMinBlocks <= 160 * 1024, "step buffers must fit in LDS");
   // Vector-memory loads complete in issue order, and a step issues its copies
   // before its inner loads, so the hand-over need not wait for the last
   // kPending loads (inner planes for the next step, still in flight); half of
   // the inner loads keeps a margin.
-  static constexpr int kPending = HI * 8 / 2;
-  static_assert(kPending <= HI * 8 && kPending < 64, "vmcnt holds the pending inner loads");
+  static constexpr int kPending = kInner / 2;
+  static_assert(kPending < 64, "vmcnt holds the pending inner loads");
 };
 
 // Descriptors and offsets of one k step: the wave's inner strips and the
@@ -706,25 +725,29 @@ struct LRegs {
   v4i (&acc)[2 * SA][2 * SB][8];
   v4i (&z)[Sh::HO];      // outer limb 0
   v4i (&ob)[2][Sh::HO];  // outer limbs 1..7: limb l in ob[l & 1]
-  const v4i (&dcur)[Sh::HI][8];  // inner planes of this step
-  v4i (&dnext)[Sh::HI][8];       // and of the next
+  v4i (&inner)[Sh::HI][8];  // inner planes kDbl..7 (reloaded in place)
+  const v4i (&dcur)[Sh::HI][Sh::kDbl];  // inner planes 0..kDbl-1 of this step
+  v4i (&dnext)[Sh::HI][Sh::kDbl];       // and of the next
 
   const lds_u8* cur;  // this step's outer blocks
   lds_u8* next;       // the next step's
 };
 
 // Global load number Q of level L: the step's copies come first, then the
-// next step's inner planes.
+// next step's double-buffered inner planes, then its in-place planes.
 template <int SA, int SB, int L, int Q>
 __device__ __forceinline__ void lds_level_load(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
                                                const LaneOff& lo) {
   using Sh = LShape<SA, SB>;
-  constexpr int q = Sh::loads_upto(L - 1) + Q;
+  constexpr int q = Sh::loads_upto(L - 1) + Q, ND = Sh::kDbl;
   if constexpr (q < Sh::kCopies) {
     copy_unit(c, next, r.next, q);
+  } else if constexpr (q < Sh::kCopies + Sh::HI * ND) {
+    constexpr int h = (q - Sh::kCopies) / ND, i = (q - Sh::kCopies) % ND;
+    r.dnext[h][i] = ld_buf(next.inner, lo.lo, next.off(h >> 1) + LaneOff::sub(h, i));
   } else {
-    constexpr int h = (q - Sh::kCopies) / 8, i = (q - Sh::kCopies) % 8;
-    r.dnext[h][i] = ld_buf(next.inner, lo.at(h, i), next.off(h >> 1));
+    constexpr int u = q - Sh::kCopies - Sh::HI * ND, h = u % Sh::HI, i = 7 - u / Sh::HI;
+    r.inner[h][i] = ld_buf(next.inner, lo.lo, next.off(h >> 1) + LaneOff::sub(h, i));
   }
 }
 
@@ -740,7 +763,7 @@ __device__ __forceinline__ void lds_level(LRegs<SA, SB>& r, const LCtx& c, const
   constexpr int NM = (8 - L) * HO * HI;
   if constexpr (M < NM) {
     constexpr int s = L + M / (HO * HI), o = (M / HI) % HO, i = M % HI;
-    const v4i& in = r.dcur[i][s - L];
+    const v4i& in = (s - L) < Sh::kDbl ? r.dcur[i][(s - L) % Sh::kDbl] : r.inner[i][s - L];
     const v4i& out = L == 0 ? r.z[o] : r.ob[L & 1][o];
     v4i& acc = Sh::S::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
     const v4i& a = Sh::S::kOuterA ? out : in;
@@ -783,11 +806,16 @@ __device__ __forceinline__ void lds_levels(LRegs<SA, SB>& r, const LCtx& c, cons
 
 template <int SA, int SB, bool FIRST, bool LAST>
 __device__ __forceinline__ void lds_step(LRegs<SA, SB> r, const LCtx& c, const LStep& next, const LaneOff& lo) {
-  lds_levels<SA, SB, FIRST, LAST, 0>(r, c, next, lo);
+  // Re-define the LDS read base in every step: otherwise each (buffer, half,
+  // limb) address is hoisted out of the loop into a register of its own,
+  // instead of one base register and the read's immediate offset.
+  LCtx cs = c;
+  asm volatile("" : "+v"(cs.rd));
+  lds_levels<SA, SB, FIRST, LAST, 0>(r, cs, next, lo);
 }
 
 template <int SA, int SB>
-__global__ void __launch_bounds__(kThreads, 1)
+__global__ void __launch_bounds__(kThreads, (SA * SB == 1 ? 2 : 1))  // LShape::kMinBlocks
     k_limb_gemm_lds(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
   using S = Shape<SA, SB>;
   using Sh = LShape<SA, SB>;
@@ -819,7 +847,7 @@ __global__ void __launch_bounds__(kThreads, 1)
   lds_u8* b0 = (lds_u8*)&stage[0][0];
   lds_u8* b1 = (lds_u8*)&stage[1][0];
 
-  v4i z[Sh::HO], ob[2][Sh::HO], d0[Sh::HI][8], d1[Sh::HI][8];
+  v4i z[Sh::HO], ob[2][Sh::HO], inner[Sh::HI][8], d0[Sh::HI][Sh::kDbl], d1[Sh::HI][Sh::kDbl];
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
     auto off = [&](int st) {
@@ -831,9 +859,12 @@ __global__ void __launch_bounds__(kThreads, 1)
 #pragma unroll
       for (int j = 0; j < Sh::kCopies; ++j) copy_unit(c, o, b0, j);
 #pragma unroll
-      for (int h = 0; h < Sh::HI; ++h)
+      for (int h = 0; h < Sh::HI; ++h) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) d0[h][i] = ld_buf(o.inner, lo.at(h, i), o.off(h >> 1));
+        for (int i = 0; i < Sh::kDbl; ++i) d0[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
+#pragma unroll
+        for (int i = Sh::kDbl; i < 8; ++i) inner[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
+      }
       lds_handover<0>();
 #pragma unroll
       for (int h = 0; h < Sh::HO; ++h) z[h] = lds_frag(b0, c, h, 0);
@@ -843,13 +874,13 @@ __global__ void __launch_bounds__(kThreads, 1)
     // issues no loads; otherwise loads past the last step re-read its blocks
     // (valid memory, results unused) and complete at its hand-over.
     using R = LRegs<SA, SB>;
-    lds_step<SA, SB, true, false>(R{acc, z, ob, d0, d1, b0, b1}, c, off(1), lo);
+    lds_step<SA, SB, true, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(1), lo);
     int st = 1;
     for (; st + 1 < nsteps; st += 2) {
-      lds_step<SA, SB, false, false>(R{acc, z, ob, d1, d0, b1, b0}, c, off(st + 1), lo);
-      lds_step<SA, SB, false, false>(R{acc, z, ob, d0, d1, b0, b1}, c, off(st + 2), lo);
+      lds_step<SA, SB, false, false>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
+      lds_step<SA, SB, false, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(st + 2), lo);
     }
-    if (st < nsteps) lds_step<SA, SB, false, true>(R{acc, z, ob, d1, d0, b1, b0}, c, off(st + 1), lo);
+    if (st < nsteps) lds_step<SA, SB, false, true>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
   } else {
 #pragma unroll
     for (int x = 0; x < S::HA; ++x)
