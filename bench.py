@@ -113,12 +113,14 @@ def main():
     if args.form == "limb8":
         per_launch_ops = 72.0 * g["ring_macs"] / max(1, g["launches"])  # 36 int8 MACs per ring MAC
         achieved = per_launch_ops / (avg_ms * 1e-3) / 1e12
-        traffic, alg_bytes = measured_traffic()
+        tile = ctx.default_tile_config()
+        kernel = "k_limb_gemm_lds" if tile["variant"].startswith("lds") else "k_limb_gemm"
+        traffic, alg_bytes = measured_traffic(kernel)
         roofline = {"bound": "mfma", "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
                     "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE "
                     "+ WRITE_SIZE, copy-calibrated)", "algorithmic_bytes_per_launch": alg_bytes,
-                    "kernel": "k_limb_gemm", "launches": g["launches"],
+                    "kernel": kernel, "tile": tile["variant"], "launches": g["launches"],
                     "avg_launch_ms": round(avg_ms, 4),
                     "work_per_launch": "72 int8 ops per ring multiply-accumulate (36 limb pairs)"}
     else:
@@ -175,7 +177,10 @@ def main():
     return 0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_limb_gemm_secure_gemm_4096_traffic.md")
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_secure_gemm_4096_traffic.md")
+
+
 LIMB_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "gemm_limb.hip")
 API_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "api.cpp")
 
@@ -190,14 +195,14 @@ def kernel_fingerprint():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per limb-GEMM launch of this workload (and the algorithmic
     bytes beside them), from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary, each counter scaled by its reading on a copy of known size.
     (None, None) when no summary exists or the kernel or its default schedule
     has changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(traffic_file(kernel)).read()
     except OSError:
         return None, None
     keys = ("kernel_sha256", "hbm_bytes_per_launch", "algorithmic_bytes_per_launch")

@@ -256,8 +256,11 @@ mpc_status mpc_autotune_matmul(mpc_ctx *ctx, size_t count, const int64_t *dims, 
 /* Writes / reads the tuned schedules (a text file, one entry per line). */
 mpc_status mpc_autotune_save(const mpc_ctx *ctx, const char *path);
 mpc_status mpc_autotune_load(mpc_ctx *ctx, const char *path);
-/* Schedule used when no tuned entry matches (default: 64x128, 8, remap on). */
+/* Schedule used when no tuned entry matches (default: shape 5, the 64x64
+ * LDS tile at two workgroups per compute unit, group_m 8, remap on): set it,
+ * or read it back (`ms` reads 0). */
 mpc_status mpc_set_default_tile_config(mpc_ctx *ctx, const mpc_tile_config *cfg);
+mpc_status mpc_get_default_tile_config(const mpc_ctx *ctx, mpc_tile_config *cfg);
 
 /* Stream capture of the context's work into a HIP graph: begin, issue calls,
  * end.  Party 0's stream must not be the null stream.  The workspace must

@@ -97,6 +97,7 @@ _SIGS = {
     "mpc_autotune_save": (INT, [VP, ctypes.c_char_p]),
     "mpc_autotune_load": (INT, [VP, ctypes.c_char_p]),
     "mpc_set_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
+    "mpc_get_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
     "mpc_graph_begin": (INT, [VP]),
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
     "mpc_graph_launch": (INT, [VP, VP]),
@@ -590,6 +591,12 @@ class Context:
         cfg = TileConfig(variant, group_m, 1 if xcd_remap else 0, 0.0)
         _check(_lib.mpc_set_default_tile_config(self._h, ctypes.byref(cfg)),
                "mpc_set_default_tile_config")
+
+    def default_tile_config(self):
+        cfg = TileConfig()
+        _check(_lib.mpc_get_default_tile_config(self._h, ctypes.byref(cfg)), "mpc_get_default_tile_config")
+        return {"variant": TILE_VARIANTS[cfg.variant], "variant_id": int(cfg.variant),
+                "group_m": int(cfg.group_m), "xcd_remap": bool(cfg.xcd_remap)}
 
     # -------------------------------------------------------------- graphs
     def graph_begin(self):

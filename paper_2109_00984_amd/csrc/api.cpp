@@ -80,7 +80,7 @@ struct mpc_ctx {
   std::vector<hipEvent_t> event_pool;
   // limb GEMM tile schedule used when no tuned entry matches, and the tuned
   // schedules keyed by the hash of a matmul shape list
-  TileSched sched_default{kLimb64x128, 8, 1};
+  TileSched sched_default{kLimbLds64x64, 8, 1};
   std::map<uint64_t, TileSched> tuned;
   // vendor BLAS handle of the fp64 limb form (created on first use)
   rocblas_handle blas = nullptr;
@@ -1532,6 +1532,12 @@ mpc_status mpc_autotune_load(mpc_ctx* c, const char* path) {
   while (std::fscanf(f, "%llx %d %d %d", &key, &v, &gm, &remap) == 4)
     if (v >= 0 && v < kLimbVariants && gm >= 1) c->tuned[(uint64_t)key] = TileSched{v, gm, remap ? 1 : 0};
   std::fclose(f);
+  return MPC_OK;
+}
+
+mpc_status mpc_get_default_tile_config(const mpc_ctx* c, mpc_tile_config* cfg) {
+  if (!c || !cfg) return MPC_E_INVAL;
+  *cfg = mpc_tile_config{c->sched_default.variant, c->sched_default.group_m, c->sched_default.xcd_remap, 0.0};
   return MPC_OK;
 }
 

@@ -435,19 +435,20 @@ __device__ __forceinline__ void mfma_step(StepRegs<SA, SB> r, const StepOff& cur
 // Output tile of this workgroup.  One workgroup per tile.  Workgroups are
 // dispatched to the 8 XCDs round-robin in index order, so index b runs on XCD
 // b % 8 as that XCD's (b / 8)-th workgroup.  With the remap, each XCD takes
-// runs of kXcdRun consecutive tiles (one per compute unit, the tiles it runs
-// at the same time), the runs going round the XCDs in turn: the tiles an XCD
-// runs together are neighbours that share operand blocks in its L2, and when
-// tiles differ in cost (a grouped launch lists its longest problems first)
-// every XCD gets its share of each kind.  Inside a problem the tiles follow a
-// grouped raster: runs of group_m tile rows, column by column.
-constexpr int kXcds = 8, kXcdRun = 32;
+// runs of `run` consecutive tiles, the tiles it holds at one time (its 32
+// compute units times the workgroups per unit), the runs going round the XCDs
+// in turn: the tiles an XCD runs together are neighbours that share operand
+// blocks in its L2, and when tiles differ in cost (a grouped launch lists its
+// longest problems first) every XCD gets its share of each kind.  Inside a
+// problem the tiles follow a grouped raster: runs of group_m tile rows, column
+// by column.
+constexpr int kXcds = 8, kXcdCUs = 32;
 
-__device__ __forceinline__ int remap_tile(int b, int G) {
-  constexpr int span = kXcds * kXcdRun;
+__device__ __forceinline__ int remap_tile(int b, int G, int run) {
+  const int span = kXcds * run;
   if (b >= G / span * span) return b;  // the last partial round keeps dispatch order
   const int x = b % kXcds, j = b / kXcds;
-  return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
+  return ((j / run) * kXcds + x) * run + j % run;
 }
 
 struct TilePos {
@@ -455,11 +456,11 @@ struct TilePos {
   i64 tm, tn;
 };
 
-template <int BM, int BN>
+template <int BM, int BN, int PER_CU>
 __device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ probs, const TileMap& map,
                                             const TileSched& sched) {
   const int b = blockIdx.x;
-  const int t = sched.xcd_remap ? remap_tile(b, gridDim.x) : b;
+  const int t = sched.xcd_remap ? remap_tile(b, gridDim.x, kXcdCUs * PER_CU) : b;
   TilePos q;
   q.pi = find_problem(map.tile_start, map.nprob, t);
   const LimbProblem& p = probs[q.pi];
@@ -532,7 +533,7 @@ __global__ void __launch_bounds__(kThreads, 1)
   // derived from it) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const TilePos tp = tile_pos<S::BM, S::BN>(probs, map, sched);
+  const TilePos tp = tile_pos<S::BM, S::BN, 1>(probs, map, sched);
   const LimbProblem& p = probs[tp.pi];
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mb0 = tm * 2 * SA + wr * SA;  // this wave's first left 32-block
@@ -824,7 +825,7 @@ __global__ void __launch_bounds__(kThreads, (SA * SB == 1 ? 2 : 1))  // LShape::
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const TilePos tp = tile_pos<S::BM, S::BN>(probs, map, sched);
+  const TilePos tp = tile_pos<S::BM, S::BN, Sh::kMinBlocks>(probs, map, sched);
   const LimbProblem& p = probs[tp.pi];
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mw = tm * 2 * SA, nw = tn * 2 * SB;  // the workgroup's first left / right 32-block

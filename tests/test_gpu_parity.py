@@ -434,3 +434,13 @@ def test_live_graph_pins_workspace(m):
             assert z.s0.shape == (big, big)
         finally:
             c.close()
+
+
+def test_default_tile_config_roundtrip(m):
+    c = m.Context(device=0, seed=SEED)
+    assert c.default_tile_config() == {"variant": "lds64x64", "variant_id": 5, "group_m": 8, "xcd_remap": True}
+    c.set_default_tile_config(1, 4, False)
+    assert c.default_tile_config() == {"variant": "64x128", "variant_id": 1, "group_m": 4, "xcd_remap": False}
+    with pytest.raises(m.MPCError):
+        c.set_default_tile_config(6, 8, True)
+    c.close()
