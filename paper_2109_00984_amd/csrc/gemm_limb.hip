@@ -164,8 +164,14 @@ __global__ void __launch_bounds__(kPackThreads)
   const int ji = find_job(block_start, njobs, blk);
   const PackJob& jb = jobs[ji];
   const i64 local = blk - block_start[ji];
-  const i64 rb = local / jb.kblocks, kb = local % jb.kblocks;
-  const size_t boff = (size_t)local << 13;
+  // Traversal order: the waves of a workgroup take neighbouring blocks along
+  // the operand's rows in memory, so that together they read contiguous runs
+  // of each row: k-blocks for a left operand (rows are m, contiguous in k),
+  // row blocks for a right one (rows are k, contiguous in n).  The packed
+  // layout is the same either way: block (rb, kb) at rb * kblocks + kb.
+  const i64 rb = KIND == kPackRow ? local / jb.kblocks : local % jb.rblocks;
+  const i64 kb = KIND == kPackRow ? local % jb.kblocks : local / jb.rblocks;
+  const size_t boff = (size_t)(rb * jb.kblocks + kb) << 13;
 
   i64 off[16];
   bool ok[16];
