@@ -19,13 +19,16 @@
 // GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a
 // (64*SA) x (64*SB) output tile; each wave a (32*SA) x (32*SB) sub-tile held
 // as 16x16 blocks with 8 diagonal int32 accumulators each (256 accumulation
-// registers for the 128x64 and 64x128 tiles).  Each wave streams its own
-// fragments from global memory through buffer loads, one k step of loads in
-// flight behind the MFMAs of the current step: no LDS and no barrier.  One
-// workgroup per tile; tiles are remapped so each XCD works on a contiguous
-// run of them and shares operand blocks in its L2.  The 16x16x64 instruction
-// sustains a higher rate than 32x32x32 on this chip, with uniformly random
-// operands as well as constant ones.
+// registers for the 128x64 and 64x128 tiles, 128 for 64x64).  Two forms:
+// k_limb_gemm, where each wave streams its own fragments from global memory
+// through buffer loads, one k step of loads in flight behind the MFMAs of the
+// current step, with no LDS and no barrier; and k_limb_gemm_lds, where the
+// operand with more fragments per wave is copied once per workgroup into LDS
+// (its 64x64 tile runs two workgroups per CU).  One workgroup per tile; tiles
+// are remapped so the tiles an XCD holds at a time are neighbours sharing
+// operand blocks in its L2.  The 16x16x64 instruction sustains a higher rate
+// than 32x32x32 on this chip, with uniformly random operands as well as
+// constant ones.
 #include "internal.h"
 
 namespace mpc {
