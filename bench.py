@@ -186,10 +186,15 @@ API_SOURCE = os.path.join(ROOT, "paper_2109_00984_amd", "csrc", "api.cpp")
 
 
 def kernel_fingerprint():
-    """sha256 over the limb GEMM source and the library's default tile schedule
-    (the two things the GEMM's HBM traffic depends on)."""
+    """sha256 over the limb GEMM source (comments and blank space dropped) and
+    the library's default tile schedule: the two things the GEMM's HBM traffic
+    depends on."""
     import hashlib
-    h = hashlib.sha256(open(LIMB_SOURCE, "rb").read())
+    import re
+    src = open(LIMB_SOURCE).read()
+    src = re.sub(r"//[^\n]*", "", src)
+    src = "\n".join(" ".join(ln.split()) for ln in src.splitlines() if ln.strip())
+    h = hashlib.sha256(src.encode())
     sched = [ln.strip() for ln in open(API_SOURCE).read().splitlines() if "TileSched sched_default" in ln]
     h.update("\n".join(sched).encode())
     return h.hexdigest()
