@@ -293,8 +293,60 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     ex.update(binary_bench(ctx, mpc, torch, X))
     ctx.sync()
     ex.update(grouped_bench(mpc, torch, workloads))
+    ex.update(grouped_mul_bench(mpc, torch, workloads))
     ex.update(conv_bench(mpc, torch, workloads))
     return ex
+
+
+def grouped_mul_bench(mpc, torch, workloads):
+    """256 element-wise Beaver products / squares of log-uniform length in
+    [2^10, 2^20] with 2^16 truncation, captured in HIP graphs and replayed:
+    one grouped launch against one launch per product.  Algorithmic bytes: 96
+    per product element, 64 per square."""
+    rng = np.random.default_rng(workloads.seeds(6)[0])
+    ns = np.exp(rng.uniform(np.log(2 ** 10), np.log(2 ** 20), 256)).astype(np.int64)
+    sq = rng.random(256) < 0.25
+    side = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(side):
+        c = mpc.Context(device=0, seed=7)
+        probs, outs = [], []
+        nbytes = 0
+        for i, (n, s) in enumerate(zip(ns, sq)):
+            n = int(n)
+            x = c.share(c.empty((n,)), 0, 3 * i)
+            y = None if s else c.share(c.empty((n,)), 1, 3 * i + 1)
+            t = c.dealer(mpc.TRIPLE_SQUARE if s else mpc.TRIPLE_MUL, 11, i, (n,))
+            probs.append((x, y, t))
+            outs.append(mpc.SharedPair(c.empty((n,)), c.empty((n,))))
+            nbytes += (64 if s else 96) * n
+        c.sync()
+
+        def replay_ms(issue):
+            c.graph_begin()
+            issue()
+            g = c.graph_end()
+            c.graph_launch(g)
+            c.sync()
+            ms = _event_time(torch, side, lambda: c.graph_launch(g), 20)
+            mpc.Context.graph_destroy(g)
+            return ms
+
+        grouped = replay_ms(lambda: c.beaver_mul_grouped(probs, FRAC, outs=outs))
+
+        def singles():
+            for (x, y, t), o in zip(probs, outs):
+                c.beaver_mul(x, y, t, FRAC, out=o)
+
+        single = replay_ms(singles)
+        c.close()
+    out["grouped_mul256_elements"] = int(ns.sum())
+    out["grouped_mul256_graph_ms"] = round(grouped, 4)
+    out["grouped_mul256_GBps_algorithmic"] = round(nbytes / (grouped * 1e-3) / 1e9, 1)
+    out["grouped_mul256_one_launch_each_graph_ms"] = round(single, 4)
+    log(f"bench: 256 Beaver products, graph replay: grouped {grouped:.3f} ms "
+        f"({nbytes / (grouped * 1e-3) / 1e9:.0f} GB/s), one launch each {single:.3f} ms")
+    return out
 
 
 def grouped_bench(mpc, torch, workloads):

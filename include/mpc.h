@@ -233,6 +233,24 @@ typedef struct {
 mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
                                      int trunc_bits, mpc_form form);
 
+/* Many independent element-wise Beaver products (or squares) of uneven
+ * lengths in ONE launch (section 5.2; batching amortises the rounds, Section
+ * 6.1): each descriptor is what mpc_beaver_mul takes (y0 == y1 == NULL for a
+ * square with the pair a, b = a^2; c unused then), all truncated by
+ * trunc_bits.  One workgroup per chunk of 1024 elements of one product, found
+ * through a chunk table uploaded with the call (a permanent buffer made
+ * before capture when the call is captured in a graph).  Validation and
+ * aliasing rules are those of mpc_beaver_mul, and outputs of different
+ * products must not overlap.  `descs` is a HOST array of `count`
+ * descriptors. */
+typedef struct {
+  size_t n;
+  const uint64_t *x0, *x1, *y0, *y1;
+  mpc_triple t;
+  uint64_t *z0, *z1;
+} mpc_mul_desc;
+mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc *descs, int trunc_bits);
+
 /* ---- autotuning of the limb GEMM ---------------------------------------- */
 /* A tile schedule: the workgroup tile shape (0: 128x64, 1: 64x128, 2: 64x64
  * outputs, every wave fetching its operand fragments from global memory;

@@ -46,6 +46,11 @@ class MatmulDesc(ctypes.Structure):
                 ("y1", VP), ("t", Triple), ("z0", VP), ("z1", VP)]
 
 
+class MulDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_size_t), ("x0", VP), ("x1", VP), ("y0", VP), ("y1", VP), ("t", Triple),
+                ("z0", VP), ("z1", VP)]
+
+
 MAX_PARTIES = 16
 
 
@@ -97,6 +102,7 @@ _SIGS = {
     "mpc_autotune_save": (INT, [VP, ctypes.c_char_p]),
     "mpc_autotune_load": (INT, [VP, ctypes.c_char_p]),
     "mpc_set_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
+    "mpc_beaver_mul_grouped": (INT, [VP, ctypes.c_size_t, ctypes.POINTER(MulDesc), INT]),
     "mpc_get_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
     "mpc_graph_begin": (INT, [VP]),
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
@@ -567,6 +573,24 @@ class Context:
                                   y.s1.data_ptr(), t.struct(), z.s0.data_ptr(), z.s1.data_ptr())
         _check(_lib.mpc_beaver_matmul_grouped(self._h, len(problems), descs, trunc_bits,
                                               FORMS[form]), "mpc_beaver_matmul_grouped")
+        return results
+
+    def beaver_mul_grouped(self, problems, trunc_bits=0, outs=None):
+        """problems: list of (x, y or None, triple); one launch for all of them;
+        returns the list of output pairs (y None: square with the pair a, a^2)."""
+        descs = (MulDesc * max(1, len(problems)))()
+        results = []
+        for i, (x, y, t) in enumerate(problems):
+            ts = [x.s0, x.s1, t.a0, t.a1, t.b0, t.b1]
+            if y is not None:
+                ts += [y.s0, y.s1, t.c0, t.c1]
+            self._check_t(*ts)
+            z = outs[i] if outs is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+            results.append(z)
+            descs[i] = MulDesc(x.s0.numel(), _ptr(x.s0), _ptr(x.s1), _ptr(y.s0 if y is not None else None),
+                               _ptr(y.s1 if y is not None else None), t.struct(), _ptr(z.s0), _ptr(z.s1))
+        _check(_lib.mpc_beaver_mul_grouped(self._h, len(problems), descs, trunc_bits),
+               "mpc_beaver_mul_grouped")
         return results
 
     # -------------------------------------------------------------- autotuning

@@ -1433,6 +1433,74 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
   return end_call(c);
 }
 
+mpc_status mpc_beaver_mul_grouped(mpc_ctx* c, size_t count, const mpc_mul_desc* descs, int trunc_bits) {
+  if (!c || (count && !descs)) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  std::vector<MulJob> jobs;
+  uint64_t open_bytes = 0;
+  for (size_t i = 0; i < count; ++i) {
+    const mpc_mul_desc& d = descs[i];
+    const bool sq = d.y0 == nullptr && d.y1 == nullptr;
+    if (!sq && (d.y0 == nullptr || d.y1 == nullptr)) return MPC_E_INVAL;
+    const size_t n = d.n;
+    const void* in[10] = {d.x0, d.x1, d.y0, d.y1, d.t.a0, d.t.a1, d.t.b0, d.t.b1, d.t.c0, d.t.c1};
+    const int nin = sq ? 8 : 10;
+    for (int k = 0; k < nin; ++k) {
+      if (sq && (k == 2 || k == 3)) continue;
+      CHK(check_ptr(in[k], n));
+    }
+    CHK(check_ptr(d.z0, n));
+    CHK(check_ptr(d.z1, n));
+    if (overlap(d.z0, n, d.z1, n)) return MPC_E_ALIAS;
+    for (int k = 0; k < nin; ++k)
+      if (overlap(d.z0, n, in[k], n) || overlap(d.z1, n, in[k], n)) return MPC_E_ALIAS;
+    if (!n) continue;
+    // outputs of different products must not overlap either
+    for (const MulJob& o : jobs)
+      if (overlap(d.z0, n, o.z0, (size_t)o.n) || overlap(d.z0, n, o.z1, (size_t)o.n) ||
+          overlap(d.z1, n, o.z0, (size_t)o.n) || overlap(d.z1, n, o.z1, (size_t)o.n))
+        return MPC_E_ALIAS;
+    MulJob j{};
+    j.n = (i64)n;
+    j.x0 = d.x0;
+    j.x1 = d.x1;
+    j.y0 = sq ? nullptr : d.y0;
+    j.y1 = sq ? nullptr : d.y1;
+    j.a0 = d.t.a0;
+    j.a1 = d.t.a1;
+    j.b0 = d.t.b0;
+    j.b1 = d.t.b1;
+    j.c0 = sq ? nullptr : d.t.c0;
+    j.c1 = sq ? nullptr : d.t.c1;
+    j.z0 = d.z0;
+    j.z1 = d.z1;
+    bool al = true;
+    for (const void* p : {(const void*)j.x0, (const void*)j.x1, (const void*)j.y0, (const void*)j.y1,
+                          (const void*)j.a0, (const void*)j.a1, (const void*)j.b0, (const void*)j.b1,
+                          (const void*)j.c0, (const void*)j.c1, (const void*)j.z0, (const void*)j.z1})
+      if (((uintptr_t)p & 15) != 0) al = false;
+    j.vec2 = al ? 1 : 0;
+    jobs.push_back(j);
+    open_bytes += (sq ? 1 : 2) * 8 * (uint64_t)n;
+  }
+  if (jobs.empty()) return MPC_OK;
+  CHK(set_device(c));
+  std::vector<i64> cs(jobs.size() + 1, 0);
+  for (size_t i = 0; i < jobs.size(); ++i) cs[i + 1] = cs[i] + (jobs[i].n + kMulChunk - 1) / kMulChunk;
+  Blob blob;
+  const size_t ojobs = blob.add(jobs.data(), jobs.size());
+  const size_t ostart = blob.add(cs.data(), cs.size());
+  uint8_t* dev = nullptr;
+  CHK(upload(c, blob, &dev));
+  CHK(hip_status(launch_beaver_mul_grouped(c->s[0], (const MulJob*)(dev + ojobs), (const i64*)(dev + ostart),
+                                           (int)jobs.size(), cs.back(), trunc_bits)));
+  c->stats.launches++;
+  c->stats.opens += jobs.size();  // one open per product, all in the same round
+  c->stats.open_bytes_per_party += open_bytes;
+  if (trunc_bits) c->stats.truncations += jobs.size();
+  return end_call(c);
+}
+
 // ------------------------------------------------------------------ autotuning
 mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mpc_tile_config* best) {
   if (!c || (count && !dims) || c->capturing) return MPC_E_INVAL;

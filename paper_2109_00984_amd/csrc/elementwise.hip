@@ -212,6 +212,96 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// Beaver product (or square) of element i of one job: both parties' shares.
+__device__ __forceinline__ void mul_one(const MulJob& jb, i64 i, int trunc) {
+  const u64 va0 = jb.a0[i], va1 = jb.a1[i], vb0 = jb.b0[i], vb1 = jb.b1[i];
+  const u64 eps = (jb.x0[i] - va0) + (jb.x1[i] - va1);
+  u64 r0, r1;
+  if (jb.y0) {
+    const u64 del = (jb.y0[i] - vb0) + (jb.y1[i] - vb1);
+    r0 = jb.c0[i] + eps * vb0 + va0 * del + eps * del;
+    r1 = jb.c1[i] + eps * vb1 + va1 * del;
+  } else {
+    r0 = vb0 + 2 * eps * va0 + eps * eps;
+    r1 = vb1 + 2 * eps * va1;
+  }
+  jb.z0[i] = trunc_share(r0, trunc);
+  jb.z1[i] = trunc_share(r1, trunc);
+}
+
+// Many Beaver products in one launch: workgroup = one chunk of one job (the
+// job is found once per workgroup by binary search over the chunk table).
+// Aligned jobs move two elements per 16-byte load, as k_beaver_mul2 does;
+// each thread takes kMulPairs pairs kThreads apart and issues all their loads
+// before any store (the arrays of one job never overlap its outputs).
+constexpr int kMulPairs = (int)(kMulChunk / 2 / kThreads);
+static_assert(kMulPairs * 2 * kThreads == kMulChunk, "a chunk is whole rounds of pairs");
+
+__global__ void __launch_bounds__(kThreads)
+    k_beaver_mul_grouped(const MulJob* __restrict__ jobs, const i64* __restrict__ chunk_start, int njobs,
+                         int trunc) {
+  const i64 c = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (chunk_start[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const MulJob jb = jobs[lo];
+  const i64 base = (c - chunk_start[lo]) * kMulChunk;
+  const i64 end = min(base + kMulChunk, jb.n);
+  if (!jb.vec2) {
+    for (i64 i = base + threadIdx.x; i < end; i += kThreads) mul_one(jb, i, trunc);
+    return;
+  }
+  const u64 *__restrict__ x0 = jb.x0, *__restrict__ x1 = jb.x1, *__restrict__ y0 = jb.y0,
+                          *__restrict__ y1 = jb.y1, *__restrict__ a0 = jb.a0, *__restrict__ a1 = jb.a1,
+                          *__restrict__ b0 = jb.b0, *__restrict__ b1 = jb.b1, *__restrict__ c0 = jb.c0,
+                          *__restrict__ c1 = jb.c1;
+  u64* __restrict__ z0 = jb.z0;
+  u64* __restrict__ z1 = jb.z1;
+  const bool sq = y0 == nullptr;
+  const i64 p_end = base / 2 + (end - base) / 2;  // whole pairs of the chunk
+  u64x2 v[kMulPairs][10];
+#pragma unroll
+  for (int u = 0; u < kMulPairs; ++u) {
+    const i64 p = base / 2 + threadIdx.x + (i64)u * kThreads;
+    if (p < p_end) {
+      v[u][0] = ld2(x0, p);
+      v[u][1] = ld2(x1, p);
+      v[u][2] = ld2(a0, p);
+      v[u][3] = ld2(a1, p);
+      v[u][4] = ld2(b0, p);
+      v[u][5] = ld2(b1, p);
+      if (!sq) {
+        v[u][6] = ld2(y0, p);
+        v[u][7] = ld2(y1, p);
+        v[u][8] = ld2(c0, p);
+        v[u][9] = ld2(c1, p);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMulPairs; ++u) {
+    const i64 p = base / 2 + threadIdx.x + (i64)u * kThreads;
+    if (p < p_end) {
+      const u64x2 eps = (v[u][0] - v[u][2]) + (v[u][1] - v[u][3]);
+      u64x2 r0, r1;
+      if (!sq) {
+        const u64x2 del = (v[u][6] - v[u][4]) + (v[u][7] - v[u][5]);
+        r0 = v[u][8] + eps * v[u][4] + v[u][2] * del + eps * del;
+        r1 = v[u][9] + eps * v[u][5] + v[u][3] * del;
+      } else {
+        r0 = v[u][4] + 2 * eps * v[u][2] + eps * eps;
+        r1 = v[u][5] + 2 * eps * v[u][3];
+      }
+      st2(z0, p, u64x2{trunc_share(r0.x, trunc), trunc_share(r0.y, trunc)});
+      st2(z1, p, u64x2{trunc_share(r1.x, trunc), trunc_share(r1.y, trunc)});
+    }
+  }
+  if ((end - base) % 2 && threadIdx.x == 0) mul_one(jb, end - 1, trunc);  // odd last element
+}
+
 __global__ void __launch_bounds__(kThreads)
     k_im2col(const u64* __restrict__ x, const u64* __restrict__ add, i64 cin, i64 len, i64 ksz,
              i64 stride, i64 lout, i64 ncols, size_t total, u64* __restrict__ col) {
@@ -227,6 +317,14 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 }  // namespace
+
+hipError_t launch_beaver_mul_grouped(hipStream_t s, const MulJob* jobs, const i64* chunk_start, int njobs,
+                                     i64 total_chunks, int trunc) {
+  if (total_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_beaver_mul_grouped, dim3((unsigned)total_chunks), dim3(kThreads), 0, s, jobs, chunk_start,
+                     njobs, trunc);
+  return hipGetLastError();
+}
 
 hipError_t launch_prg_fill(hipStream_t s, u64 key, u64* out, size_t n) {
   if (!n) return hipSuccess;

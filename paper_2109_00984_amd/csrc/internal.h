@@ -194,6 +194,19 @@ struct OpenJob {
 constexpr i64 kOpenChunk = 4096;
 hipError_t launch_open(hipStream_t s, const OpenJob* jobs, const i64* chunk_start, int njobs,
                        i64 total_chunks);
+// Grouped element-wise Beaver products: job j multiplies (or, with y0 null,
+// squares with the pair a, b = a^2) n shared elements, then truncates; one
+// workgroup per chunk of kMulChunk elements of one job.  chunk_start
+// (njobs+1 prefix sums of per-job chunk counts) and jobs are device arrays.
+struct MulJob {
+  i64 n;
+  int vec2;  // every array 16-byte aligned: two elements per load
+  const u64 *x0, *x1, *y0, *y1, *a0, *a1, *b0, *b1, *c0, *c1;
+  u64 *z0, *z1;
+};
+constexpr i64 kMulChunk = 1024;  // even, so a chunk's first element keeps the pairs aligned
+hipError_t launch_beaver_mul_grouped(hipStream_t s, const MulJob* jobs, const i64* chunk_start, int njobs,
+                                     i64 total_chunks, int trunc);
 // col[k][n] = x[b][c][l*stride + j] (+ add) with k = c*ksz + j, n = b*Lout + l
 hipError_t launch_im2col(hipStream_t s, const u64* x, const u64* add, i64 B, i64 cin, i64 len,
                          i64 ksz, i64 stride, i64 lout, u64* col);
