@@ -255,7 +255,8 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
 /* A tile schedule: the workgroup tile shape (0: 128x64, 1: 64x128, 2: 64x64
  * outputs, every wave fetching its operand fragments from global memory;
  * 3, 4, 5: the same shapes with the operand that has more fragments per wave
- * copied once per workgroup into LDS and read from there), the number of tile
+ * copied once per workgroup into LDS and read from there; 6: 64x128 and
+ * 7: 128x64 in that LDS form with eight waves, two per SIMD), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
  * runs together share operand blocks in its L2) instead of one by one. */

@@ -66,7 +66,8 @@ class TileConfig(ctypes.Structure):
     _fields_ = [("variant", INT), ("group_m", INT), ("xcd_remap", INT), ("ms", ctypes.c_double)]
 
 
-TILE_VARIANTS = {0: "128x64", 1: "64x128", 2: "64x64", 3: "lds128x64", 4: "lds64x128", 5: "lds64x64"}
+TILE_VARIANTS = {0: "128x64", 1: "64x128", 2: "64x64", 3: "lds128x64", 4: "lds64x128", 5: "lds64x64",
+                 6: "lds64x128w8", 7: "lds128x64w8"}
 
 
 class Stats(ctypes.Structure):

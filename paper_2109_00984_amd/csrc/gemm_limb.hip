@@ -491,27 +491,26 @@ __device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ prob
 // C = sum_s 2^(8s) X_s (mod 2^64) and the shared epilogue.  16x16 accumulator
 // layout: lane l, register e holds row 4*(l/16) + e and column l%16 of the
 // 16x16 block.
-template <int SA, int SB>
-__device__ __forceinline__ void store_tile(v4i (&acc)[2 * SA][2 * SB][8], const LimbProblem& p, i64 tm,
-                                           i64 tn, int wr, int wc, int lane) {
-  using S = Shape<SA, SB>;
+template <int HA, int HB, int BM, int BN>
+__device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], const LimbProblem& p, i64 tm, i64 tn, int wr,
+                                           int wc, int lane) {
 #pragma unroll
   for (int s = 0; s < 8; ++s)
 #pragma unroll
-    for (int x = 0; x < S::HA; ++x)
+    for (int x = 0; x < HA; ++x)
 #pragma unroll
-      for (int y = 0; y < S::HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
+      for (int y = 0; y < HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
   const Epilogue& ep = p.ep;
 #pragma unroll
-  for (int y = 0; y < S::HB; ++y) {
-    const i64 n = tn * S::BN + wc * 32 * SB + y * 16 + (lane & 15);
+  for (int y = 0; y < HB; ++y) {
+    const i64 n = tn * BN + wc * 16 * HB + y * 16 + (lane & 15);
     const bool n_ok = n < p.N;
     const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
 #pragma unroll
-    for (int x = 0; x < S::HA; ++x) {
+    for (int x = 0; x < HA; ++x) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const i64 m = tm * S::BM + wr * 32 * SA + x * 16 + 4 * (lane >> 4) + e;
+        const i64 m = tm * BM + wr * 16 * HA + x * 16 + 4 * (lane >> 4) + e;
         u64 v = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
@@ -596,51 +595,56 @@ __global__ void __launch_bounds__(kThreads, 1)
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  store_tile<SA, SB>(acc, p, tm, tn, wr, wc, lane);
+  store_tile<S::HA, S::HB, S::BM, S::BN>(acc, p, tm, tn, wr, wc, lane);
 }
 
 
 // ------------------------------------------------------------------ LDS-staged GEMM
 // The same product with the outer operand staged through LDS.  In k_limb_gemm
-// the two waves that share an outer strip both fetch it from global memory,
-// so the workgroup fetches every outer block twice.  Here each k step's outer
-// blocks of the whole workgroup (one 16 KiB run of two k-blocks per strip)
-// are copied once into LDS by buffer loads that write LDS directly, a quarter
-// of them by each wave, and every wave reads its fragments back with 16-byte
-// LDS reads (64 lanes reading four 256-byte runs: no bank conflicts).  The
-// inner operand still goes from global memory straight into registers.  This
-// cuts the vector-memory instructions per wave and k step from
-// 8 * (HO + HI) to 8 * HI + 4 * kStrips.
+// the waves that share an outer strip each fetch it from global memory.  Here
+// each k step's outer blocks of the whole workgroup (one 16 KiB run of two
+// k-blocks per strip) are copied once into LDS by buffer loads that write LDS
+// directly, an equal share by each wave, and every wave reads its fragments
+// back with 16-byte LDS reads (64 lanes reading four 256-byte runs: no bank
+// conflicts).  The inner operand still goes from global memory straight into
+// registers.
+//
+// Geometry LGeo<HA, HB, WR, WC>: a WR x WC grid of waves, each owning HA x HB
+// blocks of 16x16 outputs (8 diagonal accumulators each).  Four waves (one per
+// SIMD) with 2x2.. 4x2 blocks, or eight waves (two per SIMD) with 1x4 or 4x1
+// blocks and 128 accumulator registers each, so that a second wave on every
+// SIMD covers the first one's stalls without shrinking the tile.
 //
 // Two LDS buffers alternate between steps: a step computes from one while its
 // copies for the next step land in the other.  One barrier per step hands
 // them over; it sits in level 6, after the last read of the step's buffer
 // (outer limb 7) has returned and after the wave's copies have landed, so
-// that the next step's limb 0 can be read during levels 6 and 7.  Every
-// global load of a step is issued in levels 0..2, the copies first, so the
-// wait for the copies at the barrier normally finds them done.
+// that the next step's limb 0 can be read during levels 6 and 7.
 
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) v4i lds_v4i;
 
-template <int SA, int SB>
-struct LShape {
-  using S = Shape<SA, SB>;
-  static constexpr int HO = S::HO, HI = S::HI;
-  static constexpr int SO = S::kOuterA ? SA : SB;  // outer strips per wave
-  static constexpr int kStrips = 2 * SO;           // outer strips per workgroup
-  static constexpr int kBufBytes = kStrips << 14;  // two 8 KiB k-blocks per strip
-  static constexpr int kCopies = kStrips * 4;      // 1 KiB copies per wave and step
-  // Workgroups per CU.  The 64x64 tile (128 accumulator registers) runs two
-  // per CU, so one's prologue, epilogue and stalls overlap the other's
-  // MFMAs; that leaves 128 other registers per lane.
-  static constexpr int kMinBlocks = SA * SB == 1 ? 2 : 1;
+template <int HA_, int HB_, int WR_, int WC_>
+struct LGeo {
+  static constexpr int HA = HA_, HB = HB_, WR = WR_, WC = WC_;
+  static constexpr int kWaves = WR * WC, kThreads = 64 * kWaves;
+  static constexpr int BM = 16 * HA * WR, BN = 16 * HB * WC;
+  static constexpr bool kOuterA = HA >= HB;  // the operand with more halves per wave
+  static constexpr int HO = kOuterA ? HA : HB, HI = kOuterA ? HB : HA;
+  static constexpr int kStrips = (kOuterA ? BM : BN) / 32;  // outer strips per workgroup
+  static constexpr int kBufBytes = kStrips << 14;           // two 8 KiB k-blocks per strip
+  static constexpr int kCopies = kStrips * 16 / kWaves;     // 1 KiB copies per wave and step
+  // Workgroups per CU: two for the four-wave 64x64 tile (128 accumulator
+  // registers), whose prologue, epilogue and stalls then overlap the other
+  // workgroup's MFMAs.  Both that and the eight-wave shapes leave 128 other
+  // registers per lane.
+  static constexpr int kMinBlocks = (HA * HB == 4 && kWaves == 4) ? 2 : 1;
+  static constexpr bool kTight = kMinBlocks == 2 || kWaves == 8;
   // Inner planes 0..kDbl-1 are double-buffered; planes kDbl..7 are reloaded
-  // in place for the next step at level 8 - p, after their last use.  The
-  // large tiles double-buffer all of them (the registers the outer operand no
-  // longer needs pay for it); the 64x64 tile cannot afford that at two
-  // workgroups per CU.
-  static constexpr int kDbl = kMinBlocks == 2 ? 3 : 8;
+  // in place for the next step at level 8 - p, after their last use.  With
+  // 256 registers per lane every plane is double-buffered (the registers the
+  // outer operand no longer needs pay for it).
+  static constexpr int kDbl = kTight ? 3 : 8;
   // Levels 0..kLoadLevels-1 issue every global load of a step: the copies
   // first, then the double-buffered planes, then the in-place planes 7, 6,
   // ..., kDbl, each load in the level of its position in proportion to the
@@ -675,6 +679,10 @@ struct LShape {
   }
   static_assert(schedule_ok(), "load schedule");
   static_assert(2 * kBufBytes * kMinBlocks <= 160 * 1024, "step buffers must fit in LDS");
+  static_assert(HO % 2 == 0, "a wave's outer halves cover whole strips");
+  static_assert(HI == 1 || HI % 2 == 0, "a wave's inner halves start on a strip unless there is one");
+  static_assert(kCopies * kWaves == kStrips * 16 && (16 % kCopies == 0 || kCopies % 16 == 0),
+                "copies split evenly over the waves");
   // Vector-memory loads complete in issue order, and a step issues its copies
   // before its inner loads, so the hand-over need not wait for the last
   // kPending loads (inner planes for the next step, still in flight); half of
@@ -705,7 +713,7 @@ __device__ __forceinline__ LStep lstep(const SegSrc& s0, const SegSrc& s1, const
 
 // Per-wave constants of the LDS path.
 struct LCtx {
-  unsigned rd;    // LDS byte offset of this lane's fragment in the wave's first strip
+  unsigned rd;    // LDS byte offset of this lane's fragment in the wave's first outer strip
   unsigned lane;  // lane * 16: a copy's per-lane source offset (LDS takes lane * 16 itself)
   int cx, cu0;    // strip and first 1 KiB unit of this wave's copies
 };
@@ -729,34 +737,30 @@ __device__ __forceinline__ void lds_handover() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(PENDING) : "memory");
 }
 
-template <int SA, int SB>
+template <class G>
 struct LRegs {
-  using Sh = LShape<SA, SB>;
-  v4i (&acc)[2 * SA][2 * SB][8];
-  v4i (&z)[Sh::HO];      // outer limb 0
-  v4i (&ob)[2][Sh::HO];  // outer limbs 1..7: limb l in ob[l & 1]
-  v4i (&inner)[Sh::HI][8];  // inner planes kDbl..7 (reloaded in place)
-  const v4i (&dcur)[Sh::HI][Sh::kDbl];  // inner planes 0..kDbl-1 of this step
-  v4i (&dnext)[Sh::HI][Sh::kDbl];       // and of the next
-
+  v4i (&acc)[G::HA][G::HB][8];
+  v4i (&z)[G::HO];      // outer limb 0
+  v4i (&ob)[2][G::HO];  // outer limbs 1..7: limb l in ob[l & 1]
+  v4i (&inner)[G::HI][8];  // inner planes kDbl..7 (reloaded in place)
+  const v4i (&dcur)[G::HI][G::kDbl];  // inner planes 0..kDbl-1 of this step
+  v4i (&dnext)[G::HI][G::kDbl];       // and of the next
   const lds_u8* cur;  // this step's outer blocks
   lds_u8* next;       // the next step's
 };
 
 // Global load number Q of level L: the step's copies come first, then the
 // next step's double-buffered inner planes, then its in-place planes.
-template <int SA, int SB, int L, int Q>
-__device__ __forceinline__ void lds_level_load(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
-                                               const LaneOff& lo) {
-  using Sh = LShape<SA, SB>;
-  constexpr int q = Sh::loads_upto(L - 1) + Q, ND = Sh::kDbl;
-  if constexpr (q < Sh::kCopies) {
+template <class G, int L, int Q>
+__device__ __forceinline__ void lds_level_load(LRegs<G>& r, const LCtx& c, const LStep& next, const LaneOff& lo) {
+  constexpr int q = G::loads_upto(L - 1) + Q, ND = G::kDbl;
+  if constexpr (q < G::kCopies) {
     copy_unit(c, next, r.next, q);
-  } else if constexpr (q < Sh::kCopies + Sh::HI * ND) {
-    constexpr int h = (q - Sh::kCopies) / ND, i = (q - Sh::kCopies) % ND;
+  } else if constexpr (q < G::kCopies + G::HI * ND) {
+    constexpr int h = (q - G::kCopies) / ND, i = (q - G::kCopies) % ND;
     r.dnext[h][i] = ld_buf(next.inner, lo.lo, next.off(h >> 1) + LaneOff::sub(h, i));
   } else {
-    constexpr int u = q - Sh::kCopies - Sh::HI * ND, h = u % Sh::HI, i = 7 - u / Sh::HI;
+    constexpr int u = q - G::kCopies - G::HI * ND, h = u % G::HI, i = 7 - u / G::HI;
     r.inner[h][i] = ld_buf(next.inner, lo.lo, next.off(h >> 1) + LaneOff::sub(h, i));
   }
 }
@@ -765,19 +769,17 @@ __device__ __forceinline__ void lds_level_load(LRegs<SA, SB>& r, const LCtx& c, 
 // limb L + 1 (this step's buffer); in level 6, half way, the hand-over and the
 // reads of the next step's limb 0; and the level's global loads, evenly spread.
 // A tile's odd last step issues no loads, copies or hand-over.
-template <int SA, int SB, bool FIRST, bool LAST, int L, int M>
-__device__ __forceinline__ void lds_level(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
-                                          const LaneOff& lo) {
-  using Sh = LShape<SA, SB>;
-  constexpr int HO = Sh::HO, HI = Sh::HI;
+template <class G, bool FIRST, bool LAST, int L, int M>
+__device__ __forceinline__ void lds_level(LRegs<G>& r, const LCtx& c, const LStep& next, const LaneOff& lo) {
+  constexpr int HO = G::HO, HI = G::HI;
   constexpr int NM = (8 - L) * HO * HI;
   if constexpr (M < NM) {
     constexpr int s = L + M / (HO * HI), o = (M / HI) % HO, i = M % HI;
-    const v4i& in = (s - L) < Sh::kDbl ? r.dcur[i][(s - L) % Sh::kDbl] : r.inner[i][s - L];
+    const v4i& in = (s - L) < G::kDbl ? r.dcur[i][(s - L) % G::kDbl] : r.inner[i][s - L];
     const v4i& out = L == 0 ? r.z[o] : r.ob[L & 1][o];
-    v4i& acc = Sh::S::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
-    const v4i& a = Sh::S::kOuterA ? out : in;
-    const v4i& b = Sh::S::kOuterA ? in : out;
+    v4i& acc = G::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
+    const v4i& a = G::kOuterA ? out : in;
+    const v4i& b = G::kOuterA ? in : out;
     if constexpr (FIRST && L == 0) mfma16_first(acc, a, b);
     else mfma16(acc, a, b);
     if constexpr (M == 0 && L < 7) {
@@ -788,118 +790,120 @@ __device__ __forceinline__ void lds_level(LRegs<SA, SB>& r, const LCtx& c, const
     }
     if constexpr (!LAST && L == 6 && M == NM / 2 - 1) {
       __builtin_amdgcn_sched_barrier(0);
-      lds_handover<Sh::kPending>();
+      lds_handover<G::kPending>();
 #pragma unroll
       for (int h = 0; h < HO; ++h) r.z[h] = lds_frag(r.next, c, h, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
-    constexpr int NL = LAST ? 0 : Sh::loads_at(L);
+    constexpr int NL = LAST ? 0 : G::loads_at(L);
     constexpr int Q = (M + 1) * (NL + 1) / NM - 1, QPREV = M * (NL + 1) / NM - 1;
     if constexpr (Q >= 0 && Q < NL && Q != QPREV) {
       __builtin_amdgcn_sched_barrier(0);
-      lds_level_load<SA, SB, L, Q>(r, c, next, lo);
+      lds_level_load<G, L, Q>(r, c, next, lo);
       __builtin_amdgcn_sched_barrier(0);
     }
-    lds_level<SA, SB, FIRST, LAST, L, M + 1>(r, c, next, lo);
+    lds_level<G, FIRST, LAST, L, M + 1>(r, c, next, lo);
   }
 }
 
-template <int SA, int SB, bool FIRST, bool LAST, int L>
-__device__ __forceinline__ void lds_levels(LRegs<SA, SB>& r, const LCtx& c, const LStep& next,
-                                           const LaneOff& lo) {
+template <class G, bool FIRST, bool LAST, int L>
+__device__ __forceinline__ void lds_levels(LRegs<G>& r, const LCtx& c, const LStep& next, const LaneOff& lo) {
   if constexpr (L < 8) {
-    lds_level<SA, SB, FIRST, LAST, L, 0>(r, c, next, lo);
+    lds_level<G, FIRST, LAST, L, 0>(r, c, next, lo);
     __builtin_amdgcn_sched_barrier(0);
-    lds_levels<SA, SB, FIRST, LAST, L + 1>(r, c, next, lo);
+    lds_levels<G, FIRST, LAST, L + 1>(r, c, next, lo);
   }
 }
 
-template <int SA, int SB, bool FIRST, bool LAST>
-__device__ __forceinline__ void lds_step(LRegs<SA, SB> r, const LCtx& c, const LStep& next, const LaneOff& lo) {
+template <class G, bool FIRST, bool LAST>
+__device__ __forceinline__ void lds_step(LRegs<G> r, const LCtx& c, const LStep& next, const LaneOff& lo) {
   // Re-define the LDS read base in every step: otherwise each (buffer, half,
   // limb) address is hoisted out of the loop into a register of its own,
   // instead of one base register and the read's immediate offset.
   LCtx cs = c;
   asm volatile("" : "+v"(cs.rd));
-  lds_levels<SA, SB, FIRST, LAST, 0>(r, cs, next, lo);
+  lds_levels<G, FIRST, LAST, 0>(r, cs, next, lo);
 }
 
-template <int SA, int SB>
-__global__ void __launch_bounds__(kThreads, (SA * SB == 1 ? 2 : 1))  // LShape::kMinBlocks
+template <int HA, int HB, int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ? 2 : 1)  // LGeo::kMinBlocks
     k_limb_gemm_lds(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
-  using S = Shape<SA, SB>;
-  using Sh = LShape<SA, SB>;
-  __shared__ v4i stage[2][Sh::kBufBytes / 16];
+  using G = LGeo<HA, HB, WR, WC>;
+  __shared__ v4i stage[2][G::kBufBytes / 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
-  const TilePos tp = tile_pos<S::BM, S::BN, Sh::kMinBlocks>(probs, map, sched);
+  const int wr = wave / WC, wc = wave % WC;
+  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(probs, map, sched);
   const LimbProblem& p = probs[tp.pi];
   const i64 tm = tp.tm, tn = tp.tn;
-  const i64 mw = tm * 2 * SA, nw = tn * 2 * SB;  // the workgroup's first left / right 32-block
-  const i64 mb0 = mw + wr * SA, nb0 = nw + wc * SB;
+  const i64 mw = tm * (G::BM / 32), nw = tn * (G::BN / 32);  // the workgroup's first left / right 32-block
+  // the wave's first outer and inner 16-half inside the workgroup tile
+  const int ho0 = (G::kOuterA ? wr : wc) * G::HO, hi0 = (G::kOuterA ? wc : wr) * G::HI;
 
-  v4i acc[S::HA][S::HB][8];
+  v4i acc[HA][HB][8];
   const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
   const int g = lane >> 4;
   const unsigned lane_off = (unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16);
-  const LaneOff lo{lane_off};
+  // inner loads: the wave's descriptor starts at the strip of its first half;
+  // a single inner half may be the second half of that strip
+  const LaneOff lo{lane_off + (unsigned)((hi0 & 1) << 8)};
   const uint8_t* PA1 = p.PA1 ? p.PA1 : p.PA0;
   const uint8_t* PB1 = p.PB1 ? p.PB1 : p.PB0;
-  const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mb0, nb0, SA, SB);
-  const SegSrc s1 = seg_src(PA1, PB1, p.kb1, mb0, nb0, SA, SB);
-  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, 2 * SA, 2 * SB);
-  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, 2 * SA, 2 * SB);
-  const int c0 = wave * Sh::kCopies;
-  const LCtx c{(unsigned)(((S::kOuterA ? wr : wc) * Sh::SO) << 14) + lane_off, (unsigned)lane * 16u, c0 >> 4,
-               c0 & 15};
+  constexpr int kInStrips = (G::HI + 1) / 2;
+  const i64 mi = G::kOuterA ? mw : mw + (hi0 >> 1), ni = G::kOuterA ? nw + (hi0 >> 1) : nw;
+  const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
+  const SegSrc s1 = seg_src(PA1, PB1, p.kb1, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
+  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, G::BM / 32, G::BN / 32);
+  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, G::BM / 32, G::BN / 32);
+  const int c0 = wave * G::kCopies;
+  const LCtx c{(unsigned)((ho0 >> 1) << 14) + lane_off, (unsigned)lane * 16u, c0 >> 4, c0 & 15};
   lds_u8* b0 = (lds_u8*)&stage[0][0];
   lds_u8* b1 = (lds_u8*)&stage[1][0];
 
-  v4i z[Sh::HO], ob[2][Sh::HO], inner[Sh::HI][8], d0[Sh::HI][Sh::kDbl], d1[Sh::HI][Sh::kDbl];
+  v4i z[G::HO], ob[2][G::HO], inner[G::HI][8], d0[G::HI][G::kDbl], d1[G::HI][G::kDbl];
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
     auto off = [&](int st) {
-      return lstep<S::kOuterA>(s0, s1, w0, w1, p.kb0, min(kbeg + 2 * st, klast));
+      return lstep<G::kOuterA>(s0, s1, w0, w1, p.kb0, min(kbeg + 2 * st, klast));
     };
     // prologue: step 0's outer run into buffer 0, its inner planes into registers
     {
       const LStep o = off(0);
 #pragma unroll
-      for (int j = 0; j < Sh::kCopies; ++j) copy_unit(c, o, b0, j);
+      for (int j = 0; j < G::kCopies; ++j) copy_unit(c, o, b0, j);
 #pragma unroll
-      for (int h = 0; h < Sh::HI; ++h) {
+      for (int h = 0; h < G::HI; ++h) {
 #pragma unroll
-        for (int i = 0; i < Sh::kDbl; ++i) d0[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
+        for (int i = 0; i < G::kDbl; ++i) d0[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
 #pragma unroll
-        for (int i = Sh::kDbl; i < 8; ++i) inner[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
+        for (int i = G::kDbl; i < 8; ++i) inner[h][i] = ld_buf(o.inner, lo.lo, o.off(h >> 1) + LaneOff::sub(h, i));
       }
       lds_handover<0>();
 #pragma unroll
-      for (int h = 0; h < Sh::HO; ++h) z[h] = lds_frag(b0, c, h, 0);
+      for (int h = 0; h < G::HO; ++h) z[h] = lds_frag(b0, c, h, 0);
     }
     // Steps alternate between the two LDS buffers and the two sets of inner
     // planes; the loop body holds two steps.  An odd last step (the tail)
     // issues no loads; otherwise loads past the last step re-read its blocks
     // (valid memory, results unused) and complete at its hand-over.
-    using R = LRegs<SA, SB>;
-    lds_step<SA, SB, true, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(1), lo);
+    using R = LRegs<G>;
+    lds_step<G, true, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(1), lo);
     int st = 1;
     for (; st + 1 < nsteps; st += 2) {
-      lds_step<SA, SB, false, false>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
-      lds_step<SA, SB, false, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(st + 2), lo);
+      lds_step<G, false, false>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
+      lds_step<G, false, false>(R{acc, z, ob, inner, d0, d1, b0, b1}, c, off(st + 2), lo);
     }
-    if (st < nsteps) lds_step<SA, SB, false, true>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
+    if (st < nsteps) lds_step<G, false, true>(R{acc, z, ob, inner, d1, d0, b1, b0}, c, off(st + 1), lo);
   } else {
 #pragma unroll
-    for (int x = 0; x < S::HA; ++x)
+    for (int x = 0; x < HA; ++x)
 #pragma unroll
-      for (int y = 0; y < S::HB; ++y)
+      for (int y = 0; y < HB; ++y)
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  store_tile<SA, SB>(acc, p, tm, tn, wr, wc, lane);
+  store_tile<HA, HB, G::BM, G::BN>(acc, p, tm, tn, wr, wc, lane);
 }
 
 }  // namespace
@@ -913,8 +917,12 @@ int limb_tiles(i64 M, i64 N, int variant) {
   const i64 bm = 64 * limb_variant_sa(variant), bn = 64 * limb_variant_sb(variant);
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
-int limb_variant_sa(int variant) { return variant == kLimb128x64 || variant == kLimbLds128x64 ? 2 : 1; }
-int limb_variant_sb(int variant) { return variant == kLimb64x128 || variant == kLimbLds64x128 ? 2 : 1; }
+int limb_variant_sa(int variant) {
+  return variant == kLimb128x64 || variant == kLimbLds128x64 || variant == kLimbLds128x64w8 ? 2 : 1;
+}
+int limb_variant_sb(int variant) {
+  return variant == kLimb64x128 || variant == kLimbLds64x128 || variant == kLimbLds64x128w8 ? 2 : 1;
+}
 
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
                        i64 total_blocks, int kind, int mode) {
@@ -944,16 +952,23 @@ hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map
                             TileSched sched) {
   if (total_tiles <= 0) return hipSuccess;
   if (sched.group_m < 1) sched.group_m = 1;
-  const dim3 grid(total_tiles), block(kThreads);
+  const dim3 grid(total_tiles);
+#define MPC_LDS_CASE(V, HA, HB, WR, WC)                                                                    \
+  case V:                                                                                                 \
+    hipLaunchKernelGGL((k_limb_gemm_lds<HA, HB, WR, WC>), grid, dim3(64 * WR * WC), 0, s, probs, map, sched); \
+    break;
   switch (sched.variant) {
-    case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, block, 0, s, probs, map, sched); break;
-    case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, block, 0, s, probs, map, sched); break;
-    case kLimb64x64: hipLaunchKernelGGL((k_limb_gemm<1, 1>), grid, block, 0, s, probs, map, sched); break;
-    case kLimbLds128x64: hipLaunchKernelGGL((k_limb_gemm_lds<2, 1>), grid, block, 0, s, probs, map, sched); break;
-    case kLimbLds64x128: hipLaunchKernelGGL((k_limb_gemm_lds<1, 2>), grid, block, 0, s, probs, map, sched); break;
-    case kLimbLds64x64: hipLaunchKernelGGL((k_limb_gemm_lds<1, 1>), grid, block, 0, s, probs, map, sched); break;
+    case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
+    case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
+    case kLimb64x64: hipLaunchKernelGGL((k_limb_gemm<1, 1>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
+    MPC_LDS_CASE(kLimbLds128x64, 4, 2, 2, 2)
+    MPC_LDS_CASE(kLimbLds64x128, 2, 4, 2, 2)
+    MPC_LDS_CASE(kLimbLds64x64, 2, 2, 2, 2)
+    MPC_LDS_CASE(kLimbLds64x128w8, 1, 4, 4, 2)
+    MPC_LDS_CASE(kLimbLds128x64w8, 4, 1, 2, 4)
     default: return hipErrorInvalidValue;
   }
+#undef MPC_LDS_CASE
   return hipGetLastError();
 }
 

@@ -229,12 +229,14 @@ hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
                        i64 total_blocks, int kind, int mode);
 // Tile shapes of the limb GEMM (workgroup output tile) and the tile order.
-// Variants 3..5 stage the outer operand through LDS (k_limb_gemm_lds).
+// Variants 3..7 stage the outer operand through LDS (k_limb_gemm_lds); 6 and
+// 7 run eight waves per workgroup (two per SIMD).
 enum LimbVariant : int {
   kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2,
-  kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5
+  kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5,
+  kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7
 };
-constexpr int kLimbVariants = 6;
+constexpr int kLimbVariants = 8;
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group
