@@ -229,7 +229,9 @@ typedef struct {
  * operand kind and one grouped GEMM launch over the tiles of all problems and
  * both parties (a tile-to-problem table; one workgroup per tile, handed out
  * by the hardware dispatcher); the plain form likewise with one open launch.
- * `descs` is a HOST array of `count` descriptors. */
+ * Each problem follows mpc_beaver_matmul's rules, and since the problems run
+ * concurrently no output may overlap another problem's inputs or outputs
+ * (MPC_E_ALIAS).  `descs` is a HOST array of `count` descriptors. */
 mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
                                      int trunc_bits, mpc_form form);
 
@@ -240,9 +242,9 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmu
  * trunc_bits.  One workgroup per chunk of 1024 elements of one product, found
  * through a chunk table uploaded with the call (a permanent buffer made
  * before capture when the call is captured in a graph).  Validation and
- * aliasing rules are those of mpc_beaver_mul, and outputs of different
- * products must not overlap.  `descs` is a HOST array of `count`
- * descriptors. */
+ * aliasing rules are those of mpc_beaver_mul, and since the products run
+ * concurrently no output may overlap another product's inputs or outputs
+ * (MPC_E_ALIAS).  `descs` is a HOST array of `count` descriptors. */
 typedef struct {
   size_t n;
   const uint64_t *x0, *x1, *y0, *y1;

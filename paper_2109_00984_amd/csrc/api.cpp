@@ -244,6 +244,28 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return a0 < b1 && b0 < a1;
 }
 
+// A batch's problems run concurrently: its outputs must be pairwise disjoint
+// and must not overlap any input of the batch.  Sorted outputs, then one
+// binary search per input.
+struct Span {
+  uintptr_t lo, hi;
+};
+void add_span(std::vector<Span>& v, const void* p, size_t n) {
+  if (p && n) v.push_back(Span{(uintptr_t)p, (uintptr_t)p + n * 8});
+}
+mpc_status batch_disjoint(std::vector<Span> outs, const std::vector<Span>& ins) {
+  std::sort(outs.begin(), outs.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+  for (size_t i = 1; i < outs.size(); ++i)
+    if (outs[i].lo < outs[i - 1].hi) return MPC_E_ALIAS;
+  for (const Span& s : ins) {
+    // the last output starting before s ends is the only one that can reach into s
+    auto it = std::lower_bound(outs.begin(), outs.end(), s.hi,
+                               [](const Span& o, uintptr_t v) { return o.lo < v; });
+    if (it != outs.begin() && std::prev(it)->hi > s.lo) return MPC_E_ALIAS;
+  }
+  return MPC_OK;
+}
+
 mpc_status hip_status(hipError_t e) {
   if (e == hipSuccess) return MPC_OK;
   g_last_hip_error = (int)e;
@@ -1414,16 +1436,24 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
     MatmulPlan m{d.M, d.N, d.K, d.x0, d.x1, d.y0, d.y1, d.t, d.z0, d.z1};
     CHK(validate_matmul(m));
     if (d.M == 0 || d.N == 0) continue;
-    // outputs of different problems must not overlap either
-    for (const MatmulPlan& o : plans) {
-      const size_t a = (size_t)(m.M * m.N), b = (size_t)(o.M * o.N);
-      if (overlap(m.z0, a, o.z0, b) || overlap(m.z0, a, o.z1, b) || overlap(m.z1, a, o.z0, b) ||
-          overlap(m.z1, a, o.z1, b))
-        return MPC_E_ALIAS;
-    }
     plans.push_back(m);
   }
   if (plans.empty()) return MPC_OK;
+  {
+    std::vector<Span> outs, ins;
+    for (const MatmulPlan& m : plans) {
+      const size_t na = (size_t)(m.M * m.K), nb = (size_t)(m.K * m.N), nc = (size_t)(m.M * m.N);
+      add_span(outs, m.z0, nc);
+      add_span(outs, m.z1, nc);
+      for (const void* p : {(const void*)m.x0, (const void*)m.x1, (const void*)m.t.a0, (const void*)m.t.a1})
+        add_span(ins, p, na);
+      for (const void* p : {(const void*)m.y0, (const void*)m.y1, (const void*)m.t.b0, (const void*)m.t.b1})
+        add_span(ins, p, nb);
+      add_span(ins, m.t.c0, nc);
+      add_span(ins, m.t.c1, nc);
+    }
+    CHK(batch_disjoint(std::move(outs), ins));
+  }
   CHK(set_device(c));
   // heavy problems first, so the GEMM's tile list front-loads the long tiles
   std::stable_sort(plans.begin(), plans.end(), [](const MatmulPlan& a, const MatmulPlan& b) {
@@ -1455,11 +1485,6 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx* c, size_t count, const mpc_mul_desc* 
     for (int k = 0; k < nin; ++k)
       if (overlap(d.z0, n, in[k], n) || overlap(d.z1, n, in[k], n)) return MPC_E_ALIAS;
     if (!n) continue;
-    // outputs of different products must not overlap either
-    for (const MulJob& o : jobs)
-      if (overlap(d.z0, n, o.z0, (size_t)o.n) || overlap(d.z0, n, o.z1, (size_t)o.n) ||
-          overlap(d.z1, n, o.z0, (size_t)o.n) || overlap(d.z1, n, o.z1, (size_t)o.n))
-        return MPC_E_ALIAS;
     MulJob j{};
     j.n = (i64)n;
     j.x0 = d.x0;
@@ -1484,6 +1509,18 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx* c, size_t count, const mpc_mul_desc* 
     open_bytes += (sq ? 1 : 2) * 8 * (uint64_t)n;
   }
   if (jobs.empty()) return MPC_OK;
+  {
+    std::vector<Span> outs, ins;
+    for (const MulJob& j : jobs) {
+      add_span(outs, j.z0, (size_t)j.n);
+      add_span(outs, j.z1, (size_t)j.n);
+      for (const void* p : {(const void*)j.x0, (const void*)j.x1, (const void*)j.y0, (const void*)j.y1,
+                            (const void*)j.a0, (const void*)j.a1, (const void*)j.b0, (const void*)j.b1,
+                            (const void*)j.c0, (const void*)j.c1})
+        add_span(ins, p, (size_t)j.n);
+    }
+    CHK(batch_disjoint(std::move(outs), ins));
+  }
   CHK(set_device(c));
   std::vector<i64> cs(jobs.size() + 1, 0);
   for (size_t i = 0; i < jobs.size(); ++i) cs[i + 1] = cs[i] + (jobs[i].n + kMulChunk - 1) / kMulChunk;

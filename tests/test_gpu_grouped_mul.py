@@ -115,6 +115,18 @@ def test_grouped_mul_errors(m):
     with pytest.raises(m.MPCError) as e:  # output aliases an input
         c.beaver_mul_grouped([(gx, gy, t)], 0, outs=[m.SharedPair(gx.s0, out.s1)])
     assert e.value.status == -3
+    (hx, hy, ht), hout, _ = make_problem(m, c, 1, 64, False, False)
+    with pytest.raises(m.MPCError) as e:  # one product writes another's input (they run concurrently)
+        c.beaver_mul_grouped([(gx, gy, t), (hx, hy, ht)], 0, outs=[m.SharedPair(hx.s0, out.s1), hout])
+    assert e.value.status == -3
+    with pytest.raises(m.MPCError) as e:  # the same for grouped matmuls: output onto another's triple share c
+        tm = c.dealer(m.TRIPLE_MATMUL, 3, 5, (8, 8, 8))
+        tm2 = c.dealer(m.TRIPLE_MATMUL, 3, 6, (8, 8, 8))
+        xs = c.share(torch.zeros((8, 8), dtype=torch.int64, device=c.device), 0, 7)
+        ys = c.share(torch.zeros((8, 8), dtype=torch.int64, device=c.device), 1, 8)
+        c.beaver_matmul_grouped([(xs, ys, tm), (xs, ys, tm2)], 0, "limb8",
+                                outs=[m.SharedPair(tm2.c0, c.empty((8, 8))), m.SharedPair(c.empty((8, 8)), c.empty((8, 8)))])
+    assert e.value.status == -3
     with pytest.raises(m.MPCError) as e:
         c.beaver_mul_grouped([(gx, gy, t)], 64)
     assert e.value.status == -1
