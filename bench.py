@@ -286,6 +286,7 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     for form in ("plain", "limb8"):
         total, ops = mlp_latency(ctx, mpc, torch, workloads, form)
         ex[f"mlp_ms_{form}"] = round(total, 4)
+        ex[f"mlp_graph_ms_{form}"] = round(mlp_graph_latency(mpc, torch, workloads, form), 4)
         ex[f"mlp_ops_ms_{form}"] = ops
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
     ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
@@ -475,6 +476,54 @@ def mlp_latency(ctx, mpc, torch, workloads, form):
             label = f"square{i + 1}_{B}x{dims[i + 1]}"
         ops[label] = round(_event_time(torch, ctx.streams[0], fn, 20), 4)
     return total, ops
+
+
+def mlp_graph_latency(mpc, torch, workloads, form):
+    """The same forward pass captured once in a HIP graph (outputs allocated
+    up front) and replayed: the latency without host launch overhead.  Every
+    replay must reproduce the eager result bit for bit."""
+    cfg = workloads.MLP
+    B, dims = cfg["batch"], cfg["dims"]
+    dseed = workloads.seeds(2)[2]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = mpc.Context(device=0, seed=workloads.seeds(2)[1])
+        dv = lambda a: torch.from_numpy(a).to(c.device)
+        x = c.share(dv(mpc.encode(workloads.uniform(1002, (B, dims[0]), -1, 1), FRAC)), 0, 100)
+        ws = [c.share(dv(mpc.encode(workloads.uniform(1102 + i, (dims[i], dims[i + 1]), -1, 1), FRAC)), 1, 101 + i)
+              for i in range(3)]
+        trip = [c.dealer(mpc.TRIPLE_MATMUL, dseed, 200 + i, (B, dims[i + 1], dims[i])) for i in range(3)]
+        pairs = [c.dealer(mpc.TRIPLE_SQUARE, dseed, 300 + i, (B * dims[i + 1],)) for i in range(2)]
+        hs = [mpc.SharedPair(c.empty((B, d)), c.empty((B, d))) for d in dims[1:]]
+        sqs = [mpc.SharedPair(c.empty((B * d,)), c.empty((B * d,))) for d in dims[1:3]]
+
+        def forward():
+            h = x
+            for i in range(3):
+                h = c.beaver_matmul(h, ws[i], trip[i], FRAC, form, out=hs[i])
+                if i < 2:
+                    flat = mpc.SharedPair(h.s0.view(-1), h.s1.view(-1))
+                    sq = c.beaver_mul(flat, None, pairs[i], FRAC, out=sqs[i])
+                    h = mpc.SharedPair(sq.s0.view(B, dims[i + 1]), sq.s1.view(B, dims[i + 1]))
+            return h
+
+        out = forward()  # eager: sizes the workspace and split-K buffers
+        c.sync()
+        want = (out.s0.clone(), out.s1.clone())
+        c.graph_begin()
+        forward()
+        g = c.graph_end()
+        for _ in range(3):
+            hs[-1].s0.zero_()
+            hs[-1].s1.zero_()
+            c.graph_launch(g)
+            c.sync()
+            assert torch.equal(hs[-1].s0, want[0]) and torch.equal(hs[-1].s1, want[1]), "graph replay differs"
+        ms = _event_time(torch, side, lambda: c.graph_launch(g), 50)
+        mpc.Context.graph_destroy(g)
+        c.close()
+    log(f"bench: MLP {form} graph replay {ms:.4f} ms")
+    return ms
 
 
 def multiparty_bench(ctx, mpc, torch, X, Y):
