@@ -50,9 +50,8 @@ def main():
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(both parties share the one device; see DESIGN.md for how the path shards)",
-              file=sys.stderr)
+        print(f"bench.py: measures one GPU, which holds both parties' shares; --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
         return 2
 
     import torch
