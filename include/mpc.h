@@ -53,7 +53,7 @@ typedef enum {
   MPC_E_ALIAS = -3,       /* an output overlaps an input */
   MPC_E_NOMEM = -4,       /* workspace allocation failed */
   MPC_E_HIP = -5,         /* a HIP runtime call failed (see mpc_last_hip_error) */
-  MPC_E_UNSUPPORTED = -6, /* valid request this build does not support */
+  MPC_E_UNSUPPORTED = -6, /* valid request the library does not support */
   MPC_E_RANGE = -7        /* a real value does not fit the fixed-point range */
 } mpc_status;
 
