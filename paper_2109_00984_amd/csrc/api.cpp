@@ -534,6 +534,7 @@ PackJob place_job(const JobSpec& j, Carve& cv) {
     p.share[i] = j.share[i];
   }
   p.rblocks = limb_rblocks(j.rows);
+  p.rreal = (j.rows + 31) / 32;
   p.kblocks = limb_kblocks(j.K);
   for (int o = 0; o < kPackMaxOut; ++o)
     p.dst[o] = o < pack_nout(j.mode) ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
@@ -632,7 +633,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   for (size_t L = 0; L < launch_km.size(); ++L) {
     std::vector<i64> bstart(1, 0);
     for (size_t i = first_job[L]; i < first_job[L + 1]; ++i)
-      bstart.push_back(bstart.back() + jobs[i].rblocks * jobs[i].kblocks);
+      bstart.push_back(bstart.back() + jobs[i].rreal * jobs[i].kblocks);
     obstart[L] = blob.add(bstart.data(), bstart.size());
     nblocks[L] = bstart.back();
   }

@@ -13,8 +13,8 @@
 //
 // Packing.  pack kernels turn uint64 operands into the blocked limb layout
 // described in internal.h (one 8 KiB block = eight 1 KiB planes of a 32x32
-// tile, each plane stored as 64 lanes' 16-byte runs in lane order), padding
-// with zeros, so no conversion work is left in the GEMM's inner loop.
+// tile, each plane stored as 64 lanes' 16-byte runs in lane order), with
+// zeros past K, so no conversion work is left in the GEMM's inner loop.
 //
 // GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a
 // (64*SA) x (64*SB) output tile; each wave a (32*SA) x (32*SB) sub-tile held
@@ -172,8 +172,8 @@ __global__ void __launch_bounds__(kPackThreads)
   // of each row: k-blocks for a left operand (rows are m, contiguous in k),
   // row blocks for a right one (rows are k, contiguous in n).  The packed
   // layout is the same either way: block (rb, kb) at rb * kblocks + kb.
-  const i64 rb = KIND == kPackRow ? local / jb.kblocks : local % jb.rblocks;
-  const i64 kb = KIND == kPackRow ? local % jb.kblocks : local / jb.rblocks;
+  const i64 rb = KIND == kPackRow ? local / jb.kblocks : local % jb.rreal;
+  const i64 kb = KIND == kPackRow ? local % jb.kblocks : local / jb.rreal;
   const size_t boff = (size_t)(rb * jb.kblocks + kb) << 13;
 
   i64 off[16];

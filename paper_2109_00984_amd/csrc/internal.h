@@ -120,6 +120,11 @@ struct PackJob {
   uint8_t* dst[kPackMaxOut];
   i64 rblocks;  // padded block counts of every output
   i64 kblocks;
+  // Row blocks that hold data, ceil(rows / 32).  Only these are written: the
+  // padding row blocks beyond them (up to rblocks) are read by the GEMM's edge
+  // tiles but only reach outputs past the last row or column, which are never
+  // stored.  (All kblocks are written: zeros past K enter every output.)
+  i64 rreal;
   u64 key[2];    // kModePrgSum2: PRG stream keys of the two shares
   u64* share[2];  // kModePrgSum2: where the two shares are written
 };
@@ -224,7 +229,7 @@ constexpr int kPlainBK = 16;  // k tile of the plain GEMM (split-K slices are mu
 hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M, i64 N, const Epilogue& ep);
 
 // Limb form (gemm_limb.hip).
-// jobs and block_start (njobs+1 prefix sums of rblocks*kblocks) are device
+// jobs and block_start (njobs+1 prefix sums of rreal*kblocks) are device
 // arrays; every job of one launch has the given kind and mode.
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
                        i64 total_blocks, int kind, int mode);
