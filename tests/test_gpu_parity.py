@@ -329,7 +329,10 @@ def test_limb_tile_variants(m, variant, group_m, remap):
     say(f"limb tile variant {variant} group_m={group_m} remap={remap}")
     c = m.Context(device=0, seed=SEED)
     c.set_default_tile_config(variant, group_m, remap)
-    for (M, N, K) in [(200, 136, 70), (64, 64, 64), (1, 300, 33), (513, 65, 260), (130, 260, 1100)]:
+    # the last shape's Beaver finish concatenates 2K = 18000 > 16320 (K chunks)
+    # over few tiles (split-K)
+    for (M, N, K) in [(200, 136, 70), (64, 64, 64), (1, 300, 33), (513, 65, 260), (130, 260, 1100),
+                      (96, 64, 9000)]:
         A, B = rnd(M + variant, (M, K)), rnd(N + 7, (K, N))
         Cl = c.ring_gemm(dev(A), dev(B), "limb8")
         assert np.array_equal(host(c, Cl), oracle.ring_gemm(A, B)), (M, N, K)
