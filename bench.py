@@ -37,6 +37,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+EXTRAS = ("ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul", "conv")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +48,8 @@ def main():
     ap.add_argument("--form", default="limb8", choices=["limb8", "plain"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--extra", action="append", choices=EXTRAS, metavar="NAME",
+                    help="run only these secondary measurements (repeatable): " + ", ".join(EXTRAS))
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="after the JSON line, run three device-to-device copies of MIB MiB "
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
@@ -135,7 +140,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = secondary(ctx, mpc, torch, workloads, X, Y)
+        extras = secondary(ctx, mpc, torch, workloads, X, Y, set(args.extra or EXTRAS))
 
     cpu = None
     if not args.no_cpu:
@@ -230,7 +235,31 @@ def _event_time(torch, stream, fn, reps):
     return s.elapsed_time(e) / reps
 
 
-def secondary(ctx, mpc, torch, workloads, X, Y):
+def secondary(ctx, mpc, torch, workloads, X, Y, only):
+    ex = {}
+    if "ring_gemm" in only:
+        ex.update(ring_gemm_forms(ctx, torch, X, Y))
+    if "beaver_mul" in only:
+        ex.update(beaver_mul_2e24(ctx, mpc, torch, X, Y))
+    if "mlp" in only:
+        ex.update(mlp_bench(ctx, mpc, torch, workloads))
+    if "sweep" in only:
+        ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
+    if "multiparty" in only:
+        ex.update(multiparty_bench(ctx, mpc, torch, X, Y))
+    if "binary" in only:
+        ex.update(binary_bench(ctx, mpc, torch, X))
+    ctx.sync()
+    if "grouped" in only:
+        ex.update(grouped_bench(mpc, torch, workloads))
+    if "grouped_mul" in only:
+        ex.update(grouped_mul_bench(mpc, torch, workloads))
+    if "conv" in only:
+        ex.update(conv_bench(mpc, torch, workloads))
+    return ex
+
+
+def ring_gemm_forms(ctx, torch, X, Y):
     ex = {}
     # ring GEMM alone, both forms, timed with the library's launch events
     # (the fp64 limb form is the paper's method: four 16-bit limbs, ten exact
@@ -262,7 +291,11 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     ctx.sync()
     ex["ring_gemm_forms_bit_identical"] = bool(torch.equal(C0, C1) and torch.equal(C0, C2))
     del C, C0, C1, C2
+    return ex
 
+
+def beaver_mul_2e24(ctx, mpc, torch, X, Y):
+    ex = {}
     # Beaver element-wise product (fused mask/open/finish/truncate), HBM-bound:
     # 2^24 elements = 128 MiB per share buffer, 1.5 GiB moved per call
     n = M * K
@@ -280,7 +313,11 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
     ex["beaver_mul_hbm_frac"] = round(ex["beaver_mul_hbm_GBps_algorithmic"] / HBM_PEAK_GBS, 4)
     log(f"bench: Beaver mul n=2^24: {ms:.3f} ms")
     del x, y, tm, zz
+    return ex
 
+
+def mlp_bench(ctx, mpc, torch, workloads):
+    ex = {}
     # secure MLP 784-1024-1024-10, batch 128, square activations
     for form in ("plain", "limb8"):
         total, ops = mlp_latency(ctx, mpc, torch, workloads, form)
@@ -288,13 +325,6 @@ def secondary(ctx, mpc, torch, workloads, X, Y):
         ex[f"mlp_graph_ms_{form}"] = round(mlp_graph_latency(mpc, torch, workloads, form), 4)
         ex[f"mlp_ops_ms_{form}"] = ops
     log(f"bench: MLP plain {ex['mlp_ms_plain']} ms, limb8 {ex['mlp_ms_limb8']} ms")
-    ex["beaver_mul_sweep"] = beaver_mul_sweep(ctx, mpc, torch)
-    ex.update(multiparty_bench(ctx, mpc, torch, X, Y))
-    ex.update(binary_bench(ctx, mpc, torch, X))
-    ctx.sync()
-    ex.update(grouped_bench(mpc, torch, workloads))
-    ex.update(grouped_mul_bench(mpc, torch, workloads))
-    ex.update(conv_bench(mpc, torch, workloads))
     return ex
 
 
