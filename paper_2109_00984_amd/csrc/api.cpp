@@ -335,7 +335,7 @@ size_t packed_bytes(i64 rows, i64 K) {
 // k each) so that about two workgroups per compute unit run; the slices'
 // partial sums live in the context's split buffer.  Never grows that buffer
 // during capture (the launch then runs unsplit).
-constexpr i64 kPlainMinSlice = 128;
+constexpr i64 kPlainMinSlice = 32;
 
 // Makes the split-K partial buffer at least `bytes` large; false when it
 // would have to move while a graph is being captured or still refers to it
@@ -391,8 +391,34 @@ mpc_status plan_splitk(mpc_ctx* c, std::vector<PlainProblem>& probs) {
   return MPC_OK;
 }
 
+// Split-K reductions of one call: their job table rides in the call's
+// descriptor blob, and one launch reduces every split problem.
+struct ReduceTable {
+  size_t ojobs = 0, ostart = 0;
+  int njobs = 0;
+  i64 chunks = 0;
+};
+ReduceTable add_reduces(Blob& blob, const std::vector<ReduceJob>& jobs) {
+  ReduceTable t;
+  if (jobs.empty()) return t;
+  std::vector<i64> cs(jobs.size() + 1, 0);
+  for (size_t i = 0; i < jobs.size(); ++i) cs[i + 1] = cs[i] + (jobs[i].M * jobs[i].N + kReduceChunk - 1) / kReduceChunk;
+  t.ojobs = blob.add(jobs.data(), jobs.size());
+  t.ostart = blob.add(cs.data(), cs.size());
+  t.njobs = (int)jobs.size();
+  t.chunks = cs.back();
+  return t;
+}
+mpc_status issue_reduces(mpc_ctx* c, hipStream_t st, const ReduceTable& t, const uint8_t* dev) {
+  if (!t.njobs || !t.chunks) return MPC_OK;
+  CHK(hip_status(launch_splitk_reduce_grouped(st, (const ReduceJob*)(dev + t.ojobs), (const i64*)(dev + t.ostart),
+                                              t.njobs, t.chunks)));
+  c->stats.launches++;
+  return MPC_OK;
+}
+
 // One launch of the plain GEMM over `probs` (party 0's stream), plus one
-// reduction per split problem.
+// launch reducing every split problem.
 mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs_in) {
   const size_t n = probs_in.size();
   if (!n) return MPC_OK;
@@ -404,21 +430,20 @@ mpc_status issue_plain(mpc_ctx* c, const std::vector<PlainProblem>& probs_in) {
     tstart[q + 1] = tstart[q] + plain_tiles(probs[q].M, probs[q].N) * probs[q].ksplit;
     macs += (double)probs[q].M * (double)probs[q].N * (double)(probs[q].K0 + probs[q].K1);
   }
+  std::vector<ReduceJob> reduces;
+  for (const PlainProblem& p : probs)
+    if (p.ksplit > 1) reduces.push_back(ReduceJob{p.partial, p.ksplit, p.M, p.N, p.ep});
   Blob blob;
   const size_t oprob = blob.add(probs.data(), n);
   const size_t otile = blob.add(tstart.data(), n + 1);
+  const ReduceTable rt = add_reduces(blob, reduces);
   uint8_t* dev = nullptr;
   CHK(upload(c, blob, &dev));
   TileMap map{(int)n, (const int*)(dev + otile)};
   LaunchTimer tm(c, MPC_FORM_PLAIN, macs);
   CHK(tm.start());
   CHK(hip_status(launch_plain_gemm(c->s[0], (const PlainProblem*)(dev + oprob), map, tstart[n])));
-  for (size_t q = 0; q < n; ++q) {
-    if (probs[q].ksplit <= 1) continue;
-    CHK(hip_status(launch_splitk_reduce(c->s[0], probs[q].partial, probs[q].ksplit, probs[q].M, probs[q].N,
-                                        probs[q].ep)));
-    c->stats.launches++;
-  }
+  CHK(issue_reduces(c, c->s[0], rt, dev));
   CHK(tm.stop());
   c->stats.launches++;
   c->stats.gemm_problems += n;
@@ -675,13 +700,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   std::vector<std::vector<LimbProblem>> pieces(nlaunch);
   std::vector<std::vector<int>> tstarts(nlaunch, std::vector<int>(1, 0));
   std::vector<double> cmacs(nlaunch, 0.0);
-  struct Reduce {
-    const u64* partial;
-    int ks;
-    i64 M, N;
-    Epilogue ep;
-  };
-  std::vector<Reduce> reduces;
+  std::vector<ReduceJob> reduces;
   size_t part_off = 0;
   for (size_t q = 0; q < nreq; ++q) {
     const LimbReq& r = reqs[q];
@@ -720,7 +739,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
         const int b0 = (int)(2 * (steps * sl / ks)), b1 = (int)(2 * (steps * (sl + 1) / ks));
         CHK(piece(0, b0, b1, make_ep(nullptr, +1, 0, part + (size_t)sl * (size_t)(r.M * r.N), rowmajor_view(r.N))));
       }
-      reduces.push_back(Reduce{part, ks, r.M, r.N, r.ep});
+      reduces.push_back(ReduceJob{part, ks, r.M, r.N, r.ep});
     } else {
       for (int ch = 0; ch < nchunks[q]; ++ch) {
         Epilogue ep = r.ep;
@@ -738,6 +757,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     oprob[L] = blob.add(pieces[L].data(), pieces[L].size());
     otile[L] = blob.add(tstarts[L].data(), tstarts[L].size());
   }
+  const ReduceTable rt = add_reduces(blob, reduces);
   uint8_t* dev = nullptr;
   CHK(upload(c, blob, &dev));
   for (size_t L = 0; L < launch_km.size(); ++L) {
@@ -755,10 +775,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     CHK(tm.stop());
     c->stats.launches++;
   }
-  for (const Reduce& rd : reduces) {
-    CHK(hip_status(launch_splitk_reduce(st, rd.partial, rd.ks, rd.M, rd.N, rd.ep)));
-    c->stats.launches++;
-  }
+  CHK(issue_reduces(c, st, rt, dev));
   c->stats.gemm_problems += nreq;
   return MPC_OK;
 }

@@ -161,29 +161,51 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-__global__ void __launch_bounds__(kThreads)
-    k_splitk_reduce(const u64* __restrict__ partial, int ks, i64 M, i64 N, Epilogue ep) {
-  const i64 total = M * N;
-  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (i64)gridDim.x * blockDim.x) {
-    u64 v = 0;
-    for (int s = 0; s < ks; ++s) v += partial[s * total + e];
-    const i64 m = e / N, n = e % N;
-    const i64 off = m * ep.view.ld_m + (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
-    if (ep.accumulate) v += ep.Out[off];
-    if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
-    if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
-    ep.Out[off] = v;
+__device__ __forceinline__ void reduce_one(const u64* __restrict__ partial, int ks, i64 total, i64 N,
+                                           const Epilogue& ep, i64 e) {
+  // four independent sums keep several loads in flight (the ring sum does
+  // not depend on the order)
+  u64 v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+  int s = 0;
+  for (; s + 4 <= ks; s += 4) {
+    v0 += partial[(i64)s * total + e];
+    v1 += partial[(i64)(s + 1) * total + e];
+    v2 += partial[(i64)(s + 2) * total + e];
+    v3 += partial[(i64)(s + 3) * total + e];
   }
+  for (; s < ks; ++s) v0 += partial[(i64)s * total + e];
+  u64 v = (v0 + v1) + (v2 + v3);
+  const i64 m = e / N, n = e % N;
+  const i64 off = m * ep.view.ld_m + (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
+  if (ep.accumulate) v += ep.Out[off];
+  if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
+  if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
+  ep.Out[off] = v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_splitk_reduce_grouped(const ReduceJob* __restrict__ jobs, const i64* __restrict__ chunk_start, int njobs) {
+  const i64 c = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (chunk_start[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const ReduceJob& jb = jobs[lo];
+  const i64 total = jb.M * jb.N;
+  const i64 base = (c - chunk_start[lo]) * kReduceChunk;
+  const i64 end = min(base + kReduceChunk, total);
+  for (i64 e = base + threadIdx.x; e < end; e += kThreads) reduce_one(jb.partial, jb.ks, total, jb.N, jb.ep, e);
 }
 
 }  // namespace
 
-hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M, i64 N, const Epilogue& ep) {
-  const i64 total = M * N;
-  if (total <= 0) return hipSuccess;
-  const i64 b = (total + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(kThreads), 0, s, partial, ks, M,
-                     N, ep);
+hipError_t launch_splitk_reduce_grouped(hipStream_t s, const ReduceJob* jobs, const i64* chunk_start, int njobs,
+                                        i64 total_chunks) {
+  if (total_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_splitk_reduce_grouped, dim3((unsigned)total_chunks), dim3(kThreads), 0, s, jobs,
+                     chunk_start, njobs);
   return hipGetLastError();
 }
 

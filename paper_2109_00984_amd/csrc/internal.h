@@ -224,9 +224,20 @@ hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap m
                              int total_tiles);
 int plain_tiles(i64 M, i64 N);
 constexpr int kPlainBK = 16;  // k tile of the plain GEMM (split-K slices are multiples)
-// Split-K reduction shared by both GEMM forms: v = sum of the ks partial
-// M x N results (partial[slice][M][N]), then the epilogue.
-hipError_t launch_splitk_reduce(hipStream_t s, const u64* partial, int ks, i64 M, i64 N, const Epilogue& ep);
+// Split-K reduction shared by both GEMM forms, for every split problem of a
+// call at once: v = sum of a job's ks partial M x N results
+// (partial[slice][M][N]), then its epilogue.  One workgroup per chunk of
+// kReduceChunk outputs of one job (chunk_start: njobs+1 prefix sums of per-job
+// chunk counts; jobs and chunk_start are device arrays).
+struct ReduceJob {
+  const u64* partial;
+  int ks;
+  i64 M, N;
+  Epilogue ep;
+};
+constexpr i64 kReduceChunk = 256;  // one output per thread
+hipError_t launch_splitk_reduce_grouped(hipStream_t s, const ReduceJob* jobs, const i64* chunk_start, int njobs,
+                                        i64 total_chunks);
 
 // Limb form (gemm_limb.hip).
 // jobs and block_start (njobs+1 prefix sums of rreal*kblocks) are device
