@@ -37,7 +37,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-EXTRAS = ("ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul", "conv")
+EXTRAS = ("small", "ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul",
+          "conv")
 
 
 def main():
@@ -237,6 +238,8 @@ def _event_time(torch, stream, fn, reps):
 
 def secondary(ctx, mpc, torch, workloads, X, Y, only):
     ex = {}
+    if "small" in only:
+        ex.update(small_latency(mpc, torch, workloads))
     if "ring_gemm" in only:
         ex.update(ring_gemm_forms(ctx, torch, X, Y))
     if "beaver_mul" in only:
@@ -257,6 +260,45 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only):
     if "conv" in only:
         ex.update(conv_bench(mpc, torch, workloads))
     return ex
+
+
+def small_latency(mpc, torch, workloads):
+    """The small workload: Beaver matmul X[64x128] @ W[128x32] with 2^16
+    truncation (both forms) and an element-wise Beaver product over 4096
+    elements; latency per call, eager and replayed from a HIP graph."""
+    out = {}
+    dseed = workloads.seeds(1)[2]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = mpc.Context(device=0, seed=workloads.seeds(1)[1])
+        dv = lambda a: torch.from_numpy(a).to(c.device)
+        x = c.share(dv(mpc.encode(workloads.uniform(1001, (64, 128), -4, 4), FRAC)), 0, 1)
+        w = c.share(dv(mpc.encode(workloads.uniform(1002, (128, 32), -4, 4), FRAC)), 1, 2)
+        t = c.dealer(mpc.TRIPLE_MATMUL, dseed, 3, (64, 32, 128))
+        z = mpc.SharedPair(c.empty((64, 32)), c.empty((64, 32)))
+        ex_ = c.share(dv(mpc.encode(workloads.uniform(1003, (4096,), -4, 4), FRAC)), 0, 4)
+        ey = c.share(dv(mpc.encode(workloads.uniform(1004, (4096,), -4, 4), FRAC)), 1, 5)
+        te = c.dealer(mpc.TRIPLE_MUL, dseed, 6, (4096,))
+        ez = mpc.SharedPair(c.empty((4096,)), c.empty((4096,)))
+        calls = {"matmul_64x128x32_plain": lambda: c.beaver_matmul(x, w, t, FRAC, "plain", out=z),
+                 "matmul_64x128x32_limb8": lambda: c.beaver_matmul(x, w, t, FRAC, "limb8", out=z),
+                 "mul_4096": lambda: c.beaver_mul(ex_, ey, te, FRAC, out=ez)}
+        for name, fn in calls.items():
+            fn()
+            c.sync()
+            eager = _event_time(torch, side, fn, 50)
+            c.graph_begin()
+            fn()
+            g = c.graph_end()
+            c.graph_launch(g)
+            c.sync()
+            graph = _event_time(torch, side, lambda: c.graph_launch(g), 50)
+            mpc.Context.graph_destroy(g)
+            out[f"small_{name}_us"] = round(eager * 1e3, 2)
+            out[f"small_{name}_graph_us"] = round(graph * 1e3, 2)
+            log(f"bench: small {name}: {eager * 1e3:.1f} us eager, {graph * 1e3:.1f} us graph")
+        c.close()
+    return out
 
 
 def ring_gemm_forms(ctx, torch, X, Y):
