@@ -37,7 +37,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-EXTRAS = ("small", "ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul",
+EXTRAS = ("ceilings", "small", "ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul",
           "conv")
 
 
@@ -142,6 +142,13 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = secondary(ctx, mpc, torch, workloads, X, Y, set(args.extra or EXTRAS))
+        if "ceiling_mfma_i8_random_TOPs" in extras and args.form == "limb8":
+            # the dominant kernel against the sustained matrix-core rate on random data
+            extras["gemm_frac_of_mfma_random_ceiling"] = round(
+                roofline["achieved"] / extras["ceiling_mfma_i8_random_TOPs"], 4)
+        if "ceiling_valu_ring_TMACs" in extras and "ring_gemm_4096_plain_ms" in extras:
+            extras["plain_gemm_frac_of_valu_ceiling"] = round(
+                M * N * K / (extras["ring_gemm_4096_plain_ms"] * 1e-3) / 1e12 / extras["ceiling_valu_ring_TMACs"], 4)
 
     cpu = None
     if not args.no_cpu:
@@ -238,6 +245,8 @@ def _event_time(torch, stream, fn, reps):
 
 def secondary(ctx, mpc, torch, workloads, X, Y, only):
     ex = {}
+    if "ceilings" in only:
+        ex.update(ceilings())
     if "small" in only:
         ex.update(small_latency(mpc, torch, workloads))
     if "ring_gemm" in only:
@@ -260,6 +269,19 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only):
     if "conv" in only:
         ex.update(conv_bench(mpc, torch, workloads))
     return ex
+
+
+def ceilings():
+    """Sustained arithmetic ceilings measured by the library's standalone
+    microbenchmark (no memory traffic): INT8 MFMA on random fragments and the
+    plain form's VALU ring multiply-accumulate."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2109_00984_amd", "ceilings")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120, check=True)
+    c = json.loads(r.stdout.strip().splitlines()[-1])
+    log(f"bench: ceilings: INT8 MFMA on random data {c['mfma_i8_random_tops']} TOP/s, "
+        f"VALU ring MAC {c['valu_ring_tmacs']} T/s")
+    return {"ceiling_mfma_i8_random_TOPs": c["mfma_i8_random_tops"], "ceiling_valu_ring_TMACs": c["valu_ring_tmacs"]}
 
 
 def small_latency(mpc, torch, workloads):

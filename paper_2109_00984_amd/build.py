@@ -41,6 +41,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
+    # the arithmetic-ceiling microbenchmark (a standalone program)
+    cmd = ["hipcc", *[f for f in FLAGS if f != "-fPIC"], os.path.join(CSRC, "ceilings.hip"), "-o",
+           os.path.join(HERE, "ceilings")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
     return OUT
 
 
