@@ -47,6 +47,7 @@ def lib():
             "orc_encode": (SZ, [dblp, SZ, INT, i64p]),
             "orc_decode": (None, [u64p, SZ, INT, dblp]),
             "orc_share": (None, [u64p, SZ, INT, U64, U64, u64p, u64p]),
+            "orc_share_at": (None, [u64p, u64p, SZ, INT, U64, U64, u64p, u64p]),
             "orc_reveal": (None, [u64p, u64p, SZ, u64p]),
             "orc_add": (None, [u64p, u64p, SZ, u64p]),
             "orc_truncate": (None, [u64p, SZ, INT]),
@@ -57,6 +58,8 @@ def lib():
             "orc_conv1d_at": (None, [I64] * 6 + [u64p, u64p, I64, i64p, i64p, i64p, u64p]),
             "orc_dealer_mul": (None, [U64, U64, SZ] + [u64p] * 6),
             "orc_dealer_square": (None, [U64, U64, SZ] + [u64p] * 4),
+            "orc_dealer_mul_at": (None, [U64, U64, u64p, SZ] + [u64p] * 6),
+            "orc_dealer_square_at": (None, [U64, U64, u64p, SZ] + [u64p] * 4),
             "orc_dealer_matmul": (None, [U64, U64, I64, I64, I64] + [u64p] * 6),
             "orc_dealer_matmul_c_at": (None, [U64, U64, I64, I64, I64] + [u64p] * 4
                                        + [I64, i64p, i64p, u64p, u64p]),
@@ -172,6 +175,17 @@ def share(x, src, seed, tag):
     return s0, s1
 
 
+def share_at(x, idx, src, seed, tag):
+    """Shares of the elements idx of a shared vector, x holding their values:
+    the same shares ``share`` gives those elements, for vectors of any length."""
+    x, px = _u(as_ring(x))
+    idx, pi = _u(idx)
+    s0, p0 = _out(x.shape)
+    s1, p1 = _out(x.shape)
+    lib().orc_share_at(px, pi, x.size, src, seed, tag, p0, p1)
+    return s0, s1
+
+
 def reveal(s0, s1):
     s0, p0 = _u(s0)
     s1, p1 = _u(s1)
@@ -266,6 +280,24 @@ def dealer_mul(dseed, tag, n):
 def dealer_square(dseed, tag, n):
     bufs = [_out(n) for _ in range(4)]
     lib().orc_dealer_square(dseed, tag, n, *[p for _, p in bufs])
+    a0, a1, b0, b1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1))
+
+
+def dealer_mul_at(dseed, tag, idx):
+    """Elements idx of the product triple ``dealer_mul`` draws (any length)."""
+    idx, pi = _u(idx)
+    bufs = [_out(idx.size) for _ in range(6)]
+    lib().orc_dealer_mul_at(dseed, tag, pi, idx.size, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
+
+
+def dealer_square_at(dseed, tag, idx):
+    """Elements idx of the square pair ``dealer_square`` draws (any length)."""
+    idx, pi = _u(idx)
+    bufs = [_out(idx.size) for _ in range(4)]
+    lib().orc_dealer_square_at(dseed, tag, pi, idx.size, *[p for _, p in bufs])
     a0, a1, b0, b1 = [b for b, _ in bufs]
     return Triple((a0, a1), (b0, b1))
 

@@ -115,19 +115,28 @@ void orc_decode(const u64 *v, size_t n, int frac_bits, double *out) {
 /* Two parties: the zero-share is (-m, m) with m = G(seed, tag, SHARE, i);    */
 /* the source party adds its value, so s_src = x - m and s_other = m.         */
 /* ------------------------------------------------------------------------ */
-void orc_share(const u64 *x, size_t n, int src, u64 seed, u64 tag, u64 *s0, u64 *s1) {
-  for (size_t i = 0; i < n; ++i) {
-    u64 m = orc_prg(seed, tag, SLOT_SHARE, (u64)i);
-    u64 zs_src = (u64)0 - m; /* the two zero-share entries sum to 0 mod Q */
-    u64 zs_other = m;
-    if (src == 0) {
-      s0[i] = x[i] + zs_src;
-      s1[i] = zs_other;
-    } else {
-      s0[i] = zs_other;
-      s1[i] = x[i] + zs_src;
-    }
+/* Element i of the vector, whose value there is x. */
+static void share_elem(u64 x, u64 i, int src, u64 seed, u64 tag, u64 *s0, u64 *s1) {
+  u64 m = orc_prg(seed, tag, SLOT_SHARE, i);
+  u64 zs_src = (u64)0 - m; /* the two zero-share entries sum to 0 mod Q */
+  u64 zs_other = m;
+  if (src == 0) {
+    *s0 = x + zs_src;
+    *s1 = zs_other;
+  } else {
+    *s0 = zs_other;
+    *s1 = x + zs_src;
   }
+}
+
+void orc_share(const u64 *x, size_t n, int src, u64 seed, u64 tag, u64 *s0, u64 *s1) {
+  for (size_t i = 0; i < n; ++i) share_elem(x[i], (u64)i, src, seed, tag, &s0[i], &s1[i]);
+}
+
+/* Selected elements only: x[t] is the value of element idx[t]. */
+void orc_share_at(const u64 *x, const u64 *idx, size_t n, int src, u64 seed, u64 tag, u64 *s0,
+                  u64 *s1) {
+  for (size_t t = 0; t < n; ++t) share_elem(x[t], idx[t], src, seed, tag, &s0[t], &s1[t]);
 }
 
 /* x = sum_p [x]_p mod Q */
@@ -232,28 +241,47 @@ void orc_conv1d_at(i64 Bt, i64 Cin, i64 L, i64 Cout, i64 ksz, i64 stride, const 
 /*   c_0 = G(dseed, tag, C_0, i),  c_1 = c - c_0.                             */
 /* For the square pair (App. C.1.1, Square) b = a^2, so b_1 = a^2 - b_0.     */
 /* ------------------------------------------------------------------------ */
+/* Element i of a product triple and of a square pair. */
+static void dealer_mul_elem(u64 dseed, u64 tag, u64 i, u64 *a0, u64 *a1, u64 *b0, u64 *b1, u64 *c0,
+                            u64 *c1) {
+  *a0 = orc_prg(dseed, tag, SLOT_A0, i);
+  *a1 = orc_prg(dseed, tag, SLOT_A1, i);
+  *b0 = orc_prg(dseed, tag, SLOT_B0, i);
+  *b1 = orc_prg(dseed, tag, SLOT_B1, i);
+  u64 a = *a0 + *a1, b = *b0 + *b1;
+  u64 c = a * b;
+  *c0 = orc_prg(dseed, tag, SLOT_C0, i);
+  *c1 = c - *c0;
+}
+
+static void dealer_square_elem(u64 dseed, u64 tag, u64 i, u64 *a0, u64 *a1, u64 *b0, u64 *b1) {
+  *a0 = orc_prg(dseed, tag, SLOT_A0, i);
+  *a1 = orc_prg(dseed, tag, SLOT_A1, i);
+  u64 a = *a0 + *a1;
+  *b0 = orc_prg(dseed, tag, SLOT_B0, i);
+  *b1 = a * a - *b0;
+}
+
 void orc_dealer_mul(u64 dseed, u64 tag, size_t n, u64 *a0, u64 *a1, u64 *b0, u64 *b1,
                     u64 *c0, u64 *c1) {
-  for (size_t i = 0; i < n; ++i) {
-    a0[i] = orc_prg(dseed, tag, SLOT_A0, i);
-    a1[i] = orc_prg(dseed, tag, SLOT_A1, i);
-    b0[i] = orc_prg(dseed, tag, SLOT_B0, i);
-    b1[i] = orc_prg(dseed, tag, SLOT_B1, i);
-    u64 a = a0[i] + a1[i], b = b0[i] + b1[i];
-    u64 c = a * b;
-    c0[i] = orc_prg(dseed, tag, SLOT_C0, i);
-    c1[i] = c - c0[i];
-  }
+  for (size_t i = 0; i < n; ++i)
+    dealer_mul_elem(dseed, tag, (u64)i, &a0[i], &a1[i], &b0[i], &b1[i], &c0[i], &c1[i]);
 }
 
 void orc_dealer_square(u64 dseed, u64 tag, size_t n, u64 *a0, u64 *a1, u64 *b0, u64 *b1) {
-  for (size_t i = 0; i < n; ++i) {
-    a0[i] = orc_prg(dseed, tag, SLOT_A0, i);
-    a1[i] = orc_prg(dseed, tag, SLOT_A1, i);
-    u64 a = a0[i] + a1[i];
-    b0[i] = orc_prg(dseed, tag, SLOT_B0, i);
-    b1[i] = a * a - b0[i];
-  }
+  for (size_t i = 0; i < n; ++i) dealer_square_elem(dseed, tag, (u64)i, &a0[i], &a1[i], &b0[i], &b1[i]);
+}
+
+/* Selected elements idx[0..n) of a triple (pair) of any length. */
+void orc_dealer_mul_at(u64 dseed, u64 tag, const u64 *idx, size_t n, u64 *a0, u64 *a1, u64 *b0,
+                       u64 *b1, u64 *c0, u64 *c1) {
+  for (size_t t = 0; t < n; ++t)
+    dealer_mul_elem(dseed, tag, idx[t], &a0[t], &a1[t], &b0[t], &b1[t], &c0[t], &c1[t]);
+}
+
+void orc_dealer_square_at(u64 dseed, u64 tag, const u64 *idx, size_t n, u64 *a0, u64 *a1, u64 *b0,
+                          u64 *b1) {
+  for (size_t t = 0; t < n; ++t) dealer_square_elem(dseed, tag, idx[t], &a0[t], &a1[t], &b0[t], &b1[t]);
 }
 
 /* Matrix triple: a is MxK, b is KxN, c = a @ b is MxN. */

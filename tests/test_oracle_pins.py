@@ -54,6 +54,58 @@ def test_prg_domains_distinct_and_deterministic():
     assert int(a[17]) == bigint.splitmix64_stream(s, 18)[17]
 
 
+# element indices past 2^31 and 2^32, where 32-bit index arithmetic would wrap
+FAR = np.array([(1 << 31) - 1, 1 << 31, (1 << 31) + 37, (1 << 32) + 3, (1 << 40) + 11],
+               dtype=np.uint64)
+
+
+def test_prg_far_indices_jump_ahead():
+    # a SplitMix64 stream's state only advances by the gamma, so output idx of
+    # the stream with state s is the first output of the stream with state
+    # s + idx * gamma: the Python twin reaches far indices in one step
+    seed, tag = 2005, 7
+    t = bigint.splitmix64_stream(seed, tag + 1)[tag]
+    for slot in (oracle.SLOT_SHARE, oracle.SLOT_A0, oracle.SLOT_C0):
+        s = bigint.splitmix64_stream(t, slot + 1)[slot]
+        for i in pyints(FAR):
+            want = bigint.splitmix64_stream((s + i * 0x9E3779B97F4A7C15) % Q, 1)[0]
+            assert oracle.prg(seed, tag, slot, i) == want
+
+
+@pytest.mark.parametrize("src", [0, 1])
+def test_share_at_far_indices(src):
+    x = rand_ring(61, FAR.size)
+    s0, s1 = oracle.share_at(x, FAR, src, 2005, 7)
+    # reveals x, and the non-source share is the PRG mask of that element
+    assert pyints(s0 + s1) == pyints(x)
+    other = s1 if src == 0 else s0
+    assert pyints(other) == [oracle.prg(2005, 7, oracle.SLOT_SHARE, i) for i in pyints(FAR)]
+    # near the start the selected elements are those of the whole vector
+    idx = np.array([0, 3, 999, 500], dtype=np.uint64)
+    full = oracle.share(rand_ring(62, 1000), src, 2005, 7)
+    part = oracle.share_at(rand_ring(62, 1000)[idx.astype(np.int64)], idx, src, 2005, 7)
+    for p in (0, 1):
+        assert np.array_equal(full[p][idx.astype(np.int64)], part[p])
+
+
+def test_dealer_at_far_indices():
+    t = oracle.dealer_mul_at(3005, 9, FAR)
+    sq = oracle.dealer_square_at(3005, 9, FAR)
+    for k in range(FAR.size):
+        a = (int(t.a[0][k]) + int(t.a[1][k])) % Q
+        b = (int(t.b[0][k]) + int(t.b[1][k])) % Q
+        assert (int(t.c[0][k]) + int(t.c[1][k])) % Q == a * b % Q
+        a2 = (int(sq.a[0][k]) + int(sq.a[1][k])) % Q
+        assert (int(sq.b[0][k]) + int(sq.b[1][k])) % Q == a2 * a2 % Q
+    # the pair shares its a with the product triple of the same (seed, tag)
+    assert np.array_equal(t.a[0], sq.a[0]) and np.array_equal(t.a[1], sq.a[1])
+    idx = np.array([0, 7, 63], dtype=np.uint64)
+    full, part = oracle.dealer_mul(3005, 9, 64), oracle.dealer_mul_at(3005, 9, idx)
+    for k in "abc":
+        for p in (0, 1):
+            assert np.array_equal(getattr(full, k)[p][idx.astype(np.int64)], getattr(part, k)[p])
+
+
 def test_prg_bits_balanced():
     v = oracle.prg_fill(11, 1, 0, 1 << 16)
     bits = np.unpackbits(v.view(np.uint8)).reshape(-1, 64).mean(axis=0)
