@@ -44,6 +44,7 @@ def lib():
             "orc_sm64_at": (U64, [U64, U64]),
             "orc_prg": (U64, [U64, U64, U64, U64]),
             "orc_prg_fill": (None, [U64, U64, U64, SZ, u64p]),
+            "orc_prg_at": (None, [U64, U64, U64, u64p, SZ, u64p]),
             "orc_encode": (SZ, [dblp, SZ, INT, i64p]),
             "orc_decode": (None, [u64p, SZ, INT, dblp]),
             "orc_share": (None, [u64p, SZ, INT, U64, U64, u64p, u64p]),
@@ -64,6 +65,7 @@ def lib():
             "orc_dealer_matmul_c_at": (None, [U64, U64, I64, I64, I64] + [u64p] * 4
                                        + [I64, i64p, i64p, u64p, u64p]),
             "orc_dealer_conv1d": (None, [U64, U64] + [I64] * 6 + [u64p] * 6),
+            "orc_dealer_matmul_rows": (None, [U64, U64, I64, I64, I64, i64p] + [u64p] * 6),
             "orc_beaver_mul": (None, [SZ] + [u64p] * 10 + [INT, u64p, u64p]),
             "orc_beaver_square": (None, [SZ] + [u64p] * 6 + [INT, u64p, u64p]),
             "orc_beaver_matmul": (None, [I64, I64, I64] + [u64p] * 10 + [INT, u64p, u64p]),
@@ -140,6 +142,14 @@ def prg(seed, tag, slot, idx):
 def prg_fill(seed, tag, slot, n):
     out, p = _out(n)
     lib().orc_prg_fill(seed, tag, slot, n, p)
+    return out
+
+
+def prg_at(seed, tag, slot, idx):
+    """G(seed, tag, slot, i) for each i of the index array idx (same shape)."""
+    idx, pi = _u(idx)
+    out, p = _out(idx.shape)
+    lib().orc_prg_at(seed, tag, slot, pi, idx.size, p)
     return out
 
 
@@ -329,6 +339,18 @@ def dealer_matmul_c_at(dseed, tag, M, N, K, a, b, rows, cols):
     lib().orc_dealer_matmul_c_at(dseed, tag, M, N, K, pa0, pa1, pb0, pb1, rows.size, pr, pcl,
                                  pc0, pc1)
     return c0, c1
+
+
+def dealer_matmul_rows(dseed, tag, N, K, rows):
+    """Rows `rows` of the matrix triple ``dealer_matmul`` draws, for any
+    height: a_p and c_p restricted to those rows, and all of b_p."""
+    rows, pr = _i(rows)
+    R = rows.size
+    shapes = [(R, K), (R, K), (K, N), (K, N), (R, N), (R, N)]
+    bufs = [_out(s) for s in shapes]
+    lib().orc_dealer_matmul_rows(dseed, tag, N, K, R, pr, *[p for _, p in bufs])
+    a0, a1, b0, b1, c0, c1 = [b for b, _ in bufs]
+    return Triple((a0, a1), (b0, b1), (c0, c1))
 
 
 def dealer_conv1d(dseed, tag, Bt, Cin, L, Cout, ksz, stride):

@@ -85,6 +85,10 @@ void orc_prg_fill(u64 seed, u64 tag, u64 slot, size_t n, u64 *out) {
   for (size_t i = 0; i < n; ++i) out[i] = orc_prg(seed, tag, slot, (u64)i);
 }
 
+void orc_prg_at(u64 seed, u64 tag, u64 slot, const u64 *idx, size_t n, u64 *out) {
+  for (size_t t = 0; t < n; ++t) out[t] = orc_prg(seed, tag, slot, idx[t]);
+}
+
 /* PRG slots (domains inside one tag). */
 enum { SLOT_SHARE = 0, SLOT_A0 = 1, SLOT_A1 = 2, SLOT_B0 = 3, SLOT_B1 = 4, SLOT_C0 = 5 };
 
@@ -321,6 +325,33 @@ void orc_dealer_matmul_c_at(u64 dseed, u64 tag, i64 M, i64 N, i64 K, const u64 *
     c0[t] = orc_prg(dseed, tag, SLOT_C0, (u64)(rows[t] * N + cols[t]));
     c1[t] = c - c0[t];
   }
+}
+
+/* Rows rows[0..R) of a matrix triple with k = K and N columns, for matrices
+ * of any height: a_p and c_p of those rows (R x K and R x N) and all of b_p. */
+void orc_dealer_matmul_rows(u64 dseed, u64 tag, i64 N, i64 K, i64 R, const i64 *rows, u64 *a0,
+                            u64 *a1, u64 *b0, u64 *b1, u64 *c0, u64 *c1) {
+  for (i64 r = 0; r < R; ++r)
+    for (i64 k = 0; k < K; ++k) {
+      a0[r * K + k] = orc_prg(dseed, tag, SLOT_A0, (u64)(rows[r] * K + k));
+      a1[r * K + k] = orc_prg(dseed, tag, SLOT_A1, (u64)(rows[r] * K + k));
+    }
+  orc_prg_fill(dseed, tag, SLOT_B0, (size_t)(K * N), b0);
+  orc_prg_fill(dseed, tag, SLOT_B1, (size_t)(K * N), b1);
+  u64 *a = (u64 *)malloc(sizeof(u64) * (size_t)(R * K));
+  u64 *b = (u64 *)malloc(sizeof(u64) * (size_t)(K * N));
+  u64 *c = (u64 *)malloc(sizeof(u64) * (size_t)(R * N));
+  orc_add(a0, a1, (size_t)(R * K), a);
+  orc_add(b0, b1, (size_t)(K * N), b);
+  orc_ring_gemm(R, N, K, a, b, c);
+  for (i64 r = 0; r < R; ++r)
+    for (i64 j = 0; j < N; ++j) {
+      c0[r * N + j] = orc_prg(dseed, tag, SLOT_C0, (u64)(rows[r] * N + j));
+      c1[r * N + j] = c[r * N + j] - c0[r * N + j];
+    }
+  free(a);
+  free(b);
+  free(c);
 }
 
 /* Convolution triple: a has activation shape [Bt][Cin][L], b has weight

@@ -70,6 +70,11 @@ def test_prg_far_indices_jump_ahead():
         for i in pyints(FAR):
             want = bigint.splitmix64_stream((s + i * 0x9E3779B97F4A7C15) % Q, 1)[0]
             assert oracle.prg(seed, tag, slot, i) == want
+    # the array form agrees element by element, at far and near indices
+    idx = np.concatenate([FAR, np.arange(5, dtype=np.uint64)])
+    got = oracle.prg_at(seed, tag, oracle.SLOT_B1, idx)
+    assert pyints(got) == [oracle.prg(seed, tag, oracle.SLOT_B1, i) for i in pyints(idx)]
+    assert np.array_equal(got[FAR.size:], oracle.prg_fill(seed, tag, oracle.SLOT_B1, 5))
 
 
 @pytest.mark.parametrize("src", [0, 1])
@@ -104,6 +109,27 @@ def test_dealer_at_far_indices():
     for k in "abc":
         for p in (0, 1):
             assert np.array_equal(getattr(full, k)[p][idx.astype(np.int64)], getattr(part, k)[p])
+
+
+def test_dealer_matmul_rows():
+    M, N, K = 9, 4, 13
+    rows = np.array([0, 8, 3], dtype=np.int64)
+    full, part = oracle.dealer_matmul(3006, 2, M, N, K), oracle.dealer_matmul_rows(3006, 2, N, K, rows)
+    for p in (0, 1):
+        assert np.array_equal(full.a[p][rows], part.a[p])
+        assert np.array_equal(full.b[p], part.b[p])
+        assert np.array_equal(full.c[p][rows], part.c[p])
+    # far rows: c = a @ b, checked with Python integers on the revealed values
+    far = np.array([(1 << 31) // K + 1, (1 << 33) // K], dtype=np.int64)
+    t = oracle.dealer_matmul_rows(3006, 2, N, K, far)
+    A = [[(int(t.a[0][r, k]) + int(t.a[1][r, k])) % Q for k in range(K)] for r in range(far.size)]
+    B = [[(int(t.b[0][k, j]) + int(t.b[1][k, j])) % Q for j in range(N)] for k in range(K)]
+    C = bigint.matmul(A, B)
+    for r in range(far.size):
+        for j in range(N):
+            assert (int(t.c[0][r, j]) + int(t.c[1][r, j])) % Q == C[r][j]
+        assert int(t.a[0][r, 5]) == oracle.prg(3006, 2, oracle.SLOT_A0, int(far[r]) * K + 5)
+        assert int(t.c[0][r, 1]) == oracle.prg(3006, 2, oracle.SLOT_C0, int(far[r]) * N + 1)
 
 
 def test_prg_bits_balanced():
