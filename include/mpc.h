@@ -63,7 +63,11 @@ typedef enum {
  *          pairs (i, j) with i + j <= 7 are multiplied on INT8 matrix cores
  *          with exact int32 accumulation (K split so no sum can overflow) and
  *          combined as sum 2^(8(i+j)) D_i E_j mod 2^64.  Bit-identical to PLAIN.
- *   AUTO:  the library's choice (LIMB8 unless the problem is tiny).
+ *          Each operand's k range (K of a product; each of the two halves of
+ *          a Beaver finish, whose summed k is 2K) is at most 2,097,088 long;
+ *          longer ones return MPC_E_UNSUPPORTED.
+ *   AUTO:  the library's choice (LIMB8 unless the problem is tiny or its k
+ *          is longer than LIMB8 takes; then PLAIN).
  *   FP64LIMB: the paper's own GPU method (Section 5.3, off-loading to the
  *          GPU): operands split into four 16-bit limbs (ten pairwise products)
  *          or, when the summed k is below 1024, three 22-bit limbs (six), each

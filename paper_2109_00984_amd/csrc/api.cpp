@@ -319,10 +319,18 @@ Epilogue make_ep(const u64* cadd, int csign, int trunc, u64* out, OutView v) {
   return e;
 }
 
-mpc_form resolve_form(mpc_form f, i64 M, i64 N, i64 K) {
+// AUTO: the limb form for products of 2^22 ring MACs or more, when it can
+// address their k segments (each kseg long; K is the total).
+mpc_form resolve_form(mpc_form f, i64 M, i64 N, i64 K, i64 kseg) {
   if (f != MPC_FORM_AUTO) return f;
+  if (kseg > kLimbMaxSegK) return MPC_FORM_PLAIN;
   const double work = (double)M * (double)N * (double)K;
   return work >= (double)(1 << 22) ? MPC_FORM_LIMB8 : MPC_FORM_PLAIN;
+}
+
+// The limb form asked for a k segment longer than it addresses.
+mpc_status check_limb_k(mpc_form f, i64 kseg) {
+  return f == MPC_FORM_LIMB8 && kseg > kLimbMaxSegK ? MPC_E_UNSUPPORTED : MPC_OK;
 }
 
 // ------------------------------------------------------------------ plain form
@@ -631,6 +639,9 @@ struct LimbReq {
 // launch, adding into its output; truncation is applied by its last chunk).
 mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std::vector<LimbReq>& reqs,
                       TileSched sched) {
+  // every entry point checks this before it issues any work
+  for (const LimbReq& r : reqs)
+    if (r.K0 > kLimbMaxSegK || r.K1 > kLimbMaxSegK) return MPC_E_UNSUPPORTED;
   hipStream_t st = c->s[0];
   // one pack launch per (kind, mode): the kernel is specialised on both
   std::vector<PackJob> jobs;
@@ -1050,7 +1061,7 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
     for (int j = 0; j < i; ++j)
       if (overlap(bufs[i], ns[i], bufs[j], ns[j])) return MPC_E_ALIAS;
 
-  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K);
+  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K, K);
   const Epilogue ep = make_ep(t->c0, -1, 0, t->c1, view);
   // the left factor is a (matmul) or the weight b (conv); the right one b or im2col(a)
   const u64 *L0 = kind == MPC_TRIPLE_MATMUL ? t->a0 : t->b0, *L1 = kind == MPC_TRIPLE_MATMUL ? t->a1 : t->b1;
@@ -1333,9 +1344,11 @@ mpc_status mpc_beaver_matmul(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const 
   CHK(check_form(form));
   MatmulPlan m{M, N, K, x0, x1, y0, y1, *t, z0, z1};
   CHK(validate_matmul(m));
+  form = resolve_form(form, M, N, 2 * K, K);
+  CHK(check_limb_k(form, K));
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
-  CHK(run_matmuls(c, {m}, trunc_bits, resolve_form(form, M, N, 2 * K)));
+  CHK(run_matmuls(c, {m}, trunc_bits, form));
   return end_call(c);
 }
 
@@ -1365,7 +1378,8 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
   // transposed orientation: z_p[b][o][l] is element (o, b*Lout + l) of
   //   c_p + Wm(b_p) @ im2col(eps) + Wm(delta) @ im2col(g_p),  g_0 = a_0 + eps, g_1 = a_1
   const i64 M = s.cout, N = s.batch * lout, K = s.cin * s.ksize;
-  form = resolve_form(form, M, N, 2 * K);
+  form = resolve_form(form, M, N, 2 * K, K);
+  CHK(check_limb_k(form, K));
   const OutView view{lout, std::max<i64>(lout, 1), s.cout * lout};
   if (form == MPC_FORM_LIMB8) {
     JobSpec jw = left_job(M, K, K), jx = im2col_job(s, lout);
@@ -1421,7 +1435,8 @@ mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint
     return MPC_E_ALIAS;
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
-  form = resolve_form(form, M, N, K);
+  form = resolve_form(form, M, N, K, K);
+  CHK(check_limb_k(form, K));
   const Epilogue ep = make_ep(nullptr, +1, 0, C, rowmajor_view(N));
   if (form == MPC_FORM_LIMB8) {
     JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
@@ -1447,7 +1462,6 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
   if (!c || (count && !descs)) return MPC_E_INVAL;
   CHK(check_trunc(trunc_bits));
   CHK(check_form(form));
-  if (form == MPC_FORM_AUTO) form = MPC_FORM_LIMB8;
   std::vector<MatmulPlan> plans;
   for (size_t i = 0; i < count; ++i) {
     const mpc_matmul_desc& d = descs[i];
@@ -1456,6 +1470,11 @@ mpc_status mpc_beaver_matmul_grouped(mpc_ctx* c, size_t count, const mpc_matmul_
     if (d.M == 0 || d.N == 0) continue;
     plans.push_back(m);
   }
+  // AUTO: the limb form, unless a problem's k is longer than it addresses
+  i64 kmax = 0;
+  for (const MatmulPlan& m : plans) kmax = std::max(kmax, m.K);
+  if (form == MPC_FORM_AUTO) form = kmax > kLimbMaxSegK ? MPC_FORM_PLAIN : MPC_FORM_LIMB8;
+  CHK(check_limb_k(form, kmax));
   if (plans.empty()) return MPC_OK;
   {
     std::vector<Span> outs, ins;
@@ -1563,6 +1582,7 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
   for (size_t i = 0; i < count; ++i) {
     const i64 M = dims[3 * i], N = dims[3 * i + 1], K = dims[3 * i + 2];
     if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+    CHK(check_limb_k(MPC_FORM_LIMB8, K));
     if (M && N) shapes.push_back({M, N, K});
   }
   if (shapes.empty()) return MPC_OK;
@@ -2003,7 +2023,7 @@ mpc_status mpc_mp_dealer_triples(mpc_ctx* c, int P, mpc_triple_kind kind, uint64
   CHK(mp_alias(a, P, na, {{&bi, nb}, {&ci, nc}}));
   CHK(mp_alias(b, P, nb, {{&ci, nc}}));
   if (!na && !nb && !nc) return MPC_OK;
-  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K);
+  const mpc_form form = resolve_form(MPC_FORM_AUTO, M, N, K, K);
   // workspace: a = sum a_p, b = sum b_p, S = sum_{p<P-1} c_p, then the GEMM's packs
   JobSpec ja = left_job(M, K, K), jb = right_job(K, N, N);
   size_t need = kAlign + align_up(na * 8) + align_up(nb * 8) + align_up(nc * 8);
@@ -2093,7 +2113,8 @@ mpc_status mpc_mp_beaver_matmul(mpc_ctx* c, int P, int64_t M, int64_t N, int64_t
   CHK(mp_alias(zo, P, nc, {{&xi, na}, {&yi, nb}, {&ai, na}, {&bi, nb}, {&ci, nc}}));
   if (!nc) return MPC_OK;
   CHK(set_device(c));
-  form = resolve_form(form, M, N, 2 * K);
+  form = resolve_form(form, M, N, 2 * K, K);
+  CHK(check_limb_k(form, K));
   const hipStream_t st = c->s[0];
   // open eps (MxK) and delta (KxN) into the workspace, then party p's finish
   // z_p = c_p + [a_p + [p=0] eps | eps] @ [delta ; b_p]

@@ -156,6 +156,11 @@ constexpr int kLimbMaxKBlocks = 510;  // 510 * 32 = 16320
 // Smallest split-K slice of the limb GEMM, in 64-wide k steps.
 constexpr int kLimbMinSliceSteps = 4;
 static_assert(kLimbMaxKBlocks % 2 == 0, "chunks must hold whole k steps");
+// Longest k segment the limb GEMM addresses.  A wave reads up to 4 strips of
+// 32 rows of one packed segment through one buffer descriptor, whose byte
+// range and offsets are 32-bit: 4 strips * 65534 k-blocks * 8 KiB stays below
+// 2^31.  Longer segments take the plain form.
+constexpr i64 kLimbMaxSegK = 65534 * 32;  // 2,097,088
 
 // Tile-to-problem table for grouped launches.
 struct TileMap {
