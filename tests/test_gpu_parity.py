@@ -88,6 +88,34 @@ def test_empty_inputs(m, ctx):
     ctx.sync()
 
 
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+def test_zero_k(m, ctx, form):
+    # k = 0: every product is the empty sum, so the dealer's c is 0 (shared as
+    # c0, -c0) and each party's Beaver output is its c share, truncated
+    M, N = 70, 9
+    say(f"k = 0 ({form})")
+    X, Y = np.zeros((M, 0), np.uint64), np.zeros((0, N), np.uint64)
+    xs, ys = oracle.share(X, 0, SEED, 61), oracle.share(Y, 1, SEED, 62)
+    w = oracle.dealer_matmul(3007, 63, M, N, 0)
+    t = ctx.dealer(m.TRIPLE_MATMUL, 3007, 63, (M, N, 0))
+    assert_pair(ctx, m.SharedPair(t.c0, t.c1), w.c, "dealer c at k = 0")
+    gx, gy = ctx.share(dev(X), 0, 61), ctx.share(dev(Y), 1, 62)
+    z = ctx.beaver_matmul(gx, gy, t, 16, form)
+    assert_pair(ctx, z, oracle.beaver_matmul(xs, ys, w, 16), "Beaver matmul at k = 0")
+    C = ctx.ring_gemm(gx.s0, gy.s0, form=form)
+    assert not np.any(host(ctx, C))
+    # a grouped call mixing k = 0 with an ordinary problem
+    M2, N2, K2 = 33, 17, 40
+    X2, Y2 = rnd(64, (M2, K2)), rnd(65, (K2, N2))
+    gx2, gy2 = ctx.share(dev(X2), 0, 66), ctx.share(dev(Y2), 1, 67)
+    t2 = ctx.dealer(m.TRIPLE_MATMUL, 3007, 68, (M2, N2, K2))
+    zs = ctx.beaver_matmul_grouped([(gx, gy, t), (gx2, gy2, t2)], 16, form)
+    assert_pair(ctx, zs[0], oracle.beaver_matmul(xs, ys, w, 16), "grouped, k = 0 problem")
+    want2 = oracle.beaver_matmul(oracle.share(X2, 0, SEED, 66), oracle.share(Y2, 1, SEED, 67),
+                                 oracle.dealer_matmul(3007, 68, M2, N2, K2), 16)
+    assert_pair(ctx, zs[1], want2, "grouped, ordinary problem")
+
+
 def test_argument_errors(m, ctx):
     say("errors")
     x = ctx.share(dev(rnd(1, 16)), 0, 1)
