@@ -146,6 +146,10 @@ def main():
             # the dominant kernel against the sustained matrix-core rate on random data
             extras["gemm_frac_of_mfma_random_ceiling"] = round(
                 roofline["achieved"] / extras["ceiling_mfma_i8_random_TOPs"], 4)
+        if "ceiling_hbm_stream_10r2w_GBps" in extras and "beaver_mul_hbm_GBps_algorithmic" in extras:
+            # the fused Beaver product against its own access pattern with trivial arithmetic
+            extras["beaver_mul_frac_of_stream_ceiling"] = round(
+                extras["beaver_mul_hbm_GBps_algorithmic"] / extras["ceiling_hbm_stream_10r2w_GBps"], 4)
         if "ceiling_valu_ring_TMACs" in extras and "ring_gemm_4096_plain_ms" in extras:
             extras["plain_gemm_frac_of_valu_ceiling"] = round(
                 M * N * K / (extras["ring_gemm_4096_plain_ms"] * 1e-3) / 1e12 / extras["ceiling_valu_ring_TMACs"], 4)
@@ -280,8 +284,10 @@ def ceilings():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120, check=True)
     c = json.loads(r.stdout.strip().splitlines()[-1])
     log(f"bench: ceilings: INT8 MFMA on random data {c['mfma_i8_random_tops']} TOP/s, "
-        f"VALU ring MAC {c['valu_ring_tmacs']} T/s")
-    return {"ceiling_mfma_i8_random_TOPs": c["mfma_i8_random_tops"], "ceiling_valu_ring_TMACs": c["valu_ring_tmacs"]}
+        f"VALU ring MAC {c['valu_ring_tmacs']} T/s, HBM stream (10 in, 2 out) {c['hbm_stream_10r2w_gbs']} GB/s, "
+        f"HBM copy {c['hbm_copy_gbs']} GB/s")
+    return {"ceiling_mfma_i8_random_TOPs": c["mfma_i8_random_tops"], "ceiling_valu_ring_TMACs": c["valu_ring_tmacs"],
+            "ceiling_hbm_stream_10r2w_GBps": c["hbm_stream_10r2w_gbs"], "ceiling_hbm_copy_GBps": c["hbm_copy_gbs"]}
 
 
 def small_latency(mpc, torch, workloads):

@@ -10,6 +10,13 @@
 //  * Vector ALUs: the plain GEMM's ring multiply-accumulate on 32-bit halves
 //    (a 64-bit lo*lo multiply-add and two 32-bit cross products) over 8x4
 //    register blocks.
+//
+// and two streaming rates of HBM, with buffers far larger than the caches:
+//
+//  * ten input streams and two output streams per element with trivial
+//    arithmetic (a sum and an exclusive or): the access pattern of the fused
+//    Beaver product, 96 bytes per element;
+//  * one input and one output stream (a copy), 16 bytes per element.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
@@ -120,6 +127,32 @@ __global__ void __launch_bounds__(256) k_valu_ceiling(int iters, u64 seed, u64* 
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+// Streaming kernels: 16-byte non-temporal loads and stores, grid-stride over
+// pairs of 64-bit elements, every load of an iteration issued before its
+// stores.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u64x2 ld(const u64x2* p, size_t i) { return __builtin_nontemporal_load(p + i); }
+__device__ __forceinline__ void st(u64x2* p, size_t i, u64x2 v) { __builtin_nontemporal_store(v, p + i); }
+
+__global__ void __launch_bounds__(256)
+    k_stream_10r2w(size_t n2, const u64x2* __restrict__ i0, const u64x2* __restrict__ i1,
+                   const u64x2* __restrict__ i2, const u64x2* __restrict__ i3, const u64x2* __restrict__ i4,
+                   const u64x2* __restrict__ i5, const u64x2* __restrict__ i6, const u64x2* __restrict__ i7,
+                   const u64x2* __restrict__ i8, const u64x2* __restrict__ i9, u64x2* __restrict__ o0,
+                   u64x2* __restrict__ o1) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
+    const u64x2 v0 = ld(i0, i), v1 = ld(i1, i), v2 = ld(i2, i), v3 = ld(i3, i), v4 = ld(i4, i);
+    const u64x2 v5 = ld(i5, i), v6 = ld(i6, i), v7 = ld(i7, i), v8 = ld(i8, i), v9 = ld(i9, i);
+    st(o0, i, v0 + v1 + v2 + v3 + v4 + v5 + v6 + v7 + v8 + v9);
+    st(o1, i, v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7 ^ v8 ^ v9);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy(size_t n2, const u64x2* __restrict__ in, u64x2* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) st(out, i, ld(in, i));
+}
+
 // SplitMix64 bytes for the operand fragments (Steele, Lea and Flood, 2014).
 __global__ void k_fill(u64* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,8 +205,40 @@ int main() {
     return 1;
   const double mfma_ops = 2.0 * 16 * 16 * 64 * (36.0 * RB) * steps * 4.0 * blocks;
   const double valu_macs = (double)blocks * 256 * iters * 16 * TM * TN;
-  std::printf("{\"mfma_i8_random_tops\": %.1f, \"valu_ring_tmacs\": %.3f}\n", mfma_ops / (mfma_ms * 1e-3) / 1e12,
-              valu_macs / (valu_ms * 1e-3) / 1e12);
+
+  // streams: 12 buffers of 2^24 elements (1.5 GiB) for the Beaver pattern,
+  // 2 of 2^27 (2 GiB) for the copy; the grid is capped at 65536 workgroups
+  // as in the library's element-wise kernels
+  const size_t n_bv = (size_t)1 << 24, n_cp = (size_t)1 << 27;
+  u64x2* bufs[12];
+  for (auto& b : bufs) {
+    CK(hipMalloc(&b, n_bv * sizeof(u64)));
+    CK(hipMemset(b, 0x5a, n_bv * sizeof(u64)));
+  }
+  u64x2 *cin = nullptr, *cout = nullptr;
+  CK(hipMalloc(&cin, n_cp * sizeof(u64)));
+  CK(hipMalloc(&cout, n_cp * sizeof(u64)));
+  CK(hipMemset(cin, 0x5a, n_cp * sizeof(u64)));
+  auto grid = [](size_t n2) { return dim3((unsigned)(n2 / 256 > 65536 ? 65536 : (n2 + 255) / 256)); };
+  float bv_ms = 0.f, cp_ms = 0.f;
+  if (time_ms(
+          [&] {
+            hipLaunchKernelGGL(k_stream_10r2w, grid(n_bv / 2), dim3(256), 0, 0, n_bv / 2, bufs[0], bufs[1], bufs[2],
+                               bufs[3], bufs[4], bufs[5], bufs[6], bufs[7], bufs[8], bufs[9], bufs[10], bufs[11]);
+          },
+          5, 20, &bv_ms))
+    return 1;
+  if (time_ms([&] { hipLaunchKernelGGL(k_copy, grid(n_cp / 2), dim3(256), 0, 0, n_cp / 2, cin, cout); }, 5, 20,
+              &cp_ms))
+    return 1;
+  const double bv_gbs = 96.0 * n_bv / (bv_ms * 1e-3) / 1e9, cp_gbs = 16.0 * n_cp / (cp_ms * 1e-3) / 1e9;
+
+  std::printf("{\"mfma_i8_random_tops\": %.1f, \"valu_ring_tmacs\": %.3f, \"hbm_stream_10r2w_gbs\": %.1f, "
+              "\"hbm_copy_gbs\": %.1f}\n",
+              mfma_ops / (mfma_ms * 1e-3) / 1e12, valu_macs / (valu_ms * 1e-3) / 1e12, bv_gbs, cp_gbs);
+  for (auto b : bufs) CK(hipFree(b));
+  CK(hipFree(cin));
+  CK(hipFree(cout));
   CK(hipFree(rnd));
   CK(hipFree(iout));
   CK(hipFree(uout));
