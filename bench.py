@@ -141,7 +141,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = secondary(ctx, mpc, torch, workloads, X, Y, set(args.extra or EXTRAS))
+        extras = secondary(ctx, mpc, torch, workloads, X, Y, set(args.extra or EXTRAS), cpu=not args.no_cpu)
         if "ceiling_mfma_i8_random_TOPs" in extras and args.form == "limb8":
             # the dominant kernel against the sustained matrix-core rate on random data
             extras["gemm_frac_of_mfma_random_ceiling"] = round(
@@ -247,7 +247,7 @@ def _event_time(torch, stream, fn, reps):
     return s.elapsed_time(e) / reps
 
 
-def secondary(ctx, mpc, torch, workloads, X, Y, only):
+def secondary(ctx, mpc, torch, workloads, X, Y, only, cpu=True):
     ex = {}
     if "ceilings" in only:
         ex.update(ceilings())
@@ -271,7 +271,7 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only):
     if "grouped_mul" in only:
         ex.update(grouped_mul_bench(mpc, torch, workloads))
     if "conv" in only:
-        ex.update(conv_bench(mpc, torch, workloads))
+        ex.update(conv_bench(mpc, torch, workloads, cpu))
     return ex
 
 
@@ -491,9 +491,10 @@ def grouped_bench(mpc, torch, workloads):
     return out
 
 
-def conv_bench(mpc, torch, workloads):
+def conv_bench(mpc, torch, workloads, cpu=True):
     """The Wav2Letter-shaped conv stack (batch 8, 40x1600): 10 Beaver conv1d
-    layers with truncation and 9 Beaver squares, online phase only."""
+    layers with truncation and 9 Beaver squares, online phase only.  With
+    `cpu`, also the whole stack in the CPU oracle, checked against it."""
     data_seed, pseed, dseed = workloads.seeds(4)
     cfg = workloads.CONV
     layers = workloads.conv_shapes(cfg["batch"], cfg["length"])
@@ -520,16 +521,47 @@ def conv_bench(mpc, torch, workloads):
                 h = mpc.SharedPair(sq.s0.view(b, cout, lout), sq.s1.view(b, cout, lout))
         return h
 
+    first = None
     for form, reps in (("limb8", 5), ("plain", 1)):
-        forward(form)
+        h = forward(form)
         c.sync()
+        if first is None:  # the limb form's output, for the oracle leg
+            first = (h.s0.cpu().numpy().view(np.uint64), h.s1.cpu().numpy().view(np.uint64))
         ms = _event_time(torch, c.streams[0], lambda: forward(form), reps)
         out[f"conv_stack_{form}_ms"] = round(ms, 3)
         out[f"conv_stack_{form}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
         log(f"bench: conv stack {form}: {ms:.3f} ms")
     out["conv_stack_plaintext_macs"] = macs
     c.close()
+    if cpu:
+        # the same seeded real inputs, encoded by the oracle itself
+        Xf = workloads.uniform(data_seed, (cfg["batch"], cfg["channels"], cfg["length"]), cfg["lo"], cfg["hi"])
+        Wfs = [workloads.uniform(data_seed + 100 + i, (cout, cin, k), cfg["lo"], cfg["hi"])
+               for i, (b, cin, L, cout, k, s, lout) in enumerate(layers)]
+        out["conv_stack_cpu_oracle"] = conv_cpu_oracle(Xf, Wfs, layers, pseed, dseed, first, macs)
     return out
+
+
+def conv_cpu_oracle(Xf, Wfs, layers, pseed, dseed, want, macs):
+    """The whole conv stack (all batch elements) in the CPU oracle, timed and
+    checked bit for bit against the GPU's output."""
+    import oracle
+    t0 = time.perf_counter()
+    h = oracle.share(oracle.encode(Xf, FRAC), 0, pseed, 1)
+    for i, (b, cin, L, cout, k, s, lout) in enumerate(layers):
+        w = oracle.share(oracle.encode(Wfs[i], FRAC), 1, pseed, 20 + i)
+        h = oracle.beaver_conv1d(h, w, oracle.dealer_conv1d(dseed, 40 + i, b, cin, L, cout, k, s), s, FRAC)
+        if i < len(layers) - 1:
+            sq = oracle.beaver_square((h[0].ravel(), h[1].ravel()),
+                                      oracle.dealer_square(dseed, 60 + i, b * cout * lout), FRAC)
+            h = (sq[0].reshape(b, cout, lout), sq[1].reshape(b, cout, lout))
+    dt = time.perf_counter() - t0
+    ok = bool(np.array_equal(h[0], want[0]) and np.array_equal(h[1], want[1]))
+    log(f"bench: conv stack cpu oracle, whole stack: {dt:.2f} s, matches the GPU: {ok}")
+    return {"value": round(2.0 * macs / dt / 1e12, 6), "unit": "Tops/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"the whole stack at batch {layers[0][0]} (share, dealer, 10 Beaver conv1d "
+                                         f"with truncation, 9 Beaver squares) in the CPU oracle; {dt:.1f} s",
+            "sample_matches_gpu_bit_exact": ok}
 
 
 def mlp_latency(ctx, mpc, torch, workloads, form):
