@@ -144,7 +144,7 @@ mpc_status mpc_reserve(mpc_ctx *ctx, size_t bytes);
 mpc_status mpc_share(mpc_ctx *ctx, const uint64_t *x, size_t n, int src, uint64_t tag,
                      uint64_t *s0, uint64_t *s1);
 /* out = s0 + s1 mod 2^64 (read it as int64 for the signed value).  out may
- * alias s0 or s1. */
+ * be s0 or s1 itself (in place); any other overlap returns MPC_E_ALIAS. */
 mpc_status mpc_reveal(mpc_ctx *ctx, const uint64_t *s0, const uint64_t *s1, size_t n,
                       uint64_t *out);
 /* Local truncation, in place: each party replaces its share s by

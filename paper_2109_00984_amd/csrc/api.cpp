@@ -232,7 +232,20 @@ mpc_status end_call(mpc_ctx* c) { return mark_slot(c); }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 
+// Element counts above 2^46 (512 TiB of uint64) cannot be device buffers;
+// refusing them keeps every size computed from a shape far from overflow.
+constexpr i64 kMaxElems = (i64)1 << 46;
+
+bool count_ok(i64 a, i64 b) { return a >= 0 && b >= 0 && (a == 0 || b <= kMaxElems / a); }
+
+// M x K, K x N and M x N operands of a matrix product.
+mpc_status check_mnk(i64 M, i64 N, i64 K) {
+  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  return count_ok(M, K) && count_ok(K, N) && count_ok(M, N) ? MPC_OK : MPC_E_SHAPE;
+}
+
 mpc_status check_ptr(const void* p, size_t n) {
+  if (n > (size_t)kMaxElems) return MPC_E_SHAPE;
   if (n == 0) return MPC_OK;
   if (!p || !aligned8(p)) return MPC_E_INVAL;
   return MPC_OK;
@@ -812,7 +825,13 @@ mpc_status check_conv(const mpc_conv1d_shape* s) {
   if (!s) return MPC_E_INVAL;
   if (s->batch < 0 || s->cin < 0 || s->length < 0 || s->cout < 0 || s->ksize <= 0 || s->stride <= 0)
     return MPC_E_SHAPE;
-  return MPC_OK;
+  // activation, weight and output tensors, and the lowered product's k x n
+  const i64 lout = conv_lout(*s);
+  const bool ok = count_ok(s->batch, s->cin) && count_ok(s->batch * s->cin, s->length) &&
+                  count_ok(s->cout, s->cin) && count_ok(s->cout * s->cin, s->ksize) && count_ok(s->batch, lout) &&
+                  count_ok(s->cout, s->batch * lout) && count_ok(s->cin, s->ksize) &&
+                  count_ok(s->cin * s->ksize, s->batch * lout);
+  return ok ? MPC_OK : MPC_E_SHAPE;
 }
 
 }  // namespace
@@ -969,6 +988,8 @@ mpc_status mpc_reveal(mpc_ctx* c, const uint64_t* s0, const uint64_t* s1, size_t
   CHK(check_ptr(s0, n));
   CHK(check_ptr(s1, n));
   CHK(check_ptr(out, n));
+  // in place (out is s0 or s1) is element-wise safe; any other overlap is not
+  if ((out != s0 && overlap(out, n, s0, n)) || (out != s1 && overlap(out, n, s1, n))) return MPC_E_ALIAS;
   if (!n) return MPC_OK;
   CHK(set_device(c));
   CHK(hip_status(launch_reveal(c->s[0], s0, s1, n, out)));
@@ -1031,7 +1052,7 @@ mpc_status mpc_dealer_triples(mpc_ctx* c, mpc_triple_kind kind, uint64_t dseed, 
     M = dims[0];
     N = dims[1];
     K = dims[2];
-    if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+    CHK(check_mnk(M, N, K));
     na = (size_t)(M * K);
     nb = (size_t)(K * N);
     nc = (size_t)(M * N);
@@ -1183,7 +1204,7 @@ struct MatmulPlan {
 };
 
 mpc_status validate_matmul(const MatmulPlan& m) {
-  if (m.M < 0 || m.N < 0 || m.K < 0) return MPC_E_SHAPE;
+  CHK(check_mnk(m.M, m.N, m.K));
   const size_t na = (size_t)(m.M * m.K), nb = (size_t)(m.K * m.N), nc = (size_t)(m.M * m.N);
   const void* in[10] = {m.x0, m.x1, m.y0, m.y1, m.t.a0, m.t.a1, m.t.b0, m.t.b1, m.t.c0, m.t.c1};
   const size_t ns[10] = {na, na, nb, nb, na, na, nb, nb, nc, nc};
@@ -1427,7 +1448,7 @@ mpc_status mpc_ring_gemm(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint
                          const uint64_t* B, uint64_t* C, mpc_form form) {
   if (!c) return MPC_E_INVAL;
   CHK(check_form(form));
-  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  CHK(check_mnk(M, N, K));
   CHK(check_ptr(A, (size_t)(M * K)));
   CHK(check_ptr(B, (size_t)(K * N)));
   CHK(check_ptr(C, (size_t)(M * N)));
@@ -1581,7 +1602,7 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
   std::vector<std::array<i64, 3>> shapes;
   for (size_t i = 0; i < count; ++i) {
     const i64 M = dims[3 * i], N = dims[3 * i + 1], K = dims[3 * i + 2];
-    if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+    CHK(check_mnk(M, N, K));
     CHK(check_limb_k(MPC_FORM_LIMB8, K));
     if (M && N) shapes.push_back({M, N, K});
   }
@@ -2013,7 +2034,7 @@ mpc_status mpc_mp_dealer_triples(mpc_ctx* c, int P, mpc_triple_kind kind, uint64
   }
   if (kind != MPC_TRIPLE_MATMUL) return MPC_E_UNSUPPORTED;
   const i64 M = dims[0], N = dims[1], K = dims[2];
-  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  CHK(check_mnk(M, N, K));
   const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
   MpOut a, b, cc;
   CHK(mp_out(t->a, P, na, &a));
@@ -2100,7 +2121,7 @@ mpc_status mpc_mp_beaver_matmul(mpc_ctx* c, int P, int64_t M, int64_t N, int64_t
   CHK(check_parties(P));
   CHK(check_form(form));
   if (form == MPC_FORM_FP64LIMB) return MPC_E_UNSUPPORTED;
-  if (M < 0 || N < 0 || K < 0) return MPC_E_SHAPE;
+  CHK(check_mnk(M, N, K));
   const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
   MpIn xi, yi, ai, bi, ci;
   CHK(mp_in(x, P, na, &xi));

@@ -1,5 +1,7 @@
 """GPU parity: every library call against the CPU oracle on identical seeded
 inputs, bit for bit (ring results are exact, so the tolerance is zero)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -128,6 +130,41 @@ def test_argument_errors(m, ctx):
     with pytest.raises(m.MPCError):
         ctx.beaver_mul(x, x, t, 16, out=m.SharedPair(x.s0, t.c1.clone()))
     ctx.sync()
+
+
+def test_oversized_shapes_refused(m, ctx):
+    # element counts that no device holds (or whose products wrap 64 bits)
+    # are refused before any work is issued, through the raw C ABI
+    say("oversized shapes")
+    L, p = m._lib, m._ptr
+    buf = ctx.empty((64,))
+    q = p(buf)
+    big = 1 << 40
+    assert L.mpc_ring_gemm(ctx._h, big, big, big, q, q, q, 0) == -2
+    assert L.mpc_ring_gemm(ctx._h, 1 << 62, 4, 4, q, q, q, 1) == -2
+    assert L.mpc_share(ctx._h, q, 1 << 50, 0, 1, q, q) == -2
+    assert L.mpc_reveal(ctx._h, q, q, 1 << 62, q) == -2
+    t = ctx.dealer(m.TRIPLE_MUL, 1, 1, (64,))
+    st = t.struct()
+    assert L.mpc_beaver_matmul(ctx._h, big, big, big, q, q, q, q, ctypes.byref(st), 0, 0, q, q) == -2
+    dims = (m.I64 * 6)(big, big, big, 0, 0, 0)
+    assert L.mpc_dealer_triples(ctx._h, m.TRIPLE_MATMUL, 1, 1, dims, ctypes.byref(st)) == -2
+    shape = m.Conv1dShape(1 << 20, 1 << 20, 1 << 20, 4, 3, 1)
+    assert L.mpc_beaver_conv1d(ctx._h, ctypes.byref(shape), q, q, q, q, ctypes.byref(st), 0, 0, q, q) == -2
+    ctx.sync()
+
+
+def test_reveal_in_place_and_overlap(m, ctx):
+    say("reveal in place / overlapping output")
+    x = rnd(71, 100)
+    buf = ctx.empty((202,))
+    s0, s1 = buf[0:100], buf[101:201]
+    s = ctx.share(dev(x), 1, 72, out=m.SharedPair(s0, s1))
+    ctx.reveal(s, out=s1)  # in place
+    assert np.array_equal(host(ctx, s1), x)
+    with pytest.raises(m.MPCError) as e:  # one element past s0: overlaps it, not in place
+        ctx.reveal(m.SharedPair(s0, s1), out=buf[1:101])
+    assert e.value.status == -3
 
 
 # ------------------------------------------------------------------ dealer
