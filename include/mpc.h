@@ -103,9 +103,11 @@ typedef struct {
 
 typedef struct mpc_ctx mpc_ctx;
 
-/* Counters kept by a context: opens (one per Beaver product, the only
- * communication round of the protocol), bytes a two-GPU deployment would send
- * per party for those opens, kernel launches and GEMM problems issued. */
+/* Counters kept by a context: opens (communication rounds: one per Beaver
+ * product, AND gate, B2A conversion and reveal, seven per A2B conversion, one
+ * per truncation among more than two parties, none for a two-party
+ * truncation), bytes a two-GPU deployment would send per party in those
+ * rounds, truncations, kernel launches and GEMM problems issued. */
 typedef struct {
   uint64_t opens, open_bytes_per_party, truncations, launches, gemm_problems;
 } mpc_stats;

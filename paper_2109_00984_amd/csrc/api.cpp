@@ -994,6 +994,8 @@ mpc_status mpc_reveal(mpc_ctx* c, const uint64_t* s0, const uint64_t* s1, size_t
   CHK(set_device(c));
   CHK(hip_status(launch_reveal(c->s[0], s0, s1, n, out)));
   c->stats.launches++;
+  c->stats.opens++;  // each party sends its share: one round
+  c->stats.open_bytes_per_party += 8 * (uint64_t)n;
   return end_call(c);
 }
 
