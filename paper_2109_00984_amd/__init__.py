@@ -287,12 +287,35 @@ class Context:
         self.close()
 
     # -------------------------------------------------------------- basics
-    def _check_t(self, *ts):
+    def _check_t(self, *ts, n=None, at_least=None):
+        """Every tensor: contiguous int64 on this context's device; with n,
+        exactly n elements; with at_least, at least that many.  The library
+        takes bare pointers, so this is what keeps its kernels inside them."""
         for t in ts:
             if t is None:
                 continue
             if t.device != self.device or t.dtype != torch.int64 or not t.is_contiguous():
                 raise ValueError("expected contiguous int64 tensors on " + str(self.device))
+            if n is not None and t.numel() != n:
+                raise ValueError(f"expected {n} elements, got {t.numel()}")
+            if at_least is not None and t.numel() < at_least:
+                raise ValueError(f"expected at least {at_least} elements, got {t.numel()}")
+
+    @staticmethod
+    def _check_parties(P, *groups):
+        for g in groups:
+            if g is not None and len(g) != P:
+                raise ValueError(f"expected the shares of {P} parties, got {len(g)}")
+
+    def _check_triple(self, t, na, nb, nc):
+        """A two-party triple holding at least na, nb, nc elements in a, b, c
+        (nc None: a Beaver pair, whose c is not used)."""
+        self._check_t(t.a0, t.a1, at_least=na)
+        self._check_t(t.b0, t.b1, at_least=nb)
+        if nc is not None:
+            if t.c0 is None or t.c1 is None:
+                raise ValueError("this product needs the triple's c shares")
+            self._check_t(t.c0, t.c1, at_least=nc)
 
     def empty(self, shape):
         return torch.empty(shape, dtype=torch.int64, device=self.device)
@@ -323,19 +346,20 @@ class Context:
     def share(self, x, src, tag, out=None):
         self._check_t(x)
         s0, s1 = (self.empty(x.shape), self.empty(x.shape)) if out is None else (out.s0, out.s1)
+        self._check_t(s0, s1, n=x.numel())
         _check(_lib.mpc_share(self._h, _ptr(x), x.numel(), src, tag, _ptr(s0), _ptr(s1)),
                "mpc_share")
         return SharedPair(s0, s1)
 
     def reveal(self, x, out=None):
-        self._check_t(x.s0, x.s1)
+        self._check_t(x.s0, x.s1, out, n=x.s0.numel())
         out = self.empty(x.shape) if out is None else out
         _check(_lib.mpc_reveal(self._h, _ptr(x.s0), _ptr(x.s1), x.s0.numel(), _ptr(out)),
                "mpc_reveal")
         return out
 
     def truncate(self, x, bits):
-        self._check_t(x.s0, x.s1)
+        self._check_t(x.s0, x.s1, n=x.s0.numel())
         _check(_lib.mpc_truncate(self._h, _ptr(x.s0), _ptr(x.s1), x.s0.numel(), bits),
                "mpc_truncate")
         return x
@@ -362,6 +386,16 @@ class Context:
         return t
 
     def dealer_into(self, kind, dseed, tag, dims, t):
+        if kind in (TRIPLE_MUL, TRIPLE_SQUARE):
+            (n,) = dims
+            self._check_triple(t, n, n, None if kind == TRIPLE_SQUARE else n)
+        elif kind == TRIPLE_MATMUL:
+            M, N, K = dims
+            self._check_triple(t, M * K, K * N, M * N)
+        elif kind == TRIPLE_CONV1D:
+            B, cin, L, cout, k, s = dims
+            lout = (L - k) // s + 1 if L >= k and s > 0 else 0
+            self._check_triple(t, B * cin * L, cout * cin * k, B * cout * lout)
         d = (I64 * 6)(*list(dims) + [0] * (6 - len(dims)))
         st = t.struct()
         _check(_lib.mpc_dealer_triples(self._h, kind, dseed, tag, d, ctypes.byref(st)),
@@ -374,13 +408,16 @@ class Context:
     def bin_share(self, x, src, tag, out=None):
         self._check_t(x)
         z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        self._check_t(z.s0, z.s1, n=x.numel())
         _check(_lib.mpc_bin_share(self._h, _ptr(x), x.numel(), src, tag, _ptr(z.s0), _ptr(z.s1)),
                "mpc_bin_share")
         return z
 
     def bin_reveal(self, s, out=None):
+        n = s.s0.numel()
+        self._check_t(s.s0, s.s1, out, n=n)
         out = out if out is not None else self.empty(s.shape)
-        _check(_lib.mpc_bin_reveal(self._h, _ptr(s.s0), _ptr(s.s1), out.numel(), _ptr(out)),
+        _check(_lib.mpc_bin_reveal(self._h, _ptr(s.s0), _ptr(s.s1), n, _ptr(out)),
                "mpc_bin_reveal")
         return out
 
@@ -393,7 +430,10 @@ class Context:
         return t
 
     def bin_and(self, x, y, t, out=None):
+        n = x.s0.numel()
         z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        self._check_t(x.s0, x.s1, y.s0, y.s1, z.s0, z.s1, n=n)
+        self._check_triple(t, n, n, n)
         st = t.struct()
         _check(_lib.mpc_bin_and(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), _ptr(y.s0), _ptr(y.s1),
                                 ctypes.byref(st), _ptr(z.s0), _ptr(z.s1)), "mpc_bin_and")
@@ -401,7 +441,10 @@ class Context:
 
     def a2b(self, x, tag, t, out=None):
         """Arithmetic to binary sharing; t holds 12 * n AND triples."""
+        n = x.s0.numel()
         z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        self._check_t(x.s0, x.s1, z.s0, z.s1, n=n)
+        self._check_triple(t, self.A2B_TRIPLES * n, self.A2B_TRIPLES * n, self.A2B_TRIPLES * n)
         st = t.struct()
         _check(_lib.mpc_a2b(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), tag, ctypes.byref(st),
                             _ptr(z.s0), _ptr(z.s1)), "mpc_a2b")
@@ -416,7 +459,10 @@ class Context:
         return rb, ra
 
     def b2a_bit(self, b, bit, rb, ra, out=None):
+        n = b.s0.numel()
         z = out if out is not None else SharedPair(self.empty(b.shape), self.empty(b.shape))
+        self._check_t(b.s0, b.s1, z.s0, z.s1, n=n)
+        self._check_t(rb.s0, rb.s1, ra.s0, ra.s1, at_least=n)
         _check(_lib.mpc_b2a_bit(self._h, b.s0.numel(), bit, _ptr(b.s0), _ptr(b.s1), _ptr(rb.s0),
                                 _ptr(rb.s1), _ptr(ra.s0), _ptr(ra.s1), _ptr(z.s0), _ptr(z.s1)),
                "mpc_b2a_bit")
@@ -424,7 +470,12 @@ class Context:
 
     def relu(self, x, tag, t, rb, ra, m, out=None):
         """ReLU of a fixed-point sharing: t 12*n AND triples, (rb, ra) B2A bits, m MUL triple."""
+        n = x.s0.numel()
         z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        self._check_t(x.s0, x.s1, z.s0, z.s1, n=n)
+        self._check_triple(t, self.A2B_TRIPLES * n, self.A2B_TRIPLES * n, self.A2B_TRIPLES * n)
+        self._check_t(rb.s0, rb.s1, ra.s0, ra.s1, at_least=n)
+        self._check_triple(m, n, n, n)
         st, sm = t.struct(), m.struct()
         _check(_lib.mpc_relu(self._h, x.s0.numel(), _ptr(x.s0), _ptr(x.s1), tag, ctypes.byref(st),
                              _ptr(rb.s0), _ptr(rb.s1), _ptr(ra.s0), _ptr(ra.s1), ctypes.byref(sm),
@@ -436,15 +487,17 @@ class Context:
         """Shares x among P parties (pseudorandom zero-share; party src adds x)."""
         self._check_t(x)
         s = out if out is not None else Shared([self.empty(x.shape) for _ in range(P)])
-        self._check_t(*s.shares)
+        self._check_parties(P, s.shares)
+        self._check_t(*s.shares, n=x.numel())
         _check(_lib.mpc_mp_share(self._h, P, _ptr(x), x.numel(), src, tag, _pptr(s.shares)),
                "mpc_mp_share")
         return s
 
     def mp_reveal(self, s, out=None):
-        self._check_t(*s.shares)
+        n = s.shares[0].numel()
+        self._check_t(*s.shares, out, n=n)
         out = out if out is not None else self.empty(s.shape)
-        _check(_lib.mpc_mp_reveal(self._h, s.P, _pptr(s.shares), out.numel(), _ptr(out)),
+        _check(_lib.mpc_mp_reveal(self._h, s.P, _pptr(s.shares), n, _ptr(out)),
                "mpc_mp_reveal")
         return out
 
@@ -476,8 +529,16 @@ class Context:
     def mp_beaver_mul(self, x, y, t, out=None):
         """P-party Beaver product; y=None selects the square with the pair t."""
         P = x.P
-        self._check_t(*x.shares, *(y.shares if y is not None else []), *t.a, *t.b, *(t.c or []))
+        n = x.shares[0].numel()
         z = out if out is not None else Shared([self.empty(x.shape) for _ in range(P)])
+        self._check_parties(P, y.shares if y is not None else None, t.a, t.b, t.c if y is not None else None,
+                            z.shares)
+        self._check_t(*x.shares, *(y.shares if y is not None else []), *z.shares, n=n)
+        self._check_t(*t.a, *t.b, at_least=n)
+        if y is not None:
+            if t.c is None:
+                raise ValueError("a product needs the triple's c shares")
+            self._check_t(*t.c, at_least=n)
         st = t.struct()
         _check(_lib.mpc_mp_beaver_mul(self._h, P, x.shares[0].numel(), _pptr(x.shares),
                                       _pptr(y.shares) if y is not None else None, ctypes.byref(st),
@@ -487,9 +548,17 @@ class Context:
     def mp_beaver_matmul(self, x, y, t, form="auto", out=None):
         P = x.P
         M, K = x.shape
-        N = y.shape[1]
-        self._check_t(*x.shares, *y.shares, *t.a, *t.b, *t.c)
+        K2, N = y.shape
+        if K != K2:
+            raise ValueError("inner dimensions differ")
         z = out if out is not None else Shared([self.empty((M, N)) for _ in range(P)])
+        self._check_parties(P, y.shares, t.a, t.b, t.c, z.shares)
+        self._check_t(*x.shares, n=M * K)
+        self._check_t(*y.shares, n=K * N)
+        self._check_t(*z.shares, n=M * N)
+        self._check_t(*t.a, at_least=M * K)
+        self._check_t(*t.b, at_least=K * N)
+        self._check_t(*t.c, at_least=M * N)
         st = t.struct()
         _check(_lib.mpc_mp_beaver_matmul(self._h, P, M, N, K, _pptr(x.shares), _pptr(y.shares),
                                          ctypes.byref(st), FORMS[form], _pptr(z.shares)),
@@ -498,7 +567,10 @@ class Context:
 
     def mp_truncate(self, x, bits, r, theta_r):
         """In-place truncation by 2^bits (Algorithm 1, eta = 0)."""
-        self._check_t(*x.shares, *r.shares, *theta_r.shares)
+        n = x.shares[0].numel()
+        self._check_parties(x.P, r.shares, theta_r.shares)
+        self._check_t(*x.shares, n=n)
+        self._check_t(*r.shares, *theta_r.shares, at_least=n)
         _check(_lib.mpc_mp_truncate(self._h, x.P, x.shares[0].numel(), bits, _pptr(x.shares),
                                     _pptr(r.shares), _pptr(theta_r.shares)), "mpc_mp_truncate")
         return x
@@ -506,12 +578,10 @@ class Context:
     # -------------------------------------------------------------- Beaver
     def beaver_mul(self, x, y, t, trunc_bits=0, out=None):
         """y=None selects the square with a Beaver pair (t.a, t.b = a^2)."""
-        ts = [x.s0, x.s1, t.a0, t.a1, t.b0, t.b1]
-        if y is not None:
-            ts += [y.s0, y.s1, t.c0, t.c1]
-        self._check_t(*ts)
         n = x.s0.numel()
         z = out if out is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+        self._check_t(x.s0, x.s1, z.s0, z.s1, *((y.s0, y.s1) if y is not None else ()), n=n)
+        self._check_triple(t, n, n, n if y is not None else None)
         st = t.struct()
         _check(_lib.mpc_beaver_mul(self._h, n, _ptr(x.s0), _ptr(x.s1),
                                    _ptr(y.s0 if y is not None else None),
@@ -524,8 +594,11 @@ class Context:
         K2, N = y.s0.shape
         if K != K2:
             raise ValueError("inner dimensions differ")
-        self._check_t(x.s0, x.s1, y.s0, y.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
         z = out if out is not None else SharedPair(self.empty((M, N)), self.empty((M, N)))
+        self._check_t(x.s0, x.s1, n=M * K)
+        self._check_t(y.s0, y.s1, n=K * N)
+        self._check_t(z.s0, z.s1, n=M * N)
+        self._check_triple(t, M * K, K * N, M * N)
         st = t.struct()
         _check(_lib.mpc_beaver_matmul(self._h, M, N, K, _ptr(x.s0), _ptr(x.s1), _ptr(y.s0),
                                       _ptr(y.s1), ctypes.byref(st), trunc_bits, FORMS[form],
@@ -537,11 +610,14 @@ class Context:
         cout, cin2, k = w.s0.shape
         if cin != cin2:
             raise ValueError("channel counts differ")
-        self._check_t(x.s0, x.s1, w.s0, w.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
-        lout = (L - k) // stride + 1 if L >= k else 0
+        lout = (L - k) // stride + 1 if L >= k and stride > 0 else 0
         shape = Conv1dShape(B, cin, L, cout, k, stride)
         z = out if out is not None else SharedPair(self.empty((B, cout, lout)),
                                                    self.empty((B, cout, lout)))
+        self._check_t(x.s0, x.s1, n=B * cin * L)
+        self._check_t(w.s0, w.s1, n=cout * cin * k)
+        self._check_t(z.s0, z.s1, n=B * cout * lout)
+        self._check_triple(t, B * cin * L, cout * cin * k, B * cout * lout)
         st = t.struct()
         _check(_lib.mpc_beaver_conv1d(self._h, ctypes.byref(shape), _ptr(x.s0), _ptr(x.s1),
                                       _ptr(w.s0), _ptr(w.s1), ctypes.byref(st), trunc_bits,
@@ -553,8 +629,10 @@ class Context:
         K2, N = B.shape
         if K != K2:
             raise ValueError("inner dimensions differ")
-        self._check_t(A, B)
         C = out if out is not None else self.empty((M, N))
+        self._check_t(A, n=M * K)
+        self._check_t(B, n=K * N)
+        self._check_t(C, n=M * N)
         _check(_lib.mpc_ring_gemm(self._h, M, N, K, _ptr(A), _ptr(B), _ptr(C), FORMS[form]),
                "mpc_ring_gemm")
         return C
@@ -565,10 +643,15 @@ class Context:
         results = []
         for i, (x, y, t) in enumerate(problems):
             M, K = x.s0.shape
-            N = y.s0.shape[1]
-            self._check_t(x.s0, x.s1, y.s0, y.s1, t.a0, t.a1, t.b0, t.b1, t.c0, t.c1)
+            K2, N = y.s0.shape
+            if K != K2:
+                raise ValueError(f"problem {i}: inner dimensions differ")
             z = outs[i] if outs is not None else SharedPair(self.empty((M, N)),
                                                             self.empty((M, N)))
+            self._check_t(x.s0, x.s1, n=M * K)
+            self._check_t(y.s0, y.s1, n=K * N)
+            self._check_t(z.s0, z.s1, n=M * N)
+            self._check_triple(t, M * K, K * N, M * N)
             results.append(z)
             descs[i] = MatmulDesc(M, N, K, x.s0.data_ptr(), x.s1.data_ptr(), y.s0.data_ptr(),
                                   y.s1.data_ptr(), t.struct(), z.s0.data_ptr(), z.s1.data_ptr())
@@ -582,11 +665,10 @@ class Context:
         descs = (MulDesc * max(1, len(problems)))()
         results = []
         for i, (x, y, t) in enumerate(problems):
-            ts = [x.s0, x.s1, t.a0, t.a1, t.b0, t.b1]
-            if y is not None:
-                ts += [y.s0, y.s1, t.c0, t.c1]
-            self._check_t(*ts)
+            n = x.s0.numel()
             z = outs[i] if outs is not None else SharedPair(self.empty(x.shape), self.empty(x.shape))
+            self._check_t(x.s0, x.s1, z.s0, z.s1, *((y.s0, y.s1) if y is not None else ()), n=n)
+            self._check_triple(t, n, n, n if y is not None else None)
             results.append(z)
             descs[i] = MulDesc(x.s0.numel(), _ptr(x.s0), _ptr(x.s1), _ptr(y.s0 if y is not None else None),
                                _ptr(y.s1 if y is not None else None), t.struct(), _ptr(z.s0), _ptr(z.s1))

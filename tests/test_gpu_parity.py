@@ -154,6 +154,40 @@ def test_oversized_shapes_refused(m, ctx):
     ctx.sync()
 
 
+def test_binding_refuses_bad_tensors(m, ctx):
+    # the library takes bare pointers: the binding checks device, dtype,
+    # layout and element counts before any call
+    say("binding argument checks")
+    x = ctx.share(dev(rnd(81, 32)), 0, 81)
+    t = ctx.dealer(m.TRIPLE_MUL, 1, 82, (32,))
+    short = ctx.dealer(m.TRIPLE_MUL, 1, 83, (31,))
+    with pytest.raises(ValueError):  # output on the host
+        ctx.reveal(x, out=torch.empty(32, dtype=torch.int64))
+    with pytest.raises(ValueError):  # output too small
+        ctx.reveal(x, out=ctx.empty((31,)))
+    with pytest.raises(ValueError):  # output of another dtype
+        ctx.share(dev(rnd(84, 32)), 0, 84, out=m.SharedPair(ctx.empty((32,)), torch.empty(32, device="cuda")))
+    with pytest.raises(ValueError):  # triple shorter than the operands
+        ctx.beaver_mul(x, x, short, 16)
+    with pytest.raises(ValueError):  # shares of different lengths
+        ctx.beaver_mul(x, m.SharedPair(x.s0, ctx.empty((33,))), t, 16)
+    with pytest.raises(ValueError):  # product without the triple's c
+        ctx.beaver_mul(x, x, m.TripleShares(t.a0, t.a1, t.b0, t.b1), 16)
+    with pytest.raises(ValueError):  # non-contiguous operand
+        ctx.ring_gemm(ctx.empty((8, 16)).t(), ctx.empty((8, 4)))
+    with pytest.raises(ValueError):  # matmul triple of the wrong shape
+        ctx.beaver_matmul(m.SharedPair(ctx.empty((4, 8)), ctx.empty((4, 8))),
+                          m.SharedPair(ctx.empty((8, 4)), ctx.empty((8, 4))),
+                          ctx.dealer(m.TRIPLE_MATMUL, 1, 85, (4, 4, 4)), 16)
+    with pytest.raises(ValueError):  # dealer into buffers too small for the shape
+        ctx.dealer_into(m.TRIPLE_MATMUL, 1, 86, (4, 4, 8), ctx.dealer(m.TRIPLE_MATMUL, 1, 87, (4, 4, 4)))
+    s3 = ctx.mp_share(dev(rnd(88, 32)), 3, 0, 88)
+    t2 = ctx.mp_dealer(2, m.TRIPLE_MUL, 1, 89, (32,))
+    with pytest.raises(ValueError):  # a 2-party triple for 3-party shares
+        ctx.mp_beaver_mul(s3, s3, t2)
+    ctx.sync()
+
+
 def test_reveal_in_place_and_overlap(m, ctx):
     say("reveal in place / overlapping output")
     x = rnd(71, 100)
