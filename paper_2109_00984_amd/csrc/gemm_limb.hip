@@ -16,10 +16,13 @@
 // tile, each plane stored as 64 lanes' 16-byte runs in lane order), with
 // zeros past K, so no conversion work is left in the GEMM's inner loop.
 //
-// GEMM.  A 256-thread workgroup (four waves, one per SIMD) owns a
-// (64*SA) x (64*SB) output tile; each wave a (32*SA) x (32*SB) sub-tile held
-// as 16x16 blocks with 8 diagonal int32 accumulators each (256 accumulation
-// registers for the 128x64 and 64x128 tiles, 128 for 64x64).  Two forms:
+// GEMM.  A workgroup of four waves (one per SIMD; eight for two of the LDS
+// shapes) owns one output tile of 64x64, 64x128 or 128x64; each wave a
+// sub-tile held as 16x16 blocks with 8 diagonal int32 accumulators each (256
+// accumulation registers for a 32x64 or 64x32 sub-tile, 128 for 32x32).
+// Operand blocks are read through buffer descriptors, whose 32-bit range
+// bounds one k segment to 65534 k-blocks (the host refuses longer ones).
+// Two forms:
 // k_limb_gemm, where each wave streams its own fragments from global memory
 // through buffer loads, one k step of loads in flight behind the MFMAs of the
 // current step, with no LDS and no barrier; and k_limb_gemm_lds, where the
