@@ -264,7 +264,8 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
  * outputs, every wave fetching its operand fragments from global memory;
  * 3, 4, 5: the same shapes with the operand that has more fragments per wave
  * copied once per workgroup into LDS and read from there; 6: 64x128 and
- * 7: 128x64 in that LDS form with eight waves, two per SIMD), the number of tile
+ * 7: 128x64 in that LDS form with eight waves, two per SIMD, each wave 16x64
+ * or 64x16 outputs; 8: 64x128 with eight waves of 32x32 outputs), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
  * runs together share operand blocks in its L2) instead of one by one. */

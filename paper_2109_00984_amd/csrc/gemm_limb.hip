@@ -924,7 +924,10 @@ int limb_variant_sa(int variant) {
   return variant == kLimb128x64 || variant == kLimbLds128x64 || variant == kLimbLds128x64w8 ? 2 : 1;
 }
 int limb_variant_sb(int variant) {
-  return variant == kLimb64x128 || variant == kLimbLds64x128 || variant == kLimbLds64x128w8 ? 2 : 1;
+  return variant == kLimb64x128 || variant == kLimbLds64x128 || variant == kLimbLds64x128w8 ||
+                 variant == kLimbLds64x128w8s
+             ? 2
+             : 1;
 }
 
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
@@ -969,6 +972,7 @@ hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map
     MPC_LDS_CASE(kLimbLds64x64, 2, 2, 2, 2)
     MPC_LDS_CASE(kLimbLds64x128w8, 1, 4, 4, 2)
     MPC_LDS_CASE(kLimbLds128x64w8, 4, 1, 2, 4)
+    MPC_LDS_CASE(kLimbLds64x128w8s, 2, 2, 2, 4)
     default: return hipErrorInvalidValue;
   }
 #undef MPC_LDS_CASE

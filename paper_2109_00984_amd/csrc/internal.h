@@ -250,14 +250,15 @@ hipError_t launch_splitk_reduce_grouped(hipStream_t s, const ReduceJob* jobs, co
 hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
                        i64 total_blocks, int kind, int mode);
 // Tile shapes of the limb GEMM (workgroup output tile) and the tile order.
-// Variants 3..7 stage the outer operand through LDS (k_limb_gemm_lds); 6 and
-// 7 run eight waves per workgroup (two per SIMD).
+// Variants 3..8 stage the outer operand through LDS (k_limb_gemm_lds); 6, 7
+// and 8 run eight waves per workgroup (two per SIMD): 6 and 7 with 16x64 and
+// 64x16 wave sub-tiles, 8 with 32x32 ones, as in the four-wave 64x64 tile.
 enum LimbVariant : int {
   kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2,
   kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5,
-  kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7
+  kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7, kLimbLds64x128w8s = 8
 };
-constexpr int kLimbVariants = 8;
+constexpr int kLimbVariants = 9;
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group

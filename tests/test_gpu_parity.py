@@ -421,7 +421,7 @@ def test_beaver_mul_unaligned_views(m, ctx, n):
     assert_pair(ctx, sq, wsq, "beaver square on views")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("group_m,remap", [(1, False), (8, True)])
 def test_limb_tile_variants(m, variant, group_m, remap):
     # every tile shape and schedule of the limb GEMM gives the plain result
@@ -544,5 +544,5 @@ def test_default_tile_config_roundtrip(m):
     c.set_default_tile_config(1, 4, False)
     assert c.default_tile_config() == {"variant": "64x128", "variant_id": 1, "group_m": 4, "xcd_remap": False}
     with pytest.raises(m.MPCError):
-        c.set_default_tile_config(8, 8, True)
+        c.set_default_tile_config(9, 8, True)
     c.close()
