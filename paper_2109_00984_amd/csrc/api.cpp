@@ -1337,6 +1337,14 @@ mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int tru
       shapes.push_back({m.M, m.N, m.K});
     }
     CHK(issue_limb(c, jobs, reqs, sched_for(c, shapes)));
+  } else if (plans.size() == 1 && plans[0].M * plans[0].N <= kSmallMatmulMacs && plans[0].K <= kSmallMatmulMacs &&
+             plans[0].M * plans[0].N * plans[0].K <= kSmallMatmulMacs) {
+    // a small product: open and finish in one launch, no workspace
+    const MatmulPlan& m = plans[0];
+    const SmallMatmul s{m.M, m.N, m.K, m.x0, m.x1, m.y0, m.y1, m.t.a0, m.t.a1, m.t.b0, m.t.b1,
+                        m.t.c0, m.t.c1, m.z0, m.z1, trunc};
+    CHK(hip_status(launch_beaver_matmul_small(c->s[0], s)));
+    c->stats.launches++;
   } else {
     size_t need = kAlign;
     for (const MatmulPlan& m : plans) need += matmul_ws(m, form);

@@ -209,7 +209,66 @@ hipError_t launch_splitk_reduce_grouped(hipStream_t s, const ReduceJob* jobs, co
   return hipGetLastError();
 }
 
+// Whole Beaver matmul of a small product in one launch.  A workgroup owns a
+// 4x4 block of outputs of both parties' shares; its 256 threads are those 16
+// outputs times 16 lanes of k (k = lane, lane + 16, ...).  Each thread forms
+// the opened eps = x - a and delta = y - b of the elements it reads from the
+// shares themselves (an open pass and its workspace would cost more than the
+// product at this size), accumulates
+//   z_0 = eps b_0 + (a_0 + eps) delta,  z_1 = eps b_1 + a_1 delta
+// over its k, and the 16 partial sums of an output are added through LDS
+// before c_p and the truncation.  Ring sums do not depend on their order.
+constexpr int kSmallSide = 4, kSmallOut = kSmallSide * kSmallSide, kSmallKl = kThreads / kSmallOut;
+
+__global__ void __launch_bounds__(kThreads) k_beaver_matmul_small(SmallMatmul s) {
+  __shared__ u64 part[2][kSmallKl][kSmallOut];
+  const int o = threadIdx.x % kSmallOut, kl = threadIdx.x / kSmallOut;
+  const i64 ntn = (s.N + kSmallSide - 1) / kSmallSide;
+  const i64 m = (blockIdx.x / ntn) * kSmallSide + o / kSmallSide;
+  const i64 n = (blockIdx.x % ntn) * kSmallSide + o % kSmallSide;
+  const bool ok = m < s.M && n < s.N;
+  u64 z0 = 0, z1 = 0;
+  if (ok) {
+#pragma unroll 8
+    for (i64 k = kl; k < s.K; k += kSmallKl) {
+      const i64 ia = m * s.K + k, ib = k * s.N + n;
+      const u64 a0 = s.a0[ia], a1 = s.a1[ia], b0 = s.b0[ib], b1 = s.b1[ib];
+      const u64 eps = (s.x0[ia] - a0) + (s.x1[ia] - a1);
+      const u64 del = (s.y0[ib] - b0) + (s.y1[ib] - b1);
+      z0 += eps * b0 + (a0 + eps) * del;
+      z1 += eps * b1 + a1 * del;
+    }
+  }
+  part[0][kl][o] = z0;
+  part[1][kl][o] = z1;
+  __syncthreads();
+  if (kl == 0 && ok) {
+    u64 v0 = 0, v1 = 0;
+#pragma unroll
+    for (int q = 0; q < kSmallKl; ++q) {
+      v0 += part[0][q][o];
+      v1 += part[1][q][o];
+    }
+    const i64 off = m * s.N + n;
+    v0 += s.c0[off];
+    v1 += s.c1[off];
+    if (s.trunc) {
+      v0 = (u64)((i64)v0 >> s.trunc);
+      v1 = (u64)((i64)v1 >> s.trunc);
+    }
+    s.z0[off] = v0;
+    s.z1[off] = v1;
+  }
+}
+
 int plain_tiles(i64 M, i64 N) { return (int)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)); }
+
+hipError_t launch_beaver_matmul_small(hipStream_t s, const SmallMatmul& m) {
+  const i64 tiles = ((m.M + kSmallSide - 1) / kSmallSide) * ((m.N + kSmallSide - 1) / kSmallSide);
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_beaver_matmul_small, dim3((unsigned)tiles), dim3(kThreads), 0, s, m);
+  return hipGetLastError();
+}
 
 hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
                              int total_tiles) {

@@ -225,6 +225,17 @@ hipError_t launch_add(hipStream_t s, const u64* x, const u64* y, size_t n, u64* 
 
 // Plain ring GEMM (gemm_plain.hip): one launch over all problems of `probs`
 // (a device array), tiles listed by `map`.
+// A whole two-party Beaver matmul of a small product (plain arithmetic) in
+// one launch: operands, triple shares and outputs as in mpc_beaver_matmul.
+struct SmallMatmul {
+  i64 M, N, K;
+  const u64 *x0, *x1, *y0, *y1, *a0, *a1, *b0, *b1, *c0, *c1;
+  u64 *z0, *z1;
+  int trunc;
+};
+// Products of at most this many ring multiply-accumulates per party take it.
+constexpr i64 kSmallMatmulMacs = (i64)1 << 18;
+hipError_t launch_beaver_matmul_small(hipStream_t s, const SmallMatmul& m);
 hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
                              int total_tiles);
 int plain_tiles(i64 M, i64 N);
