@@ -1337,7 +1337,7 @@ mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int tru
       shapes.push_back({m.M, m.N, m.K});
     }
     CHK(issue_limb(c, jobs, reqs, sched_for(c, shapes)));
-  } else if (plans.size() == 1 && plans[0].M * plans[0].N <= kSmallMatmulMacs && plans[0].K <= kSmallMatmulMacs &&
+  } else if (plans.size() == 1 && plans[0].K <= kSmallMatmulK && plans[0].M * plans[0].N <= kSmallMatmulMacs &&
              plans[0].M * plans[0].N * plans[0].K <= kSmallMatmulMacs) {
     // a small product: open and finish in one launch, no workspace
     const MatmulPlan& m = plans[0];

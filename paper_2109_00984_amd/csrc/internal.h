@@ -233,8 +233,10 @@ struct SmallMatmul {
   u64 *z0, *z1;
   int trunc;
 };
-// Products of at most this many ring multiply-accumulates per party take it.
-constexpr i64 kSmallMatmulMacs = (i64)1 << 18;
+// Products of at most kSmallMatmulMacs ring multiply-accumulates per party
+// with k at most kSmallMatmulK (each thread then runs at most 64 steps of k)
+// take it.
+constexpr i64 kSmallMatmulMacs = (i64)1 << 18, kSmallMatmulK = 1024;
 hipError_t launch_beaver_matmul_small(hipStream_t s, const SmallMatmul& m);
 hipError_t launch_plain_gemm(hipStream_t s, const PlainProblem* probs, TileMap map,
                              int total_tiles);
