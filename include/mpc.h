@@ -28,6 +28,9 @@
  *     reported synchronously; faults in kernels are reported by mpc_sync().
  *   - No call throws, aborts or prints.  Outputs must not alias inputs unless a
  *     call says so (MPC_E_ALIAS).
+ *   - A context is used by one host thread at a time (its workspace, upload
+ *     buffers and counters are not locked); different contexts may be used
+ *     from different threads at once.
  *   - Sizes are element counts.  n = 0 (or an empty matrix) is valid and does
  *     nothing.
  *   - Randomness: G(seed, tag, slot, i) is a counter-based SplitMix64 value

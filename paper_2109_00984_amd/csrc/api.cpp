@@ -12,6 +12,7 @@
 #include <array>
 #include <new>
 #include <vector>
+#include <atomic>
 
 #include "internal.h"
 #include "mpc.h"
@@ -20,13 +21,14 @@ using namespace mpc;
 
 namespace {
 
-int g_last_hip_error = 0;
+// Written by whichever thread meets a HIP error, on any context.
+std::atomic<int> g_last_hip_error{0};
 
 #define HIPCHK(expr)                             \
   do {                                           \
     hipError_t _e = (expr);                      \
     if (_e != hipSuccess) {                      \
-      g_last_hip_error = (int)_e;                \
+      g_last_hip_error.store((int)_e);           \
       return MPC_E_HIP;                          \
     }                                            \
   } while (0)
@@ -281,7 +283,7 @@ mpc_status batch_disjoint(std::vector<Span> outs, const std::vector<Span>& ins) 
 
 mpc_status hip_status(hipError_t e) {
   if (e == hipSuccess) return MPC_OK;
-  g_last_hip_error = (int)e;
+  g_last_hip_error.store((int)e);
   return MPC_E_HIP;
 }
 
@@ -853,7 +855,7 @@ const char* mpc_status_str(mpc_status s) {
   return "unknown status";
 }
 
-int mpc_last_hip_error(void) { return g_last_hip_error; }
+int mpc_last_hip_error(void) { return g_last_hip_error.load(); }
 
 mpc_status mpc_encode(const double* x, size_t n, int frac_bits, int64_t* out) {
   if (n && (!x || !out)) return MPC_E_INVAL;
@@ -886,7 +888,7 @@ mpc_status mpc_ctx_create(int device, void* stream0, void* stream1, uint64_t see
   c->device = device;
   c->seed = seed;
   auto fail = [&](hipError_t e) {
-    g_last_hip_error = (int)e;
+    g_last_hip_error.store((int)e);
     mpc_ctx_destroy(c);
     return MPC_E_HIP;
   };
