@@ -414,6 +414,42 @@ def test_graph_replay_matches_eager(m, M, N, K):
             c.close()
 
 
+@pytest.mark.parametrize("M,N,K", [(64, 32, 128), (130, 70, 300)])
+def test_graph_replay_plain_matches_eager(m, M, N, K):
+    # the plain form from a graph: the single fused launch of a small product
+    # (64x32x128), and the open + GEMM + split-K reduction of a larger one
+    say(f"graph replay plain {M}x{N}x{K}")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = m.Context(device=0, seed=SEED)
+        X, Y = rnd(5, (M, K)), rnd(6, (K, N))
+        gx, gy = c.share(dev(X), 0, 83), c.share(dev(Y), 1, 84)
+        t = c.dealer(m.TRIPLE_MATMUL, 2, 85, (M, N, K))
+        eager = pair(c, c.beaver_matmul(gx, gy, t, 16, "plain"))
+        want = oracle.beaver_matmul(oracle.share(X, 0, SEED, 83), oracle.share(Y, 1, SEED, 84),
+                                    oracle.dealer_matmul(2, 85, M, N, K), 16)
+        assert np.array_equal(eager[0], want[0]) and np.array_equal(eager[1], want[1])
+        out = m.SharedPair(c.empty((M, N)), c.empty((M, N)))
+        c.beaver_matmul(gx, gy, t, 16, "plain", out=out)  # sizes the workspace
+        c.sync()
+        c.graph_begin()
+        c.beaver_matmul(gx, gy, t, 16, "plain", out=out)
+        g = c.graph_end()
+        try:
+            for rep in range(4):
+                out.s0.zero_()
+                out.s1.zero_()
+                c.graph_launch(g)
+                got = pair(c, out)
+                assert np.array_equal(got[0], eager[0]), rep
+                assert np.array_equal(got[1], eager[1]), rep
+                c.reveal(gx)  # eager work between replays
+                c.sync()
+        finally:
+            m.Context.graph_destroy(g)
+            c.close()
+
+
 @pytest.mark.parametrize("n", [4096, 4097])
 def test_beaver_mul_unaligned_views(m, ctx, n):
     # views starting one element in are only 8-byte aligned: the element-wise
