@@ -56,3 +56,14 @@ def test_host_codec_rejects_out_of_range():
         m.encode(np.array([np.nan]), 16)
     with pytest.raises(m.MPCError):
         m.encode(np.array([1.0]), 63)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU (both parties' shares live on it); it
+    # says so and exits before touching any device
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "8"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
