@@ -134,6 +134,8 @@ mpc_status mpc_decode(const int64_t *v, size_t n, int frac_bits, double *out);
  * for sharing. */
 mpc_status mpc_ctx_create(int device, void *stream0, void *stream1, uint64_t seed,
                           mpc_ctx **out);
+/* Waits for both party streams and frees the context and its buffers;
+ * MPC_E_INVAL (nothing freed) while a graph it captured still exists. */
 mpc_status mpc_ctx_destroy(mpc_ctx *ctx);
 /* Waits for both party streams; reports kernel faults. */
 mpc_status mpc_sync(mpc_ctx *ctx);
@@ -271,7 +273,9 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
  * or 64x16 outputs; 8: 64x128 with eight waves of 32x32 outputs), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
- * runs together share operand blocks in its L2) instead of one by one. */
+ * runs together share operand blocks in its L2) instead of one by one.
+ * group_m is 1..64: schedules outside that range (from mpc_set_default_tile_config
+ * or a cache file) are refused or, when loaded, skipped. */
 typedef struct {
   int variant, group_m, xcd_remap;
   double ms; /* measured time of the tuned launch(es), filled by the tuner */
@@ -301,7 +305,10 @@ mpc_status mpc_get_default_tile_config(const mpc_ctx *ctx, mpc_tile_config *cfg)
  * mpc_graph_destroy frees it.  A graph refers to the context's workspace by
  * address, so while any graph of a context exists the workspace cannot move:
  * a call that would need a larger one returns MPC_E_NOMEM (reserve enough
- * before capturing).  Destroy a context's graphs before the context. */
+ * before capturing).  A graph owns the descriptor buffers made while it was
+ * captured and frees them in mpc_graph_destroy, which first waits for party
+ * 0's stream.  Destroy a context's graphs before the context:
+ * mpc_ctx_destroy returns MPC_E_INVAL and frees nothing while any exists. */
 mpc_status mpc_graph_begin(mpc_ctx *ctx);
 mpc_status mpc_graph_end(mpc_ctx *ctx, void **graph_exec);
 mpc_status mpc_graph_launch(mpc_ctx *ctx, void *graph_exec);

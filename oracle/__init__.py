@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# MPC_ORACLE_LIB may name another build of oracle.c (the sanitizer build)
+_LIB_PATH = os.environ.get("MPC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 u64p = ctypes.POINTER(ctypes.c_uint64)

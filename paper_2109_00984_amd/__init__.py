@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libmpc.so")
 FORM_PLAIN, FORM_LIMB8, FORM_AUTO, FORM_FP64LIMB = 0, 1, 2, 3
 TRIPLE_MUL, TRIPLE_SQUARE, TRIPLE_MATMUL, TRIPLE_CONV1D = 0, 1, 2, 3
 FORMS = {"plain": FORM_PLAIN, "limb8": FORM_LIMB8, "auto": FORM_AUTO, "fp64limb": FORM_FP64LIMB}
+# mpc_status values (include/mpc.h)
+(MPC_OK, MPC_E_INVAL, MPC_E_SHAPE, MPC_E_ALIAS, MPC_E_NOMEM, MPC_E_HIP, MPC_E_UNSUPPORTED,
+ MPC_E_RANGE) = 0, -1, -2, -3, -4, -5, -6, -7
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2109_00984_amd/build.py "
@@ -268,10 +271,13 @@ class Context:
                                    VP(streams[1].cuda_stream), seed, ctypes.byref(h)),
                "mpc_ctx_create")
         self._h = h
+        self._graphs = set()
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.mpc_ctx_destroy(self._h)
+            for g in list(self._graphs):
+                g.destroy()
+            _check(_lib.mpc_ctx_destroy(self._h), "mpc_ctx_destroy")
             self._h = None
 
     def __del__(self):
@@ -710,13 +716,39 @@ class Context:
         _check(_lib.mpc_graph_begin(self._h), "mpc_graph_begin")
 
     def graph_end(self):
-        g = VP()
-        _check(_lib.mpc_graph_end(self._h, ctypes.byref(g)), "mpc_graph_end")
+        """Ends the capture; returns a Graph, which keeps this context alive
+        until it is destroyed (the library refuses to destroy a context whose
+        graphs still exist)."""
+        h = VP()
+        _check(_lib.mpc_graph_end(self._h, ctypes.byref(h)), "mpc_graph_end")
+        g = Graph(self, h)
+        self._graphs.add(g)
         return g
 
     def graph_launch(self, g):
-        _check(_lib.mpc_graph_launch(self._h, g), "mpc_graph_launch")
+        if not isinstance(g, Graph) or g.ctx is not self or not g._h:
+            raise ValueError("not a live graph of this context")
+        _check(_lib.mpc_graph_launch(self._h, g._h), "mpc_graph_launch")
 
     @staticmethod
     def graph_destroy(g):
-        _check(_lib.mpc_graph_destroy(g), "mpc_graph_destroy")
+        g.destroy()
+
+
+class Graph:
+    """An instantiated capture of a context's calls (see Context.graph_end)."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self._h = ctx, h
+
+    def destroy(self):
+        if self._h:
+            h, self._h = self._h, None
+            self.ctx._graphs.discard(self)
+            _check(_lib.mpc_graph_destroy(h), "mpc_graph_destroy")
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -69,6 +69,8 @@ struct mpc_ctx {
   int next_slot = 0;
   int cur_slot = -1;
   bool capturing = false;
+  // descriptor buffers made during the capture in progress; the graph that
+  // capture becomes owns them and frees them when it is destroyed
   std::vector<void*> capture_allocs;
   mpc_stats stats{};
   // event timing of GEMM launches
@@ -93,10 +95,12 @@ struct mpc_ctx {
   // no buffer may move while any exists
   int live_graphs = 0;
 };
-// An instantiated graph and the context whose buffers it references.
+// An instantiated graph, the context whose buffers it references and the
+// descriptor buffers its kernels read.
 struct mpc_graph {
   hipGraphExec_t exec;
   mpc_ctx* ctx;
+  std::vector<void*> allocs;
 };
 
 namespace {
@@ -237,6 +241,11 @@ bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 // Element counts above 2^46 (512 TiB of uint64) cannot be device buffers;
 // refusing them keeps every size computed from a shape far from overflow.
 constexpr i64 kMaxElems = (i64)1 << 46;
+// Tile rows per raster group of the limb GEMM's schedule.
+constexpr int kMaxGroupM = 64;
+bool sched_ok(int variant, int group_m) {
+  return variant >= 0 && variant < kLimbVariants && group_m >= 1 && group_m <= kMaxGroupM;
+}
 
 bool count_ok(i64 a, i64 b) { return a >= 0 && b >= 0 && (a == 0 || b <= kMaxElems / a); }
 
@@ -924,6 +933,8 @@ mpc_status mpc_ctx_create(int device, void* stream0, void* stream1, uint64_t see
 
 mpc_status mpc_ctx_destroy(mpc_ctx* c) {
   if (!c) return MPC_OK;
+  // its graphs hold the context's address and buffers
+  if (c->live_graphs > 0) return MPC_E_INVAL;
   (void)hipSetDevice(c->device);
   for (int p = 0; p < 2; ++p)
     if (c->s[p]) (void)hipStreamSynchronize(c->s[p]);
@@ -1706,7 +1717,7 @@ mpc_status mpc_autotune_load(mpc_ctx* c, const char* path) {
   unsigned long long key;
   int v, gm, remap;
   while (std::fscanf(f, "%llx %d %d %d", &key, &v, &gm, &remap) == 4)
-    if (v >= 0 && v < kLimbVariants && gm >= 1) c->tuned[(uint64_t)key] = TileSched{v, gm, remap ? 1 : 0};
+    if (sched_ok(v, gm)) c->tuned[(uint64_t)key] = TileSched{v, gm, remap ? 1 : 0};
   std::fclose(f);
   return MPC_OK;
 }
@@ -1718,7 +1729,7 @@ mpc_status mpc_get_default_tile_config(const mpc_ctx* c, mpc_tile_config* cfg) {
 }
 
 mpc_status mpc_set_default_tile_config(mpc_ctx* c, const mpc_tile_config* cfg) {
-  if (!c || !cfg || cfg->variant < 0 || cfg->variant >= kLimbVariants || cfg->group_m < 1) return MPC_E_INVAL;
+  if (!c || !cfg || !sched_ok(cfg->variant, cfg->group_m)) return MPC_E_INVAL;
   c->sched_default = TileSched{cfg->variant, cfg->group_m, cfg->xcd_remap ? 1 : 0};
   return MPC_OK;
 }
@@ -2233,12 +2244,29 @@ mpc_status mpc_graph_end(mpc_ctx* c, void** graph_exec) {
   CHK(set_device(c));
   hipGraph_t g = nullptr;
   c->capturing = false;
-  HIPCHK(hipStreamEndCapture(c->s[0], &g));
+  std::vector<void*> allocs;
+  allocs.swap(c->capture_allocs);
+  auto drop = [&]() {
+    for (void* p : allocs) (void)hipFree(p);
+  };
+  hipError_t e = hipStreamEndCapture(c->s[0], &g);
+  if (e != hipSuccess) {
+    drop();
+    return hip_status(e);
+  }
   hipGraphExec_t ge = nullptr;
-  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return hip_status(e);
-  *graph_exec = (void*)new mpc_graph{ge, c};
+  if (e != hipSuccess) {
+    drop();
+    return hip_status(e);
+  }
+  mpc_graph* mg = new (std::nothrow) mpc_graph{ge, c, std::move(allocs)};
+  if (!mg) {
+    (void)hipGraphExecDestroy(ge);
+    return MPC_E_NOMEM;
+  }
+  *graph_exec = (void*)mg;
   c->live_graphs++;
   return MPC_OK;
 }
@@ -2255,7 +2283,11 @@ mpc_status mpc_graph_launch(mpc_ctx* c, void* graph_exec) {
 mpc_status mpc_graph_destroy(void* graph_exec) {
   if (!graph_exec) return MPC_OK;
   mpc_graph* g = (mpc_graph*)graph_exec;
+  (void)hipSetDevice(g->ctx->device);
+  // a replay still running reads the descriptor buffers
+  (void)hipStreamSynchronize(g->ctx->s[0]);
   const hipError_t e = hipGraphExecDestroy(g->exec);
+  for (void* p : g->allocs) (void)hipFree(p);
   g->ctx->live_graphs--;
   delete g;
   HIPCHK(e);

@@ -476,13 +476,13 @@ __device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ prob
   TilePos q;
   q.pi = find_problem(map.tile_start, map.nprob, t);
   const LimbProblem& p = probs[q.pi];
-  const int local = t - map.tile_start[q.pi];
-  const int ntm = (int)((p.M + BM - 1) / BM), ntn = (int)((p.N + BN - 1) / BN);
-  const int gm = sched.group_m;
-  const int per_group = gm * ntn;
-  const int first_m = (local / per_group) * gm;
-  const int gsize = min(ntm - first_m, gm);
-  const int in_group = local % per_group;
+  const i64 local = t - map.tile_start[q.pi];
+  const i64 ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
+  const i64 gm = sched.group_m;  // 1..64, checked by the host
+  const i64 per_group = gm * ntn;
+  const i64 first_m = (local / per_group) * gm;
+  const i64 gsize = min(ntm - first_m, gm);
+  const i64 in_group = local % per_group;
   q.tm = first_m + in_group % gsize;
   q.tn = in_group / gsize;
   return q;
@@ -957,7 +957,7 @@ hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_star
 hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
                             TileSched sched) {
   if (total_tiles <= 0) return hipSuccess;
-  if (sched.group_m < 1) sched.group_m = 1;
+  if (sched.group_m < 1 || sched.group_m > 64) return hipErrorInvalidValue;
   const dim3 grid(total_tiles);
 #define MPC_LDS_CASE(V, HA, HB, WR, WC)                                                                    \
   case V:                                                                                                 \

@@ -1,0 +1,77 @@
+"""Host-side contracts of the library on a live context: graph and context
+lifetimes, and the bounds of a tile schedule (its raster group height)."""
+import ctypes
+
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2109_00984_amd as mod
+    return mod
+
+
+def test_context_refuses_destroy_with_live_graph(m):
+    say("lifetimes: context destroy with a live graph")
+    c = m.Context(device=0, seed=1)
+    x = c.share(torch.arange(1024, dtype=torch.int64, device=c.device), 0, 1)
+    t = c.dealer(m.TRIPLE_SQUARE, 3, 4, (1024,))
+    c.sync()
+    c.graph_begin()
+    c.beaver_mul(x, None, t, 16)
+    g = c.graph_end()
+    # the raw C ABI refuses while the graph exists
+    st = m._lib.mpc_ctx_destroy(c._h)
+    assert st == m.MPC_E_INVAL
+    c.graph_launch(g)
+    c.sync()
+    # the binding destroys the context's graphs first
+    c.close()
+    assert g._h is None
+    g.destroy()  # a second destroy is a no-op
+
+
+def test_graph_of_other_context_refused(m):
+    a, b = m.Context(device=0, seed=1), m.Context(device=0, seed=2)
+    try:
+        x = a.share(torch.arange(64, dtype=torch.int64, device=a.device), 0, 1)
+        a.sync()
+        a.graph_begin()
+        a.truncate(x, 3)
+        g = a.graph_end()
+        with pytest.raises(ValueError):
+            b.graph_launch(g)
+        g.destroy()
+        with pytest.raises(ValueError):
+            a.graph_launch(g)
+    finally:
+        a.close()
+        b.close()
+
+
+def test_tile_schedule_bounds(m, tmp_path):
+    c = m.Context(device=0, seed=workloads.seeds(0)[1])
+    try:
+        before = c.default_tile_config()
+        for gm in (0, 65, 1 << 20):
+            with pytest.raises(m.MPCError):
+                c.set_default_tile_config(variant=before["variant_id"], group_m=gm)
+        assert c.default_tile_config() == before
+        c.set_default_tile_config(variant=before["variant_id"], group_m=64)
+        assert c.default_tile_config()["group_m"] == 64
+        # a cache file with out-of-range entries: those lines are ignored
+        p = tmp_path / "tune.txt"
+        p.write_text("00000000000000aa 5 100000 1\n00000000000000bb 99 8 1\n00000000000000cc 5 8 1\n")
+        c.autotune_load(p)
+        out = tmp_path / "saved.txt"
+        c.autotune_save(out)
+        lines = out.read_text().split()
+        assert lines[:1] == ["00000000000000cc"] and len(lines) == 4
+    finally:
+        c.close()
