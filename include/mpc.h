@@ -298,7 +298,7 @@ mpc_status mpc_set_default_tile_config(mpc_ctx *ctx, const mpc_tile_config *cfg)
 mpc_status mpc_get_default_tile_config(const mpc_ctx *ctx, mpc_tile_config *cfg);
 
 /* Stream capture of the context's work into a HIP graph: begin, issue calls,
- * end.  Party 0's stream must not be the null stream.  The workspace must
+ * end.  Party 0's stream must not be the null stream (MPC_E_INVAL).  The workspace must
  * already be large enough (issue the same calls once eagerly first, or call
  * mpc_reserve).  mpc_graph_launch replays the graph on party 0's stream of
  * the context that captured it (MPC_E_INVAL for another context);

@@ -2230,7 +2230,8 @@ mpc_status mpc_mp_truncate(mpc_ctx* c, int P, size_t n, int bits, uint64_t* cons
 
 // ------------------------------------------------------------------ graphs
 mpc_status mpc_graph_begin(mpc_ctx* c) {
-  if (!c || c->capturing) return MPC_E_INVAL;
+  // the null stream cannot be captured
+  if (!c || c->capturing || !c->s[0]) return MPC_E_INVAL;
   CHK(set_device(c));
   // finish eager work that still uses the upload slots before capturing
   CHK(sync_all(c));

@@ -17,8 +17,30 @@ def m():
     return mod
 
 
+def test_graph_begin_refuses_null_stream(m):
+    # torch's default stream is the null stream, which cannot be captured
+    c = m.Context(device=0, seed=1, streams=(torch.cuda.default_stream(0), torch.cuda.Stream(0)))
+    try:
+        if c.streams[0].cuda_stream == 0:
+            with pytest.raises(m.MPCError) as ei:
+                c.graph_begin()
+            assert ei.value.status == m.MPC_E_INVAL
+        # the context still works eagerly
+        x = c.share(torch.arange(64, dtype=torch.int64, device=c.device), 0, 1)
+        r = c.reveal(x)
+        c.sync()
+        assert torch.equal(r.cpu(), torch.arange(64, dtype=torch.int64))
+    finally:
+        c.close()
+
+
 def test_context_refuses_destroy_with_live_graph(m):
     say("lifetimes: context destroy with a live graph")
+    with torch.cuda.stream(torch.cuda.Stream()):
+        _destroy_with_live_graph(m)
+
+
+def _destroy_with_live_graph(m):
     c = m.Context(device=0, seed=1)
     x = c.share(torch.arange(1024, dtype=torch.int64, device=c.device), 0, 1)
     t = c.dealer(m.TRIPLE_SQUARE, 3, 4, (1024,))
@@ -38,6 +60,11 @@ def test_context_refuses_destroy_with_live_graph(m):
 
 
 def test_graph_of_other_context_refused(m):
+    with torch.cuda.stream(torch.cuda.Stream()):
+        _graph_of_other_context(m)
+
+
+def _graph_of_other_context(m):
     a, b = m.Context(device=0, seed=1), m.Context(device=0, seed=2)
     try:
         x = a.share(torch.arange(64, dtype=torch.int64, device=a.device), 0, 1)
