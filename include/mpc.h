@@ -270,7 +270,10 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
  * 3, 4, 5: the same shapes with the operand that has more fragments per wave
  * copied once per workgroup into LDS and read from there; 6: 64x128 and
  * 7: 128x64 in that LDS form with eight waves, two per SIMD, each wave 16x64
- * or 64x16 outputs; 8: 64x128 with eight waves of 32x32 outputs), the number of tile
+ * or 64x16 outputs; 8: 64x128 with eight waves of 32x32 outputs; 9, 10, 11:
+ * 64x64 (two workgroups per compute unit), 64x128 and 128x64 (eight waves)
+ * with both operands copied once per workgroup into LDS and every wave
+ * owning 32x32 outputs), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
  * runs together share operand blocks in its L2) instead of one by one.

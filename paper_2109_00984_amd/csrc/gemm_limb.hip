@@ -909,6 +909,288 @@ __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ?
   store_tile<HA, HB, G::BM, G::BN>(acc, p, tm, tn, wr, wc, lane);
 }
 
+// ------------------------------------------------------------------ GEMM with both operands in LDS
+// k_limb_gemm_lds still streams the inner operand from global memory into
+// every wave's registers, so each inner strip crosses the vector-memory path
+// once per wave that uses it; that traffic, not the matrix cores, is what
+// holds the LDS kernel back (with operands resident in L2, leaving out the
+// inner loads alone speeds it up by a tenth).  Here both operands of a k step
+// are copied once per workgroup into LDS, and every fragment is read from
+// there.  LDS holds exactly one k step of both operands (64 KiB for a 64x64
+// tile, 96 KiB for 64x128), not two: a step's limb planes die at different
+// levels, so each plane is refilled as soon as every wave is past its last
+// read.  Level l reads outer limb l + 1 (limb 0 of the next step at level 7),
+// and inner limb j of the next step is read into registers right after its
+// last use, at level 8 - j (limbs 0..2, used up to the last level, into a
+// second register set at level 3).  Two barriers per step certify which planes
+// are dead and which copies have landed:
+//   B2, before level 0 of step t: copy outer 4..7 of step t, outer 0 and
+//       inner 0..5 of step t + 1;
+//   B1, before level 3 of step t: copy outer 1..3 of step t + 1 and inner 6, 7
+//       of step t + 2.
+// Every copy issued after one barrier lands before the next (each waits for
+// its own copies, then the barrier), and every plane it overwrites was read
+// before the barrier it follows:
+//   outer 1..3 read at levels 0..2, outer 4..7 at levels 3..6 (after B1),
+//   outer 0 of the next step at level 7; inner 7 and 6 (next step) at levels 1
+//   and 2, inner 5 and 0..2 at level 3 (after B1), inner 4 at level 4, inner 3
+//   at level 5.
+// Geometry SGeo<WR, WC>: WR x WC waves of 32x32 outputs (2x2 blocks of 16x16,
+// 8 diagonal accumulators each): 64x64 with four waves, two workgroups per CU
+// (one's barrier is covered by the other's matrix-core work), or 64x128 and
+// 128x64 with eight waves, which hold both halves of the tile at the same k
+// (neighbouring tiles share operand blocks in L2 for longer).
+template <int WR_, int WC_>
+struct SGeo {
+  static constexpr int WR = WR_, WC = WC_;
+  static constexpr int kWaves = WR * WC, kThreads = 64 * kWaves;
+  static constexpr int BM = 32 * WR, BN = 32 * WC;
+  static constexpr bool kOuterA = WR > WC;  // the operand with more strips is outer
+  static constexpr int SO = kOuterA ? WR : WC, SI = kOuterA ? WC : WR;  // strips per workgroup
+  static constexpr int kOPlane = SO * 2048, kIPlane = SI * 2048;       // one limb plane of a step
+  static constexpr int kIBase = 8 * kOPlane;
+  static constexpr int kBytes = 8 * (kOPlane + kIPlane);
+  static constexpr int kMinBlocks = kWaves == 4 ? 2 : 1;
+  // 1 KiB copy units per plane (strips x 2 k-blocks)
+  static constexpr int kOU = 2 * SO, kIU = 2 * SI;
+  static constexpr int kB1 = 3 * kOU + 2 * kIU, kB2 = 5 * kOU + 6 * kIU;
+  static constexpr int kC1 = kB1 / kWaves, kC2 = kB2 / kWaves;  // copies per wave
+  // a tile's last step still copies its own outer limbs 4..7 (the head of
+  // the level-0 batch), but nothing for later steps
+  static constexpr int kC2Last = 4 * kOU / kWaves;
+  static_assert(kB1 % kWaves == 0 && kB2 % kWaves == 0, "copies split evenly over the waves");
+  // every group of a batch starts at a multiple of kWaves, so a copy's group
+  // is a compile-time property of its position in the wave's list
+  static_assert((3 * kOU) % kWaves == 0 && (4 * kOU) % kWaves == 0 && (5 * kOU) % kWaves == 0,
+                "batch groups aligned to the waves");
+  static_assert(kC1 < 5 * 4 && kC2 < 8 * 4, "at most one copy per MFMA");
+  static_assert(kBytes * kMinBlocks <= 160 * 1024, "one step of both operands per workgroup fits in LDS");
+};
+
+// Descriptors and k-block of one k step (both operands, the workgroup's strips).
+struct SStep {
+  __amdgpu_buffer_rsrc_t a, b;
+  int kb, kbs;
+  __device__ int off(int x) const { return (kb + x * kbs) << 13; }
+};
+
+__device__ __forceinline__ SStep sstep(const SegSrc& w0, const SegSrc& w1, int kb0, int kg) {
+  const bool seg0 = kg < kb0;
+  SStep o;
+  o.a = seg0 ? w0.a : w1.a;
+  o.b = seg0 ? w0.b : w1.b;
+  o.kb = seg0 ? kg : kg - kb0;
+  o.kbs = seg0 ? w0.kbs : w1.kbs;
+  return o;
+}
+
+// The k steps a step's copies draw from: this one, the next, the one after.
+struct SSteps {
+  SStep t0, t1, t2;
+};
+
+struct SCtx {
+  unsigned rdo, rdi;  // LDS byte offsets of this lane's fragment in its outer / inner strip
+  unsigned lane16;    // lane * 16: a copy's per-lane source offset
+  int wave;
+};
+
+// Fragment (half h, limb i) of the outer / inner operand from LDS.
+template <class G>
+__device__ __forceinline__ v4i sh_frag_o(const lds_u8* lds, const SCtx& c, int h, int i) {
+  return *(const lds_v4i*)(lds + c.rdo + h * 256 + i * G::kOPlane);
+}
+template <class G>
+__device__ __forceinline__ v4i sh_frag_i(const lds_u8* lds, const SCtx& c, int h, int i) {
+  return *(const lds_v4i*)(lds + c.rdi + h * 256 + i * G::kIPlane);
+}
+
+// Copy number J of this wave in batch B (1: before level 3, 2: before level 0;
+// 1 is also the prologue's, with the steps shifted back by one).  Unit
+// u = J * waves + wave of the batch's list of (plane, strip, k-block) units.
+template <class G, int B, int J>
+__device__ __forceinline__ void sh_copy(const SCtx& c, lds_u8* lds, const SSteps& st) {
+  constexpr int u0 = J * G::kWaves;
+  // group: outer planes [p0, p0 + n) or inner planes, from step `sel`
+  constexpr bool outer = B == 1 ? u0 < 3 * G::kOU : u0 < 5 * G::kOU;
+  constexpr int start = B == 1 ? (outer ? 0 : 3 * G::kOU)
+                               : (u0 < 4 * G::kOU ? 0 : outer ? 4 * G::kOU : 5 * G::kOU);
+  constexpr int p0 = B == 1 ? (outer ? 1 : 6) : (u0 < 4 * G::kOU ? 4 : outer ? 0 : 0);
+  constexpr int sel = B == 1 ? (outer ? 1 : 2) : (u0 < 4 * G::kOU ? 0 : 1);
+  constexpr int upp = outer ? G::kOU : G::kIU;
+  const SStep& s = sel == 0 ? st.t0 : sel == 1 ? st.t1 : st.t2;
+  const int v = u0 - start + c.wave;
+  const int plane = p0 + v / upp, x = (v % upp) >> 1, kk = v & 1;
+  const bool is_a = outer == G::kOuterA;
+  const unsigned dst = (outer ? 0u : (unsigned)G::kIBase) + plane * (outer ? G::kOPlane : G::kIPlane) + x * 2048 + kk * 1024;
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(is_a ? s.a : s.b, (__attribute__((address_space(3))) void*)(lds + dst), 16,
+                                           c.lane16, s.off(x) + kk * 8192 + plane * 1024, 0, 0);
+}
+
+// All of this wave's copies of batch B from number J on, back to back.
+template <class G, int B, int J>
+__device__ __forceinline__ void sh_copies(const SCtx& c, lds_u8* lds, const SSteps& st) {
+  if constexpr (J < (B == 1 ? G::kC1 : G::kC2)) {
+    sh_copy<G, B, J>(c, lds, st);
+    sh_copies<G, B, J + 1>(c, lds, st);
+  }
+}
+
+template <class G>
+struct SRegs {
+  v4i (&acc)[2][2][8];
+  v4i (&z)[2];             // outer limb 0
+  v4i (&ob)[2][2];         // outer limbs 1..7: limb l in ob[l & 1]
+  v4i (&inner)[2][8];      // inner limbs 3..7, reloaded in place with the next step's
+  const v4i (&dcur)[2][3]; // inner limbs 0..2 of this step
+  v4i (&dnext)[2][3];      // and of the next
+};
+
+// Waits for this wave's copies and LDS reads, then for the other waves.
+__device__ __forceinline__ void sh_barrier() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// MFMA number M of level L and what follows it.  A tile's odd last step
+// copies and reads nothing for a next step.
+template <class G, bool FIRST, bool LAST, int L, int M>
+__device__ __forceinline__ void sh_level(SRegs<G>& r, const SCtx& c, lds_u8* lds, const SSteps& st) {
+  constexpr int NM = (8 - L) * 4;
+  if constexpr (M < NM) {
+    if constexpr (M == 0 && (L == 0 || L == 3)) {
+      __builtin_amdgcn_sched_barrier(0);
+      sh_barrier();  // B2 (level 0) or B1 (level 3)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    constexpr int s = L + M / 4, o = (M / 2) % 2, i = M % 2;
+    const v4i& in = (s - L) < 3 ? r.dcur[i][s - L] : r.inner[i][s - L];
+    const v4i& out = L == 0 ? r.z[o] : r.ob[L & 1][o];
+    v4i& acc = G::kOuterA ? r.acc[o][i][s] : r.acc[i][o][s];
+    const v4i& a = G::kOuterA ? out : in;
+    const v4i& b = G::kOuterA ? in : out;
+    if constexpr (FIRST && L == 0) mfma16_first(acc, a, b);
+    else mfma16(acc, a, b);
+    if constexpr (M == 0) {
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (L < 7) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) r.ob[(L + 1) & 1][h] = sh_frag_o<G>(lds, c, h, L + 1);
+      } else if constexpr (!LAST) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) r.z[h] = sh_frag_o<G>(lds, c, h, 0);
+      }
+      if constexpr (!LAST && L >= 1 && L <= 5) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) r.inner[h][8 - L] = sh_frag_i<G>(lds, c, h, 8 - L);
+      }
+      if constexpr (!LAST && L == 3) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) r.dnext[h][j] = sh_frag_i<G>(lds, c, h, j);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    constexpr int NL = L == 0 ? (LAST ? G::kC2Last : G::kC2) : (L == 3 && !LAST) ? G::kC1 : 0;
+    constexpr int Q = (M + 1) * (NL + 1) / NM - 1, QPREV = M * (NL + 1) / NM - 1;
+    if constexpr (Q >= 0 && Q < NL && Q != QPREV) {
+      __builtin_amdgcn_sched_barrier(0);
+      sh_copy<G, L == 0 ? 2 : 1, Q>(c, lds, st);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    sh_level<G, FIRST, LAST, L, M + 1>(r, c, lds, st);
+  }
+}
+
+template <class G, bool FIRST, bool LAST, int L>
+__device__ __forceinline__ void sh_levels(SRegs<G>& r, const SCtx& c, lds_u8* lds, const SSteps& st) {
+  if constexpr (L < 8) {
+    sh_level<G, FIRST, LAST, L, 0>(r, c, lds, st);
+    __builtin_amdgcn_sched_barrier(0);
+    sh_levels<G, FIRST, LAST, L + 1>(r, c, lds, st);
+  }
+}
+
+template <class G, bool FIRST, bool LAST>
+__device__ __forceinline__ void sh_step(SRegs<G> r, const SCtx& c, lds_u8* lds, const SSteps& st) {
+  // one base register per operand, the plane and half in each read's offset
+  SCtx cs = c;
+  asm volatile("" : "+v"(cs.rdo), "+v"(cs.rdi));
+  sh_levels<G, FIRST, LAST, 0>(r, cs, lds, st);
+}
+
+template <int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC, WR * WC == 4 ? 2 : 1)  // SGeo::kMinBlocks
+    k_limb_gemm_sh(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
+  using G = SGeo<WR, WC>;
+  __shared__ v4i lds_words[G::kBytes / 16];
+  lds_u8* lds = (lds_u8*)&lds_words[0];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave / WC, wc = wave % WC;
+  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(probs, map, sched);
+  const LimbProblem& p = probs[tp.pi];
+  const i64 tm = tp.tm, tn = tp.tn;
+  const i64 mw = tm * WR, nw = tn * WC;  // the workgroup's first left / right 32-block
+  const int xo = G::kOuterA ? wr : wc, xi = G::kOuterA ? wc : wr;  // the wave's outer / inner strip
+
+  v4i acc[2][2][8];
+  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int g = lane >> 4;
+  const unsigned lane_lds = (unsigned)((g >> 1) * 1024 + (g & 1) * 512 + (lane & 15) * 16);
+  const SCtx c{(unsigned)(xo * 2048) + lane_lds, (unsigned)(G::kIBase + xi * 2048) + lane_lds,
+               (unsigned)lane * 16u, wave};
+  const uint8_t* PA1 = p.PA1 ? p.PA1 : p.PA0;
+  const uint8_t* PB1 = p.PB1 ? p.PB1 : p.PB0;
+  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, WR, WC);
+  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, WR, WC);
+
+  v4i z[2], ob[2][2], inner[2][8], d0[2][3], d1[2][3];
+  const int klast = kbeg + 2 * (nsteps - 1);
+  if (nsteps > 0) {
+    // steps past the last re-read the last step's blocks (valid memory, unused)
+    auto off = [&](int t) { return sstep(w0, w1, p.kb0, min(kbeg + 2 * max(t, 0), klast)); };
+    // prologue: step 0's outer limb 0 and inner limbs straight into registers
+    // (global fragment offsets: k-block g/2 of the step is 8 KiB further);
+    // then the copies a B1 barrier of step -1 would have issued
+    {
+      const SStep s0 = off(0);
+      const unsigned lane_g = (unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16);
+      const __amdgpu_buffer_rsrc_t ro = G::kOuterA ? s0.a : s0.b, ri = G::kOuterA ? s0.b : s0.a;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        z[h] = ld_buf(ro, lane_g, s0.off(xo) + h * 256);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) d0[h][j] = ld_buf(ri, lane_g, s0.off(xi) + h * 256 + j * 1024);
+#pragma unroll
+        for (int j = 3; j < 8; ++j) inner[h][j] = ld_buf(ri, lane_g, s0.off(xi) + h * 256 + j * 1024);
+      }
+      const SSteps pro{s0, s0, off(1)};
+      sh_copies<G, 1, 0>(c, lds, pro);
+    }
+    using R = SRegs<G>;
+    auto steps = [&](int t) { return SSteps{off(t), off(t + 1), off(t + 2)}; };
+    sh_step<G, true, false>(R{acc, z, ob, inner, d0, d1}, c, lds, steps(0));
+    int t = 1;
+    for (; t + 1 < nsteps; t += 2) {
+      sh_step<G, false, false>(R{acc, z, ob, inner, d1, d0}, c, lds, steps(t));
+      sh_step<G, false, false>(R{acc, z, ob, inner, d0, d1}, c, lds, steps(t + 1));
+    }
+    if (t < nsteps) sh_step<G, false, true>(R{acc, z, ob, inner, d1, d0}, c, lds, steps(t));
+    // no copy may still be writing this workgroup's LDS when it ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
+  }
+  store_tile<2, 2, G::BM, G::BN>(acc, p, tm, tn, wr, wc, lane);
+}
+
 }  // namespace
 
 i64 limb_rblocks(i64 rows) {
@@ -921,11 +1203,14 @@ int limb_tiles(i64 M, i64 N, int variant) {
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
 int limb_variant_sa(int variant) {
-  return variant == kLimb128x64 || variant == kLimbLds128x64 || variant == kLimbLds128x64w8 ? 2 : 1;
+  return variant == kLimb128x64 || variant == kLimbLds128x64 || variant == kLimbLds128x64w8 ||
+                 variant == kLimbSh128x64
+             ? 2
+             : 1;
 }
 int limb_variant_sb(int variant) {
   return variant == kLimb64x128 || variant == kLimbLds64x128 || variant == kLimbLds64x128w8 ||
-                 variant == kLimbLds64x128w8s
+                 variant == kLimbLds64x128w8s || variant == kLimbSh64x128
              ? 2
              : 1;
 }
@@ -963,6 +1248,10 @@ hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map
   case V:                                                                                                 \
     hipLaunchKernelGGL((k_limb_gemm_lds<HA, HB, WR, WC>), grid, dim3(64 * WR * WC), 0, s, probs, map, sched); \
     break;
+#define MPC_SH_CASE(V, WR, WC)                                                                        \
+  case V:                                                                                         \
+    hipLaunchKernelGGL((k_limb_gemm_sh<WR, WC>), grid, dim3(64 * WR * WC), 0, s, probs, map, sched); \
+    break;
   switch (sched.variant) {
     case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
     case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
@@ -973,9 +1262,13 @@ hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map
     MPC_LDS_CASE(kLimbLds64x128w8, 1, 4, 4, 2)
     MPC_LDS_CASE(kLimbLds128x64w8, 4, 1, 2, 4)
     MPC_LDS_CASE(kLimbLds64x128w8s, 2, 2, 2, 4)
+    MPC_SH_CASE(kLimbSh64x64, 2, 2)
+    MPC_SH_CASE(kLimbSh64x128, 2, 4)
+    MPC_SH_CASE(kLimbSh128x64, 4, 2)
     default: return hipErrorInvalidValue;
   }
 #undef MPC_LDS_CASE
+#undef MPC_SH_CASE
   return hipGetLastError();
 }
 

@@ -266,12 +266,16 @@ hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_star
 // Variants 3..8 stage the outer operand through LDS (k_limb_gemm_lds); 6, 7
 // and 8 run eight waves per workgroup (two per SIMD): 6 and 7 with 16x64 and
 // 64x16 wave sub-tiles, 8 with 32x32 ones, as in the four-wave 64x64 tile.
+// Variants 9..11 stage both operands through LDS (k_limb_gemm_sh), every wave
+// owning 32x32 outputs: 9 with four waves (two workgroups per CU), 10 and 11
+// with eight.
 enum LimbVariant : int {
   kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2,
   kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5,
-  kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7, kLimbLds64x128w8s = 8
+  kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7, kLimbLds64x128w8s = 8,
+  kLimbSh64x64 = 9, kLimbSh64x128 = 10, kLimbSh128x64 = 11
 };
-constexpr int kLimbVariants = 9;
+constexpr int kLimbVariants = 12;
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group

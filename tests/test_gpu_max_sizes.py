@@ -187,7 +187,7 @@ def long_k():
     return X, Y, want
 
 
-@pytest.mark.parametrize("variant", [0, 3, 5, 7])
+@pytest.mark.parametrize("variant", [0, 3, 5, 7, 9, 10])
 def test_longest_limb_k_segment(m, long_k, variant):
     X, Y, want = long_k
     M, K = X.shape
