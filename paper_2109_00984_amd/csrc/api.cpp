@@ -661,6 +661,8 @@ struct LimbReq {
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
 // whose concatenated K exceeds the int32-safe range continues in the next
 // launch, adding into its output; truncation is applied by its last chunk).
+// Descriptor tables go inside the kernels' arguments when every launch's are
+// short (no upload), else in one upload for the call.
 mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std::vector<LimbReq>& reqs,
                       TileSched sched) {
   // every entry point checks this before it issues any work
@@ -686,18 +688,14 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     }
   first_job.push_back(jobs.size());
   const size_t nj = jobs.size(), nreq = reqs.size();
-  Blob blob;
   // per launch: prefix sums of its jobs' block counts
-  std::vector<size_t> obstart(launch_km.size());
-  std::vector<i64> nblocks(launch_km.size());
+  std::vector<std::vector<i64>> bstarts(launch_km.size());
   for (size_t L = 0; L < launch_km.size(); ++L) {
-    std::vector<i64> bstart(1, 0);
+    std::vector<i64>& bstart = bstarts[L];
+    bstart.assign(1, 0);
     for (size_t i = first_job[L]; i < first_job[L + 1]; ++i)
       bstart.push_back(bstart.back() + jobs[i].rreal * jobs[i].kblocks);
-    obstart[L] = blob.add(bstart.data(), bstart.size());
-    nblocks[L] = bstart.back();
   }
-  const size_t ojobs = blob.add(jobs.data(), nj);
 
   // K pieces per request.  The int32 bound needs kbt / kLimbMaxKBlocks chunks,
   // run as consecutive launches that add into the output.  When the whole
@@ -787,30 +785,59 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       }
     }
   }
-  std::vector<size_t> oprob(nlaunch), otile(nlaunch);
-  for (int L = 0; L < nlaunch; ++L) {
-    oprob[L] = blob.add(pieces[L].data(), pieces[L].size());
-    otile[L] = blob.add(tstarts[L].data(), tstarts[L].size());
-  }
-  const ReduceTable rt = add_reduces(blob, reduces);
+  bool inl = reduces.empty();
+  for (size_t L = 0; L < launch_km.size(); ++L)
+    if (first_job[L + 1] - first_job[L] > (size_t)kInlineJobs) inl = false;
+  for (int L = 0; L < nlaunch; ++L)
+    if (pieces[L].size() > (size_t)kInlineProbs) inl = false;
+  Blob blob;
+  std::vector<size_t> obstart(launch_km.size()), oprob(nlaunch), otile(nlaunch);
+  size_t ojobs = 0;
+  ReduceTable rt{};
   uint8_t* dev = nullptr;
-  CHK(upload(c, blob, &dev));
+  if (!inl) {
+    for (size_t L = 0; L < launch_km.size(); ++L) obstart[L] = blob.add(bstarts[L].data(), bstarts[L].size());
+    ojobs = blob.add(jobs.data(), nj);
+    for (int L = 0; L < nlaunch; ++L) {
+      oprob[L] = blob.add(pieces[L].data(), pieces[L].size());
+      otile[L] = blob.add(tstarts[L].data(), tstarts[L].size());
+    }
+    rt = add_reduces(blob, reduces);
+    CHK(upload(c, blob, &dev));
+  }
   for (size_t L = 0; L < launch_km.size(); ++L) {
     const int njl = (int)(first_job[L + 1] - first_job[L]);
-    CHK(hip_status(launch_pack(st, (const PackJob*)(dev + ojobs) + first_job[L], (const i64*)(dev + obstart[L]),
-                               njl, nblocks[L], launch_km[L].first, launch_km[L].second)));
+    PackTables t{};
+    t.njobs = njl;
+    if (inl) {
+      for (int i = 0; i < njl; ++i) t.ijobs[i] = jobs[first_job[L] + i];
+      for (int i = 0; i <= njl; ++i) t.ibstart[i] = bstarts[L][i];
+    } else {
+      t.jobs = (const PackJob*)(dev + ojobs) + first_job[L];
+      t.block_start = (const i64*)(dev + obstart[L]);
+    }
+    CHK(hip_status(launch_pack(st, t, bstarts[L].back(), launch_km[L].first, launch_km[L].second)));
     c->stats.launches++;
   }
   for (int L = 0; L < nlaunch; ++L) {
     if (pieces[L].empty()) continue;
-    TileMap map{(int)pieces[L].size(), (const int*)(dev + otile[L])};
+    GemmTables t{};
+    t.sched = sched;
+    t.map.nprob = (int)pieces[L].size();
+    if (inl) {
+      for (size_t i = 0; i < pieces[L].size(); ++i) t.iprobs[i] = pieces[L][i];
+      for (size_t i = 0; i < tstarts[L].size(); ++i) t.itile_start[i] = tstarts[L][i];
+    } else {
+      t.probs = (const LimbProblem*)(dev + oprob[L]);
+      t.map.tile_start = (const int*)(dev + otile[L]);
+    }
     LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[L]);
     CHK(tm.start());
-    CHK(hip_status(launch_limb_gemm(st, (const LimbProblem*)(dev + oprob[L]), map, tstarts[L].back(), sched)));
+    CHK(hip_status(launch_limb_gemm(st, t, tstarts[L].back())));
     CHK(tm.stop());
     c->stats.launches++;
   }
-  CHK(issue_reduces(c, st, rt, dev));
+  if (!inl) CHK(issue_reduces(c, st, rt, dev));
   c->stats.gemm_problems += nreq;
   return MPC_OK;
 }

@@ -48,11 +48,57 @@ typedef __attribute__((address_space(1))) v4i gv4i;
 __device__ __forceinline__ gcu64* gptr(const u64* p) { return (gcu64*)p; }
 
 
+// Constant-memory views of a launch's descriptor tables (PackTables,
+// GemmTables): inline entries are read from the kernel-argument segment,
+// uploaded ones through the same constant address space, so that every
+// access is a scalar load.  Each kernel takes its table struct as its only
+// argument, so the struct starts the segment.  (The host compilation pass
+// only parses the kernels; it gets plain pointers, which it can copy through.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using cptr = __attribute__((address_space(4))) const T*;
+#define MPC_KERNARG_PTR() __builtin_amdgcn_kernarg_segment_ptr()
+#else
+template <class T>
+using cptr = const T*;
+#define MPC_KERNARG_PTR() nullptr
+#endif
+
+struct PackView {
+  cptr<PackJob> jobs;
+  cptr<i64> bstart;
+  int njobs;
+};
+__device__ __forceinline__ PackView pack_view() {
+  const cptr<PackTables> t = (cptr<PackTables>)MPC_KERNARG_PTR();
+  PackView v;
+  v.njobs = t->njobs;
+  v.jobs = t->jobs ? (cptr<PackJob>)(uintptr_t)t->jobs : t->ijobs;
+  v.bstart = t->jobs ? (cptr<i64>)(uintptr_t)t->block_start : t->ibstart;
+  return v;
+}
+
+struct GemmView {
+  cptr<LimbProblem> probs;
+  cptr<int> tile_start;
+  int nprob;
+  TileSched sched;
+};
+__device__ __forceinline__ GemmView gemm_view() {
+  const cptr<GemmTables> t = (cptr<GemmTables>)MPC_KERNARG_PTR();
+  GemmView v;
+  v.nprob = t->map.nprob;
+  v.sched = t->sched;
+  v.probs = t->probs ? (cptr<LimbProblem>)(uintptr_t)t->probs : t->iprobs;
+  v.tile_start = t->probs ? (cptr<int>)(uintptr_t)t->map.tile_start : t->itile_start;
+  return v;
+}
+
 // ------------------------------------------------------------------ packing
 constexpr int kPackThreads = 256;  // 4 waves, one 32x32 block each
 constexpr int kTPad = 33;          // LDS row stride (elements) of the transpose tile
 
-__device__ __forceinline__ int find_job(const i64* __restrict__ start, int njobs, i64 blk) {
+__device__ __forceinline__ int find_job(cptr<i64> start, int njobs, i64 blk) {
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -158,9 +204,11 @@ __device__ __forceinline__ void pack_offsets(const PackJob& jb, i64 rb, i64 kb, 
 // read 32 consecutive columns.  Left operands (ROW) are read with 32 lanes
 // along a row (coalesced) and transposed through a padded LDS tile.
 template <int KIND, int MODE>
-__global__ void __launch_bounds__(kPackThreads)
-    k_pack(const PackJob* __restrict__ jobs, const i64* __restrict__ block_start, int njobs) {
+__global__ void __launch_bounds__(kPackThreads) k_pack(PackTables) {
   using Md = Mode<MODE>;
+  const PackView tv = pack_view();
+  const cptr<i64> block_start = tv.bstart;
+  const int njobs = tv.njobs;
   __shared__ u64 tile[4][32 * kTPad];
   // the wave index is uniform across the wave: everything derived from the
   // block index (job, block coordinates, the interior test) stays scalar
@@ -168,7 +216,7 @@ __global__ void __launch_bounds__(kPackThreads)
   const i64 blk = (i64)blockIdx.x * 4 + wave;
   if (blk >= block_start[njobs]) return;  // whole wave leaves; only wave-level sync below
   const int ji = find_job(block_start, njobs, blk);
-  const PackJob& jb = jobs[ji];
+  const PackJob jb = tv.jobs[ji];
   const i64 local = blk - block_start[ji];
   // Traversal order: the waves of a workgroup take neighbouring blocks along
   // the operand's rows in memory, so that together they read contiguous runs
@@ -230,7 +278,7 @@ __global__ void __launch_bounds__(kPackThreads)
 // ------------------------------------------------------------------ GEMM
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int find_problem(const int* __restrict__ start, int nprob, int t) {
+__device__ __forceinline__ int find_problem(cptr<int> start, int nprob, int t) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -469,16 +517,15 @@ struct TilePos {
 };
 
 template <int BM, int BN, int PER_CU>
-__device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ probs, const TileMap& map,
-                                            const TileSched& sched) {
+__device__ __forceinline__ TilePos tile_pos(const GemmView& v) {
   const int b = blockIdx.x;
-  const int t = sched.xcd_remap ? remap_tile(b, gridDim.x, kXcdCUs * PER_CU) : b;
+  const int t = v.sched.xcd_remap ? remap_tile(b, gridDim.x, kXcdCUs * PER_CU) : b;
   TilePos q;
-  q.pi = find_problem(map.tile_start, map.nprob, t);
-  const LimbProblem& p = probs[q.pi];
-  const i64 local = t - map.tile_start[q.pi];
-  const i64 ntm = (p.M + BM - 1) / BM, ntn = (p.N + BN - 1) / BN;
-  const i64 gm = sched.group_m;  // 1..64, checked by the host
+  q.pi = find_problem(v.tile_start, v.nprob, t);
+  const i64 M = v.probs[q.pi].M, N = v.probs[q.pi].N;
+  const i64 local = t - v.tile_start[q.pi];
+  const i64 ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+  const i64 gm = v.sched.group_m;  // 1..64, checked by the host
   const i64 per_group = gm * ntn;
   const i64 first_m = (local / per_group) * gm;
   const i64 gsize = min(ntm - first_m, gm);
@@ -495,7 +542,7 @@ __device__ __forceinline__ TilePos tile_pos(const LimbProblem* __restrict__ prob
 // layout: lane l, register e holds row 4*(l/16) + e and column l%16 of the
 // 16x16 block.
 template <int HA, int HB, int BM, int BN>
-__device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], const LimbProblem& p, i64 tm, i64 tn, int wr,
+__device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], cptr<LimbProblem> pp, i64 tm, i64 tn, int wr,
                                            int wc, int lane) {
 #pragma unroll
   for (int s = 0; s < 8; ++s)
@@ -503,11 +550,11 @@ __device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], const LimbProb
     for (int x = 0; x < HA; ++x)
 #pragma unroll
       for (int y = 0; y < HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
-  const Epilogue& ep = p.ep;
+  const Epilogue ep = pp->ep;
 #pragma unroll
   for (int y = 0; y < HB; ++y) {
     const i64 n = tn * BN + wc * 16 * HB + y * 16 + (lane & 15);
-    const bool n_ok = n < p.N;
+    const bool n_ok = n < pp->N;
     const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
 #pragma unroll
     for (int x = 0; x < HA; ++x) {
@@ -517,7 +564,7 @@ __device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], const LimbProb
         u64 v = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
-        if (n_ok && m < p.M) {
+        if (n_ok && m < pp->M) {
           const i64 off = m * ep.view.ld_m + coff;
           if (ep.accumulate) v += ep.Out[off];
           if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
@@ -535,8 +582,7 @@ __device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], const LimbProb
 // between MFMAs.  The four waves of a workgroup read overlapping blocks at
 // about the same time, which the CU's L1 and the XCD's L2 serve.
 template <int SA, int SB>
-__global__ void __launch_bounds__(kThreads, 1)
-    k_limb_gemm(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
+__global__ void __launch_bounds__(kThreads, 1) k_limb_gemm(GemmTables) {
   using S = Shape<SA, SB>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -544,8 +590,9 @@ __global__ void __launch_bounds__(kThreads, 1)
   // derived from it) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const TilePos tp = tile_pos<S::BM, S::BN, 1>(probs, map, sched);
-  const LimbProblem& p = probs[tp.pi];
+  const GemmView tv = gemm_view();
+  const TilePos tp = tile_pos<S::BM, S::BN, 1>(tv);
+  const cptr<LimbProblem> pp = tv.probs + tp.pi;
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mb0 = tm * 2 * SA + wr * SA;  // this wave's first left 32-block
   const i64 nb0 = tn * 2 * SB + wc * SB;  // this wave's first right 32-block
@@ -554,14 +601,14 @@ __global__ void __launch_bounds__(kThreads, 1)
 
   // k runs in steps of two 32-blocks; every segment holds an even number of
   // blocks, so a step never straddles two segments
-  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int kbeg = pp->kb_begin, nsteps = (pp->kb_end - pp->kb_begin) >> 1;
   const int g = lane >> 4;
   const LaneOff lo{(unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16)};
-  const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mb0, nb0, SA, SB);
-  const SegSrc s1 = seg_src(p.PA1 ? p.PA1 : p.PA0, p.PB1 ? p.PB1 : p.PB0, p.kb1, mb0, nb0, SA, SB);
+  const SegSrc s0 = seg_src(pp->PA0, pp->PB0, pp->kb0, mb0, nb0, SA, SB);
+  const SegSrc s1 = seg_src(pp->PA1 ? pp->PA1 : pp->PA0, pp->PB1 ? pp->PB1 : pp->PB0, pp->kb1, mb0, nb0, SA, SB);
   v4i outer[S::HO][8], inner[S::HI][8], d0[S::HI][S::kDbl], d1[S::HI][S::kDbl];
   if (nsteps > 0) {
-    const StepOff o = step_off(s0, s1, p.kb0, kbeg);
+    const StepOff o = step_off(s0, s1, pp->kb0, kbeg);
     const __amdgpu_buffer_rsrc_t ro = S::kOuterA ? o.a : o.b, ri = S::kOuterA ? o.b : o.a;
 #pragma unroll
     for (int h = 0; h < S::HO; ++h)
@@ -582,7 +629,7 @@ __global__ void __launch_bounds__(kThreads, 1)
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
     using R = StepRegs<SA, SB>;
-    auto off = [&](int st) { return step_off(s0, s1, p.kb0, min(kbeg + 2 * st, klast)); };
+    auto off = [&](int st) { return step_off(s0, s1, pp->kb0, min(kbeg + 2 * st, klast)); };
     mfma_step<SA, SB, true>(R{acc, outer, inner, d0, d1}, off(0), off(1), lo);
     int st = 1;
     for (; st + 1 < nsteps; st += 2) {
@@ -598,7 +645,7 @@ __global__ void __launch_bounds__(kThreads, 1)
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  store_tile<S::HA, S::HB, S::BM, S::BN>(acc, p, tm, tn, wr, wc, lane);
+  store_tile<S::HA, S::HB, S::BM, S::BN>(acc, pp, tm, tn, wr, wc, lane);
 }
 
 
@@ -830,35 +877,36 @@ __device__ __forceinline__ void lds_step(LRegs<G> r, const LCtx& c, const LStep&
 
 template <int HA, int HB, int WR, int WC>
 __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ? 2 : 1)  // LGeo::kMinBlocks
-    k_limb_gemm_lds(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
+    k_limb_gemm_lds(GemmTables) {
   using G = LGeo<HA, HB, WR, WC>;
   __shared__ v4i stage[2][G::kBufBytes / 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / WC, wc = wave % WC;
-  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(probs, map, sched);
-  const LimbProblem& p = probs[tp.pi];
+  const GemmView tv = gemm_view();
+  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(tv);
+  const cptr<LimbProblem> pp = tv.probs + tp.pi;
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mw = tm * (G::BM / 32), nw = tn * (G::BN / 32);  // the workgroup's first left / right 32-block
   // the wave's first outer and inner 16-half inside the workgroup tile
   const int ho0 = (G::kOuterA ? wr : wc) * G::HO, hi0 = (G::kOuterA ? wc : wr) * G::HI;
 
   v4i acc[HA][HB][8];
-  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int kbeg = pp->kb_begin, nsteps = (pp->kb_end - pp->kb_begin) >> 1;
   const int g = lane >> 4;
   const unsigned lane_off = (unsigned)((g >> 1) * 8192 + (g & 1) * 512 + (lane & 15) * 16);
   // inner loads: the wave's descriptor starts at the strip of its first half;
   // a single inner half may be the second half of that strip
   const LaneOff lo{lane_off + (unsigned)((hi0 & 1) << 8)};
-  const uint8_t* PA1 = p.PA1 ? p.PA1 : p.PA0;
-  const uint8_t* PB1 = p.PB1 ? p.PB1 : p.PB0;
+  const uint8_t* PA1 = pp->PA1 ? pp->PA1 : pp->PA0;
+  const uint8_t* PB1 = pp->PB1 ? pp->PB1 : pp->PB0;
   constexpr int kInStrips = (G::HI + 1) / 2;
   const i64 mi = G::kOuterA ? mw : mw + (hi0 >> 1), ni = G::kOuterA ? nw + (hi0 >> 1) : nw;
-  const SegSrc s0 = seg_src(p.PA0, p.PB0, p.kb0, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
-  const SegSrc s1 = seg_src(PA1, PB1, p.kb1, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
-  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, G::BM / 32, G::BN / 32);
-  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, G::BM / 32, G::BN / 32);
+  const SegSrc s0 = seg_src(pp->PA0, pp->PB0, pp->kb0, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
+  const SegSrc s1 = seg_src(PA1, PB1, pp->kb1, mi, ni, G::kOuterA ? 1 : kInStrips, G::kOuterA ? kInStrips : 1);
+  const SegSrc w0 = seg_src(pp->PA0, pp->PB0, pp->kb0, mw, nw, G::BM / 32, G::BN / 32);
+  const SegSrc w1 = seg_src(PA1, PB1, pp->kb1, mw, nw, G::BM / 32, G::BN / 32);
   const int c0 = wave * G::kCopies;
   const LCtx c{(unsigned)((ho0 >> 1) << 14) + lane_off, (unsigned)lane * 16u, c0 >> 4, c0 & 15};
   lds_u8* b0 = (lds_u8*)&stage[0][0];
@@ -868,7 +916,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ?
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
     auto off = [&](int st) {
-      return lstep<G::kOuterA>(s0, s1, w0, w1, p.kb0, min(kbeg + 2 * st, klast));
+      return lstep<G::kOuterA>(s0, s1, w0, w1, pp->kb0, min(kbeg + 2 * st, klast));
     };
     // prologue: step 0's outer run into buffer 0, its inner planes into registers
     {
@@ -906,7 +954,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ?
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  store_tile<HA, HB, G::BM, G::BN>(acc, p, tm, tn, wr, wc, lane);
+  store_tile<HA, HB, G::BM, G::BN>(acc, pp, tm, tn, wr, wc, lane);
 }
 
 // ------------------------------------------------------------------ GEMM with both operands in LDS
@@ -1121,7 +1169,7 @@ __device__ __forceinline__ void sh_step(SRegs<G> r, const SCtx& c, lds_u8* lds, 
 
 template <int WR, int WC>
 __global__ void __launch_bounds__(64 * WR * WC, WR * WC == 4 ? 2 : 1)  // SGeo::kMinBlocks
-    k_limb_gemm_sh(const LimbProblem* __restrict__ probs, TileMap map, TileSched sched) {
+    k_limb_gemm_sh(GemmTables) {
   using G = SGeo<WR, WC>;
   __shared__ v4i lds_words[G::kBytes / 16];
   lds_u8* lds = (lds_u8*)&lds_words[0];
@@ -1129,28 +1177,29 @@ __global__ void __launch_bounds__(64 * WR * WC, WR * WC == 4 ? 2 : 1)  // SGeo::
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / WC, wc = wave % WC;
-  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(probs, map, sched);
-  const LimbProblem& p = probs[tp.pi];
+  const GemmView tv = gemm_view();
+  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(tv);
+  const cptr<LimbProblem> pp = tv.probs + tp.pi;
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mw = tm * WR, nw = tn * WC;  // the workgroup's first left / right 32-block
   const int xo = G::kOuterA ? wr : wc, xi = G::kOuterA ? wc : wr;  // the wave's outer / inner strip
 
   v4i acc[2][2][8];
-  const int kbeg = p.kb_begin, nsteps = (p.kb_end - p.kb_begin) >> 1;
+  const int kbeg = pp->kb_begin, nsteps = (pp->kb_end - pp->kb_begin) >> 1;
   const int g = lane >> 4;
   const unsigned lane_lds = (unsigned)((g >> 1) * 1024 + (g & 1) * 512 + (lane & 15) * 16);
   const SCtx c{(unsigned)(xo * 2048) + lane_lds, (unsigned)(G::kIBase + xi * 2048) + lane_lds,
                (unsigned)lane * 16u, wave};
-  const uint8_t* PA1 = p.PA1 ? p.PA1 : p.PA0;
-  const uint8_t* PB1 = p.PB1 ? p.PB1 : p.PB0;
-  const SegSrc w0 = seg_src(p.PA0, p.PB0, p.kb0, mw, nw, WR, WC);
-  const SegSrc w1 = seg_src(PA1, PB1, p.kb1, mw, nw, WR, WC);
+  const uint8_t* PA1 = pp->PA1 ? pp->PA1 : pp->PA0;
+  const uint8_t* PB1 = pp->PB1 ? pp->PB1 : pp->PB0;
+  const SegSrc w0 = seg_src(pp->PA0, pp->PB0, pp->kb0, mw, nw, WR, WC);
+  const SegSrc w1 = seg_src(PA1, PB1, pp->kb1, mw, nw, WR, WC);
 
   v4i z[2], ob[2][2], inner[2][8], d0[2][3], d1[2][3];
   const int klast = kbeg + 2 * (nsteps - 1);
   if (nsteps > 0) {
     // steps past the last re-read the last step's blocks (valid memory, unused)
-    auto off = [&](int t) { return sstep(w0, w1, p.kb0, min(kbeg + 2 * max(t, 0), klast)); };
+    auto off = [&](int t) { return sstep(w0, w1, pp->kb0, min(kbeg + 2 * max(t, 0), klast)); };
     // prologue: step 0's outer limb 0 and inner limbs straight into registers
     // (global fragment offsets: k-block g/2 of the step is 8 KiB further);
     // then the copies a B1 barrier of step -1 would have issued
@@ -1188,7 +1237,7 @@ __global__ void __launch_bounds__(64 * WR * WC, WR * WC == 4 ? 2 : 1)  // SGeo::
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
-  store_tile<2, 2, G::BM, G::BN>(acc, p, tm, tn, wr, wc, lane);
+  store_tile<2, 2, G::BM, G::BN>(acc, pp, tm, tn, wr, wc, lane);
 }
 
 }  // namespace
@@ -1215,13 +1264,12 @@ int limb_variant_sb(int variant) {
              : 1;
 }
 
-hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
-                       i64 total_blocks, int kind, int mode) {
+hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int kind, int mode) {
   if (total_blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)((total_blocks + 3) / 4)), block(kPackThreads);
 #define MPC_PACK_CASE(K, MO)                                                            \
   if (kind == K && mode == MO) {                                                         \
-    hipLaunchKernelGGL((k_pack<K, MO>), grid, block, 0, s, jobs, block_start, njobs);   \
+    hipLaunchKernelGGL((k_pack<K, MO>), grid, block, 0, s, t);                          \
     return hipGetLastError();                                                            \
   }
   MPC_PACK_CASE(kPackRow, kModeCopy)
@@ -1239,23 +1287,23 @@ hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_star
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
-                            TileSched sched) {
+hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles) {
   if (total_tiles <= 0) return hipSuccess;
+  const TileSched& sched = t.sched;
   if (sched.group_m < 1 || sched.group_m > 64) return hipErrorInvalidValue;
   const dim3 grid(total_tiles);
 #define MPC_LDS_CASE(V, HA, HB, WR, WC)                                                                    \
   case V:                                                                                                 \
-    hipLaunchKernelGGL((k_limb_gemm_lds<HA, HB, WR, WC>), grid, dim3(64 * WR * WC), 0, s, probs, map, sched); \
+    hipLaunchKernelGGL((k_limb_gemm_lds<HA, HB, WR, WC>), grid, dim3(64 * WR * WC), 0, s, t); \
     break;
 #define MPC_SH_CASE(V, WR, WC)                                                                        \
   case V:                                                                                         \
-    hipLaunchKernelGGL((k_limb_gemm_sh<WR, WC>), grid, dim3(64 * WR * WC), 0, s, probs, map, sched); \
+    hipLaunchKernelGGL((k_limb_gemm_sh<WR, WC>), grid, dim3(64 * WR * WC), 0, s, t); \
     break;
   switch (sched.variant) {
-    case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
-    case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
-    case kLimb64x64: hipLaunchKernelGGL((k_limb_gemm<1, 1>), grid, dim3(kThreads), 0, s, probs, map, sched); break;
+    case kLimb128x64: hipLaunchKernelGGL((k_limb_gemm<2, 1>), grid, dim3(kThreads), 0, s, t); break;
+    case kLimb64x128: hipLaunchKernelGGL((k_limb_gemm<1, 2>), grid, dim3(kThreads), 0, s, t); break;
+    case kLimb64x64: hipLaunchKernelGGL((k_limb_gemm<1, 1>), grid, dim3(kThreads), 0, s, t); break;
     MPC_LDS_CASE(kLimbLds128x64, 4, 2, 2, 2)
     MPC_LDS_CASE(kLimbLds64x128, 2, 4, 2, 2)
     MPC_LDS_CASE(kLimbLds64x64, 2, 2, 2, 2)

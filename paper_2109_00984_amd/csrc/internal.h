@@ -258,10 +258,23 @@ hipError_t launch_splitk_reduce_grouped(hipStream_t s, const ReduceJob* jobs, co
                                         i64 total_chunks);
 
 // Limb form (gemm_limb.hip).
-// jobs and block_start (njobs+1 prefix sums of rreal*kblocks) are device
-// arrays; every job of one launch has the given kind and mode.
-hipError_t launch_pack(hipStream_t s, const PackJob* jobs, const i64* block_start, int njobs,
-                       i64 total_blocks, int kind, int mode);
+// The descriptor tables of one pack or GEMM launch travel either as device
+// arrays (uploaded by the host) or, when they are short, inside the kernel's
+// arguments: then no upload (no copy on the stream, no host staging) precedes
+// the launch.  The kernels read whichever the host filled through the
+// kernel-argument segment, as constant memory.
+constexpr int kInlineJobs = 4, kInlineProbs = 4;
+// Jobs of one pack launch: `jobs`/`block_start` (device; njobs+1 prefix sums
+// of rreal*kblocks), or when `jobs` is null the first njobs entries of
+// ijobs/ibstart.  Every job of one launch has the launch's kind and mode.
+struct PackTables {
+  const PackJob* jobs;
+  const i64* block_start;
+  int njobs;
+  PackJob ijobs[kInlineJobs];
+  i64 ibstart[kInlineJobs + 1];
+};
+hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int kind, int mode);
 // Tile shapes of the limb GEMM (workgroup output tile) and the tile order.
 // Variants 3..8 stage the outer operand through LDS (k_limb_gemm_lds); 6, 7
 // and 8 run eight waves per workgroup (two per SIMD): 6 and 7 with 16x64 and
@@ -357,8 +370,16 @@ hipError_t launch_fp64_pack_right(hipStream_t s, i64 N, i64 K0, i64 K1, const u6
 // X: L x M x N row-major diagonal sums -> epilogue
 hipError_t launch_fp64_combine(hipStream_t s, i64 M, i64 N, int L, const double* X, const Epilogue& ep);
 
-hipError_t launch_limb_gemm(hipStream_t s, const LimbProblem* probs, TileMap map, int total_tiles,
-                            TileSched sched);
+// Problems of one GEMM launch: `probs` with `map.tile_start` (device), or when
+// `probs` is null the first map.nprob entries of iprobs/itile_start.
+struct GemmTables {
+  const LimbProblem* probs;
+  TileMap map;
+  TileSched sched;
+  LimbProblem iprobs[kInlineProbs];
+  int itile_start[kInlineProbs + 1];
+};
+hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles);
 int limb_tiles(i64 M, i64 N, int variant);
 int limb_variant_sa(int variant);
 int limb_variant_sb(int variant);

@@ -597,6 +597,7 @@ def test_default_tile_config_roundtrip(m):
     assert c.default_tile_config() == {"variant": "lds64x64", "variant_id": 5, "group_m": 8, "xcd_remap": True}
     c.set_default_tile_config(1, 4, False)
     assert c.default_tile_config() == {"variant": "64x128", "variant_id": 1, "group_m": 4, "xcd_remap": False}
-    with pytest.raises(m.MPCError):
-        c.set_default_tile_config(9, 8, True)
+    for bad in (len(m.TILE_VARIANTS), -1):
+        with pytest.raises(m.MPCError):
+            c.set_default_tile_config(bad, 8, True)
     c.close()
