@@ -192,6 +192,26 @@ mpc_status mpc_beaver_matmul(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, cons
                              const mpc_triple *t, int trunc_bits, mpc_form form, uint64_t *z0,
                              uint64_t *z1);
 
+/* mpc_beaver_matmul for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product, bit for bit, with no hipMalloc, hipFree or host pinned
+ * allocation in the call.  Its workspace is one 64 MiB array per device,
+ * part of the library's code object (resident from the first context on that
+ * device until the process ends), that every such call on that device shares:
+ * calls that overlap in time on one device (any context, any stream) race and
+ * must be ordered by the caller.  The packed operands must fit it:
+ * 24*(M*K + K*N) bytes up to padding (e.g. M = N = K = 1024), else
+ * MPC_E_SHAPE.  form: MPC_FORM_LIMB8, or MPC_FORM_AUTO, which also takes the
+ * one-launch plain product for products of at most 2^18 multiply-accumulates
+ * (no workspace); other forms return MPC_E_UNSUPPORTED.  The limb GEMM runs
+ * without split-K and its descriptor tables travel in the kernel arguments.
+ * MPC_E_HIP if the array's address could not be found when the context was
+ * created.  GEMM launches of this call are not timed by mpc_profile_*. */
+mpc_status mpc_beaver_matmul_noalloc(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const uint64_t *x0,
+                                     const uint64_t *x1, const uint64_t *y0, const uint64_t *y1,
+                                     const mpc_triple *t, int trunc_bits, mpc_form form, uint64_t *z0,
+                                     uint64_t *z1);
+
 /* Convolution of a shared activation x [B][Cin][L] with a shared weight
  * w [Cout][Cin][k] (valid padding) with a CONV1D triple, lowered onto the ring
  * GEMM (weights as the left operand, im2col of the activation as the right):

@@ -96,6 +96,8 @@ _SIGS = {
     "mpc_beaver_mul": (INT, [VP, SZ, VP, VP, VP, VP, ctypes.POINTER(Triple), INT, VP, VP]),
     "mpc_beaver_matmul": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), INT,
                                 INT, VP, VP]),
+    "mpc_beaver_matmul_noalloc": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), INT,
+                                        INT, VP, VP]),
     "mpc_beaver_conv1d": (INT, [VP, ctypes.POINTER(Conv1dShape), VP, VP, VP, VP,
                                 ctypes.POINTER(Triple), INT, INT, VP, VP]),
     "mpc_ring_gemm": (INT, [VP, I64, I64, I64, VP, VP, VP, INT]),
@@ -610,6 +612,25 @@ class Context:
         _check(_lib.mpc_beaver_matmul(self._h, M, N, K, _ptr(x.s0), _ptr(x.s1), _ptr(y.s0),
                                       _ptr(y.s1), ctypes.byref(st), trunc_bits, FORMS[form],
                                       _ptr(z.s0), _ptr(z.s1)), "mpc_beaver_matmul")
+        return z
+
+    def beaver_matmul_noalloc(self, x, y, t, trunc_bits=0, form="auto", out=None):
+        """beaver_matmul through the entry point that allocates nothing (its
+        workspace is the library's static per-device array); `out` should be
+        given by callers that must not allocate either."""
+        M, K = x.s0.shape
+        K2, N = y.s0.shape
+        if K != K2:
+            raise ValueError("inner dimensions differ")
+        z = out if out is not None else SharedPair(self.empty((M, N)), self.empty((M, N)))
+        self._check_t(x.s0, x.s1, n=M * K)
+        self._check_t(y.s0, y.s1, n=K * N)
+        self._check_t(z.s0, z.s1, n=M * N)
+        self._check_triple(t, M * K, K * N, M * N)
+        st = t.struct()
+        _check(_lib.mpc_beaver_matmul_noalloc(self._h, M, N, K, _ptr(x.s0), _ptr(x.s1), _ptr(y.s0),
+                                              _ptr(y.s1), ctypes.byref(st), trunc_bits, FORMS[form],
+                                              _ptr(z.s0), _ptr(z.s1)), "mpc_beaver_matmul_noalloc")
         return z
 
     def beaver_conv1d(self, x, w, t, stride, trunc_bits=0, form="auto", out=None):

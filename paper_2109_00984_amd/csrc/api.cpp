@@ -13,6 +13,7 @@
 #include <new>
 #include <vector>
 #include <atomic>
+#include <mutex>
 
 #include "internal.h"
 #include "mpc.h"
@@ -52,6 +53,35 @@ struct UploadSlot {
   bool pending = false;
 };
 constexpr int kSlots = 16;
+
+// Workspace of mpc_beaver_matmul_noalloc, for callers that cannot allocate:
+// one array per device that loads the library, held until the process ends.
+// In host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, looked up once per device (with that device current)
+// when the first context on it is created.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];
+
+// The device address of `scratch` on the current device `device`, or null
+// (with the HIP error recorded) if it cannot be found.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      g_last_hip_error.store((int)e);
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
 
 }  // namespace
 
@@ -94,6 +124,8 @@ struct mpc_ctx {
   // instantiated graphs not yet destroyed: they hold workspace addresses, so
   // no buffer may move while any exists
   int live_graphs = 0;
+  // this device's no-alloc workspace (`scratch`), or null if not found
+  uint8_t* scratch = nullptr;
 };
 // An instantiated graph, the context whose buffers it references and the
 // descriptor buffers its kernels read.
@@ -662,9 +694,12 @@ struct LimbReq {
 // whose concatenated K exceeds the int32-safe range continues in the next
 // launch, adding into its output; truncation is applied by its last chunk).
 // Descriptor tables go inside the kernels' arguments when every launch's are
-// short (no upload), else in one upload for the call.
+// short (no upload), else in one upload for the call.  no_alloc: the caller
+// cannot allocate, so no split-K (its partials and reduction table would need
+// memory) and the tables must go inline; nothing is timed (timing events may
+// be created on first use).
 mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std::vector<LimbReq>& reqs,
-                      TileSched sched) {
+                      TileSched sched, bool no_alloc = false) {
   // every entry point checks this before it issues any work
   for (const LimbReq& r : reqs)
     if (r.K0 > kLimbMaxSegK || r.K1 > kLimbMaxSegK) return MPC_E_UNSUPPORTED;
@@ -711,7 +746,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     tiles_all += limb_tiles(reqs[q].M, reqs[q].N, sched.variant);
   }
   size_t part_bytes = 0;
-  if (tiles_all > 0 && tiles_all < c->num_cu) {
+  if (!no_alloc && tiles_all > 0 && tiles_all < c->num_cu) {
     const i64 want = (2 * (i64)c->num_cu + tiles_all - 1) / tiles_all;
     for (size_t q = 0; q < nreq; ++q) {
       const i64 steps = (limb_kblocks(reqs[q].K0) + limb_kblocks(reqs[q].K1)) / 2;
@@ -790,6 +825,9 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     if (first_job[L + 1] - first_job[L] > (size_t)kInlineJobs) inl = false;
   for (int L = 0; L < nlaunch; ++L)
     if (pieces[L].size() > (size_t)kInlineProbs) inl = false;
+  // with split-K off, a no-alloc call has one job per operand side and two
+  // problems per launch
+  if (no_alloc && !inl) return MPC_E_UNSUPPORTED;
   Blob blob;
   std::vector<size_t> obstart(launch_km.size()), oprob(nlaunch), otile(nlaunch);
   size_t ojobs = 0;
@@ -832,6 +870,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       t.map.tile_start = (const int*)(dev + otile[L]);
     }
     LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[L]);
+    if (no_alloc) tm.on = false;
     CHK(tm.start());
     CHK(hip_status(launch_limb_gemm(st, t, tstarts[L].back())));
     CHK(tm.stop());
@@ -954,6 +993,9 @@ mpc_status mpc_ctx_create(int device, void* stream0, void* stream1, uint64_t see
     e = hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming);
     if (e != hipSuccess) return fail(e);
   }
+  // the device is current: find its no-alloc workspace (a failure only
+  // disables mpc_beaver_matmul_noalloc)
+  c->scratch = (uint8_t*)scratch_address(device);
   *out = c;
   return MPC_OK;
 }
@@ -1420,6 +1462,41 @@ mpc_status mpc_beaver_matmul(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const 
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
   CHK(run_matmuls(c, {m}, trunc_bits, form));
+  return end_call(c);
+}
+
+mpc_status mpc_beaver_matmul_noalloc(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint64_t* x0,
+                                     const uint64_t* x1, const uint64_t* y0, const uint64_t* y1,
+                                     const mpc_triple* t, int trunc_bits, mpc_form form, uint64_t* z0,
+                                     uint64_t* z1) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  CHK(check_form(form));
+  if (form != MPC_FORM_LIMB8 && form != MPC_FORM_AUTO) return MPC_E_UNSUPPORTED;
+  MatmulPlan m{M, N, K, x0, x1, y0, y1, *t, z0, z1};
+  CHK(validate_matmul(m));
+  CHK(check_limb_k(MPC_FORM_LIMB8, K));
+  if (matmul_ws(m, MPC_FORM_LIMB8) > kNoAllocBytes) return MPC_E_SHAPE;
+  if (M == 0 || N == 0) return MPC_OK;
+  if (!c->scratch) return MPC_E_HIP;
+  CHK(set_device(c));
+  if (form == MPC_FORM_AUTO && resolve_form(form, M, N, 2 * K, K) == MPC_FORM_PLAIN && K <= kSmallMatmulK &&
+      M * N <= kSmallMatmulMacs && M * N * K <= kSmallMatmulMacs) {
+    // a small product: open and finish in one launch, no workspace at all
+    const SmallMatmul s{M, N, K, x0, x1, y0, y1, t->a0, t->a1, t->b0, t->b1, t->c0, t->c1, z0, z1, trunc_bits};
+    CHK(hip_status(launch_beaver_matmul_small(c->s[0], s)));
+    c->stats.launches++;
+  } else {
+    // the limb form over `scratch`: descriptor tables inline, no split-K
+    Carve cv(c->scratch);
+    std::vector<PackJob> jobs;
+    std::vector<LimbReq> reqs;
+    matmul_limb(m, cv, trunc_bits, jobs, reqs);
+    CHK(issue_limb(c, jobs, reqs, sched_for(c, {{M, N, K}}), true));
+  }
+  c->stats.opens++;
+  c->stats.open_bytes_per_party += 8 * (uint64_t)(M * K + K * N);
+  if (trunc_bits) c->stats.truncations++;
   return end_call(c);
 }
 
