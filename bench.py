@@ -150,6 +150,10 @@ def main():
             # the fused Beaver product against its own access pattern with trivial arithmetic
             extras["beaver_mul_frac_of_stream_ceiling"] = round(
                 extras["beaver_mul_hbm_GBps_algorithmic"] / extras["ceiling_hbm_stream_10r2w_GBps"], 4)
+        if "ceiling_hbm_stream_10r2w_2e28_GBps" in extras and "beaver_mul_sweep" in extras:
+            # the largest sweep point against the same pattern at the same size
+            extras["beaver_mul_2e28_frac_of_stream_ceiling"] = round(
+                extras["beaver_mul_sweep"]["2^28"]["GBps"] / extras["ceiling_hbm_stream_10r2w_2e28_GBps"], 4)
         if "ceiling_valu_ring_TMACs" in extras and "ring_gemm_4096_plain_ms" in extras:
             extras["plain_gemm_frac_of_valu_ceiling"] = round(
                 M * N * K / (extras["ring_gemm_4096_plain_ms"] * 1e-3) / 1e12 / extras["ceiling_valu_ring_TMACs"], 4)
@@ -284,10 +288,12 @@ def ceilings():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120, check=True)
     c = json.loads(r.stdout.strip().splitlines()[-1])
     log(f"bench: ceilings: INT8 MFMA on random data {c['mfma_i8_random_tops']} TOP/s, "
-        f"VALU ring MAC {c['valu_ring_tmacs']} T/s, HBM stream (10 in, 2 out) {c['hbm_stream_10r2w_gbs']} GB/s, "
-        f"HBM copy {c['hbm_copy_gbs']} GB/s")
+        f"VALU ring MAC {c['valu_ring_tmacs']} T/s, HBM stream (10 in, 2 out) {c['hbm_stream_10r2w_gbs']} GB/s "
+        f"at 2^24 and {c['hbm_stream_10r2w_2e28_gbs']} GB/s at 2^28 elements, HBM copy {c['hbm_copy_gbs']} GB/s")
     return {"ceiling_mfma_i8_random_TOPs": c["mfma_i8_random_tops"], "ceiling_valu_ring_TMACs": c["valu_ring_tmacs"],
-            "ceiling_hbm_stream_10r2w_GBps": c["hbm_stream_10r2w_gbs"], "ceiling_hbm_copy_GBps": c["hbm_copy_gbs"]}
+            "ceiling_hbm_stream_10r2w_GBps": c["hbm_stream_10r2w_gbs"],
+            "ceiling_hbm_stream_10r2w_2e28_GBps": c["hbm_stream_10r2w_2e28_gbs"],
+            "ceiling_hbm_copy_GBps": c["hbm_copy_gbs"]}
 
 
 def small_latency(mpc, torch, workloads):
@@ -310,21 +316,48 @@ def small_latency(mpc, torch, workloads):
         ez = mpc.SharedPair(c.empty((4096,)), c.empty((4096,)))
         calls = {"matmul_64x128x32_plain": lambda: c.beaver_matmul(x, w, t, FRAC, "plain", out=z),
                  "matmul_64x128x32_limb8": lambda: c.beaver_matmul(x, w, t, FRAC, "limb8", out=z),
+                 "matmul_64x128x32_auto": lambda: c.beaver_matmul(x, w, t, FRAC, "auto", out=z),
                  "mul_4096": lambda: c.beaver_mul(ex_, ey, te, FRAC, out=ez)}
+        # what AUTO runs for this product: the launches one call adds, and
+        # whether any of them is a limb GEMM
+        c.sync()
+        c.profile(True)
+        c.profile_read()
+        before = c.stats()["launches"]
+        calls["matmul_64x128x32_auto"]()
+        c.sync()
+        launches = c.stats()["launches"] - before
+        limb = c.profile_read()["limb8"]["launches"]
+        c.profile(False)
+        out["small_matmul_64x128x32_auto_path"] = (
+            "limb8" if limb else "plain, one fused launch" if launches == 1 else f"plain, {launches} launches")
+        reps = 50
         for name, fn in calls.items():
             fn()
             c.sync()
-            eager = _event_time(torch, side, fn, 50)
+            eager = _event_time(torch, side, fn, reps)
+            # one call per graph: every replay pays the runtime's graph launch
             c.graph_begin()
             fn()
             g = c.graph_end()
             c.graph_launch(g)
             c.sync()
-            graph = _event_time(torch, side, lambda: c.graph_launch(g), 50)
+            graph = _event_time(torch, side, lambda: c.graph_launch(g), reps)
+            mpc.Context.graph_destroy(g)
+            # a loop of `reps` calls captured once: what a serving loop replays
+            c.graph_begin()
+            for _ in range(reps):
+                fn()
+            g = c.graph_end()
+            c.graph_launch(g)
+            c.sync()
+            loop = _event_time(torch, side, lambda: c.graph_launch(g), 5) / reps
             mpc.Context.graph_destroy(g)
             out[f"small_{name}_us"] = round(eager * 1e3, 2)
             out[f"small_{name}_graph_us"] = round(graph * 1e3, 2)
-            log(f"bench: small {name}: {eager * 1e3:.1f} us eager, {graph * 1e3:.1f} us graph")
+            out[f"small_{name}_graph_loop_us"] = round(loop * 1e3, 2)
+            log(f"bench: small {name}: {eager * 1e3:.1f} us eager, {graph * 1e3:.1f} us one-call graph, "
+                f"{loop * 1e3:.1f} us per call in a captured loop of {reps}")
         c.close()
     return out
 
@@ -466,11 +499,11 @@ def grouped_bench(mpc, torch, workloads):
         outs = [mpc.SharedPair(c.empty((m, n)), c.empty((m, n))) for (m, n, k) in shapes]
         macs = float(sum(m * n * k for m, n, k in shapes))
 
-        def timed(label):
-            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)  # sizes the workspace
+        def timed(label, form="limb8"):
+            c.beaver_matmul_grouped(probs, FRAC, form, outs=outs)  # sizes the workspace
             c.sync()
             c.graph_begin()
-            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)
+            c.beaver_matmul_grouped(probs, FRAC, form, outs=outs)
             g = c.graph_end()
             c.graph_launch(g)
             c.sync()
@@ -479,14 +512,19 @@ def grouped_bench(mpc, torch, workloads):
             out[f"grouped256_{label}_ms"] = round(ms, 4)
             out[f"grouped256_{label}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
             # int8 work of the finish GEMMs (2 parties x M x N x 2K ring MACs, 72 int8 ops each)
-            out[f"grouped256_{label}_int8_frac"] = round(72.0 * 4.0 * macs / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)
+            if form == "limb8":
+                out[f"grouped256_{label}_int8_frac"] = round(72.0 * 4.0 * macs / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)
             log(f"bench: grouped 256 ({label}) graph replay {ms:.3f} ms")
 
+        timed("plain", "plain")
         timed("default_schedule")
         best = c.autotune_matmul(shapes)
         out["grouped256_tuned_schedule"] = best
         timed("autotuned")
         out["grouped256_plaintext_macs"] = macs
+        out["grouped256_limb_over_plain_speedup"] = round(out["grouped256_plain_ms"] / out["grouped256_autotuned_ms"], 2)
+        out["grouped256_autotuned_over_default"] = round(
+            out["grouped256_default_schedule_ms"] / out["grouped256_autotuned_ms"], 3)
         c.close()
     return out
 

@@ -293,7 +293,10 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
  * or 64x16 outputs; 8: 64x128 with eight waves of 32x32 outputs; 9, 10, 11:
  * 64x64 (two workgroups per compute unit), 64x128 and 128x64 (eight waves)
  * with both operands copied once per workgroup into LDS and every wave
- * owning 32x32 outputs), the number of tile
+ * owning 32x32 outputs; 12: 32x128 and 13: 128x32 thin tiles in the LDS
+ * form, four waves of 32x32 outputs in a row or a column, two workgroups per
+ * compute unit; 14: every product in its own tile class, 64x64, 32x128 or
+ * 128x32, in one launch), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
  * runs together share operand blocks in its L2) instead of one by one.
@@ -304,14 +307,29 @@ typedef struct {
   double ms; /* measured time of the tuned launch(es), filled by the tuner */
 } mpc_tile_config;
 
-/* Times every tile schedule on the exact GEMM problem list that a Beaver
- * matmul (count = 1) or a grouped call of these `count` shapes issues in the
- * limb form (dims: HOST array of M, N, K per problem), on random operands,
- * and remembers the fastest for later calls with the same shapes.  Uses the
- * context's workspace and party 0's stream; synchronises it.  `best` may be
- * NULL. */
+/* Tile classes: a limb-form Beaver matmul (single or grouped) gives each
+ * product a class by its shape: "thin in M" (at most 32 rows) or "thin in N"
+ * (at most 32 columns) when the 32x128 or 128x32 tile leaves at most nine
+ * tenths of the 64x64 tile's padded work, else "regular"; a grouped call
+ * issues one GEMM launch per schedule in use.  Untuned, every product takes
+ * the default schedule, unless some product is thin and no default was set
+ * with mpc_set_default_tile_config: then all of them run in one launch of
+ * schedule 14, each in its own class (with the default's group_m and
+ * remap).
+ *
+ * mpc_autotune_matmul times every tile schedule, class by class, on the
+ * exact GEMM problems that a Beaver matmul (count = 1) or a grouped call of
+ * these `count` shapes issues in the limb form (dims: HOST array of M, N, K
+ * per problem), on random operands, and remembers each class's fastest for
+ * later calls with the same shapes, unless all classes together in one launch
+ * of schedule 14 are faster than the classes' separate launches.  `best` (may be NULL) receives the
+ * schedule of the class that takes longest and, in `ms`, the summed time of
+ * all classes.  Uses the context's workspace and party 0's stream;
+ * synchronises it. */
 mpc_status mpc_autotune_matmul(mpc_ctx *ctx, size_t count, const int64_t *dims, mpc_tile_config *best);
-/* Writes / reads the tuned schedules (a text file, one entry per line). */
+/* Writes / reads the tuned schedules (a text file, one line per shape list:
+ * its hash, then variant, group_m and remap of the regular, thin-in-M and
+ * thin-in-N classes). */
 mpc_status mpc_autotune_save(const mpc_ctx *ctx, const char *path);
 mpc_status mpc_autotune_load(mpc_ctx *ctx, const char *path);
 /* Schedule used when no tuned entry matches (default: shape 5, the 64x64

@@ -54,6 +54,16 @@ struct UploadSlot {
 };
 constexpr int kSlots = 16;
 
+// Tile classes of a limb-form matrix product (the buckets the autotuner
+// tunes separately): products of at most 32 rows or columns take the thin
+// 32x128 or 128x32 tile when it leaves at most nine tenths of the 64x64
+// tile's padded work (the thin tiles keep every wave at 32x32 outputs but
+// share one operand among fewer waves).
+enum { kBucketRegular = 0, kBucketThinM = 1, kBucketThinN = 2, kBuckets = 3 };
+struct BucketScheds {
+  TileSched s[kBuckets];
+};
+
 // Workspace of mpc_beaver_matmul_noalloc, for callers that cannot allocate:
 // one array per device that loads the library, held until the process ends.
 // In host code `scratch` only names the symbol; its device address comes from
@@ -112,10 +122,12 @@ struct mpc_ctx {
   bool profiling = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
-  // limb GEMM tile schedule used when no tuned entry matches, and the tuned
-  // schedules keyed by the hash of a matmul shape list
+  // limb GEMM tile schedule used when no tuned entry matches (for the regular
+  // class; thin products take the thin tiles unless a default was set), and
+  // the tuned schedules per class keyed by the hash of a matmul shape list
   TileSched sched_default{kLimbLds64x64, 8, 1};
-  std::map<uint64_t, TileSched> tuned;
+  bool class_tiles = true;
+  std::map<uint64_t, BucketScheds> tuned;
   // vendor BLAS handle of the fp64 limb form (created on first use)
   rocblas_handle blas = nullptr;
   // partial sums of split-K plain GEMMs (grown on demand)
@@ -688,6 +700,9 @@ struct LimbReq {
   i64 M, N, K0, K1;
   const uint8_t *PA0, *PA1, *PB0, *PB1;
   Epilogue ep;
+  bool own_sched;   // use `sched` instead of the call's schedule
+  TileSched sched;
+  int cls;          // tile class under the classes variant
 };
 
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
@@ -739,11 +754,17 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   // its raw sum to a partial buffer; a reduction adds them and applies the
   // epilogue (split-K).
   std::vector<int> nchunks(nreq), nslices(nreq, 1);
+  auto sched_of = [&](size_t q) { return reqs[q].own_sched ? reqs[q].sched : sched; };
+  auto tiles_of = [&](size_t q) {
+    const TileSched t = sched_of(q);
+    return t.variant == kLimbClasses ? limb_class_tiles(reqs[q].M, reqs[q].N, reqs[q].cls)
+                                     : limb_tiles(reqs[q].M, reqs[q].N, t.variant);
+  };
   i64 tiles_all = 0;
   for (size_t q = 0; q < nreq; ++q) {
     const int kbt = (int)(limb_kblocks(reqs[q].K0) + limb_kblocks(reqs[q].K1));
     nchunks[q] = std::max(1, (kbt + kLimbMaxKBlocks - 1) / kLimbMaxKBlocks);
-    tiles_all += limb_tiles(reqs[q].M, reqs[q].N, sched.variant);
+    tiles_all += tiles_of(q);
   }
   size_t part_bytes = 0;
   if (!no_alloc && tiles_all > 0 && tiles_all < c->num_cu) {
@@ -761,13 +782,25 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       std::fill(nslices.begin(), nslices.end(), 1);
     }
   }
-  // piece lists per launch
-  int nlaunch = 1;
-  for (size_t q = 0; q < nreq; ++q)
-    if (nslices[q] == 1) nlaunch = std::max(nlaunch, nchunks[q]);
-  std::vector<std::vector<LimbProblem>> pieces(nlaunch);
-  std::vector<std::vector<int>> tstarts(nlaunch, std::vector<int>(1, 0));
-  std::vector<double> cmacs(nlaunch, 0.0);
+  // GEMM launches: one per (K chunk, tile schedule), every launch of chunk ch
+  // issued before any of chunk ch + 1 (which adds into chunk ch's outputs);
+  // split-K slices all belong to chunk 0
+  struct Launch {
+    int chunk;
+    TileSched sched;
+    std::vector<LimbProblem> pieces;
+    std::vector<int> tstarts{0};
+    double macs = 0.0;
+  };
+  std::vector<Launch> launches;
+  auto launch_of = [&](int chunk, const TileSched& ts) -> Launch& {
+    for (Launch& l : launches)
+      if (l.chunk == chunk && l.sched.variant == ts.variant && l.sched.group_m == ts.group_m &&
+          l.sched.xcd_remap == ts.xcd_remap)
+        return l;
+    launches.push_back(Launch{chunk, ts, {}, {0}, 0.0});
+    return launches.back();
+  };
   std::vector<ReduceJob> reduces;
   size_t part_off = 0;
   for (size_t q = 0; q < nreq; ++q) {
@@ -776,7 +809,8 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     auto true_k = [&](i64 kb) {
       return kb <= kb0 ? std::min<i64>(kb * 32, r.K0) : r.K0 + std::min<i64>((kb - kb0) * 32, r.K1);
     };
-    auto piece = [&](int launch, int kb_begin, int kb_end, const Epilogue& ep) -> mpc_status {
+    const TileSched ts = sched_of(q);
+    auto piece = [&](int chunk, int kb_begin, int kb_end, const Epilogue& ep) -> mpc_status {
       LimbProblem p{};
       p.M = r.M;
       p.N = r.N;
@@ -793,9 +827,11 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       p.mblocks = limb_rblocks(r.M);
       p.nblocks = limb_rblocks(r.N);
       p.ep = ep;
-      pieces[launch].push_back(p);
-      tstarts[launch].push_back(tstarts[launch].back() + limb_tiles(r.M, r.N, sched.variant));
-      cmacs[launch] += (double)r.M * (double)r.N * (double)(true_k(kb_end) - true_k(kb_begin));
+      p.cls = r.cls;
+      Launch& l = launch_of(chunk, ts);
+      l.pieces.push_back(p);
+      l.tstarts.push_back(l.tstarts.back() + tiles_of(q));
+      l.macs += (double)r.M * (double)r.N * (double)(true_k(kb_end) - true_k(kb_begin));
       return MPC_OK;
     };
     if (nslices[q] > 1) {
@@ -820,11 +856,14 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
       }
     }
   }
+  std::stable_sort(launches.begin(), launches.end(),
+                   [](const Launch& a, const Launch& b) { return a.chunk < b.chunk; });
+  const size_t nlaunch = launches.size();
   bool inl = reduces.empty();
   for (size_t L = 0; L < launch_km.size(); ++L)
     if (first_job[L + 1] - first_job[L] > (size_t)kInlineJobs) inl = false;
-  for (int L = 0; L < nlaunch; ++L)
-    if (pieces[L].size() > (size_t)kInlineProbs) inl = false;
+  for (const Launch& l : launches)
+    if (l.pieces.size() > (size_t)kInlineProbs) inl = false;
   // with split-K off, a no-alloc call has one job per operand side and two
   // problems per launch
   if (no_alloc && !inl) return MPC_E_UNSUPPORTED;
@@ -836,9 +875,9 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   if (!inl) {
     for (size_t L = 0; L < launch_km.size(); ++L) obstart[L] = blob.add(bstarts[L].data(), bstarts[L].size());
     ojobs = blob.add(jobs.data(), nj);
-    for (int L = 0; L < nlaunch; ++L) {
-      oprob[L] = blob.add(pieces[L].data(), pieces[L].size());
-      otile[L] = blob.add(tstarts[L].data(), tstarts[L].size());
+    for (size_t L = 0; L < nlaunch; ++L) {
+      oprob[L] = blob.add(launches[L].pieces.data(), launches[L].pieces.size());
+      otile[L] = blob.add(launches[L].tstarts.data(), launches[L].tstarts.size());
     }
     rt = add_reduces(blob, reduces);
     CHK(upload(c, blob, &dev));
@@ -857,22 +896,23 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     CHK(hip_status(launch_pack(st, t, bstarts[L].back(), launch_km[L].first, launch_km[L].second)));
     c->stats.launches++;
   }
-  for (int L = 0; L < nlaunch; ++L) {
-    if (pieces[L].empty()) continue;
+  for (size_t L = 0; L < nlaunch; ++L) {
+    const Launch& l = launches[L];
+    if (l.pieces.empty()) continue;
     GemmTables t{};
-    t.sched = sched;
-    t.map.nprob = (int)pieces[L].size();
+    t.sched = l.sched;
+    t.map.nprob = (int)l.pieces.size();
     if (inl) {
-      for (size_t i = 0; i < pieces[L].size(); ++i) t.iprobs[i] = pieces[L][i];
-      for (size_t i = 0; i < tstarts[L].size(); ++i) t.itile_start[i] = tstarts[L][i];
+      for (size_t i = 0; i < l.pieces.size(); ++i) t.iprobs[i] = l.pieces[i];
+      for (size_t i = 0; i < l.tstarts.size(); ++i) t.itile_start[i] = l.tstarts[i];
     } else {
       t.probs = (const LimbProblem*)(dev + oprob[L]);
       t.map.tile_start = (const int*)(dev + otile[L]);
     }
-    LaunchTimer tm(c, MPC_FORM_LIMB8, cmacs[L]);
+    LaunchTimer tm(c, MPC_FORM_LIMB8, l.macs);
     if (no_alloc) tm.on = false;
     CHK(tm.start());
-    CHK(hip_status(launch_limb_gemm(st, t, tstarts[L].back())));
+    CHK(hip_status(launch_limb_gemm(st, t, l.tstarts.back())));
     CHK(tm.stop());
     c->stats.launches++;
   }
@@ -883,7 +923,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
 
 LimbReq limb_req(i64 M, i64 N, i64 K0, i64 K1, const uint8_t* PA0, const uint8_t* PA1,
                  const uint8_t* PB0, const uint8_t* PB1, const Epilogue& ep) {
-  return LimbReq{M, N, K0, K1, PA0, PA1, PB0, PB1, ep};
+  return LimbReq{M, N, K0, K1, PA0, PA1, PB0, PB1, ep, false, TileSched{}, 0};
 }
 
 mpc_status check_trunc(int bits) { return (bits < 0 || bits > 63) ? MPC_E_INVAL : MPC_OK; }
@@ -1270,9 +1310,37 @@ uint64_t shapes_key(const std::vector<std::array<i64, 3>>& shapes) {
   return h;
 }
 
-TileSched sched_for(const mpc_ctx* c, const std::vector<std::array<i64, 3>>& shapes) {
+int bucket_of(i64 M, i64 N) {
+  auto padded = [&](i64 bm, i64 bn) { return (double)((M + bm - 1) / bm * bm) * (double)((N + bn - 1) / bn * bn); };
+  const double reg = padded(64, 64), tm = padded(32, 128), tn = padded(128, 32);
+  if (M <= 32 && tm <= 0.9 * reg && tm <= tn) return kBucketThinM;
+  if (N <= 32 && tn <= 0.9 * reg) return kBucketThinN;
+  return kBucketRegular;
+}
+
+// A problem's schedule and, under the classes variant, its tile class.
+struct ProbSched {
+  TileSched s;
+  int cls;
+};
+
+// The schedule of every problem of a matmul shape list.  Tuned: its class's
+// schedule for this list.  Untuned: the default schedule, unless some
+// product is thin and no default was set: then every problem runs in the one
+// classes launch with its own class.
+std::vector<ProbSched> scheds_for(const mpc_ctx* c, const std::vector<std::array<i64, 3>>& shapes) {
+  std::vector<ProbSched> out;
   auto it = c->tuned.find(shapes_key(shapes));
-  return it == c->tuned.end() ? c->sched_default : it->second;
+  bool thin = false;
+  for (const auto& sh : shapes) thin = thin || bucket_of(sh[0], sh[1]) != kBucketRegular;
+  const TileSched d = c->sched_default;
+  for (const auto& sh : shapes) {
+    const int b = bucket_of(sh[0], sh[1]);
+    if (it != c->tuned.end()) out.push_back(ProbSched{it->second.s[b], b});
+    else if (c->class_tiles && thin) out.push_back(ProbSched{TileSched{kLimbClasses, d.group_m, d.xcd_remap}, b});
+    else out.push_back(ProbSched{d, 0});
+  }
+  return out;
 }
 
 }  // namespace
@@ -1418,7 +1486,14 @@ mpc_status run_matmuls(mpc_ctx* c, const std::vector<MatmulPlan>& plans, int tru
       matmul_limb(m, cv, trunc, jobs, reqs);
       shapes.push_back({m.M, m.N, m.K});
     }
-    CHK(issue_limb(c, jobs, reqs, sched_for(c, shapes)));
+    // every problem's two finish GEMMs take its schedule and tile class
+    const std::vector<ProbSched> ts = scheds_for(c, shapes);
+    for (size_t q = 0; q < reqs.size(); ++q) {
+      reqs[q].own_sched = true;
+      reqs[q].sched = ts[q / 2].s;
+      reqs[q].cls = ts[q / 2].cls;
+    }
+    CHK(issue_limb(c, jobs, reqs, c->sched_default));
   } else if (plans.size() == 1 && plans[0].K <= kSmallMatmulK && plans[0].M * plans[0].N <= kSmallMatmulMacs &&
              plans[0].M * plans[0].N * plans[0].K <= kSmallMatmulMacs) {
     // a small product: open and finish in one launch, no workspace
@@ -1492,7 +1567,9 @@ mpc_status mpc_beaver_matmul_noalloc(mpc_ctx* c, int64_t M, int64_t N, int64_t K
     std::vector<PackJob> jobs;
     std::vector<LimbReq> reqs;
     matmul_limb(m, cv, trunc_bits, jobs, reqs);
-    CHK(issue_limb(c, jobs, reqs, sched_for(c, {{M, N, K}}), true));
+    const ProbSched ts = scheds_for(c, {{M, N, K}})[0];
+    for (LimbReq& r : reqs) r.cls = ts.cls;
+    CHK(issue_limb(c, jobs, reqs, ts.s, true));
   }
   c->stats.opens++;
   c->stats.open_bytes_per_party += 8 * (uint64_t)(M * K + K * N);
@@ -1746,7 +1823,7 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
     need += 3 * align_up(packed_bytes(s[0], s[2])) + 3 * align_up(packed_bytes(s[1], s[2]));
   CHK(ensure_ws(c, need));
   Carve cv(c->ws);
-  std::vector<LimbReq> reqs;
+  std::vector<LimbReq> reqs[kBuckets];
   for (const auto& s : shapes) {
     const i64 M = s[0], N = s[1], K = s[2];
     uint8_t* L[3];
@@ -1754,9 +1831,11 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
     for (auto& p : L) p = cv.take<uint8_t>(packed_bytes(M, K));
     for (auto& p : R) p = cv.take<uint8_t>(packed_bytes(N, K));
     for (int p = 0; p < 2; ++p)
-      reqs.push_back(limb_req(M, N, K, K, L[0], L[p == 0 ? 1 : 2], R[p == 0 ? 1 : 2], R[0],
-                              make_ep(nullptr, +1, 0, nullptr, rowmajor_view(N))));
+      reqs[bucket_of(M, N)].push_back(limb_req(M, N, K, K, L[0], L[p == 0 ? 1 : 2], R[p == 0 ? 1 : 2], R[0],
+                                               make_ep(nullptr, +1, 0, nullptr, rowmajor_view(N))));
   }
+  for (int b = 0; b < kBuckets; ++b)
+    for (LimbReq& r : reqs[b]) r.cls = b;
   // random limbs: the matrix cores' power draw, and so their clock, depends
   // on the data
   CHK(hip_status(launch_prg_fill(c->s[0], stream_key(c->seed, 0x7475, 0), (u64*)c->ws, cv.off / 8)));
@@ -1765,32 +1844,72 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
   for (const auto& s : shapes) maxmn = std::max(maxmn, s[0] * s[1]);
   u64* out[2] = {nullptr, nullptr};
   for (int p = 0; p < 2; ++p) HIPCHK(hipMalloc((void**)&out[p], (size_t)maxmn * 8));
-  for (size_t q = 0; q < reqs.size(); ++q) reqs[q].ep.Out = out[q & 1];
+  for (auto& rb : reqs)
+    for (size_t q = 0; q < rb.size(); ++q) rb[q].ep.Out = out[q & 1];
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  mpc_tile_config win{c->sched_default.variant, c->sched_default.group_m, c->sched_default.xcd_remap, 1e30};
   const bool prof = c->profiling;
   c->profiling = false;
   mpc_status st = MPC_OK;
-  for (int v = 0; v < kLimbVariants && st == MPC_OK; ++v)
+  // mean time of `reps` issues of a request list under one schedule
+  auto time_reqs = [&](const std::vector<LimbReq>& rq, const TileSched& ts, double* ms_out) -> mpc_status {
+    CHK(issue_limb(c, {}, rq, ts));  // warm-up
+    CHK(mark_slot(c));
+    const int reps = 3;
+    HIPCHK(hipEventRecord(e0, c->s[0]));
+    for (int r = 0; r < reps; ++r) {
+      CHK(issue_limb(c, {}, rq, ts));
+      CHK(mark_slot(c));
+    }
+    HIPCHK(hipEventRecord(e1, c->s[0]));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / reps;
+    return MPC_OK;
+  };
+  // every class on its own: all schedules on that class's GEMMs alone (one
+  // launch per class when the classes end up with different schedules)
+  const TileSched d = c->sched_default;
+  BucketScheds tuned{{d, d, d}};
+  mpc_tile_config win[kBuckets];
+  double split_ms = 0;
+  for (int b = 0; b < kBuckets && st == MPC_OK; ++b) {
+    win[b] = mpc_tile_config{d.variant, d.group_m, d.xcd_remap, 0.0};
+    if (reqs[b].empty()) continue;
+    win[b].ms = 1e30;
+    for (int v = 0; v < kLimbVariants && st == MPC_OK; ++v)
+      for (int gm : {4, 8, 16})
+        for (int remap : {1, 0}) {
+          double ms = 0;
+          st = time_reqs(reqs[b], TileSched{v, gm, remap}, &ms);
+          if (st != MPC_OK) break;
+          if (ms < win[b].ms) win[b] = mpc_tile_config{v, gm, remap, ms};
+        }
+    tuned.s[b] = TileSched{win[b].variant, win[b].group_m, win[b].xcd_remap};
+    split_ms += win[b].ms;
+  }
+  // and every problem in the one classes launch, with its own tile class
+  std::vector<LimbReq> all;
+  for (const auto& rb : reqs) all.insert(all.end(), rb.begin(), rb.end());
+  int nclasses = 0;
+  for (const auto& rb : reqs) nclasses += rb.empty() ? 0 : 1;
+  if (st == MPC_OK && nclasses > 1)
     for (int gm : {4, 8, 16})
       for (int remap : {1, 0}) {
-        const TileSched ts{v, gm, remap};
-        st = issue_limb(c, {}, reqs, ts);  // warm-up
-        if (st == MPC_OK) st = mark_slot(c);
+        double ms = 0;
+        st = time_reqs(all, TileSched{kLimbClasses, gm, remap}, &ms);
         if (st != MPC_OK) break;
-        const int reps = 3;
-        (void)hipEventRecord(e0, c->s[0]);
-        for (int r = 0; r < reps && st == MPC_OK; ++r) {
-          st = issue_limb(c, {}, reqs, ts);
-          if (st == MPC_OK) st = mark_slot(c);
+        if (ms < split_ms) {
+          split_ms = ms;
+          for (int b = 0; b < kBuckets; ++b) {
+            tuned.s[b] = TileSched{kLimbClasses, gm, remap};
+            if (!reqs[b].empty()) win[b] = mpc_tile_config{kLimbClasses, gm, remap, 0.0};
+          }
+          // the launch's time, charged to the regular class
+          win[kBucketRegular].ms = ms;
         }
-        (void)hipEventRecord(e1, c->s[0]);
-        if (st != MPC_OK || hipEventSynchronize(e1) != hipSuccess) break;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms / reps < win.ms) win = mpc_tile_config{v, gm, remap, ms / reps};
       }
   c->profiling = prof;
   (void)hipEventDestroy(e0);
@@ -1798,8 +1917,18 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
   (void)hipStreamSynchronize(c->s[0]);
   for (int p = 0; p < 2; ++p) (void)hipFree(out[p]);
   CHK(st);
-  c->tuned[shapes_key(shapes)] = TileSched{win.variant, win.group_m, win.xcd_remap};
-  if (best) *best = win;
+  c->tuned[shapes_key(shapes)] = tuned;
+  if (best) {
+    // the class that takes longest, with the time of all classes
+    int top = 0;
+    double total = 0;
+    for (int b = 0; b < kBuckets; ++b) {
+      total += win[b].ms;
+      if (win[b].ms > win[top].ms) top = b;
+    }
+    *best = win[top];
+    best->ms = total;
+  }
   return end_call(c);
 }
 
@@ -1807,9 +1936,11 @@ mpc_status mpc_autotune_save(const mpc_ctx* c, const char* path) {
   if (!c || !path) return MPC_E_INVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return MPC_E_INVAL;
-  for (const auto& kv : c->tuned)
-    std::fprintf(f, "%016llx %d %d %d\n", (unsigned long long)kv.first, kv.second.variant, kv.second.group_m,
-                 kv.second.xcd_remap);
+  for (const auto& kv : c->tuned) {
+    std::fprintf(f, "%016llx", (unsigned long long)kv.first);
+    for (const TileSched& t : kv.second.s) std::fprintf(f, " %d %d %d", t.variant, t.group_m, t.xcd_remap);
+    std::fprintf(f, "\n");
+  }
   std::fclose(f);
   return MPC_OK;
 }
@@ -1819,9 +1950,17 @@ mpc_status mpc_autotune_load(mpc_ctx* c, const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return MPC_E_INVAL;
   unsigned long long key;
-  int v, gm, remap;
-  while (std::fscanf(f, "%llx %d %d %d", &key, &v, &gm, &remap) == 4)
-    if (sched_ok(v, gm)) c->tuned[(uint64_t)key] = TileSched{v, gm, remap ? 1 : 0};
+  int v[kBuckets], gm[kBuckets], remap[kBuckets];
+  while (std::fscanf(f, "%llx %d %d %d %d %d %d %d %d %d", &key, &v[0], &gm[0], &remap[0], &v[1], &gm[1], &remap[1],
+                     &v[2], &gm[2], &remap[2]) == 10) {
+    bool ok = true;
+    BucketScheds b;
+    for (int i = 0; i < kBuckets; ++i) {
+      ok = ok && sched_ok(v[i], gm[i]);
+      b.s[i] = TileSched{v[i], gm[i], remap[i] ? 1 : 0};
+    }
+    if (ok) c->tuned[(uint64_t)key] = b;
+  }
   std::fclose(f);
   return MPC_OK;
 }
@@ -1835,6 +1974,8 @@ mpc_status mpc_get_default_tile_config(const mpc_ctx* c, mpc_tile_config* cfg) {
 mpc_status mpc_set_default_tile_config(mpc_ctx* c, const mpc_tile_config* cfg) {
   if (!c || !cfg || !sched_ok(cfg->variant, cfg->group_m)) return MPC_E_INVAL;
   c->sched_default = TileSched{cfg->variant, cfg->group_m, cfg->xcd_remap ? 1 : 0};
+  // an explicit schedule applies to thin products too
+  c->class_tiles = false;
   return MPC_OK;
 }
 

@@ -11,14 +11,18 @@
 //    (a 64-bit lo*lo multiply-add and two 32-bit cross products) over 8x4
 //    register blocks.
 //
-// and two streaming rates of HBM, with buffers far larger than the caches:
+// and two streaming rates of HBM, with buffers far larger than the caches
+// (the 256 MB Infinity Cache included), each the best over a few loop forms
+// (grid size, pairs of elements per thread and iteration):
 //
 //  * ten input streams and two output streams per element with trivial
 //    arithmetic (a sum and an exclusive or): the access pattern of the fused
-//    Beaver product, 96 bytes per element;
+//    Beaver product, 96 bytes per element, at 2^24 elements per stream (the
+//    size the Beaver product is measured at) and at 2^28;
 //  * one input and one output stream (a copy), 16 bytes per element.
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <algorithm>
 #include <cstdio>
 
 typedef uint64_t u64;
@@ -128,29 +132,57 @@ __global__ void __launch_bounds__(256) k_valu_ceiling(int iters, u64 seed, u64* 
 }
 
 // Streaming kernels: 16-byte non-temporal loads and stores, grid-stride over
-// pairs of 64-bit elements, every load of an iteration issued before its
-// stores.
+// pairs of 64-bit elements; each thread takes U pairs 256 apart per iteration
+// and issues all their loads before any store.
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u64x2 ld(const u64x2* p, size_t i) { return __builtin_nontemporal_load(p + i); }
 __device__ __forceinline__ void st(u64x2* p, size_t i, u64x2 v) { __builtin_nontemporal_store(v, p + i); }
 
-__global__ void __launch_bounds__(256)
-    k_stream_10r2w(size_t n2, const u64x2* __restrict__ i0, const u64x2* __restrict__ i1,
-                   const u64x2* __restrict__ i2, const u64x2* __restrict__ i3, const u64x2* __restrict__ i4,
-                   const u64x2* __restrict__ i5, const u64x2* __restrict__ i6, const u64x2* __restrict__ i7,
-                   const u64x2* __restrict__ i8, const u64x2* __restrict__ i9, u64x2* __restrict__ o0,
-                   u64x2* __restrict__ o1) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
-    const u64x2 v0 = ld(i0, i), v1 = ld(i1, i), v2 = ld(i2, i), v3 = ld(i3, i), v4 = ld(i4, i);
-    const u64x2 v5 = ld(i5, i), v6 = ld(i6, i), v7 = ld(i7, i), v8 = ld(i8, i), v9 = ld(i9, i);
-    st(o0, i, v0 + v1 + v2 + v3 + v4 + v5 + v6 + v7 + v8 + v9);
-    st(o1, i, v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7 ^ v8 ^ v9);
+struct Ins10 {
+  const u64x2* p[10];
+};
+
+template <int U>
+__global__ void __launch_bounds__(256) k_stream_10r2w(size_t n2, Ins10 in, u64x2* __restrict__ o0, u64x2* __restrict__ o1) {
+  const size_t step = (size_t)gridDim.x * 256 * U;
+  for (size_t i = (size_t)blockIdx.x * 256 * U + threadIdx.x; i < n2; i += step) {
+    u64x2 sum[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t j = i + (size_t)u * 256;
+      sum[u] = x[u] = u64x2{0, 0};
+      if (j < n2) {
+#pragma unroll
+        for (int a = 0; a < 10; ++a) {
+          const u64x2 v = ld(in.p[a], j);
+          sum[u] += v;
+          x[u] ^= v;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t j = i + (size_t)u * 256;
+      if (j < n2) {
+        st(o0, j, sum[u]);
+        st(o1, j, x[u]);
+      }
+    }
   }
 }
 
+template <int U>
 __global__ void __launch_bounds__(256) k_copy(size_t n2, const u64x2* __restrict__ in, u64x2* __restrict__ out) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) st(out, i, ld(in, i));
+  const size_t step = (size_t)gridDim.x * 256 * U;
+  for (size_t i = (size_t)blockIdx.x * 256 * U + threadIdx.x; i < n2; i += step) {
+    u64x2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i + (size_t)u * 256 < n2 ? ld(in, i + (size_t)u * 256) : u64x2{0, 0};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + (size_t)u * 256 < n2) st(out, i + (size_t)u * 256, v[u]);
+  }
 }
 
 // SplitMix64 bytes for the operand fragments (Steele, Lea and Flood, 2014).
@@ -206,39 +238,56 @@ int main() {
   const double mfma_ops = 2.0 * 16 * 16 * 64 * (36.0 * RB) * steps * 4.0 * blocks;
   const double valu_macs = (double)blocks * 256 * iters * 16 * TM * TN;
 
-  // streams: 12 buffers of 2^24 elements (1.5 GiB) for the Beaver pattern,
-  // 2 of 2^27 (2 GiB) for the copy; the grid is capped at 65536 workgroups
-  // as in the library's element-wise kernels
-  const size_t n_bv = (size_t)1 << 24, n_cp = (size_t)1 << 27;
+  // streams: 12 buffers of 2^28 elements (24 GiB in all) for the Beaver
+  // pattern, measured over their first 2^24 and over all 2^28 elements; the
+  // copy over 2^28 elements (4 GiB of traffic); best of grids of 16384..65536
+  // workgroups and 1, 2 or 4 pairs per thread and iteration
+  const size_t n_big = (size_t)1 << 28, n_bv = (size_t)1 << 24;
   u64x2* bufs[12];
   for (auto& b : bufs) {
-    CK(hipMalloc(&b, n_bv * sizeof(u64)));
-    CK(hipMemset(b, 0x5a, n_bv * sizeof(u64)));
+    CK(hipMalloc(&b, n_big * sizeof(u64)));
+    CK(hipMemset(b, 0x5a, n_big * sizeof(u64)));
   }
-  u64x2 *cin = nullptr, *cout = nullptr;
-  CK(hipMalloc(&cin, n_cp * sizeof(u64)));
-  CK(hipMalloc(&cout, n_cp * sizeof(u64)));
-  CK(hipMemset(cin, 0x5a, n_cp * sizeof(u64)));
-  auto grid = [](size_t n2) { return dim3((unsigned)(n2 / 256 > 65536 ? 65536 : (n2 + 255) / 256)); };
-  float bv_ms = 0.f, cp_ms = 0.f;
-  if (time_ms(
-          [&] {
-            hipLaunchKernelGGL(k_stream_10r2w, grid(n_bv / 2), dim3(256), 0, 0, n_bv / 2, bufs[0], bufs[1], bufs[2],
-                               bufs[3], bufs[4], bufs[5], bufs[6], bufs[7], bufs[8], bufs[9], bufs[10], bufs[11]);
-          },
-          5, 20, &bv_ms))
+  Ins10 ins;
+  for (int a = 0; a < 10; ++a) ins.p[a] = bufs[a];
+  const unsigned grids[] = {16384, 32768, 65536};
+  auto best_rate = [&](auto launch_u1, auto launch_u2, auto launch_u4, double bytes, int reps, double* gbs) {
+    *gbs = 0;
+    for (unsigned g : grids)
+      for (int u : {1, 2, 4}) {
+        float ms = 0.f;
+        const int r = time_ms([&] { u == 1 ? launch_u1(g) : u == 2 ? launch_u2(g) : launch_u4(g); }, 2, reps, &ms);
+        if (r) return r;
+        *gbs = std::max(*gbs, bytes / (ms * 1e-3) / 1e9);
+      }
+    return 0;
+  };
+  auto bv = [&](size_t n, int u, unsigned g) {
+    const size_t n2 = n / 2, need = (n2 + 256 * (size_t)u - 1) / (256 * (size_t)u);
+    return dim3((unsigned)std::min<size_t>(g, need));
+  };
+  double bv_gbs = 0, bv28_gbs = 0, cp_gbs = 0;
+#define MPC_BV_LAUNCH(U, N)                                                                                        \
+  [&](unsigned g) {                                                                                              \
+    hipLaunchKernelGGL(k_stream_10r2w<U>, bv(N, U, g), dim3(256), 0, 0, (N) / 2, ins, bufs[10], bufs[11]); \
+  }
+#define MPC_CP_LAUNCH(U)                                                                                        \
+  [&](unsigned g) {                                                                                           \
+    hipLaunchKernelGGL(k_copy<U>, bv(n_big, U, g), dim3(256), 0, 0, n_big / 2, bufs[0], bufs[11]); \
+  }
+  if (best_rate(MPC_BV_LAUNCH(1, n_bv), MPC_BV_LAUNCH(2, n_bv), MPC_BV_LAUNCH(4, n_bv), 96.0 * n_bv, 20, &bv_gbs))
     return 1;
-  if (time_ms([&] { hipLaunchKernelGGL(k_copy, grid(n_cp / 2), dim3(256), 0, 0, n_cp / 2, cin, cout); }, 5, 20,
-              &cp_ms))
+  if (best_rate(MPC_BV_LAUNCH(1, n_big), MPC_BV_LAUNCH(2, n_big), MPC_BV_LAUNCH(4, n_big), 96.0 * n_big, 3,
+                &bv28_gbs))
     return 1;
-  const double bv_gbs = 96.0 * n_bv / (bv_ms * 1e-3) / 1e9, cp_gbs = 16.0 * n_cp / (cp_ms * 1e-3) / 1e9;
+  if (best_rate(MPC_CP_LAUNCH(1), MPC_CP_LAUNCH(2), MPC_CP_LAUNCH(4), 16.0 * n_big, 10, &cp_gbs)) return 1;
+#undef MPC_BV_LAUNCH
+#undef MPC_CP_LAUNCH
 
   std::printf("{\"mfma_i8_random_tops\": %.1f, \"valu_ring_tmacs\": %.3f, \"hbm_stream_10r2w_gbs\": %.1f, "
-              "\"hbm_copy_gbs\": %.1f}\n",
-              mfma_ops / (mfma_ms * 1e-3) / 1e12, valu_macs / (valu_ms * 1e-3) / 1e12, bv_gbs, cp_gbs);
+              "\"hbm_stream_10r2w_2e28_gbs\": %.1f, \"hbm_copy_gbs\": %.1f}\n",
+              mfma_ops / (mfma_ms * 1e-3) / 1e12, valu_macs / (valu_ms * 1e-3) / 1e12, bv_gbs, bv28_gbs, cp_gbs);
   for (auto b : bufs) CK(hipFree(b));
-  CK(hipFree(cin));
-  CK(hipFree(cout));
   CK(hipFree(rnd));
   CK(hipFree(iout));
   CK(hipFree(uout));

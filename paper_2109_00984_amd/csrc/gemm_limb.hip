@@ -516,14 +516,21 @@ struct TilePos {
   i64 tm, tn;
 };
 
-template <int BM, int BN, int PER_CU>
-__device__ __forceinline__ TilePos tile_pos(const GemmView& v) {
+// This workgroup's problem and its tile index inside that problem.
+template <int PER_CU>
+__device__ __forceinline__ void tile_of(const GemmView& v, int& pi, i64& local) {
   const int b = blockIdx.x;
   const int t = v.sched.xcd_remap ? remap_tile(b, gridDim.x, kXcdCUs * PER_CU) : b;
+  pi = find_problem(v.tile_start, v.nprob, t);
+  local = t - v.tile_start[pi];
+}
+
+// Tile coordinates of tile `local` of problem pi for a BM x BN tile.
+template <int BM, int BN>
+__device__ __forceinline__ TilePos tile_coords(const GemmView& v, int pi, i64 local) {
   TilePos q;
-  q.pi = find_problem(v.tile_start, v.nprob, t);
-  const i64 M = v.probs[q.pi].M, N = v.probs[q.pi].N;
-  const i64 local = t - v.tile_start[q.pi];
+  q.pi = pi;
+  const i64 M = v.probs[pi].M, N = v.probs[pi].N;
   const i64 ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
   const i64 gm = v.sched.group_m;  // 1..64, checked by the host
   const i64 per_group = gm * ntn;
@@ -533,6 +540,14 @@ __device__ __forceinline__ TilePos tile_pos(const GemmView& v) {
   q.tm = first_m + in_group % gsize;
   q.tn = in_group / gsize;
   return q;
+}
+
+template <int BM, int BN, int PER_CU>
+__device__ __forceinline__ TilePos tile_pos(const GemmView& v) {
+  int pi;
+  i64 local;
+  tile_of<PER_CU>(v, pi, local);
+  return tile_coords<BM, BN>(v, pi, local);
 }
 
 // Wait states between the last MFMAs and the reads of their results: every
@@ -679,16 +694,18 @@ struct LGeo {
   static constexpr int HA = HA_, HB = HB_, WR = WR_, WC = WC_;
   static constexpr int kWaves = WR * WC, kThreads = 64 * kWaves;
   static constexpr int BM = 16 * HA * WR, BN = 16 * HB * WC;
-  static constexpr bool kOuterA = HA >= HB;  // the operand with more halves per wave
+  // the operand with more halves per wave, or when equal the one more waves
+  // share (A is shared along a row of WC waves, B along a column of WR)
+  static constexpr bool kOuterA = HA != HB ? HA > HB : WC >= WR;
   static constexpr int HO = kOuterA ? HA : HB, HI = kOuterA ? HB : HA;
   static constexpr int kStrips = (kOuterA ? BM : BN) / 32;  // outer strips per workgroup
   static constexpr int kBufBytes = kStrips << 14;           // two 8 KiB k-blocks per strip
   static constexpr int kCopies = kStrips * 16 / kWaves;     // 1 KiB copies per wave and step
   // Workgroups per CU: two for the four-wave 64x64 tile (128 accumulator
-  // registers), whose prologue, epilogue and stalls then overlap the other
-  // workgroup's MFMAs.  Both that and the eight-wave shapes leave 128 other
-  // registers per lane.
-  static constexpr int kMinBlocks = (HA * HB == 4 && kWaves == 4) ? 2 : 1;
+  // registers) and the thin 32x64 / 64x32 ones (64), whose prologue,
+  // epilogue and stalls then overlap the other workgroup's MFMAs.  Both
+  // that and the eight-wave shapes leave 128 other registers per lane.
+  static constexpr int kMinBlocks = (HA * HB <= 4 && kWaves == 4) ? 2 : 1;
   static constexpr bool kTight = kMinBlocks == 2 || kWaves == 8;
   // Inner planes 0..kDbl-1 are double-buffered; planes kDbl..7 are reloaded
   // in place for the next step at level 8 - p, after their last use.  With
@@ -875,17 +892,14 @@ __device__ __forceinline__ void lds_step(LRegs<G> r, const LCtx& c, const LStep&
   lds_levels<G, FIRST, LAST, 0>(r, cs, next, lo);
 }
 
-template <int HA, int HB, int WR, int WC>
-__global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ? 2 : 1)  // LGeo::kMinBlocks
-    k_limb_gemm_lds(GemmTables) {
-  using G = LGeo<HA, HB, WR, WC>;
-  __shared__ v4i stage[2][G::kBufBytes / 16];
+// One output tile of geometry G over its two LDS step buffers.
+template <class G>
+__device__ __forceinline__ void lds_tile(lds_u8* b0, lds_u8* b1, const GemmView& tv, const TilePos& tp) {
+  constexpr int HA = G::HA, HB = G::HB, WC = G::WC;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / WC, wc = wave % WC;
-  const GemmView tv = gemm_view();
-  const TilePos tp = tile_pos<G::BM, G::BN, G::kMinBlocks>(tv);
   const cptr<LimbProblem> pp = tv.probs + tp.pi;
   const i64 tm = tp.tm, tn = tp.tn;
   const i64 mw = tm * (G::BM / 32), nw = tn * (G::BN / 32);  // the workgroup's first left / right 32-block
@@ -909,8 +923,6 @@ __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ?
   const SegSrc w1 = seg_src(PA1, PB1, pp->kb1, mw, nw, G::BM / 32, G::BN / 32);
   const int c0 = wave * G::kCopies;
   const LCtx c{(unsigned)((ho0 >> 1) << 14) + lane_off, (unsigned)lane * 16u, c0 >> 4, c0 & 15};
-  lds_u8* b0 = (lds_u8*)&stage[0][0];
-  lds_u8* b1 = (lds_u8*)&stage[1][0];
 
   v4i z[G::HO], ob[2][G::HO], inner[G::HI][8], d0[G::HI][G::kDbl], d1[G::HI][G::kDbl];
   const int klast = kbeg + 2 * (nsteps - 1);
@@ -955,6 +967,47 @@ __global__ void __launch_bounds__(64 * WR * WC, (HA * HB == 4 && WR * WC == 4) ?
         for (int s = 0; s < 8; ++s) acc[x][y][s] = v4i{0, 0, 0, 0};
   }
   store_tile<HA, HB, G::BM, G::BN>(acc, pp, tm, tn, wr, wc, lane);
+}
+
+template <int HA, int HB, int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC, (HA * HB <= 4 && WR * WC == 4) ? 2 : 1)  // LGeo::kMinBlocks
+    k_limb_gemm_lds(GemmTables) {
+  using G = LGeo<HA, HB, WR, WC>;
+  __shared__ v4i stage[2][G::kBufBytes / 16];
+  const GemmView tv = gemm_view();
+  lds_tile<G>((lds_u8*)&stage[0][0], (lds_u8*)&stage[1][0], tv, tile_pos<G::BM, G::BN, G::kMinBlocks>(tv));
+}
+
+// Tile classes in one launch: every problem carries its class (LimbProblem::
+// cls), and each workgroup runs its problem's tile shape, all three with four
+// waves of 32x32 outputs (the 64x64 tile's per-wave register reuse) and two
+// workgroups per CU: 64x64, 32x128 (1x4 waves, for products of at most 32
+// rows) and 128x32 (4x1 waves, at most 32 columns).
+using GClass0 = LGeo<2, 2, 2, 2>;
+using GClass1 = LGeo<2, 2, 1, 4>;
+using GClass2 = LGeo<2, 2, 4, 1>;
+constexpr int kClassBuf = GClass0::kBufBytes > GClass1::kBufBytes
+                              ? (GClass0::kBufBytes > GClass2::kBufBytes ? GClass0::kBufBytes : GClass2::kBufBytes)
+                              : (GClass1::kBufBytes > GClass2::kBufBytes ? GClass1::kBufBytes : GClass2::kBufBytes);
+static_assert(GClass0::kMinBlocks == 2 && GClass1::kMinBlocks == 2 && GClass2::kMinBlocks == 2,
+              "every class runs two workgroups per CU");
+static_assert(2 * 2 * kClassBuf <= 160 * 1024, "two workgroups' step buffers fit in LDS");
+
+__global__ void __launch_bounds__(256, 2) k_limb_gemm_classes(GemmTables) {
+  __shared__ v4i stage[2][kClassBuf / 16];
+  const GemmView tv = gemm_view();
+  int pi;
+  i64 local;
+  tile_of<2>(tv, pi, local);
+  lds_u8* b0 = (lds_u8*)&stage[0][0];
+  lds_u8* b1 = (lds_u8*)&stage[1][0];
+  const int cls = tv.probs[pi].cls;
+  if (cls == 1)
+    lds_tile<GClass1>(b0, b1, tv, tile_coords<GClass1::BM, GClass1::BN>(tv, pi, local));
+  else if (cls == 2)
+    lds_tile<GClass2>(b0, b1, tv, tile_coords<GClass2::BM, GClass2::BN>(tv, pi, local));
+  else
+    lds_tile<GClass0>(b0, b1, tv, tile_coords<GClass0::BM, GClass0::BN>(tv, pi, local));
 }
 
 // ------------------------------------------------------------------ GEMM with both operands in LDS
@@ -1248,20 +1301,19 @@ i64 limb_rblocks(i64 rows) {
 }
 i64 limb_kblocks(i64 K) { return (K + 63) / 64 * 2; }
 int limb_tiles(i64 M, i64 N, int variant) {
-  const i64 bm = 64 * limb_variant_sa(variant), bn = 64 * limb_variant_sb(variant);
+  const i64 bm = limb_variant_bm(variant), bn = limb_variant_bn(variant);
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
-int limb_variant_sa(int variant) {
-  return variant == kLimb128x64 || variant == kLimbLds128x64 || variant == kLimbLds128x64w8 ||
-                 variant == kLimbSh128x64
-             ? 2
-             : 1;
-}
-int limb_variant_sb(int variant) {
-  return variant == kLimb64x128 || variant == kLimbLds64x128 || variant == kLimbLds64x128w8 ||
-                 variant == kLimbLds64x128w8s || variant == kLimbSh64x128
-             ? 2
-             : 1;
+// output rows and columns of one workgroup tile, per variant
+// (the classes variant: its class-0 tile; limb_class_tiles gives every class's)
+static const int kVariantBM[kLimbVariants] = {128, 64, 64, 128, 64, 64, 64, 128, 64, 64, 64, 128, 32, 128, 64};
+static const int kVariantBN[kLimbVariants] = {64, 128, 64, 64, 128, 64, 128, 64, 128, 64, 128, 64, 128, 32, 64};
+int limb_variant_bm(int variant) { return kVariantBM[variant]; }
+int limb_variant_bn(int variant) { return kVariantBN[variant]; }
+int limb_class_tiles(i64 M, i64 N, int cls) {
+  const i64 bm = cls == 1 ? GClass1::BM : cls == 2 ? GClass2::BM : GClass0::BM;
+  const i64 bn = cls == 1 ? GClass1::BN : cls == 2 ? GClass2::BN : GClass0::BN;
+  return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
 
 hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int kind, int mode) {
@@ -1310,6 +1362,9 @@ hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles)
     MPC_LDS_CASE(kLimbLds64x128w8, 1, 4, 4, 2)
     MPC_LDS_CASE(kLimbLds128x64w8, 4, 1, 2, 4)
     MPC_LDS_CASE(kLimbLds64x128w8s, 2, 2, 2, 4)
+    MPC_LDS_CASE(kLimbThin32x128, 2, 2, 1, 4)
+    MPC_LDS_CASE(kLimbThin128x32, 2, 2, 4, 1)
+    case kLimbClasses: hipLaunchKernelGGL(k_limb_gemm_classes, grid, dim3(256), 0, s, t); break;
     MPC_SH_CASE(kLimbSh64x64, 2, 2)
     MPC_SH_CASE(kLimbSh64x128, 2, 4)
     MPC_SH_CASE(kLimbSh128x64, 4, 2)

@@ -147,6 +147,7 @@ struct LimbProblem {
   i64 mblocks;  // padded row blocks of the left operand
   i64 nblocks;  // padded col blocks of the right operand
   Epilogue ep;
+  int cls;      // tile class, read by the classes variant only
 };
 
 // Largest number of concatenated k values one limb launch may cover: with all
@@ -281,14 +282,19 @@ hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int
 // 64x16 wave sub-tiles, 8 with 32x32 ones, as in the four-wave 64x64 tile.
 // Variants 9..11 stage both operands through LDS (k_limb_gemm_sh), every wave
 // owning 32x32 outputs: 9 with four waves (two workgroups per CU), 10 and 11
-// with eight.
+// with eight.  Variants 12 and 13 are thin tiles for products of at most 32
+// rows or columns: 32x128 and 128x32 in the LDS form, four waves of 32x32
+// outputs in a row or a column, two workgroups per CU.  Variant 14 takes
+// each problem's tile class from LimbProblem::cls (0: 64x64, 1: 32x128,
+// 2: 128x32), all in one launch.
 enum LimbVariant : int {
   kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2,
   kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5,
   kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7, kLimbLds64x128w8s = 8,
-  kLimbSh64x64 = 9, kLimbSh64x128 = 10, kLimbSh128x64 = 11
+  kLimbSh64x64 = 9, kLimbSh64x128 = 10, kLimbSh128x64 = 11,
+  kLimbThin32x128 = 12, kLimbThin128x32 = 13, kLimbClasses = 14
 };
-constexpr int kLimbVariants = 12;
+constexpr int kLimbVariants = 15;
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group
@@ -381,8 +387,9 @@ struct GemmTables {
 };
 hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles);
 int limb_tiles(i64 M, i64 N, int variant);
-int limb_variant_sa(int variant);
-int limb_variant_sb(int variant);
+int limb_variant_bm(int variant);  // output rows of a workgroup tile
+int limb_variant_bn(int variant);  // and columns
+int limb_class_tiles(i64 M, i64 N, int cls);  // tiles of an M x N product in tile class cls
 i64 limb_rblocks(i64 rows);  // padded 32-row block count
 i64 limb_kblocks(i64 K);
 

@@ -474,7 +474,7 @@ def test_beaver_mul_unaligned_views(m, ctx, n):
     assert_pair(ctx, sq, wsq, "beaver square on views")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 @pytest.mark.parametrize("group_m,remap", [(1, False), (8, True)])
 def test_limb_tile_variants(m, variant, group_m, remap):
     # every tile shape and schedule of the limb GEMM gives the oracle's result
@@ -507,18 +507,22 @@ def test_autotune_grouped_and_cache(m, tmp_path):
     assert best["variant"] in m.TILE_VARIANTS.values() and best["ms"] > 0
     probs, outs_plain = [], []
     for i, (M, N, K) in enumerate(shapes):
-        x = c.share(dev(rnd(3 * i, (M, K))), 0, 2 * i)
-        y = c.share(dev(rnd(3 * i + 1, (K, N))), 1, 2 * i + 1)
+        X, Y = rnd(3 * i, (M, K)), rnd(3 * i + 1, (K, N))
+        x = c.share(dev(X), 0, 2 * i)
+        y = c.share(dev(Y), 1, 2 * i + 1)
         t = c.dealer(m.TRIPLE_MATMUL, 5, i, (M, N, K))
         probs.append((x, y, t))
-        outs_plain.append(c.beaver_matmul(x, y, t, 16, "plain"))
-    zs = c.beaver_matmul_grouped(probs, 16, "limb8")  # uses the tuned schedule
+        want = oracle.beaver_matmul(oracle.share(X, 0, SEED, 2 * i), oracle.share(Y, 1, SEED, 2 * i + 1),
+                                    oracle.dealer_matmul(5, i, M, N, K), 16)
+        outs_plain.append(m.SharedPair(dev(want[0]), dev(want[1])))
+    zs = c.beaver_matmul_grouped(probs, 16, "limb8")  # uses the tuned schedules
     c.sync()
     for z, zp in zip(zs, outs_plain):
         assert torch.equal(z.s0, zp.s0) and torch.equal(z.s1, zp.s1)
     path = tmp_path / "tuned.txt"
     c.autotune_save(path)
-    assert len(open(path).read().split()) == 4
+    # one line: the shape list's hash and three classes' (variant, group_m, remap)
+    assert len(open(path).read().split()) == 10
     c2 = m.Context(device=0, seed=SEED)
     c2.autotune_load(path)
     zs2 = c2.beaver_matmul_grouped(probs, 16, "limb8")
@@ -526,6 +530,37 @@ def test_autotune_grouped_and_cache(m, tmp_path):
     for z, zp in zip(zs2, outs_plain):
         assert torch.equal(z.s0, zp.s0) and torch.equal(z.s1, zp.s1)
     c2.close()
+    c.close()
+
+
+def test_grouped_tile_classes(m):
+    # thin products take the thin tiles: untuned, every problem runs in one
+    # launch of the classes schedule with its own tile class (64x64, 32x128,
+    # 128x32); an explicit default schedule applies to every problem; the
+    # results are the oracle's either way
+    say("grouped tile classes")
+    c = m.Context(device=0, seed=SEED)
+    shapes = [(300, 120, 500), (17, 200, 300), (150, 20, 260), (9, 5, 70)]  # regular, thin M, thin N, thin M
+    probs, wants = [], []
+    for i, (M, N, K) in enumerate(shapes):
+        X, Y = rnd(50 + 2 * i, (M, K)), rnd(51 + 2 * i, (K, N))
+        probs.append((c.share(dev(X), 0, 30 + 2 * i), c.share(dev(Y), 1, 31 + 2 * i),
+                      c.dealer(m.TRIPLE_MATMUL, 6, i, (M, N, K))))
+        wants.append(oracle.beaver_matmul(oracle.share(X, 0, SEED, 30 + 2 * i), oracle.share(Y, 1, SEED, 31 + 2 * i),
+                                          oracle.dealer_matmul(6, i, M, N, K), 16))
+    for explicit, launches in [(False, 1), (True, 1)]:
+        if explicit:
+            c.set_default_tile_config(5, 8, True)
+        c.sync()
+        c.profile(True)
+        c.profile_read()
+        zs = c.beaver_matmul_grouped(probs, 16, "limb8")
+        c.sync()
+        assert c.profile_read()["limb8"]["launches"] == launches, explicit
+        c.profile(False)
+        for z, w in zip(zs, wants):
+            got = pair(c, z)
+            assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1])
     c.close()
 
 

@@ -60,7 +60,7 @@ def test_lds_handover_waits_cover_the_copies(tmp_path):
     subprocess.run(cmd, check=True, capture_output=True)
     hs = handovers(asm.read_text())
     kernels = {k for k, _, _ in hs}
-    assert len(kernels) == 6, kernels  # the six LDS geometries
+    assert len(kernels) == 8, kernels  # the eight LDS geometries (two of them thin)
     for k in kernels:
         assert sum(1 for kk, _, _ in hs if kk == k) >= 3, k  # prologue and steps
     for k, n, after in hs:
