@@ -92,13 +92,17 @@ def test_tile_schedule_bounds(m, tmp_path):
         assert c.default_tile_config() == before
         c.set_default_tile_config(variant=before["variant_id"], group_m=64)
         assert c.default_tile_config()["group_m"] == 64
-        # a cache file with out-of-range entries: those lines are ignored
+        # a cache file (hash, then three classes' variant, group_m, remap) with
+        # out-of-range entries in some class: those lines are ignored
         p = tmp_path / "tune.txt"
-        p.write_text("00000000000000aa 5 100000 1\n00000000000000bb 99 8 1\n00000000000000cc 5 8 1\n")
+        p.write_text("00000000000000aa 5 8 1 5 100000 1 5 8 1\n"
+                     "00000000000000bb 5 8 1 5 8 1 99 8 1\n"
+                     "00000000000000dd 5 8 1 -1 8 1 5 8 1\n"
+                     "00000000000000cc 5 8 1 12 4 0 14 16 1\n")
         c.autotune_load(p)
         out = tmp_path / "saved.txt"
         c.autotune_save(out)
         lines = out.read_text().split()
-        assert lines[:1] == ["00000000000000cc"] and len(lines) == 4
+        assert lines == ["00000000000000cc", "5", "8", "1", "12", "4", "0", "14", "16", "1"]
     finally:
         c.close()
