@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", default="limb8", choices=["limb8", "plain"])
+    ap.add_argument("--triples", default="packed", choices=["packed", "plain"],
+                    help="limb form: the dealer also packs the triple's a1, b0, b1 (offline), so that the online "
+                         "Beaver matmul packs only eps, a0 + eps and delta; or a plain triple")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--extra", action="append", choices=EXTRAS, metavar="NAME",
@@ -83,12 +86,18 @@ def main():
     z = mpc.SharedPair(ctx.empty((M, N)), ctx.empty((M, N)))
     r = ctx.empty((M, N))
     dims = (M, N, K)
+    packed_triples = args.form == "limb8" and args.triples == "packed"
+    packed = torch.empty(ctx.packed_triple_bytes(M, N, K), dtype=torch.uint8, device=dev) if packed_triples else None
 
     def step():
         ctx.share(X, 0, 1, out=x)
         ctx.share(Y, 1, 2, out=y)
-        ctx.dealer_into(mpc.TRIPLE_MATMUL, dealer_seed, 3, dims, t)
-        ctx.beaver_matmul(x, y, t, FRAC, args.form, out=z)
+        if packed_triples:
+            ctx._dealer_packed_into(dealer_seed, 3, dims, t, packed)
+            ctx.beaver_matmul_prepacked(x, y, t, packed, FRAC, out=z)
+        else:
+            ctx.dealer_into(mpc.TRIPLE_MATMUL, dealer_seed, 3, dims, t)
+            ctx.beaver_matmul(x, y, t, FRAC, args.form, out=z)
         ctx.reveal(z, out=r)
 
     ctx.profile(True)
@@ -179,6 +188,7 @@ def main():
                                "operands, dealer matrix triple, Beaver matmul with 2^16 "
                                "truncation, reveal",
                    "M": M, "N": N, "K": K, "form": args.form, "frac_bits": FRAC,
+                   "triples": "offline-packed" if packed_triples else "plain",
                    "parties": 2, "parallelism": "single GPU, two party streams"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -388,6 +398,28 @@ def ring_gemm_forms(ctx, torch, X, Y):
     # ten float64 multiply-adds per ring multiply-accumulate, against the FP64 matrix peak
     ex["fp64limb_gemm_fp64_frac"] = round(
         20.0 * M * N * K / (ex["ring_gemm_4096_fp64limb_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+    # the online Beaver matmul at 4096^3 over a regular and an offline-packed
+    # triple (the dealer packs a1, b0, b1; the online open packs eps, a0 + eps
+    # and delta only)
+    import paper_2109_00984_amd as mpc
+    x = ctx.share(X, 0, 91)
+    y = ctx.share(Y, 1, 92)
+    t = ctx.dealer(mpc.TRIPLE_MATMUL, 93, 94, (M, N, K))
+    z = mpc.SharedPair(ctx.empty((M, N)), ctx.empty((M, N)))
+    ex["beaver_matmul_4096_online_ms"] = round(
+        _event_time(torch, ctx.streams[0], lambda: ctx.beaver_matmul(x, y, t, FRAC, "limb8", out=z), 3), 4)
+    del t
+    tp, packed = ctx.dealer_packed(93, 94, (M, N, K))
+    ex["beaver_matmul_4096_prepacked_online_ms"] = round(
+        _event_time(torch, ctx.streams[0], lambda: ctx.beaver_matmul_prepacked(x, y, tp, packed, FRAC, out=z), 3), 4)
+    ex["dealer_matmul_4096_ms"] = round(
+        _event_time(torch, ctx.streams[0], lambda: ctx.dealer_into(mpc.TRIPLE_MATMUL, 93, 94, (M, N, K), tp), 3), 4)
+    ex["dealer_matmul_4096_packed_ms"] = round(
+        _event_time(torch, ctx.streams[0], lambda: ctx._dealer_packed_into(93, 94, (M, N, K), tp, packed), 3), 4)
+    log(f"bench: Beaver matmul 4096^3 online {ex['beaver_matmul_4096_online_ms']} ms, over a prepacked triple "
+        f"{ex['beaver_matmul_4096_prepacked_online_ms']} ms; dealer {ex['dealer_matmul_4096_ms']} ms, with packing "
+        f"{ex['dealer_matmul_4096_packed_ms']} ms")
+    del x, y, tp, packed, z
     C0 = ctx.ring_gemm(X, Y, "limb8")
     C1 = ctx.ring_gemm(X, Y, "plain")
     C2 = ctx.ring_gemm(X, Y, "fp64limb")
@@ -521,6 +553,25 @@ def grouped_bench(mpc, torch, workloads):
         best = c.autotune_matmul(shapes)
         out["grouped256_tuned_schedule"] = best
         timed("autotuned")
+        # the same batch over offline-packed triples: the online open packs
+        # eps, a0 + eps and delta only (a1, b0, b1 were packed by the dealer)
+        pprobs = []
+        for i, ((x, y, _), (m, n, k)) in enumerate(zip(probs, shapes)):
+            t, packed = c.dealer_packed(dseed, i, (m, n, k))
+            pprobs.append((x, y, t, packed))
+        c.beaver_matmul_grouped_prepacked(pprobs, FRAC, outs=outs)
+        c.sync()
+        c.graph_begin()
+        c.beaver_matmul_grouped_prepacked(pprobs, FRAC, outs=outs)
+        g = c.graph_end()
+        c.graph_launch(g)
+        c.sync()
+        ms = _event_time(torch, side, lambda: c.graph_launch(g), 10)
+        mpc.Context.graph_destroy(g)
+        out["grouped256_prepacked_ms"] = round(ms, 4)
+        out["grouped256_prepacked_int8_frac"] = round(72.0 * 4.0 * macs / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)
+        log(f"bench: grouped 256 (autotuned, prepacked triples) graph replay {ms:.3f} ms")
+        del pprobs
         out["grouped256_plaintext_macs"] = macs
         out["grouped256_limb_over_plain_speedup"] = round(out["grouped256_plain_ms"] / out["grouped256_autotuned_ms"], 2)
         out["grouped256_autotuned_over_default"] = round(

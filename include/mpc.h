@@ -266,6 +266,36 @@ typedef struct {
 mpc_status mpc_beaver_matmul_grouped(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
                                      int trunc_bits, mpc_form form);
 
+/* ---- offline-packed matrix triples (limb form) --------------------------- */
+/* Triples are made offline by the dealer (section 4, the trusted third
+ * party; App. C.1.1).  Three of a matrix triple's shares enter the finish
+ * unchanged, a_1 (party 1's left operand) and b_0, b_1 (the right ones), so
+ * the dealer can also store them in the limb form's packed layout; the online
+ * Beaver matmul then packs only eps, a_0 + eps and delta (the open step's
+ * writes fall from 6 to 3 packed operands).  `packed` is a caller-owned
+ * device buffer of mpc_packed_triple_bytes(M, N, K) bytes, 256-byte aligned,
+ * holding the three packed operands; it belongs to the triple and is read by
+ * the online call, never written.
+ *
+ * mpc_packed_triple_bytes: that size (0 for shapes mpc_beaver_matmul would
+ * refuse).  mpc_dealer_triples_packed: exactly the MATMUL triple of
+ * mpc_dealer_triples with the same (dseed, tag), plus `packed` (left
+ * unwritten when M, N or K is 0; MPC_E_UNSUPPORTED for K beyond the limb
+ * form's segment).  mpc_beaver_matmul_prepacked and its grouped form: the
+ * limb-form mpc_beaver_matmul / mpc_beaver_matmul_grouped (same shares, bit
+ * for bit) with the triples' packed operands; `packed` must not overlap an
+ * output (MPC_E_ALIAS); null or misaligned: MPC_E_INVAL. */
+size_t mpc_packed_triple_bytes(int64_t M, int64_t N, int64_t K);
+mpc_status mpc_dealer_triples_packed(mpc_ctx *ctx, uint64_t dseed, uint64_t tag, int64_t M, int64_t N, int64_t K,
+                                     const mpc_triple *out, void *packed);
+mpc_status mpc_beaver_matmul_prepacked(mpc_ctx *ctx, int64_t M, int64_t N, int64_t K, const uint64_t *x0,
+                                       const uint64_t *x1, const uint64_t *y0, const uint64_t *y1,
+                                       const mpc_triple *t, const void *packed, int trunc_bits, uint64_t *z0,
+                                       uint64_t *z1);
+/* `packed`: HOST array of `count` device pointers, one per descriptor. */
+mpc_status mpc_beaver_matmul_grouped_prepacked(mpc_ctx *ctx, size_t count, const mpc_matmul_desc *descs,
+                                               const void *const *packed, int trunc_bits);
+
 /* Many independent element-wise Beaver products (or squares) of uneven
  * lengths in ONE launch (section 5.2; batching amortises the rounds, Section
  * 6.1): each descriptor is what mpc_beaver_mul takes (y0 == y1 == NULL for a

@@ -96,6 +96,11 @@ _SIGS = {
     "mpc_beaver_mul": (INT, [VP, SZ, VP, VP, VP, VP, ctypes.POINTER(Triple), INT, VP, VP]),
     "mpc_beaver_matmul": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), INT,
                                 INT, VP, VP]),
+    "mpc_packed_triple_bytes": (SZ, [I64, I64, I64]),
+    "mpc_dealer_triples_packed": (INT, [VP, U64, U64, I64, I64, I64, ctypes.POINTER(Triple), VP]),
+    "mpc_beaver_matmul_prepacked": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), VP, INT,
+                                          VP, VP]),
+    "mpc_beaver_matmul_grouped_prepacked": (INT, [VP, SZ, ctypes.POINTER(MatmulDesc), ctypes.POINTER(VP), INT]),
     "mpc_beaver_matmul_noalloc": (INT, [VP, I64, I64, I64, VP, VP, VP, VP, ctypes.POINTER(Triple), INT,
                                         INT, VP, VP]),
     "mpc_beaver_conv1d": (INT, [VP, ctypes.POINTER(Conv1dShape), VP, VP, VP, VP,
@@ -410,6 +415,77 @@ class Context:
         _check(_lib.mpc_dealer_triples(self._h, kind, dseed, tag, d, ctypes.byref(st)),
                "mpc_dealer_triples")
         return t
+
+    # -------------------------------------------------------------- offline-packed triples
+    @staticmethod
+    def packed_triple_bytes(M, N, K):
+        return int(_lib.mpc_packed_triple_bytes(M, N, K))
+
+    def dealer_packed(self, dseed, tag, dims):
+        """A matrix triple (the same as dealer(TRIPLE_MATMUL, ...)) and its
+        offline-packed a1, b0, b1 (a uint8 device tensor)."""
+        M, N, K = dims
+        t = TripleShares(self.empty((M, K)), self.empty((M, K)), self.empty((K, N)), self.empty((K, N)),
+                         self.empty((M, N)), self.empty((M, N)))
+        packed = torch.empty(max(1, self.packed_triple_bytes(M, N, K)), dtype=torch.uint8, device=self.device)
+        return self._dealer_packed_into(dseed, tag, dims, t, packed), packed
+
+    def _dealer_packed_into(self, dseed, tag, dims, t, packed):
+        M, N, K = dims
+        self._check_triple(t, M * K, K * N, M * N)
+        self._check_packed(packed, M, N, K)
+        st = t.struct()
+        _check(_lib.mpc_dealer_triples_packed(self._h, dseed, tag, M, N, K, ctypes.byref(st), _ptr(packed)),
+               "mpc_dealer_triples_packed")
+        return t
+
+    def _check_packed(self, packed, M, N, K):
+        if packed.device != self.device or packed.dtype != torch.uint8 or not packed.is_contiguous():
+            raise ValueError("packed triple: a contiguous uint8 tensor on the context's device")
+        if packed.numel() < self.packed_triple_bytes(M, N, K):
+            raise ValueError("packed triple too small")
+
+    def beaver_matmul_prepacked(self, x, y, t, packed, trunc_bits=0, out=None):
+        M, K = x.s0.shape
+        K2, N = y.s0.shape
+        if K != K2:
+            raise ValueError("inner dimensions differ")
+        z = out if out is not None else SharedPair(self.empty((M, N)), self.empty((M, N)))
+        self._check_t(x.s0, x.s1, n=M * K)
+        self._check_t(y.s0, y.s1, n=K * N)
+        self._check_t(z.s0, z.s1, n=M * N)
+        self._check_triple(t, M * K, K * N, M * N)
+        self._check_packed(packed, M, N, K)
+        st = t.struct()
+        _check(_lib.mpc_beaver_matmul_prepacked(self._h, M, N, K, _ptr(x.s0), _ptr(x.s1), _ptr(y.s0), _ptr(y.s1),
+                                                ctypes.byref(st), _ptr(packed), trunc_bits, _ptr(z.s0),
+                                                _ptr(z.s1)), "mpc_beaver_matmul_prepacked")
+        return z
+
+    def beaver_matmul_grouped_prepacked(self, problems, trunc_bits=0, outs=None):
+        """problems: list of (x, y, triple, packed); returns the output pairs."""
+        n = len(problems)
+        descs = (MatmulDesc * max(1, n))()
+        ptrs = (VP * max(1, n))()
+        results = []
+        for i, (x, y, t, packed) in enumerate(problems):
+            M, K = x.s0.shape
+            K2, N = y.s0.shape
+            if K != K2:
+                raise ValueError(f"problem {i}: inner dimensions differ")
+            z = outs[i] if outs is not None else SharedPair(self.empty((M, N)), self.empty((M, N)))
+            self._check_t(x.s0, x.s1, n=M * K)
+            self._check_t(y.s0, y.s1, n=K * N)
+            self._check_t(z.s0, z.s1, n=M * N)
+            self._check_triple(t, M * K, K * N, M * N)
+            self._check_packed(packed, M, N, K)
+            results.append(z)
+            descs[i] = MatmulDesc(M, N, K, x.s0.data_ptr(), x.s1.data_ptr(), y.s0.data_ptr(),
+                                  y.s1.data_ptr(), t.struct(), z.s0.data_ptr(), z.s1.data_ptr())
+            ptrs[i] = packed.data_ptr()
+        _check(_lib.mpc_beaver_matmul_grouped_prepacked(self._h, n, descs, ptrs, trunc_bits),
+               "mpc_beaver_matmul_grouped_prepacked")
+        return results
 
     # -------------------------------------------------------------- binary sharing
     A2B_TRIPLES = 12

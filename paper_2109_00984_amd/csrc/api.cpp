@@ -617,7 +617,9 @@ struct JobSpec {
 
 size_t job_bytes(const JobSpec& j) { return (size_t)pack_nout(j.mode) * align_up(packed_bytes(j.rows, j.K)); }
 
-PackJob place_job(const JobSpec& j, Carve& cv) {
+// Places a job's packed outputs in the workspace carve; with ws_outs >= 0
+// only the first ws_outs of them (the caller points the rest elsewhere).
+PackJob place_job(const JobSpec& j, Carve& cv, int ws_outs = -1) {
   PackJob p{};
   p.kind = j.kind;
   p.mode = j.mode;
@@ -637,9 +639,20 @@ PackJob place_job(const JobSpec& j, Carve& cv) {
   p.rblocks = limb_rblocks(j.rows);
   p.rreal = (j.rows + 31) / 32;
   p.kblocks = limb_kblocks(j.K);
+  const int nws = ws_outs < 0 ? pack_nout(j.mode) : ws_outs;
   for (int o = 0; o < kPackMaxOut; ++o)
-    p.dst[o] = o < pack_nout(j.mode) ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
+    p.dst[o] = o < nws ? cv.take<uint8_t>(packed_bytes(j.rows, j.K)) : nullptr;
   return p;
+}
+
+// The offline-packed part of a matrix triple (the shares that enter the
+// finish unchanged): a_1 as a left operand, b_0 and b_1 as right operands,
+// each at its offset in one buffer.
+size_t packed_triple_layout(i64 M, i64 N, i64 K, size_t off[3]) {
+  off[0] = 0;
+  off[1] = align_up(packed_bytes(M, K));
+  off[2] = off[1] + align_up(packed_bytes(N, K));
+  return off[2] + align_up(packed_bytes(N, K));
 }
 
 // Left operand MxK (row-major, leading dimension ld).
@@ -724,7 +737,8 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   std::vector<std::pair<int, int>> launch_km;
   std::vector<size_t> first_job;
   for (int kind : {kPackRow, kPackCol, kPackIm2col})
-    for (int mode : {kModeCopy, kModeSum2, kModeOpenLeft, kModeOpenRight, kModePrgSum2}) {
+    for (int mode : {kModeCopy, kModeSum2, kModeOpenLeft, kModeOpenRight, kModePrgSum2, kModePrgSum2A, kModePrgSum2B,
+                     kModeOpenLeft2, kModeOpenRight1}) {
       bool any = false;
       for (const PackJob& j : jobs_in) {
         if (j.kind != kind || j.mode != mode) continue;
@@ -1347,12 +1361,14 @@ std::vector<ProbSched> scheds_for(const mpc_ctx* c, const std::vector<std::array
 
 namespace {
 
-// One Beaver matmul of the call (a grouped call holds many).
+// One Beaver matmul of the call (a grouped call holds many).  `packed`: the
+// triple's offline-packed a_1, b_0, b_1 (packed_triple_layout), or null.
 struct MatmulPlan {
   i64 M, N, K;
   const u64 *x0, *x1, *y0, *y1;
   mpc_triple t;
   u64 *z0, *z1;
+  const uint8_t* packed = nullptr;
 };
 
 mpc_status validate_matmul(const MatmulPlan& m) {
@@ -1396,6 +1412,8 @@ mpc_status issue_opens(mpc_ctx* c, const std::vector<OpenJob>& opens) {
 
 // Workspace of one Beaver matmul in a form.
 size_t matmul_ws(const MatmulPlan& m, mpc_form form) {
+  if (form == MPC_FORM_LIMB8 && m.packed)  // eps, g0 and delta only
+    return 2 * align_up(packed_bytes(m.M, m.K)) + align_up(packed_bytes(m.N, m.K));
   if (form == MPC_FORM_LIMB8)
     return 3 * align_up(packed_bytes(m.M, m.K)) + 3 * align_up(packed_bytes(m.N, m.K));
   return 2 * align_up((size_t)(m.M * m.K) * 8) + align_up((size_t)(m.K * m.N) * 8);
@@ -1460,6 +1478,23 @@ void matmul_limb(const MatmulPlan& m, Carve& cv, int trunc, std::vector<PackJob>
   JobSpec jl = left_job(m.M, m.K, m.K), jr = right_job(m.K, m.N, m.N);
   open_left(jl, m.x0, m.x1, m.t.a0, m.t.a1);
   open_right(jr, m.y0, m.y1, m.t.b0, m.t.b1);
+  if (m.packed) {
+    // a_1, b_0, b_1 come packed from the dealer: the open packs eps, g0 and
+    // delta only
+    jl.mode = kModeOpenLeft2;
+    jr.mode = kModeOpenRight1;
+    size_t off[3];
+    packed_triple_layout(m.M, m.N, m.K, off);
+    PackJob L = place_job(jl, cv), R = place_job(jr, cv);
+    jobs.push_back(L);
+    jobs.push_back(R);
+    const uint8_t *a1 = m.packed + off[0], *b0 = m.packed + off[1], *b1 = m.packed + off[2];
+    for (int p = 0; p < 2; ++p)
+      reqs.push_back(limb_req(m.M, m.N, m.K, m.K, L.dst[0], p == 0 ? L.dst[1] : a1, p == 0 ? b0 : b1, R.dst[0],
+                              make_ep(p == 0 ? m.t.c0 : m.t.c1, +1, trunc, p == 0 ? m.z0 : m.z1,
+                                      rowmajor_view(m.N))));
+    return;
+  }
   const PackJob L = place_job(jl, cv), R = place_job(jr, cv);
   jobs.push_back(L);
   jobs.push_back(R);
@@ -1537,6 +1572,122 @@ mpc_status mpc_beaver_matmul(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const 
   if (M == 0 || N == 0) return MPC_OK;
   CHK(set_device(c));
   CHK(run_matmuls(c, {m}, trunc_bits, form));
+  return end_call(c);
+}
+
+namespace {
+
+// Checks of an offline-packed triple buffer against a problem's outputs.
+mpc_status check_packed(const void* packed, i64 M, i64 N, i64 K, const u64* z0, const u64* z1) {
+  if (!packed || ((uintptr_t)packed & 255)) return MPC_E_INVAL;
+  size_t off[3];
+  const size_t bytes = packed_triple_layout(M, N, K, off);
+  const size_t nc = (size_t)(M * N);
+  // overlap() counts 8-byte elements; the packed size is whole 8 KiB blocks
+  if (overlap(packed, bytes / 8, z0, nc) || overlap(packed, bytes / 8, z1, nc)) return MPC_E_ALIAS;
+  return MPC_OK;
+}
+
+}  // namespace
+
+size_t mpc_packed_triple_bytes(int64_t M, int64_t N, int64_t K) {
+  if (check_mnk(M, N, K) != MPC_OK) return 0;
+  size_t off[3];
+  return packed_triple_layout(M, N, K, off);
+}
+
+mpc_status mpc_dealer_triples_packed(mpc_ctx* c, uint64_t dseed, uint64_t tag, int64_t M, int64_t N, int64_t K,
+                                     const mpc_triple* t, void* packed) {
+  if (!c || !t || !packed || ((uintptr_t)packed & 255)) return MPC_E_INVAL;
+  CHK(check_mnk(M, N, K));
+  CHK(check_limb_k(MPC_FORM_LIMB8, K));
+  const size_t na = (size_t)(M * K), nb = (size_t)(K * N), nc = (size_t)(M * N);
+  size_t off[3];
+  const size_t pbytes = packed_triple_layout(M, N, K, off);
+  // element counts (8 bytes each), as overlap() takes them
+  const void* bufs[7] = {t->a0, t->a1, t->b0, t->b1, t->c0, t->c1, packed};
+  const size_t ns[7] = {na, na, nb, nb, nc, nc, pbytes / 8};
+  for (int i = 0; i < 6; ++i) CHK(check_ptr(bufs[i], ns[i]));
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j < i; ++j)
+      if (overlap(bufs[i], ns[i], bufs[j], ns[j])) return MPC_E_ALIAS;
+  const int64_t dims[3] = {M, N, K};
+  // nothing to pack: the plain triple alone
+  if (!M || !N || !K) return mpc_dealer_triples(c, MPC_TRIPLE_MATMUL, dseed, tag, dims, t);
+  u64 key[6];
+  for (int sl = 0; sl < 6; ++sl) key[sl] = stream_key(dseed, tag, (u64)sl);
+  CHK(set_device(c));
+  // the same draws and the same c as mpc_dealer_triples: a_p, b_p drawn
+  // inside their packs (which also pack a_1, b_0, b_1 into `packed`), c_0
+  // from the PRG, c_1 = (a_0 + a_1) @ (b_0 + b_1) - c_0
+  JobSpec jl = left_job(M, K, K), jr = right_job(K, N, N);
+  set_prg_sum2(jl, key[kSlotA0], key[kSlotA0 + 1], t->a0, t->a1);
+  set_prg_sum2(jr, key[kSlotB0], key[kSlotB0 + 1], t->b0, t->b1);
+  jl.mode = kModePrgSum2A;
+  jr.mode = kModePrgSum2B;
+  CHK(ensure_ws(c, kAlign + align_up(packed_bytes(M, K)) + align_up(packed_bytes(N, K))));
+  CHK(hip_status(launch_prg_fill(c->s[0], key[kSlotC0], t->c0, nc)));
+  c->stats.launches++;
+  Carve cv(c->ws);
+  PackJob L = place_job(jl, cv, 1), R = place_job(jr, cv, 1);
+  uint8_t* pk = (uint8_t*)packed;
+  L.dst[1] = pk + off[0];
+  R.dst[1] = pk + off[1];
+  R.dst[2] = pk + off[2];
+  const Epilogue ep = make_ep(t->c0, -1, 0, t->c1, rowmajor_view(N));
+  CHK(issue_limb(c, {L, R}, {limb_req(M, N, K, 0, L.dst[0], nullptr, R.dst[0], nullptr, ep)}, c->sched_default));
+  return end_call(c);
+}
+
+mpc_status mpc_beaver_matmul_prepacked(mpc_ctx* c, int64_t M, int64_t N, int64_t K, const uint64_t* x0,
+                                       const uint64_t* x1, const uint64_t* y0, const uint64_t* y1,
+                                       const mpc_triple* t, const void* packed, int trunc_bits, uint64_t* z0,
+                                       uint64_t* z1) {
+  if (!c || !t) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  MatmulPlan m{M, N, K, x0, x1, y0, y1, *t, z0, z1, (const uint8_t*)packed};
+  CHK(validate_matmul(m));
+  CHK(check_packed(packed, M, N, K, z0, z1));
+  CHK(check_limb_k(MPC_FORM_LIMB8, K));
+  if (M == 0 || N == 0) return MPC_OK;
+  CHK(set_device(c));
+  CHK(run_matmuls(c, {m}, trunc_bits, MPC_FORM_LIMB8));
+  return end_call(c);
+}
+
+mpc_status mpc_beaver_matmul_grouped_prepacked(mpc_ctx* c, size_t count, const mpc_matmul_desc* descs,
+                                               const void* const* packed, int trunc_bits) {
+  if (!c || (count && (!descs || !packed))) return MPC_E_INVAL;
+  CHK(check_trunc(trunc_bits));
+  std::vector<MatmulPlan> plans;
+  i64 kmax = 0;
+  std::vector<Span> outs, ins;
+  for (size_t i = 0; i < count; ++i) {
+    const mpc_matmul_desc& d = descs[i];
+    MatmulPlan m{d.M, d.N, d.K, d.x0, d.x1, d.y0, d.y1, d.t, d.z0, d.z1, (const uint8_t*)packed[i]};
+    CHK(validate_matmul(m));
+    CHK(check_packed(packed[i], d.M, d.N, d.K, d.z0, d.z1));
+    if (d.M == 0 || d.N == 0) continue;
+    kmax = std::max(kmax, m.K);
+    plans.push_back(m);
+    const size_t na = (size_t)(m.M * m.K), nb = (size_t)(m.K * m.N), nc = (size_t)(m.M * m.N);
+    size_t off[3];
+    add_span(outs, m.z0, nc);
+    add_span(outs, m.z1, nc);
+    for (const void* p : {(const void*)m.x0, (const void*)m.x1, (const void*)m.t.a0, (const void*)m.t.a1})
+      add_span(ins, p, na);
+    for (const void* p : {(const void*)m.y0, (const void*)m.y1, (const void*)m.t.b0, (const void*)m.t.b1})
+      add_span(ins, p, nb);
+    add_span(ins, m.t.c0, nc);
+    add_span(ins, m.t.c1, nc);
+    add_span(ins, m.packed, packed_triple_layout(m.M, m.N, m.K, off) / 8);
+  }
+  CHK(check_limb_k(MPC_FORM_LIMB8, kmax));
+  if (plans.empty()) return MPC_OK;
+  CHK(batch_disjoint(std::move(outs), ins));
+  CHK(set_device(c));
+  std::stable_sort(plans.begin(), plans.end(), [](const MatmulPlan& a, const MatmulPlan& b) { return a.K > b.K; });
+  CHK(run_matmuls(c, plans, trunc_bits, MPC_FORM_LIMB8));
   return end_call(c);
 }
 

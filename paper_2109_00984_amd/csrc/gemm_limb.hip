@@ -154,6 +154,22 @@ template <> struct Mode<kModeOpenRight> {  // y0, y1, b0, b1 -> delta, b0, b1
     return o == 0 ? v[0] + v[1] - v[2] - v[3] : o == 1 ? v[2] : v[3];
   }
 };
+template <> struct Mode<kModePrgSum2A> {  // PRG v0, v1 -> v0 + v1, v1
+  static constexpr int nin = 2, nout = 2;
+  __device__ static u64 out(int o, const u64* v) { return o == 0 ? v[0] + v[1] : v[1]; }
+};
+template <> struct Mode<kModePrgSum2B> {  // PRG v0, v1 -> v0 + v1, v0, v1
+  static constexpr int nin = 2, nout = 3;
+  __device__ static u64 out(int o, const u64* v) { return o == 0 ? v[0] + v[1] : o == 1 ? v[0] : v[1]; }
+};
+template <> struct Mode<kModeOpenLeft2> {  // x0, x1, a0, a1 -> eps, g0 = a0 + eps
+  static constexpr int nin = 4, nout = 2;
+  __device__ static u64 out(int o, const u64* v) { return o == 0 ? v[0] + v[1] - v[2] - v[3] : v[0] + v[1] - v[3]; }
+};
+template <> struct Mode<kModeOpenRight1> {  // y0, y1, b0, b1 -> delta
+  static constexpr int nin = 4, nout = 1;
+  __device__ static u64 out(int, const u64* v) { return v[0] + v[1] - v[2] - v[3]; }
+};
 
 // Element offsets of a lane's 16 loads and whether each is inside the operand.
 template <int KIND>
@@ -235,7 +251,7 @@ __global__ void __launch_bounds__(kPackThreads) k_pack(PackTables) {
   for (int i = 0; i < Md::nin; ++i) in[i] = gptr(jb.in[i]);
   const bool interior = (rb + 1) * 32 <= jb.rows && (kb + 1) * 32 <= jb.K;
   u64 v[16][Md::nin];
-  if constexpr (MODE == kModePrgSum2) {
+  if constexpr (MODE == kModePrgSum2 || MODE == kModePrgSum2A || MODE == kModePrgSum2B) {
     // the shares are the PRG at each element's row-major offset; write them
     // out in this (coalesced) load layout
 #pragma unroll
@@ -1329,10 +1345,14 @@ hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int
   MPC_PACK_CASE(kPackRow, kModeOpenLeft)
   MPC_PACK_CASE(kPackRow, kModeOpenRight)
   MPC_PACK_CASE(kPackRow, kModePrgSum2)
+  MPC_PACK_CASE(kPackRow, kModePrgSum2A)
+  MPC_PACK_CASE(kPackRow, kModeOpenLeft2)
   MPC_PACK_CASE(kPackCol, kModeCopy)
   MPC_PACK_CASE(kPackCol, kModeSum2)
   MPC_PACK_CASE(kPackCol, kModeOpenRight)
   MPC_PACK_CASE(kPackCol, kModePrgSum2)
+  MPC_PACK_CASE(kPackCol, kModePrgSum2B)
+  MPC_PACK_CASE(kPackCol, kModeOpenRight1)
   MPC_PACK_CASE(kPackIm2col, kModeSum2)
   MPC_PACK_CASE(kPackIm2col, kModeOpenLeft)
 #undef MPC_PACK_CASE

@@ -106,7 +106,15 @@ enum PackKind : int { kPackRow = 0, kPackCol = 1, kPackIm2col = 2 };
 // element e (its row-major offset) gets v_i = G(key[i], e), which is also
 // written to share[i][e]; the packed output is v_0 + v_1.  Used by the
 // dealer for matrix operands, where every element is visited exactly once.
-enum PackMode : int { kModeCopy = 0, kModeSum2 = 1, kModeOpenLeft = 2, kModeOpenRight = 3, kModePrgSum2 = 4 };
+// The offline-packed matrix triple: kModePrgSum2A also packs the second
+// share (a_1) and kModePrgSum2B both (b_0, b_1) for the finish, and the
+// online open then packs only what it must: kModeOpenLeft2 eps and
+// g0 = a0 + eps, kModeOpenRight1 delta.
+enum PackMode : int {
+  kModeCopy = 0, kModeSum2 = 1, kModeOpenLeft = 2, kModeOpenRight = 3, kModePrgSum2 = 4,
+  kModePrgSum2A = 5, kModePrgSum2B = 6, kModeOpenLeft2 = 7, kModeOpenRight1 = 8
+};
+inline bool pack_prg(int mode) { return mode == kModePrgSum2 || mode == kModePrgSum2A || mode == kModePrgSum2B; }
 constexpr int kPackMaxIn = 4, kPackMaxOut = 3;
 
 struct PackJob {
@@ -129,10 +137,12 @@ struct PackJob {
   u64* share[2];  // kModePrgSum2: where the two shares are written
 };
 
-inline int pack_nin(int mode) {
-  return mode == kModeCopy ? 1 : (mode == kModeSum2 || mode == kModePrgSum2) ? 2 : 4;
+inline int pack_nin(int mode) { return mode == kModeCopy ? 1 : (mode == kModeSum2 || pack_prg(mode)) ? 2 : 4; }
+inline int pack_nout(int mode) {
+  return (mode <= kModeSum2 || mode == kModePrgSum2 || mode == kModeOpenRight1)
+             ? 1
+             : (mode == kModePrgSum2A || mode == kModeOpenLeft2) ? 2 : 3;
 }
-inline int pack_nout(int mode) { return (mode <= kModeSum2 || mode == kModePrgSum2) ? 1 : 3; }
 
 // Limb-form problem over packed segments; k-blocks [kb_begin, kb_end) of the
 // concatenation [segment 0 | segment 1] are processed (K chunking).

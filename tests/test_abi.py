@@ -67,3 +67,20 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_packed_triple_bytes():
+    # host-only: the offline-packed a1 (M x K), b0 and b1 (K x N), each a grid
+    # of 8 KiB blocks of 32 rows (columns) x 32 k, rows padded to 4 blocks and
+    # k to an even number of blocks, every operand 256-byte aligned
+    import paper_2109_00984_amd as m
+
+    def packed(rows, K):
+        rb = -(-(-(-rows // 32)) // 4) * 4
+        kb = -(-K // 64) * 2
+        return rb * kb * 8192
+
+    for M, N, K in [(1, 1, 1), (64, 32, 128), (300, 17, 4097), (4096, 4096, 4096), (0, 5, 7)]:
+        want = packed(M, K) + 2 * packed(N, K)
+        assert m.Context.packed_triple_bytes(M, N, K) == want, (M, N, K)
+    assert m.Context.packed_triple_bytes(-1, 2, 3) == 0
