@@ -38,7 +38,7 @@ def log(*a):
 
 
 EXTRAS = ("ceilings", "small", "ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul",
-          "conv")
+          "conv", "power")
 
 
 def main():
@@ -265,6 +265,8 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only, cpu=True):
     ex = {}
     if "ceilings" in only:
         ex.update(ceilings())
+    if "power" in only:
+        ex.update(power_draw(ctx, torch, X, Y))
     if "small" in only:
         ex.update(small_latency(mpc, torch, workloads))
     if "ring_gemm" in only:
@@ -286,6 +288,106 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only, cpu=True):
         ex.update(grouped_mul_bench(mpc, torch, workloads))
     if "conv" in only:
         ex.update(conv_bench(mpc, torch, workloads, cpu))
+    return ex
+
+
+def power_draw(ctx, torch, X, Y):
+    """Board power (hwmon power1_input, sampled every 50 ms) idle and while the
+    limb GEMM of a Beaver finish (4096x4096x8192) runs back to back for 3 s,
+    with its sustained rate; the board's power cap where hwmon shows it."""
+    import glob
+    import threading
+    files = sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_input"))
+    if not files:
+        return {}
+    cap = [f.replace("power1_input", "power1_cap") for f in files]
+
+    def read(fs):
+        out = []
+        for f in fs:
+            try:
+                out.append(int(open(f).read()) / 1e6)
+            except (OSError, ValueError):
+                pass
+        return max(out) if out else None
+
+    def sample(fn, secs):
+        vals, on = [], [True]
+
+        def loop():
+            while on[0]:
+                v = read(files)
+                if v is not None:
+                    vals.append(v)
+                time.sleep(0.05)
+        th = threading.Thread(target=loop, daemon=True)
+        th.start()
+        fn(secs)
+        on[0] = False
+        th.join()
+        tail = vals[len(vals) // 3:]  # after the clock has settled
+        return sum(tail) / len(tail) if tail else None
+
+    ex = {}
+    ctx.sync()
+    ex["power_idle_W"] = round(sample(lambda s: time.sleep(s), 1.0), 1)
+    A = torch.cat([X, X], dim=1)  # 4096 x 8192
+    B = torch.cat([Y, Y], dim=0)  # 8192 x 4096
+    C = ctx.empty((M, N))
+    ctx.ring_gemm(A, B, "limb8", out=C)
+    ctx.sync()
+    ctx.profile(True)
+    ctx.profile_read()
+
+    def gemms(secs):
+        t0 = time.time()
+        while time.time() - t0 < secs:
+            for _ in range(10):
+                ctx.ring_gemm(A, B, "limb8", out=C)
+            ctx.sync()
+    ex["power_limb_gemm_W"] = round(sample(gemms, 3.0), 1)
+    g = ctx.profile_read()["limb8"]
+    ctx.profile(False)
+    ex["power_limb_gemm_sustained_TOPs"] = round(72.0 * g["ring_macs"] / (g["total_ms"] * 1e-3) / 1e12, 1)
+    del A, B, C
+    # the MFMA-only loop of the ceilings program, back to back for 3 s
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2109_00984_amd", "ceilings")
+    res = {}
+
+    def mfma_loop(secs):
+        r = subprocess.run([exe, "mfma", str(secs)], capture_output=True, text=True, timeout=120, check=True)
+        res.update(json.loads(r.stdout.strip().splitlines()[-1]))
+    ex["power_mfma_loop_W"] = round(sample(mfma_loop, 3.0), 1)
+    ex["power_mfma_loop_TOPs"] = res.get("mfma_i8_random_tops")
+    # the vendor's int8 GEMM (torch._int_mm) on uniformly random int8, 8192^3
+    a = torch.randint(-128, 128, (8192, 8192), dtype=torch.int8, device=ctx.device)
+    b = torch.randint(-128, 128, (8192, 8192), dtype=torch.int8, device=ctx.device).t().contiguous().t()
+    torch._int_mm(a, b)
+    torch.cuda.synchronize()
+    n_mm = [0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def int_mm(secs):
+        e0.record()
+        t0 = time.time()
+        while time.time() - t0 < secs:
+            for _ in range(10):
+                torch._int_mm(a, b)
+            n_mm[0] += 10
+            torch.cuda.synchronize()
+        e1.record()
+        torch.cuda.synchronize()
+    ex["power_vendor_int8_gemm_W"] = round(sample(int_mm, 3.0), 1)
+    ex["power_vendor_int8_gemm_TOPs"] = round(2.0 * 8192 ** 3 * n_mm[0] / (e0.elapsed_time(e1) * 1e-3) / 1e12, 1)
+    del a, b
+    c = read(cap)
+    if c:
+        ex["power_cap_W"] = round(c, 1)
+    log(f"bench: power idle {ex['power_idle_W']} W, limb GEMM back to back {ex['power_limb_gemm_W']} W at "
+        f"{ex['power_limb_gemm_sustained_TOPs']} TOP/s, MFMA-only loop {ex['power_mfma_loop_W']} W at "
+        f"{ex['power_mfma_loop_TOPs']} TOP/s, vendor int8 GEMM {ex['power_vendor_int8_gemm_W']} W at "
+        f"{ex['power_vendor_int8_gemm_TOPs']} TOP/s" + (f" (cap {ex['power_cap_W']} W)" if c else ""))
     return ex
 
 

@@ -24,6 +24,8 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <string>
 
 typedef uint64_t u64;
 typedef uint32_t u32;
@@ -215,7 +217,37 @@ static int time_ms(F launch, int warm, int reps, float* ms) {
   return 0;
 }
 
-int main() {
+// `ceilings mfma <seconds>`: only the INT8 MFMA loop, launched back to back
+// for that long (for power readings under sustained matrix-core load);
+// prints its mean rate.
+static int mfma_only(double secs) {
+  const int blocks = 2048, steps = 128;
+  v4i* rnd = nullptr;
+  int* iout = nullptr;
+  constexpr int kFrags = 8 * (RB + 1) * 64;
+  CK(hipMalloc(&rnd, kFrags * sizeof(v4i)));
+  CK(hipMalloc(&iout, (size_t)blocks * 256 * sizeof(int)));
+  hipLaunchKernelGGL(k_fill, dim3((kFrags * 2 + 255) / 256), dim3(256), 0, 0, (u64*)rnd, kFrags * 2);
+  CK(hipGetLastError());
+  double total_ms = 0;
+  long launches = 0;
+  while (total_ms < secs * 1e3) {
+    float ms = 0.f;
+    if (time_ms([&] { hipLaunchKernelGGL(k_mfma_ceiling, dim3(blocks), dim3(256), 0, 0, steps, rnd, iout); }, 0, 50,
+                &ms))
+      return 1;
+    total_ms += 50.0 * ms;
+    launches += 50;
+  }
+  const double ops = 2.0 * 16 * 16 * 64 * (36.0 * RB) * steps * 4.0 * blocks * launches;
+  std::printf("{\"mfma_i8_random_tops\": %.1f, \"seconds\": %.2f}\n", ops / (total_ms * 1e-3) / 1e12, total_ms * 1e-3);
+  CK(hipFree(rnd));
+  CK(hipFree(iout));
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc == 3 && std::string(argv[1]) == "mfma") return mfma_only(std::atof(argv[2]));
   const int blocks = 2048;
   v4i* rnd = nullptr;
   int* iout = nullptr;
