@@ -351,8 +351,9 @@ typedef struct {
  * exact GEMM problems that a Beaver matmul (count = 1) or a grouped call of
  * these `count` shapes issues in the limb form (dims: HOST array of M, N, K
  * per problem), on random operands, and remembers each class's fastest for
- * later calls with the same shapes, unless all classes together in one launch
- * of schedule 14 are faster than the classes' separate launches.  `best` (may be NULL) receives the
+ * later calls with the same shapes, unless one launch of all of them is
+ * faster than the classes' separate launches (each single schedule, and
+ * schedule 14 with every product in its own class, are timed that way).  `best` (may be NULL) receives the
  * schedule of the class that takes longest and, in `ms`, the summed time of
  * all classes.  Uses the context's workspace and party 0's stream;
  * synchronises it. */

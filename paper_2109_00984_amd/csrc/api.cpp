@@ -2041,27 +2041,29 @@ mpc_status mpc_autotune_matmul(mpc_ctx* c, size_t count, const int64_t* dims, mp
     tuned.s[b] = TileSched{win[b].variant, win[b].group_m, win[b].xcd_remap};
     split_ms += win[b].ms;
   }
-  // and every problem in the one classes launch, with its own tile class
+  // and every problem in one launch: under each single schedule, and under
+  // the classes schedule with its own tile class
   std::vector<LimbReq> all;
   for (const auto& rb : reqs) all.insert(all.end(), rb.begin(), rb.end());
   int nclasses = 0;
   for (const auto& rb : reqs) nclasses += rb.empty() ? 0 : 1;
   if (st == MPC_OK && nclasses > 1)
-    for (int gm : {4, 8, 16})
-      for (int remap : {1, 0}) {
-        double ms = 0;
-        st = time_reqs(all, TileSched{kLimbClasses, gm, remap}, &ms);
-        if (st != MPC_OK) break;
-        if (ms < split_ms) {
-          split_ms = ms;
-          for (int b = 0; b < kBuckets; ++b) {
-            tuned.s[b] = TileSched{kLimbClasses, gm, remap};
-            if (!reqs[b].empty()) win[b] = mpc_tile_config{kLimbClasses, gm, remap, 0.0};
+    for (int v = 0; v < kLimbVariants && st == MPC_OK; ++v)
+      for (int gm : {4, 8, 16})
+        for (int remap : {1, 0}) {
+          double ms = 0;
+          st = time_reqs(all, TileSched{v, gm, remap}, &ms);
+          if (st != MPC_OK) break;
+          if (ms < split_ms) {
+            split_ms = ms;
+            for (int b = 0; b < kBuckets; ++b) {
+              tuned.s[b] = TileSched{v, gm, remap};
+              if (!reqs[b].empty()) win[b] = mpc_tile_config{v, gm, remap, 0.0};
+            }
+            // the launch's time, charged to the regular class
+            win[kBucketRegular].ms = ms;
           }
-          // the launch's time, charged to the regular class
-          win[kBucketRegular].ms = ms;
         }
-      }
   c->profiling = prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
