@@ -165,6 +165,33 @@ def test_gemm4k_beaver_matmul_sampled(m, ctx):
     c.close()
 
 
+def test_gemm4k_step_full_parity(m, ctx):
+    """The benchmark's whole step at M = N = K = 4096 as the bench runs it
+    (shares, dealer with offline-packed a1, b0, b1, Beaver matmul over them
+    with 2^16 truncation, reveal), every one of the 16.8 M outputs of both
+    parties against the oracle's full evaluation (its share, dealer, three
+    products per party and floor truncation; about 15 s on 16 host cores)."""
+    M = N = K = 4096
+    data_seed, pseed, dseed = workloads.seeds(3)
+    c = m.Context(device=0, seed=pseed)
+    Xh = workloads.uniform_u64(data_seed, (M, K))
+    Yh = workloads.uniform_u64(data_seed + 1, (K, N))
+    say("gemm4k full: gpu step")
+    x, y = c.share(dev(Xh), 0, 1), c.share(dev(Yh), 1, 2)
+    t, packed = c.dealer_packed(dseed, 3, (M, N, K))
+    z = c.beaver_matmul_prepacked(x, y, t, packed, FRAC)
+    r = c.reveal(z)
+    got = pair(c, z)
+    got_r = host(c, r)
+    del x, y, t, packed
+    say("gemm4k full: oracle step")
+    xs, ys = oracle.share(Xh, 0, pseed, 1), oracle.share(Yh, 1, pseed, 2)
+    want = oracle.beaver_matmul(xs, ys, oracle.dealer_matmul(dseed, 3, M, N, K), FRAC)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    assert np.array_equal(got_r, oracle.reveal(*want))
+    c.close()
+
+
 def test_gemm4k_ring_gemm_forms(m, ctx):
     M = N = K = 4096
     say("gemm4k ring gemm forms")
