@@ -326,7 +326,10 @@ mpc_status mpc_beaver_mul_grouped(mpc_ctx *ctx, size_t count, const mpc_mul_desc
  * owning 32x32 outputs; 12: 32x128 and 13: 128x32 thin tiles in the LDS
  * form, four waves of 32x32 outputs in a row or a column, two workgroups per
  * compute unit; 14: every product in its own tile class, 64x64, 32x128 or
- * 128x32, in one launch), the number of tile
+ * 128x32, in one launch; 15: schedule 14 as a persistent launch, two
+ * workgroups per compute unit taking tiles from per-XCD queues in the order
+ * that schedule 14 dispatches them, its queue heads in a 64-byte buffer of
+ * the context), the number of tile
  * rows per raster group, and whether tiles are handed to the 8 XCDs in runs
  * of 32 neighbouring tiles (one per compute unit, so that the tiles an XCD
  * runs together share operand blocks in its L2) instead of one by one.
@@ -342,7 +345,8 @@ typedef struct {
  * (at most 32 columns) when the 32x128 or 128x32 tile leaves at most nine
  * tenths of the 64x64 tile's padded work, else "regular"; a grouped call
  * issues one GEMM launch per schedule in use.  Untuned, every product takes
- * the default schedule, unless some product is thin and no default was set
+ * the default schedule (schedule 14 or 15 as the default: each product in its
+ * own class), unless some product is thin and no default was set
  * with mpc_set_default_tile_config: then all of them run in one launch of
  * schedule 14, each in its own class (with the default's group_m and
  * remap).
@@ -353,7 +357,7 @@ typedef struct {
  * per problem), on random operands, and remembers each class's fastest for
  * later calls with the same shapes, unless one launch of all of them is
  * faster than the classes' separate launches (each single schedule, and
- * schedule 14 with every product in its own class, are timed that way).  `best` (may be NULL) receives the
+ * schedules 14 and 15 with every product in its own class, are timed that way).  `best` (may be NULL) receives the
  * schedule of the class that takes longest and, in `ms`, the summed time of
  * all classes.  Uses the context's workspace and party 0's stream;
  * synchronises it. */

@@ -71,7 +71,7 @@ class TileConfig(ctypes.Structure):
 
 TILE_VARIANTS = {0: "128x64", 1: "64x128", 2: "64x64", 3: "lds128x64", 4: "lds64x128", 5: "lds64x64",
                  6: "lds64x128w8", 7: "lds128x64w8", 8: "lds64x128w8s", 9: "sh64x64", 10: "sh64x128",
-                 11: "sh128x64", 12: "lds32x128", 13: "lds128x32", 14: "classes"}
+                 11: "sh128x64", 12: "lds32x128", 13: "lds128x32", 14: "classes", 15: "classes_persistent"}
 
 
 class Stats(ctypes.Structure):

@@ -138,6 +138,9 @@ struct mpc_ctx {
   int live_graphs = 0;
   // this device's no-alloc workspace (`scratch`), or null if not found
   uint8_t* scratch = nullptr;
+  // queue heads of the persistent limb GEMM (zeroed; each launch leaves them
+  // zeroed, and all of this context's launches run on party 0's stream)
+  unsigned* queue = nullptr;
 };
 // An instantiated graph, the context whose buffers it references and the
 // descriptor buffers its kernels read.
@@ -715,7 +718,7 @@ struct LimbReq {
   Epilogue ep;
   bool own_sched;   // use `sched` instead of the call's schedule
   TileSched sched;
-  int cls;          // tile class under the classes variant
+  int cls;          // tile class under the classes variants
 };
 
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
@@ -771,7 +774,7 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   auto sched_of = [&](size_t q) { return reqs[q].own_sched ? reqs[q].sched : sched; };
   auto tiles_of = [&](size_t q) {
     const TileSched t = sched_of(q);
-    return t.variant == kLimbClasses ? limb_class_tiles(reqs[q].M, reqs[q].N, reqs[q].cls)
+    return limb_per_class(t.variant) ? limb_class_tiles(reqs[q].M, reqs[q].N, reqs[q].cls)
                                      : limb_tiles(reqs[q].M, reqs[q].N, t.variant);
   };
   i64 tiles_all = 0;
@@ -916,6 +919,8 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     GemmTables t{};
     t.sched = l.sched;
     t.map.nprob = (int)l.pieces.size();
+    t.queue = c->queue;
+    t.persist_grid = limb_persist_grid(l.tstarts.back(), c->num_cu);
     if (inl) {
       for (size_t i = 0; i < l.pieces.size(); ++i) t.iprobs[i] = l.pieces[i];
       for (size_t i = 0; i < l.tstarts.size(); ++i) t.itile_start[i] = l.tstarts[i];
@@ -1047,6 +1052,15 @@ mpc_status mpc_ctx_create(int device, void* stream0, void* stream1, uint64_t see
     e = hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming);
     if (e != hipSuccess) return fail(e);
   }
+  e = hipMalloc((void**)&c->queue, kLimbQueueWords * sizeof(unsigned));
+  if (e != hipSuccess) return fail(e);
+  {
+    // a copy from pageable host memory has completed when it returns, so the
+    // zeros are in place before any stream's first launch
+    const unsigned zeros[kLimbQueueWords] = {};
+    e = hipMemcpy(c->queue, zeros, sizeof(zeros), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(e);
+  }
   // the device is current: find its no-alloc workspace (a failure only
   // disables mpc_beaver_matmul_noalloc)
   c->scratch = (uint8_t*)scratch_address(device);
@@ -1069,6 +1083,7 @@ mpc_status mpc_ctx_destroy(mpc_ctx* c) {
     if (sl.done) (void)hipEventDestroy(sl.done);
   }
   for (void* p : c->capture_allocs) (void)hipFree(p);
+  if (c->queue) (void)hipFree(c->queue);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -1332,16 +1347,17 @@ int bucket_of(i64 M, i64 N) {
   return kBucketRegular;
 }
 
-// A problem's schedule and, under the classes variant, its tile class.
+// A problem's schedule and, under the classes variants, its tile class.
 struct ProbSched {
   TileSched s;
   int cls;
 };
 
 // The schedule of every problem of a matmul shape list.  Tuned: its class's
-// schedule for this list.  Untuned: the default schedule, unless some
-// product is thin and no default was set: then every problem runs in the one
-// classes launch with its own class.
+// schedule for this list.  Untuned: the default schedule (a classes schedule
+// with each problem's own class), unless some product is thin and no default
+// was set: then every problem runs in the one classes launch with its own
+// class.
 std::vector<ProbSched> scheds_for(const mpc_ctx* c, const std::vector<std::array<i64, 3>>& shapes) {
   std::vector<ProbSched> out;
   auto it = c->tuned.find(shapes_key(shapes));
@@ -1352,7 +1368,7 @@ std::vector<ProbSched> scheds_for(const mpc_ctx* c, const std::vector<std::array
     const int b = bucket_of(sh[0], sh[1]);
     if (it != c->tuned.end()) out.push_back(ProbSched{it->second.s[b], b});
     else if (c->class_tiles && thin) out.push_back(ProbSched{TileSched{kLimbClasses, d.group_m, d.xcd_remap}, b});
-    else out.push_back(ProbSched{d, 0});
+    else out.push_back(ProbSched{d, limb_per_class(d.variant) ? b : 0});
   }
   return out;
 }

@@ -83,12 +83,14 @@ struct GemmView {
   cptr<int> tile_start;
   int nprob;
   TileSched sched;
+  unsigned* queue;
 };
 __device__ __forceinline__ GemmView gemm_view() {
   const cptr<GemmTables> t = (cptr<GemmTables>)MPC_KERNARG_PTR();
   GemmView v;
   v.nprob = t->map.nprob;
   v.sched = t->sched;
+  v.queue = t->queue;
   v.probs = t->probs ? (cptr<LimbProblem>)(uintptr_t)t->probs : t->iprobs;
   v.tile_start = t->probs ? (cptr<int>)(uintptr_t)t->map.tile_start : t->itile_start;
   return v;
@@ -1026,6 +1028,80 @@ __global__ void __launch_bounds__(256, 2) k_limb_gemm_classes(GemmTables) {
     lds_tile<GClass0>(b0, b1, tv, tile_coords<GClass0::BM, GClass0::BN>(tv, pi, local));
 }
 
+// ------------------------------------------------------------------ persistent grouped GEMM
+// The classes launch as a persistent kernel (kLimbPersist): the grid is the
+// workgroups the chip holds at once (two per CU, a multiple of the XCD
+// count), and each workgroup runs tiles one after another, taking the next
+// from a queue of its XCD (its workgroup index modulo the XCD count, as the
+// dispatcher deals workgroups round the XCDs).  XCD x's queue lists the tiles
+// the dispatch-order remap above gives the workgroups it would receive, in
+// the order it would receive them: runs of neighbouring tiles, then the tail
+// of the list in dispatch order.  So the tiles an XCD holds at a time still
+// share operand blocks in its L2, and the longest tiles (listed first) still
+// start first.  A queue's head is a device-wide counter; every workgroup
+// keeps taking until its queue runs dry, so each tile runs exactly once
+// whichever XCD the workgroup landed on.  The last workgroup to finish sets
+// the counters back to zero for the next launch.
+
+// Tile j of XCD x's queue, or -1 past its end (T tiles in the launch).
+__device__ __forceinline__ int xcd_queue_tile(int x, int j, int T, bool remap, int run) {
+  if (remap) {
+    const int span = kXcds * run, full = T / span;
+    if (j < full * run) return ((j / run) * kXcds + x) * run + j % run;
+    const int t = full * span + (j - full * run) * kXcds + x;
+    return t < T ? t : -1;
+  }
+  const int t = j * kXcds + x;
+  return t < T ? t : -1;
+}
+
+__device__ __forceinline__ unsigned queue_take(unsigned* q) {
+  return __hip_atomic_fetch_add(q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256, 2) k_limb_gemm_persist(GemmTables) {
+  __shared__ v4i stage[2][kClassBuf / 16];
+  __shared__ int head[2];
+  const GemmView tv = gemm_view();
+  lds_u8* b0 = (lds_u8*)&stage[0][0];
+  lds_u8* b1 = (lds_u8*)&stage[1][0];
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x % kXcds;
+  const int T = tv.tile_start[tv.nprob];
+  unsigned* const q = tv.queue;
+  if (tid == 0) head[0] = (int)queue_take(q + x);
+  __syncthreads();
+  int j = __builtin_amdgcn_readfirstlane(head[0]);
+  for (int it = 1;; ++it) {
+    const int t = xcd_queue_tile(x, j, T, tv.sched.xcd_remap != 0, kXcdCUs * 2);
+    if (t < 0) break;
+    const int pi = find_problem(tv.tile_start, tv.nprob, t);
+    const i64 local = t - tv.tile_start[pi];
+    const int cls = tv.probs[pi].cls;
+    if (cls == 1)
+      lds_tile<GClass1>(b0, b1, tv, tile_coords<GClass1::BM, GClass1::BN>(tv, pi, local));
+    else if (cls == 2)
+      lds_tile<GClass2>(b0, b1, tv, tile_coords<GClass2::BM, GClass2::BN>(tv, pi, local));
+    else
+      lds_tile<GClass0>(b0, b1, tv, tile_coords<GClass0::BM, GClass0::BN>(tv, pi, local));
+    // the following queue position (taken here rather than when the tile
+    // starts: an atomic still in flight would hold up the tile's first
+    // hand-over, which waits for all of the wave's loads); head[] is
+    // double-buffered: every wave read the other slot before the barrier
+    // that ended the previous tile
+    if (tid == 0) head[it & 1] = (int)queue_take(q + x);
+    // every wave is past its last LDS read of this tile before the next
+    // tile's copies overwrite the step buffers
+    __syncthreads();
+    j = __builtin_amdgcn_readfirstlane(head[it & 1]);
+  }
+  // every workgroup took its last (empty) queue position above; the last to
+  // get here clears the counters
+  if (tid == 0 && queue_take(q + kXcds) == gridDim.x - 1) {
+    for (int i = 0; i <= kXcds; ++i) __hip_atomic_store(q + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ------------------------------------------------------------------ GEMM with both operands in LDS
 // k_limb_gemm_lds still streams the inner operand from global memory into
 // every wave's registers, so each inner strip crosses the vector-memory path
@@ -1321,9 +1397,9 @@ int limb_tiles(i64 M, i64 N, int variant) {
   return (int)(((M + bm - 1) / bm) * ((N + bn - 1) / bn));
 }
 // output rows and columns of one workgroup tile, per variant
-// (the classes variant: its class-0 tile; limb_class_tiles gives every class's)
-static const int kVariantBM[kLimbVariants] = {128, 64, 64, 128, 64, 64, 64, 128, 64, 64, 64, 128, 32, 128, 64};
-static const int kVariantBN[kLimbVariants] = {64, 128, 64, 64, 128, 64, 128, 64, 128, 64, 128, 64, 128, 32, 64};
+// (the classes variants: their class-0 tile; limb_class_tiles gives every class's)
+static const int kVariantBM[kLimbVariants] = {128, 64, 64, 128, 64, 64, 64, 128, 64, 64, 64, 128, 32, 128, 64, 64};
+static const int kVariantBN[kLimbVariants] = {64, 128, 64, 64, 128, 64, 128, 64, 128, 64, 128, 64, 128, 32, 64, 64};
 int limb_variant_bm(int variant) { return kVariantBM[variant]; }
 int limb_variant_bn(int variant) { return kVariantBN[variant]; }
 int limb_class_tiles(i64 M, i64 N, int cls) {
@@ -1359,10 +1435,21 @@ hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int
   return hipErrorInvalidValue;
 }
 
+int limb_persist_grid(int total_tiles, int num_cu) {
+  const int cap = std::max(kXcds, 2 * num_cu / kXcds * kXcds);
+  return std::min(cap, (total_tiles + kXcds - 1) / kXcds * kXcds);
+}
+
 hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles) {
   if (total_tiles <= 0) return hipSuccess;
   const TileSched& sched = t.sched;
   if (sched.group_m < 1 || sched.group_m > 64) return hipErrorInvalidValue;
+  if (sched.variant == kLimbPersist) {
+    // a multiple of the XCD count, so that every queue has workgroups
+    if (!t.queue || t.persist_grid < kXcds || t.persist_grid % kXcds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_limb_gemm_persist, dim3(t.persist_grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+  }
   const dim3 grid(total_tiles);
 #define MPC_LDS_CASE(V, HA, HB, WR, WC)                                                                    \
   case V:                                                                                                 \

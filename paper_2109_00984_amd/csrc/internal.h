@@ -296,15 +296,18 @@ hipError_t launch_pack(hipStream_t s, const PackTables& t, i64 total_blocks, int
 // rows or columns: 32x128 and 128x32 in the LDS form, four waves of 32x32
 // outputs in a row or a column, two workgroups per CU.  Variant 14 takes
 // each problem's tile class from LimbProblem::cls (0: 64x64, 1: 32x128,
-// 2: 128x32), all in one launch.
+// 2: 128x32), all in one launch.  Variant 15 is variant 14 as a persistent
+// kernel: as many workgroups as the chip holds at once, each taking tiles
+// from its XCD's queue until the queue is empty.
 enum LimbVariant : int {
   kLimb128x64 = 0, kLimb64x128 = 1, kLimb64x64 = 2,
   kLimbLds128x64 = 3, kLimbLds64x128 = 4, kLimbLds64x64 = 5,
   kLimbLds64x128w8 = 6, kLimbLds128x64w8 = 7, kLimbLds64x128w8s = 8,
   kLimbSh64x64 = 9, kLimbSh64x128 = 10, kLimbSh128x64 = 11,
-  kLimbThin32x128 = 12, kLimbThin128x32 = 13, kLimbClasses = 14
+  kLimbThin32x128 = 12, kLimbThin128x32 = 13, kLimbClasses = 14, kLimbPersist = 15
 };
-constexpr int kLimbVariants = 15;
+constexpr int kLimbVariants = 16;
+inline bool limb_per_class(int variant) { return variant == kLimbClasses || variant == kLimbPersist; }
 struct TileSched {
   int variant;    // LimbVariant
   int group_m;    // tile rows per raster group
@@ -387,15 +390,23 @@ hipError_t launch_fp64_pack_right(hipStream_t s, i64 N, i64 K0, i64 K1, const u6
 hipError_t launch_fp64_combine(hipStream_t s, i64 M, i64 N, int L, const double* X, const Epilogue& ep);
 
 // Problems of one GEMM launch: `probs` with `map.tile_start` (device), or when
-// `probs` is null the first map.nprob entries of iprobs/itile_start.
+// `probs` is null the first map.nprob entries of iprobs/itile_start.  The
+// persistent variant also takes `queue` (kLimbQueueWords zeroed words of
+// device memory, left zeroed when the launch ends; launches that share them
+// must not overlap in time) and runs `persist_grid` workgroups.
+constexpr int kLimbQueueWords = 16;
 struct GemmTables {
   const LimbProblem* probs;
   TileMap map;
   TileSched sched;
+  unsigned* queue;
+  int persist_grid;
   LimbProblem iprobs[kInlineProbs];
   int itile_start[kInlineProbs + 1];
 };
 hipError_t launch_limb_gemm(hipStream_t s, const GemmTables& t, int total_tiles);
+// Workgroups of a persistent launch over `total_tiles` tiles on `num_cu` CUs.
+int limb_persist_grid(int total_tiles, int num_cu);
 int limb_tiles(i64 M, i64 N, int variant);
 int limb_variant_bm(int variant);  // output rows of a workgroup tile
 int limb_variant_bn(int variant);  // and columns

@@ -1,7 +1,8 @@
 """The batching workload as specified: 256 Beaver matmuls of log-uniform
 shapes (M in [16, 2048], N in [16, 1024], K in [32, 4096]) with 2^16
-truncation, limb form, tile schedule chosen by the library's autotuner,
-captured once in a HIP graph and replayed.  Every replay is compared with the
+truncation, limb form, tile schedule chosen by the library's autotuner (or
+the persistent grouped launch, schedule 15, set as the default), captured
+once in a HIP graph and replayed.  Every replay is compared with the
 eager call on every element of both parties' shares, and the eager call with
 the oracle: in full where M*N*K <= 2^22, at sampled outputs of every other
 problem (section 6.1: batching amortises rounds; App. C.1.1, multiplication
@@ -33,13 +34,14 @@ def sample_positions(seed, M, N, count):
     return rows, cols
 
 
-def test_grouped_256_autotuned_graph_replay(m):
+@pytest.mark.parametrize("schedule", ["autotuned", "persistent"])
+def test_grouped_256_graph_replay(m, schedule):
     # captured on a stream of its own: the null stream cannot be captured
     with torch.cuda.stream(torch.cuda.Stream()):
-        _grouped_256_autotuned_graph_replay(m)
+        _grouped_256_graph_replay(m, schedule)
 
 
-def _grouped_256_autotuned_graph_replay(m):
+def _grouped_256_graph_replay(m, schedule):
     data_seed, pseed, dseed = workloads.seeds(5)
     shapes = workloads.grouped_shapes(data_seed, **{k: v for k, v in workloads.GROUPED.items() if k != "count"})
     assert len(shapes) == 256
@@ -53,9 +55,18 @@ def _grouped_256_autotuned_graph_replay(m):
             x, y = c.share(dev(X), 0, 2 * i), c.share(dev(Y), 1, 2 * i + 1)
             probs.append((x, y, c.dealer(m.TRIPLE_MATMUL, dseed, i, (M, N, K))))
             host_in.append((X, Y))
-        say("grouped graph: autotune")
-        best = c.autotune_matmul(shapes)
-        say(f"grouped graph: tuned schedule {best}")
+        if schedule == "autotuned":
+            say("grouped graph: autotune")
+            best = c.autotune_matmul(shapes)
+            say(f"grouped graph: tuned schedule {best}")
+        else:
+            c.set_default_tile_config(15, 8, True)  # every problem in its own tile class, one persistent launch
+            c.profile(True)
+            c.profile_read()
+            c.beaver_matmul_grouped(probs, FRAC, "limb8")
+            c.sync()
+            assert c.profile_read()["limb8"]["launches"] == 1
+            c.profile(False)
         outs = [m.SharedPair(c.empty((M, N)), c.empty((M, N))) for (M, N, K) in shapes]
         eager = c.beaver_matmul_grouped(probs, FRAC, "limb8")  # also sizes the workspace
         c.sync()

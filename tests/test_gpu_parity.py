@@ -474,7 +474,7 @@ def test_beaver_mul_unaligned_views(m, ctx, n):
     assert_pair(ctx, sq, wsq, "beaver square on views")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
 @pytest.mark.parametrize("group_m,remap", [(1, False), (8, True)])
 def test_limb_tile_variants(m, variant, group_m, remap):
     # every tile shape and schedule of the limb GEMM gives the oracle's result
@@ -536,8 +536,9 @@ def test_autotune_grouped_and_cache(m, tmp_path):
 def test_grouped_tile_classes(m):
     # thin products take the thin tiles: untuned, every problem runs in one
     # launch of the classes schedule with its own tile class (64x64, 32x128,
-    # 128x32); an explicit default schedule applies to every problem; the
-    # results are the oracle's either way
+    # 128x32); an explicit default schedule applies to every problem (the
+    # classes schedules, one-shot and persistent, each problem in its own
+    # class); the results are the oracle's either way
     say("grouped tile classes")
     c = m.Context(device=0, seed=SEED)
     shapes = [(300, 120, 500), (17, 200, 300), (150, 20, 260), (9, 5, 70)]  # regular, thin M, thin N, thin M
@@ -548,15 +549,15 @@ def test_grouped_tile_classes(m):
                       c.dealer(m.TRIPLE_MATMUL, 6, i, (M, N, K))))
         wants.append(oracle.beaver_matmul(oracle.share(X, 0, SEED, 30 + 2 * i), oracle.share(Y, 1, SEED, 31 + 2 * i),
                                           oracle.dealer_matmul(6, i, M, N, K), 16))
-    for explicit, launches in [(False, 1), (True, 1)]:
-        if explicit:
-            c.set_default_tile_config(5, 8, True)
+    for explicit in [None, 5, 14, 15]:
+        if explicit is not None:
+            c.set_default_tile_config(explicit, 8, True)
         c.sync()
         c.profile(True)
         c.profile_read()
         zs = c.beaver_matmul_grouped(probs, 16, "limb8")
         c.sync()
-        assert c.profile_read()["limb8"]["launches"] == launches, explicit
+        assert c.profile_read()["limb8"]["launches"] == 1, explicit
         c.profile(False)
         for z, w in zip(zs, wants):
             got = pair(c, z)

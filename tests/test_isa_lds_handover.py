@@ -1,6 +1,7 @@
 """Static check on the device assembly of the LDS-staged limb GEMM.
 
-Each k step of k_limb_gemm_lds hands its LDS buffers over at a barrier that
+Each k step of k_limb_gemm_lds (and of the classes kernels, one-shot and
+persistent, that run its tile) hands its LDS buffers over at a barrier that
 waits only until the wave's copies into LDS have landed: it lets the last
 few vector-memory loads (the next step's inner planes, issued after the
 copies) stay in flight.  Loads complete in issue order, so that wait is right
@@ -26,13 +27,17 @@ def build_module():
     return mod
 
 
+KERNELS = ("k_limb_gemm_lds", "k_limb_gemm_classes", "k_limb_gemm_persist")
+
+
 def handovers(asm):
-    """(kernel, waited vmcnt, register loads after the last LDS copy) per barrier."""
+    """(kernel, waited vmcnt, register loads after the last LDS copy, LDS
+    copies since the previous barrier) per barrier."""
     out, fn, seg, prev = [], None, [], ""
     for line in asm.splitlines():
         m = re.match(r"^(_Z\S*):", line)
         if m:
-            fn = m.group(1) if "k_limb_gemm_lds" in m.group(1) else None
+            fn = m.group(1) if any(k in m.group(1) for k in KERNELS) else None
             seg = []
         t = line.strip()
         if fn is None:
@@ -41,7 +46,8 @@ def handovers(asm):
         if t.startswith("s_barrier"):
             w = re.search(r"vmcnt\((\d+)\)", prev)
             last_copy = max((i for i, x in enumerate(seg) if x == "copy"), default=-1)
-            out.append((fn, int(w.group(1)) if w else None, sum(1 for x in seg[last_copy + 1:] if x == "load")))
+            out.append((fn, int(w.group(1)) if w else None, sum(1 for x in seg[last_copy + 1:] if x == "load"),
+                        seg.count("copy")))
             seg = []
         elif t.startswith("buffer_load") and t.endswith(" lds"):
             seg.append("copy")
@@ -59,12 +65,16 @@ def test_lds_handover_waits_cover_the_copies(tmp_path):
            os.path.join(b.CSRC, "gemm_limb.hip"), "-o", str(asm)]
     subprocess.run(cmd, check=True, capture_output=True)
     hs = handovers(asm.read_text())
-    kernels = {k for k, _, _ in hs}
-    assert len(kernels) == 8, kernels  # the eight LDS geometries (two of them thin)
+    kernels = {h[0] for h in hs}
+    # the eight LDS geometries (two of them thin), the classes kernel and its
+    # persistent form
+    assert len(kernels) == 10, kernels
     for k in kernels:
-        assert sum(1 for kk, _, _ in hs if kk == k) >= 3, k  # prologue and steps
-    for k, n, after in hs:
-        assert n is not None, (k, "barrier without a vmcnt wait before it")
+        assert sum(1 for h in hs if h[0] == k) >= 3, k  # prologue and steps
+    for k, n, after, copies in hs:
+        if copies == 0:
+            continue  # hands over no LDS copy (the persistent kernel's tile-to-tile barrier)
+        assert n is not None, (k, "barrier after LDS copies without a vmcnt wait before it")
         assert n == 0 or after >= n, (k, n, after)
 
 
@@ -84,5 +94,5 @@ def test_parser_flags_an_unsafe_wait():
         "\ts_barrier",
     ])
     hs = handovers(asm)
-    assert [(n, after) for _, n, after in hs] == [(2, 2), (2, 1)]
-    assert not all(n == 0 or after >= n for _, n, after in hs)
+    assert [(n, after, copies) for _, n, after, copies in hs] == [(2, 2, 1), (2, 1, 1)]
+    assert not all(n == 0 or after >= n for _, n, after, _ in hs)
