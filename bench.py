@@ -713,15 +713,22 @@ def conv_bench(mpc, torch, workloads, cpu=True):
         return h
 
     first = None
-    for form, reps in (("limb8", 5), ("plain", 1)):
+    same = True
+    # the paper's fp64 limb form too (vendor fp64 GEMMs over materialised im2col)
+    for form, reps in (("limb8", 5), ("plain", 1), ("fp64limb", 1)):
         h = forward(form)
         c.sync()
+        got = (h.s0.cpu().numpy().view(np.uint64), h.s1.cpu().numpy().view(np.uint64))
         if first is None:  # the limb form's output, for the oracle leg
-            first = (h.s0.cpu().numpy().view(np.uint64), h.s1.cpu().numpy().view(np.uint64))
+            first = got
+        same = same and all(np.array_equal(a, b) for a, b in zip(got, first))
         ms = _event_time(torch, c.streams[0], lambda: forward(form), reps)
         out[f"conv_stack_{form}_ms"] = round(ms, 3)
         out[f"conv_stack_{form}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
         log(f"bench: conv stack {form}: {ms:.3f} ms")
+    out["conv_stack_forms_bit_identical"] = bool(same)
+    out["conv_stack_limb_over_plain_speedup"] = round(out["conv_stack_plain_ms"] / out["conv_stack_limb8_ms"], 2)
+    out["conv_stack_limb_over_fp64limb_speedup"] = round(out["conv_stack_fp64limb_ms"] / out["conv_stack_limb8_ms"], 2)
     out["conv_stack_plaintext_macs"] = macs
     c.close()
     if cpu:

@@ -76,9 +76,12 @@ typedef enum {
  *          or, when the summed k is below 1024, three 22-bit limbs (six), each
  *          pairwise product an exact float64 GEMM of the vendor BLAS, combined
  *          mod 2^64.  Bit-identical to PLAIN; kept for comparison.  Supported
- *          by mpc_ring_gemm, mpc_beaver_matmul and mpc_beaver_matmul_grouped
- *          for summed k below 2^21 and outside graph capture; otherwise
- *          MPC_E_UNSUPPORTED (also from mpc_beaver_conv1d). */
+ *          by mpc_ring_gemm, mpc_beaver_matmul, mpc_beaver_matmul_grouped and
+ *          mpc_beaver_conv1d (over im2col matrices written to the workspace)
+ *          for summed k below 2^21; otherwise MPC_E_UNSUPPORTED.  The vendor
+ *          BLAS handle is made on the context's first fp64 call, which must
+ *          not be under graph capture (MPC_E_UNSUPPORTED, nothing recorded);
+ *          after that, fp64 calls are captured like any other. */
 typedef enum {
   MPC_FORM_PLAIN = 0,
   MPC_FORM_LIMB8 = 1,

@@ -559,6 +559,20 @@ size_t fp64_ws(i64 M, i64 N, i64 Kt) {
          align_up((size_t)(L * M * N) * 8);
 }
 
+// The vendor BLAS handle of the fp64 limb form, created on first use.  Its
+// creation allocates device memory, so it cannot happen inside a graph
+// capture: an fp64 call captured on a context that has never run one eagerly
+// is refused (before it issues any work).
+mpc_status fp64_ready(mpc_ctx* c) {
+  if (c->blas) return MPC_OK;
+  if (c->capturing) return MPC_E_UNSUPPORTED;
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return MPC_E_HIP;
+  }
+  return MPC_OK;
+}
+
 // C = [A0 | A1] @ [B0 ; B1] (mod 2^64) through fp64 limb planes and one vendor
 // fp64 GEMM per diagonal, on party 0's stream; `cv` provides fp64_ws bytes.
 mpc_status issue_fp64(mpc_ctx* c, Carve& cv, i64 M, i64 N, i64 K0, i64 K1, const u64* A0, i64 lda0,
@@ -566,21 +580,24 @@ mpc_status issue_fp64(mpc_ctx* c, Carve& cv, i64 M, i64 N, i64 K0, i64 K1, const
                       const Epilogue& ep) {
   const i64 Kt = K0 + K1;
   if (Kt >= kFp64MaxK) return MPC_E_UNSUPPORTED;
-  if (c->capturing) return MPC_E_UNSUPPORTED;  // vendor BLAS calls are not captured
-  if (!c->blas) {
-    if (rocblas_create_handle(&c->blas) != rocblas_status_success) return MPC_E_HIP;
-  }
+  CHK(fp64_ready(c));
   if (rocblas_set_stream(c->blas, c->s[0]) != rocblas_status_success) return MPC_E_HIP;
   const int L = fp64_limbs(Kt);
   double* LA = cv.take<double>((size_t)(M * L * Kt));
   double* RB = cv.take<double>((size_t)(L * Kt * N));
   double* X = cv.take<double>((size_t)(L * M * N));
   const hipStream_t st = c->s[0];
-  if (Kt > 0) {
-    CHK(hip_status(launch_fp64_pack_left(st, M, K0, K1, A0, lda0, A1, lda1, L, LA)));
-    CHK(hip_status(launch_fp64_pack_right(st, N, K0, K1, B0, ldb0, B1, ldb1, L, RB)));
-    c->stats.launches += 2;
+  if (Kt == 0) {
+    // an empty sum: no diagonal enters the combine (no memory clearing, which
+    // a graph capture should not record)
+    CHK(hip_status(launch_fp64_combine(st, M, N, 0, X, ep)));
+    c->stats.launches++;
+    c->stats.gemm_problems++;
+    return MPC_OK;
   }
+  CHK(hip_status(launch_fp64_pack_left(st, M, K0, K1, A0, lda0, A1, lda1, L, LA)));
+  CHK(hip_status(launch_fp64_pack_right(st, N, K0, K1, B0, ldb0, B1, ldb1, L, RB)));
+  c->stats.launches += 2;
   // diagonal s: X_s = LA[:, 0:(s+1)Kt] @ RB[(L-1-s)Kt : L Kt, :]; row-major
   // products are issued as column-major X_s^T = RB_sub^T LA_sub^T
   const double one = 1.0, zero = 0.0;
@@ -588,10 +605,6 @@ mpc_status issue_fp64(mpc_ctx* c, Carve& cv, i64 M, i64 N, i64 K0, i64 K1, const
   CHK(tm.start());
   for (int sd = 0; sd < L; ++sd) {
     double* Xs = X + (size_t)sd * (size_t)(M * N);
-    if (Kt == 0) {
-      HIPCHK(hipMemsetAsync(Xs, 0, (size_t)(M * N) * 8, st));
-      continue;
-    }
     const rocblas_status bs = rocblas_dgemm(
         c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
         (rocblas_int)((sd + 1) * Kt), &one, RB + (size_t)(L - 1 - sd) * (size_t)Kt * (size_t)N,
@@ -1445,6 +1458,7 @@ mpc_status run_matmuls_fp64(mpc_ctx* c, const std::vector<MatmulPlan>& plans, in
     need += matmul_ws(m, MPC_FORM_PLAIN);
     fp = std::max(fp, fp64_ws(m.M, m.N, 2 * m.K));
   }
+  CHK(fp64_ready(c));
   CHK(ensure_ws(c, need + fp));
   Carve cv(c->ws);
   std::vector<OpenJob> opens;
@@ -1752,7 +1766,6 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
   CHK(check_conv(shape));
   CHK(check_trunc(trunc_bits));
   CHK(check_form(form));
-  if (form == MPC_FORM_FP64LIMB) return MPC_E_UNSUPPORTED;
   const mpc_conv1d_shape s = *shape;
   const i64 lout = conv_lout(s);
   const size_t nx = (size_t)(s.batch * s.cin * s.length), nw = (size_t)(s.cout * s.cin * s.ksize);
@@ -1786,8 +1799,14 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
                               make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
     CHK(issue_limb(c, {W, X}, reqs, c->sched_default));
   } else {
+    // plain and fp64 limb forms: open, then im2col of eps, g_0 and a_1 into
+    // row-major K x N matrices
     const size_t kn = (size_t)(K * N);
-    CHK(ensure_ws(c, kAlign + 2 * align_up(nx * 8) + align_up(nw * 8) + 3 * align_up(kn * 8)));
+    const bool fp = form == MPC_FORM_FP64LIMB;
+    if (fp && 2 * K >= kFp64MaxK) return MPC_E_UNSUPPORTED;
+    if (fp) CHK(fp64_ready(c));
+    CHK(ensure_ws(c, kAlign + 2 * align_up(nx * 8) + align_up(nw * 8) + 3 * align_up(kn * 8) +
+                         (fp ? fp64_ws(M, N, 2 * K) : 0)));
     Carve cv(c->ws);
     u64* eps = cv.take<u64>(nx);
     u64* g = cv.take<u64>(nx);
@@ -1802,12 +1821,22 @@ mpc_status mpc_beaver_conv1d(mpc_ctx* c, const mpc_conv1d_shape* shape, const ui
     CHK(hip_status(launch_im2col(st, g, nullptr, s.batch, s.cin, s.length, s.ksize, s.stride, lout, col_g)));
     CHK(hip_status(launch_im2col(st, t->a1, nullptr, s.batch, s.cin, s.length, s.ksize, s.stride, lout, col_a1)));
     c->stats.launches += 3;
-    std::vector<PlainProblem> probs;
-    for (int p = 0; p < 2; ++p)
-      probs.push_back(plain_problem(M, N, K, K, p == 0 ? t->b0 : t->b1, nullptr, K, del, K, col_e, nullptr, N,
-                                    p == 0 ? col_g : col_a1, N,
-                                    make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
-    CHK(issue_plain(c, probs));
+    if (fp) {
+      // each party's [Wm(b_p) | Wm(delta)] @ [im2col(eps) ; im2col(g_p)], one
+      // after the other through one fp64 workspace
+      for (int p = 0; p < 2; ++p) {
+        Carve fcv = cv;
+        CHK(issue_fp64(c, fcv, M, N, K, K, p == 0 ? t->b0 : t->b1, K, del, K, col_e, N, p == 0 ? col_g : col_a1,
+                       N, make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
+      }
+    } else {
+      std::vector<PlainProblem> probs;
+      for (int p = 0; p < 2; ++p)
+        probs.push_back(plain_problem(M, N, K, K, p == 0 ? t->b0 : t->b1, nullptr, K, del, K, col_e, nullptr, N,
+                                      p == 0 ? col_g : col_a1, N,
+                                      make_ep(p == 0 ? t->c0 : t->c1, +1, trunc_bits, p == 0 ? z0 : z1, view)));
+      CHK(issue_plain(c, probs));
+    }
   }
   c->stats.opens++;
   c->stats.open_bytes_per_party += 8 * (uint64_t)(nx + nw);

@@ -1,7 +1,8 @@
 """GPU parity of the fp64 limb form (the paper's own GPU method, Section 5.3):
 ring GEMM and Beaver matmul against the CPU oracle, bit for bit, on both limb
 splits (three 22-bit limbs below 1024 summed k, four 16-bit limbs above), with
-limb values at the extremes of each split."""
+limb values at the extremes of each split; k = 0; replay from a HIP graph.
+(Its convolution runs with the other forms' in test_gpu_parity.py.)"""
 import numpy as np
 import pytest
 
@@ -102,11 +103,67 @@ def test_fp64limb_unsupported_cases(m, ctx):
     with pytest.raises(m.MPCError) as e:
         ctx.ring_gemm(A, B, form=FORM)
     assert e.value.status == -6
-    # convolution has no fp64 limb path
-    b, cin, L, cout, k = 1, 2, 8, 3, 3
-    x = ctx.share(dev(rnd(1, (b, cin, L))), 0, 1)
-    w = ctx.share(dev(rnd(2, (cout, cin, k))), 1, 2)
-    t = ctx.dealer(m.TRIPLE_CONV1D, 7, 3, (b, cin, L, cout, k, 1))
-    with pytest.raises(m.MPCError) as e:
-        ctx.beaver_conv1d(x, w, t, 1, 0, FORM)
-    assert e.value.status == -6
+
+
+def test_fp64limb_k_zero(m, ctx):
+    # an empty sum: the product is 0 and the epilogue still adds the triple share
+    say("fp64limb k = 0")
+    M, N = 7, 9
+    t = ctx.dealer(m.TRIPLE_MATMUL, 3102, 61, (M, N, 0))
+    x = ctx.share(dev(np.zeros((M, 0), dtype=np.uint64)), 0, 53)
+    y = ctx.share(dev(np.zeros((0, N), dtype=np.uint64)), 1, 54)
+    z = ctx.beaver_matmul(x, y, t, 16, FORM)
+    want = oracle.beaver_matmul(oracle.share(np.zeros((M, 0), dtype=np.uint64), 0, SEED, 53),
+                                oracle.share(np.zeros((0, N), dtype=np.uint64), 1, SEED, 54),
+                                oracle.dealer_matmul(3102, 61, M, N, 0), 16)
+    g0, g1 = pair(ctx, z)
+    assert np.array_equal(g0, want[0]) and np.array_equal(g1, want[1])
+
+
+def test_fp64limb_graph_replay(m):
+    # the vendor BLAS GEMMs are recorded into a graph like the library's own
+    # kernels once the context has created its BLAS handle eagerly; before
+    # that, a captured fp64 call is refused and records nothing
+    import torch
+    with torch.cuda.stream(torch.cuda.Stream()):
+        c = m.Context(device=0, seed=SEED)
+        try:
+            M, N, K = 72, 40, 300
+            X = oracle.encode(workloads.uniform(81, (M, K), -4, 4))
+            Y = oracle.encode(workloads.uniform(82, (K, N), -4, 4))
+            x, y = c.share(dev(X), 0, 55), c.share(dev(Y), 1, 56)
+            t = c.dealer(m.TRIPLE_MATMUL, 3103, 62, (M, N, K))
+            out = m.SharedPair(c.empty((M, N)), c.empty((M, N)))
+            c.sync()
+            say("fp64limb capture before any eager fp64 call")
+            c.graph_begin()
+            with pytest.raises(m.MPCError) as e:
+                c.beaver_matmul(x, y, t, 16, FORM, out=out)
+            g = c.graph_end()
+            g.destroy()
+            assert e.value.status == -6
+            eager = c.beaver_matmul(x, y, t, 16, FORM)
+            c.sync()
+            want = oracle.beaver_matmul(oracle.share(X, 0, SEED, 55), oracle.share(Y, 1, SEED, 56),
+                                        oracle.dealer_matmul(3103, 62, M, N, K), 16)
+            g0, g1 = pair(c, eager)
+            assert np.array_equal(g0, want[0]) and np.array_equal(g1, want[1])
+            say("fp64limb capture")
+            c.graph_begin()
+            c.beaver_matmul(x, y, t, 16, FORM, out=out)
+            g = c.graph_end()
+            try:
+                for rep in range(3):
+                    out.s0.fill_(-1)
+                    out.s1.fill_(-1)
+                    say(f"fp64limb replay {rep}")
+                    c.graph_launch(g)
+                    c.sync()
+                    r0, r1 = pair(c, out)
+                    assert np.array_equal(r0, want[0]) and np.array_equal(r1, want[1]), rep
+                    c.ring_gemm(dev(X[:, :8]), dev(Y[:8, :]), form=FORM)  # eager work between replays
+                    c.sync()
+            finally:
+                g.destroy()
+        finally:
+            c.close()

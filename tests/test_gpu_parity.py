@@ -360,7 +360,7 @@ CONV_SMALL = [(2, 3, 17, 4, 5, 2), (1, 40, 100, 16, 48, 2), (2, 8, 30, 8, 7, 1),
               (1, 16, 40, 32, 1, 1), (4, 16, 300, 64, 7, 1)]
 
 
-@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("form", ["plain", "limb8", "fp64limb"])
 @pytest.mark.parametrize("Bt,Cin,L,Cout,k,s", CONV_SMALL)
 def test_beaver_conv1d(m, ctx, form, Bt, Cin, L, Cout, k, s):
     say(f"beaver conv1d {form} {(Bt, Cin, L, Cout, k, s)}")
