@@ -1031,17 +1031,21 @@ __global__ void __launch_bounds__(256, 2) k_limb_gemm_classes(GemmTables) {
 // ------------------------------------------------------------------ persistent grouped GEMM
 // The classes launch as a persistent kernel (kLimbPersist): the grid is the
 // workgroups the chip holds at once (two per CU, a multiple of the XCD
-// count), and each workgroup runs tiles one after another, taking the next
-// from a queue of its XCD (its workgroup index modulo the XCD count, as the
-// dispatcher deals workgroups round the XCDs).  XCD x's queue lists the tiles
-// the dispatch-order remap above gives the workgroups it would receive, in
-// the order it would receive them: runs of neighbouring tiles, then the tail
-// of the list in dispatch order.  So the tiles an XCD holds at a time still
-// share operand blocks in its L2, and the longest tiles (listed first) still
-// start first.  A queue's head is a device-wide counter; every workgroup
-// keeps taking until its queue runs dry, so each tile runs exactly once
-// whichever XCD the workgroup landed on.  The last workgroup to finish sets
-// the counters back to zero for the next launch.
+// count), and each workgroup runs tiles one after another, taken from queues
+// of tiles per XCD.  XCD x's queue lists the tiles the dispatch-order remap
+// above gives the workgroups the dispatcher would hand to XCD x (it deals
+// workgroups round the XCDs in index order), in the order it would hand them
+// out: runs of neighbouring tiles, then the tail of the list in dispatch
+// order.  So the tiles an XCD holds at a time still share operand blocks in
+// its L2, and the longest tiles (listed first) still start first.  A
+// workgroup reads which XCD it runs on from the hardware, takes from that
+// XCD's queue until it runs dry, then from the other XCDs' queues in turn
+// (evening out the XCDs' last tiles), and leaves when all eight are dry: so
+// every tile runs exactly once wherever the workgroups land.  A queue's head
+// is a device-wide counter, taken by one vector atomic per tile (after the
+// tile: an atomic still in flight when the next tile's prologue waits for
+// its loads would stall it) and broadcast through LDS; the last workgroup
+// to leave sets the counters back to zero for the next launch.
 
 // Tile j of XCD x's queue, or -1 past its end (T tiles in the launch).
 __device__ __forceinline__ int xcd_queue_tile(int x, int j, int T, bool remap, int run) {
@@ -1059,6 +1063,13 @@ __device__ __forceinline__ unsigned queue_take(unsigned* q) {
   return __hip_atomic_fetch_add(q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The XCD this wave runs on (hardware register XCC_ID).
+__device__ __forceinline__ int xcd_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+  return (int)(v & (kXcds - 1));
+}
+
 __global__ void __launch_bounds__(256, 2) k_limb_gemm_persist(GemmTables) {
   __shared__ v4i stage[2][kClassBuf / 16];
   __shared__ int head[2];
@@ -1066,15 +1077,25 @@ __global__ void __launch_bounds__(256, 2) k_limb_gemm_persist(GemmTables) {
   lds_u8* b0 = (lds_u8*)&stage[0][0];
   lds_u8* b1 = (lds_u8*)&stage[1][0];
   const int tid = threadIdx.x;
-  const int x = blockIdx.x % kXcds;
+  const int x = xcd_id();
   const int T = tv.tile_start[tv.nprob];
   unsigned* const q = tv.queue;
+  // head[] is double-buffered: a slot is written only after the barrier
+  // that follows every wave's read of its previous value
   if (tid == 0) head[0] = (int)queue_take(q + x);
   __syncthreads();
   int j = __builtin_amdgcn_readfirstlane(head[0]);
+  int qi = 0;  // queue (x + qi) mod 8: the own XCD's first
   for (int it = 1;; ++it) {
-    const int t = xcd_queue_tile(x, j, T, tv.sched.xcd_remap != 0, kXcdCUs * 2);
-    if (t < 0) break;
+    const int xq = (x + qi) & (kXcds - 1);
+    const int t = xcd_queue_tile(xq, j, T, tv.sched.xcd_remap != 0, kXcdCUs * 2);
+    if (t < 0) {
+      if (++qi == kXcds) break;
+      if (tid == 0) head[it & 1] = (int)queue_take(q + ((x + qi) & (kXcds - 1)));
+      __syncthreads();
+      j = __builtin_amdgcn_readfirstlane(head[it & 1]);
+      continue;
+    }
     const int pi = find_problem(tv.tile_start, tv.nprob, t);
     const i64 local = t - tv.tile_start[pi];
     const int cls = tv.probs[pi].cls;
@@ -1084,19 +1105,14 @@ __global__ void __launch_bounds__(256, 2) k_limb_gemm_persist(GemmTables) {
       lds_tile<GClass2>(b0, b1, tv, tile_coords<GClass2::BM, GClass2::BN>(tv, pi, local));
     else
       lds_tile<GClass0>(b0, b1, tv, tile_coords<GClass0::BM, GClass0::BN>(tv, pi, local));
-    // the following queue position (taken here rather than when the tile
-    // starts: an atomic still in flight would hold up the tile's first
-    // hand-over, which waits for all of the wave's loads); head[] is
-    // double-buffered: every wave read the other slot before the barrier
-    // that ended the previous tile
-    if (tid == 0) head[it & 1] = (int)queue_take(q + x);
+    if (tid == 0) head[it & 1] = (int)queue_take(q + xq);
     // every wave is past its last LDS read of this tile before the next
     // tile's copies overwrite the step buffers
     __syncthreads();
     j = __builtin_amdgcn_readfirstlane(head[it & 1]);
   }
-  // every workgroup took its last (empty) queue position above; the last to
-  // get here clears the counters
+  // every workgroup found all eight queues dry above; the last to get here
+  // clears the counters
   if (tid == 0 && queue_take(q + kXcds) == gridDim.x - 1) {
     for (int i = 0; i <= kXcds; ++i) __hip_atomic_store(q + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
