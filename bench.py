@@ -652,6 +652,11 @@ def grouped_bench(mpc, torch, workloads):
 
         timed("plain", "plain")
         timed("default_schedule")
+        # the persistent grouped launch (schedule 15, each problem in its own
+        # tile class), which the autotuner below also times
+        c.set_default_tile_config(15, 8, True)
+        timed("persistent")
+        c.set_default_tile_config(5, 8, True)
         best = c.autotune_matmul(shapes)
         out["grouped256_tuned_schedule"] = best
         timed("autotuned")
@@ -678,6 +683,8 @@ def grouped_bench(mpc, torch, workloads):
         out["grouped256_limb_over_plain_speedup"] = round(out["grouped256_plain_ms"] / out["grouped256_autotuned_ms"], 2)
         out["grouped256_autotuned_over_default"] = round(
             out["grouped256_default_schedule_ms"] / out["grouped256_autotuned_ms"], 3)
+        out["grouped256_autotuned_over_persistent"] = round(
+            out["grouped256_persistent_ms"] / out["grouped256_autotuned_ms"], 3)
         c.close()
     return out
 
