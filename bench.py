@@ -39,6 +39,8 @@ def log(*a):
 
 EXTRAS = ("ceilings", "small", "ring_gemm", "beaver_mul", "mlp", "sweep", "multiparty", "binary", "grouped", "grouped_mul",
           "conv", "power")
+# run only when named: for profiling runs
+OPT_EXTRAS = ("grouped_schedules",)
 
 
 def main():
@@ -52,8 +54,9 @@ def main():
                          "Beaver matmul packs only eps, a0 + eps and delta; or a plain triple")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--extra", action="append", choices=EXTRAS, metavar="NAME",
-                    help="run only these secondary measurements (repeatable): " + ", ".join(EXTRAS))
+    ap.add_argument("--extra", action="append", choices=EXTRAS + OPT_EXTRAS, metavar="NAME",
+                    help="run only these secondary measurements (repeatable): " + ", ".join(EXTRAS) +
+                         "; only when named: " + ", ".join(OPT_EXTRAS))
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="after the JSON line, run three device-to-device copies of MIB MiB "
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
@@ -284,6 +287,8 @@ def secondary(ctx, mpc, torch, workloads, X, Y, only, cpu=True):
     ctx.sync()
     if "grouped" in only:
         ex.update(grouped_bench(mpc, torch, workloads))
+    if "grouped_schedules" in only:
+        ex.update(grouped_schedules(mpc, torch, workloads))
     if "grouped_mul" in only:
         ex.update(grouped_mul_bench(mpc, torch, workloads))
     if "conv" in only:
@@ -685,6 +690,53 @@ def grouped_bench(mpc, torch, workloads):
             out["grouped256_default_schedule_ms"] / out["grouped256_autotuned_ms"], 3)
         out["grouped256_autotuned_over_persistent"] = round(
             out["grouped256_persistent_ms"] / out["grouped256_autotuned_ms"], 3)
+        c.close()
+    return out
+
+
+def grouped_schedules(mpc, torch, workloads, reps=10):
+    """The 256-problem batch (plain triples) replayed from a graph under the
+    one-shot classes launch (schedule 14) and the persistent one (15), each
+    problem in its own tile class, `reps` replays each, for kernel traces and
+    counters of the two grouped GEMM launches."""
+    data_seed, pseed, dseed = workloads.seeds(5)
+    shapes = workloads.grouped_shapes(data_seed)
+    side = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(side):
+        c = mpc.Context(device=0, seed=pseed)
+        probs = []
+        for i, (m, n, k) in enumerate(shapes):
+            x = c.share(torch.from_numpy(workloads.uniform_u64(data_seed * 1000 + 2 * i, (m, k)).view(np.int64)).to(c.device), 0, 2 * i)
+            y = c.share(torch.from_numpy(workloads.uniform_u64(data_seed * 1000 + 2 * i + 1, (k, n)).view(np.int64)).to(c.device), 1, 2 * i + 1)
+            probs.append((x, y, c.dealer(mpc.TRIPLE_MATMUL, dseed, i, (m, n, k))))
+        outs = [mpc.SharedPair(c.empty((m, n)), c.empty((m, n))) for (m, n, k) in shapes]
+        first = None
+        for sched, label in ((14, "classes"), (15, "persistent")):
+            c.set_default_tile_config(sched, 8, True)
+            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)
+            c.sync()
+            got = torch.cat([torch.cat([o.s0.reshape(-1), o.s1.reshape(-1)]) for o in outs])
+            first = got if first is None else first
+            out["grouped256_schedules_bit_identical"] = bool(torch.equal(got, first))
+            c.graph_begin()
+            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)
+            g = c.graph_end()
+            c.profile(True)
+            c.profile_read()
+            ms = _event_time(torch, side, lambda: c.graph_launch(g), reps)
+            c.sync()
+            mpc.Context.graph_destroy(g)
+            # the GEMM launches alone, from the library's own event record
+            # (eager: graph replays record none), one eager call per schedule
+            c.beaver_matmul_grouped(probs, FRAC, "limb8", outs=outs)
+            c.sync()
+            gemm = c.profile_read()["limb8"]
+            c.profile(False)
+            out[f"grouped256_{label}_replay_ms"] = round(ms, 4)
+            out[f"grouped256_{label}_gemm_ms"] = round(gemm["total_ms"] / max(1, gemm["launches"]), 4)
+            log(f"bench: grouped 256 schedule {sched} ({label}): replay {ms:.3f} ms, GEMM launch "
+                f"{out[f'grouped256_{label}_gemm_ms']:.3f} ms")
         c.close()
     return out
 
