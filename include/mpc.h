@@ -347,7 +347,10 @@ typedef struct {
  * product a class by its shape: "thin in M" (at most 32 rows) or "thin in N"
  * (at most 32 columns) when the 32x128 or 128x32 tile leaves at most nine
  * tenths of the 64x64 tile's padded work, else "regular"; a grouped call
- * issues one GEMM launch per schedule in use.  Untuned, every product takes
+ * issues one GEMM launch per schedule in use.  Under schedules 14 and 15 a
+ * regular product's last rows (columns), when they fill at most half of a
+ * 64-row (64-column) tile, run as a strip of 32x128 (128x32) tiles beside its
+ * 64x64 tiles.  Untuned, every product takes
  * the default schedule (schedule 14 or 15 as the default: each product in its
  * own class), unless some product is thin and no default was set
  * with mpc_set_default_tile_config: then all of them run in one launch of

@@ -734,6 +734,40 @@ struct LimbReq {
   int cls;          // tile class under the classes variants
 };
 
+// A rectangle of a product's output: rows [r0, r0 + m), columns [c0, c0 + n)
+// in tile class cls.
+struct Region {
+  i64 r0, c0, m, n;
+  int cls;
+};
+
+// The regions a request runs as (see issue_limb).  Every tile of a region
+// reads only row and column blocks inside the product's packed operands,
+// whose row and column counts are padded to multiples of 32 * kLimbRowPad:
+// a strip's thin tiles span at most the padded extent of the rest (the
+// 64-aligned part), and the corner's one 64x64 tile ends at most at the
+// padded edge (checked below; otherwise the request is not split).
+std::vector<Region> limb_regions(const LimbReq& r, const TileSched& ts) {
+  const std::vector<Region> whole{Region{0, 0, r.M, r.N, r.cls}};
+  const bool rowmajor = r.ep.view.ld_q == 0 && r.ep.view.n_div >= r.N;
+  if (!limb_per_class(ts.variant) || r.cls != 0 || !rowmajor) return whole;
+  const i64 rm = r.M % 64, rn = r.N % 64;
+  const i64 m64 = (rm > 0 && rm <= 32) ? r.M - rm : r.M;
+  const i64 n64 = (rn > 0 && rn <= 32) ? r.N - rn : r.N;
+  if ((m64 == r.M && n64 == r.N) || m64 == 0 || n64 == 0) return whole;
+  std::vector<Region> g{Region{0, 0, m64, n64, 0}};
+  if (m64 < r.M) g.push_back(Region{m64, 0, r.M - m64, n64, 1});
+  if (n64 < r.N) g.push_back(Region{0, n64, m64, r.N - n64, 2});
+  if (m64 < r.M && n64 < r.N) g.push_back(Region{m64, n64, r.M - m64, r.N - n64, 0});
+  const i64 rows = limb_rblocks(r.M) * 32, cols = limb_rblocks(r.N) * 32;
+  for (const Region& x : g) {
+    int bm = 0, bn = 0;
+    limb_class_shape(x.cls, &bm, &bn);
+    if (x.r0 + (x.m + bm - 1) / bm * bm > rows || x.c0 + (x.n + bn - 1) / bn * bn > cols) return whole;
+  }
+  return g;
+}
+
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
 // whose concatenated K exceeds the int32-safe range continues in the next
 // launch, adding into its output; truncation is applied by its last chunk).
@@ -785,10 +819,25 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
   // epilogue (split-K).
   std::vector<int> nchunks(nreq), nslices(nreq, 1);
   auto sched_of = [&](size_t q) { return reqs[q].own_sched ? reqs[q].sched : sched; };
+  // Output regions of each request, each run as a problem of its own.  Under
+  // a classes schedule a regular product whose last rows (columns) fill at
+  // most half of a 64-row (64-column) tile runs those as a strip of 32x128
+  // (128x32) tiles beside 64x64 tiles over the rest, and the corner they
+  // share as one 64x64 tile: the padded work then follows the product's
+  // edges at 32 instead of 64.  (Row-major outputs only: a region is a
+  // pointer offset into the operands' packed row and column blocks and into
+  // the output and triple share.)
+  std::vector<std::vector<Region>> regions(nreq);
+  // (not for a no-alloc call: its two problems must fit the kernel arguments)
+  for (size_t q = 0; q < nreq; ++q)
+    regions[q] = no_alloc ? std::vector<Region>{Region{0, 0, reqs[q].M, reqs[q].N, reqs[q].cls}}
+                          : limb_regions(reqs[q], sched_of(q));
   auto tiles_of = [&](size_t q) {
     const TileSched t = sched_of(q);
-    return limb_per_class(t.variant) ? limb_class_tiles(reqs[q].M, reqs[q].N, reqs[q].cls)
-                                     : limb_tiles(reqs[q].M, reqs[q].N, t.variant);
+    int n = 0;
+    for (const Region& g : regions[q])
+      n += limb_per_class(t.variant) ? limb_class_tiles(g.m, g.n, g.cls) : limb_tiles(g.m, g.n, t.variant);
+    return n;
   };
   i64 tiles_all = 0;
   for (size_t q = 0; q < nreq; ++q) {
@@ -841,26 +890,36 @@ mpc_status issue_limb(mpc_ctx* c, const std::vector<PackJob>& jobs_in, const std
     };
     const TileSched ts = sched_of(q);
     auto piece = [&](int chunk, int kb_begin, int kb_end, const Epilogue& ep) -> mpc_status {
-      LimbProblem p{};
-      p.M = r.M;
-      p.N = r.N;
-      p.kb0 = kb0;
-      p.kb1 = kb1;
-      p.kb_begin = kb_begin;
-      p.kb_end = kb_end;
       // the GEMM steps over pairs of k-blocks inside one segment
-      if ((p.kb0 | p.kb1 | p.kb_begin | p.kb_end) & 1) return MPC_E_INVAL;
-      p.PA0 = r.PA0;
-      p.PA1 = r.PA1;
-      p.PB0 = r.PB0;
-      p.PB1 = r.PB1;
-      p.mblocks = limb_rblocks(r.M);
-      p.nblocks = limb_rblocks(r.N);
-      p.ep = ep;
-      p.cls = r.cls;
+      if ((kb0 | kb1 | kb_begin | kb_end) & 1) return MPC_E_INVAL;
       Launch& l = launch_of(chunk, ts);
-      l.pieces.push_back(p);
-      l.tstarts.push_back(l.tstarts.back() + tiles_of(q));
+      for (const Region& g : regions[q]) {
+        LimbProblem p{};
+        p.M = g.m;
+        p.N = g.n;
+        p.kb0 = kb0;
+        p.kb1 = kb1;
+        p.kb_begin = kb_begin;
+        p.kb_end = kb_end;
+        // a region starts at a whole 32-row (32-column) block: block (rb, kb)
+        // of a segment sits at (rb * kblocks + kb) * 8 KiB
+        const size_t ra = (size_t)(g.r0 / 32) * kLimbBlockBytes, cb = (size_t)(g.c0 / 32) * kLimbBlockBytes;
+        p.PA0 = r.PA0 + ra * (size_t)kb0;
+        p.PA1 = r.PA1 ? r.PA1 + ra * (size_t)kb1 : nullptr;
+        p.PB0 = r.PB0 + cb * (size_t)kb0;
+        p.PB1 = r.PB1 ? r.PB1 + cb * (size_t)kb1 : nullptr;
+        p.mblocks = limb_rblocks(r.M) - g.r0 / 32;
+        p.nblocks = limb_rblocks(r.N) - g.c0 / 32;
+        p.ep = ep;
+        const i64 eoff = g.r0 * ep.view.ld_m + g.c0;
+        p.ep.Out = ep.Out + eoff;
+        if (ep.Cadd) p.ep.Cadd = ep.Cadd + eoff;
+        p.cls = g.cls;
+        l.pieces.push_back(p);
+        l.tstarts.push_back(l.tstarts.back() +
+                            (limb_per_class(ts.variant) ? limb_class_tiles(g.m, g.n, g.cls)
+                                                        : limb_tiles(g.m, g.n, ts.variant)));
+      }
       l.macs += (double)r.M * (double)r.N * (double)(true_k(kb_end) - true_k(kb_begin));
       return MPC_OK;
     };

@@ -1418,6 +1418,10 @@ static const int kVariantBM[kLimbVariants] = {128, 64, 64, 128, 64, 64, 64, 128,
 static const int kVariantBN[kLimbVariants] = {64, 128, 64, 64, 128, 64, 128, 64, 128, 64, 128, 64, 128, 32, 64, 64};
 int limb_variant_bm(int variant) { return kVariantBM[variant]; }
 int limb_variant_bn(int variant) { return kVariantBN[variant]; }
+void limb_class_shape(int cls, int* bm, int* bn) {
+  *bm = cls == 1 ? GClass1::BM : cls == 2 ? GClass2::BM : GClass0::BM;
+  *bn = cls == 1 ? GClass1::BN : cls == 2 ? GClass2::BN : GClass0::BN;
+}
 int limb_class_tiles(i64 M, i64 N, int cls) {
   const i64 bm = cls == 1 ? GClass1::BM : cls == 2 ? GClass2::BM : GClass0::BM;
   const i64 bn = cls == 1 ? GClass1::BN : cls == 2 ? GClass2::BN : GClass0::BN;

@@ -411,6 +411,7 @@ int limb_tiles(i64 M, i64 N, int variant);
 int limb_variant_bm(int variant);  // output rows of a workgroup tile
 int limb_variant_bn(int variant);  // and columns
 int limb_class_tiles(i64 M, i64 N, int cls);  // tiles of an M x N product in tile class cls
+void limb_class_shape(int cls, int* bm, int* bn);  // workgroup tile of tile class cls
 i64 limb_rblocks(i64 rows);  // padded 32-row block count
 i64 limb_kblocks(i64 K);
 
