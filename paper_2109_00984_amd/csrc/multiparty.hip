@@ -105,19 +105,39 @@ __global__ void __launch_bounds__(kMpThreads)
 }
 
 // Beaver product / square among P parties, mask, open and finish in one pass.
+// The loops run over PMAX >= P parties (the smallest of 2, 4, 8, 16) with a
+// test of p against P, so that every index is known when compiling: a_p and
+// b_p, read for the open, stay in registers for the finish (each share is
+// read from memory once), and the register arrays stay small for the usual
+// party counts.
+template <int PMAX>
 __global__ void __launch_bounds__(kMpThreads)
     k_mp_beaver_mul(MpIn x, MpIn y, MpIn a, MpIn b, MpIn c, int P, size_t n, int square, MpOut z) {
   for (size_t i = first_index(); i < n; i += grid_stride()) {
+    u64 av[PMAX], bv[PMAX];
     u64 eps = 0, del = 0;
-    for (int p = 0; p < P; ++p) eps += x.p[p][i] - a.p[p][i];
-    if (!square)
-      for (int p = 0; p < P; ++p) del += y.p[p][i] - b.p[p][i];
-    for (int p = 0; p < P; ++p) {
-      u64 v;
-      if (square) v = b.p[p][i] + 2 * eps * a.p[p][i] + (p == 0 ? eps * eps : 0);
-      else v = c.p[p][i] + eps * b.p[p][i] + a.p[p][i] * del + (p == 0 ? eps * del : 0);
-      z.p[p][i] = v;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+      if (p < P) {
+        av[p] = a.p[p][i];
+        eps += x.p[p][i] - av[p];
+      }
+    if (!square) {
+#pragma unroll
+      for (int p = 0; p < PMAX; ++p)
+        if (p < P) {
+          bv[p] = b.p[p][i];
+          del += y.p[p][i] - bv[p];
+        }
     }
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+      if (p < P) {
+        u64 v;
+        if (square) v = b.p[p][i] + 2 * eps * av[p] + (p == 0 ? eps * eps : 0);
+        else v = c.p[p][i] + eps * bv[p] + av[p] * del + (p == 0 ? eps * del : 0);
+        z.p[p][i] = v;
+      }
   }
 }
 
@@ -217,8 +237,11 @@ hipError_t launch_mp_open(hipStream_t s, const MpIn& x, const MpIn& a, int P, si
 hipError_t launch_mp_beaver_mul(hipStream_t s, const MpIn& x, const MpIn& y, const MpIn& a, const MpIn& b,
                                 const MpIn& c, int P, size_t n, int square, const MpOut& z) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_mp_beaver_mul, dim3(grid_for(n)), dim3(kMpThreads), 0, s, x, y, a, b, c, P, n, square,
-                     z);
+  const dim3 grid(grid_for(n)), block(kMpThreads);
+  if (P <= 2) hipLaunchKernelGGL(k_mp_beaver_mul<2>, grid, block, 0, s, x, y, a, b, c, P, n, square, z);
+  else if (P <= 4) hipLaunchKernelGGL(k_mp_beaver_mul<4>, grid, block, 0, s, x, y, a, b, c, P, n, square, z);
+  else if (P <= 8) hipLaunchKernelGGL(k_mp_beaver_mul<8>, grid, block, 0, s, x, y, a, b, c, P, n, square, z);
+  else hipLaunchKernelGGL(k_mp_beaver_mul<kMaxParties>, grid, block, 0, s, x, y, a, b, c, P, n, square, z);
   return hipGetLastError();
 }
 
