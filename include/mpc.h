@@ -350,7 +350,8 @@ typedef struct {
  * issues one GEMM launch per schedule in use.  Under schedules 14 and 15 a
  * regular product's last rows (columns), when they fill at most half of a
  * 64-row (64-column) tile, run as a strip of 32x128 (128x32) tiles beside its
- * 64x64 tiles.  Untuned, every product takes
+ * 64x64 tiles, wherever that issues fewer outputs than the 64x64 tiles
+ * alone.  Untuned, every product takes
  * the default schedule (schedule 14 or 15 as the default: each product in its
  * own class), unless some product is thin and no default was set
  * with mpc_set_default_tile_config: then all of them run in one launch of
@@ -378,6 +379,25 @@ mpc_status mpc_autotune_load(mpc_ctx *ctx, const char *path);
  * or read it back (`ms` reads 0). */
 mpc_status mpc_set_default_tile_config(mpc_ctx *ctx, const mpc_tile_config *cfg);
 mpc_status mpc_get_default_tile_config(const mpc_ctx *ctx, mpc_tile_config *cfg);
+
+/* Host-only planning query (no context, no device work): how the limb GEMM
+ * tiles one product's M x N row-major output under tile schedule `variant`
+ * (0..15, as above).  *cls receives the product's tile class (0 regular,
+ * 1 thin in M, 2 thin in N; the rule above).  `regions` (HOST, room for 4
+ * entries of 6 int64) receives the output rectangles that run as GEMM
+ * problems of their own, each as first row, first column, rows, columns,
+ * tile rows, tile columns, and *count their number: the whole output in the
+ * variant's tile (under 14 and 15 the class's tile), except that under 14
+ * and 15 a regular product with edge strips gives its 64x64 interior, the
+ * strips and their corner.  Every rectangle starts at a multiple of 32 rows
+ * and columns, and its tiles stay inside the packed operands' padded extent
+ * (rows and columns rounded up to a multiple of 128).  `tiles` (may be NULL)
+ * receives the tile count over all regions.  Column-strided outputs (the
+ * convolution's) always run whole.  MPC_E_INVAL for a null output or a
+ * variant outside 0..15, MPC_E_SHAPE for M or N below 1 or M * N beyond the
+ * element limit. */
+mpc_status mpc_limb_plan(int64_t M, int64_t N, int variant, int *cls, int64_t *regions, int *count,
+                         int64_t *tiles);
 
 /* Stream capture of the context's work into a HIP graph: begin, issue calls,
  * end.  Party 0's stream must not be the null stream (MPC_E_INVAL).  The workspace must

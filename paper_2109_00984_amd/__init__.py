@@ -116,6 +116,8 @@ _SIGS = {
     "mpc_set_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
     "mpc_beaver_mul_grouped": (INT, [VP, ctypes.c_size_t, ctypes.POINTER(MulDesc), INT]),
     "mpc_get_default_tile_config": (INT, [VP, ctypes.POINTER(TileConfig)]),
+    "mpc_limb_plan": (INT, [I64, I64, INT, ctypes.POINTER(INT), ctypes.POINTER(I64), ctypes.POINTER(INT),
+                            ctypes.POINTER(I64)]),
     "mpc_graph_begin": (INT, [VP]),
     "mpc_graph_end": (INT, [VP, ctypes.POINTER(VP)]),
     "mpc_graph_launch": (INT, [VP, VP]),
@@ -181,6 +183,18 @@ def decode(v, frac_bits=16):
     out = np.empty(v.shape, dtype=np.float64)
     _check(_lib.mpc_decode(v.ctypes.data, v.size, frac_bits, out.ctypes.data), "mpc_decode")
     return out
+
+
+def limb_plan(M, N, variant):
+    """Host-side planning query: how the limb GEMM tiles an M x N row-major
+    output under tile schedule `variant`.  Returns (tile class, regions,
+    tiles), each region (first row, first column, rows, columns, tile rows,
+    tile columns)."""
+    cls, count, tiles = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    reg = (ctypes.c_int64 * 24)()
+    _check(_lib.mpc_limb_plan(M, N, variant, ctypes.byref(cls), reg, ctypes.byref(count), ctypes.byref(tiles)),
+           "mpc_limb_plan")
+    return cls.value, [tuple(reg[6 * i:6 * i + 6]) for i in range(count.value)], tiles.value
 
 
 # ------------------------------------------------------------------ helpers

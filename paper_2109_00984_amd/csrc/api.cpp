@@ -747,25 +747,33 @@ struct Region {
 // a strip's thin tiles span at most the padded extent of the rest (the
 // 64-aligned part), and the corner's one 64x64 tile ends at most at the
 // padded edge (checked below; otherwise the request is not split).
-std::vector<Region> limb_regions(const LimbReq& r, const TileSched& ts) {
-  const std::vector<Region> whole{Region{0, 0, r.M, r.N, r.cls}};
-  const bool rowmajor = r.ep.view.ld_q == 0 && r.ep.view.n_div >= r.N;
-  if (!limb_per_class(ts.variant) || r.cls != 0 || !rowmajor) return whole;
-  const i64 rm = r.M % 64, rn = r.N % 64;
-  const i64 m64 = (rm > 0 && rm <= 32) ? r.M - rm : r.M;
-  const i64 n64 = (rn > 0 && rn <= 32) ? r.N - rn : r.N;
-  if ((m64 == r.M && n64 == r.N) || m64 == 0 || n64 == 0) return whole;
+std::vector<Region> limb_regions(i64 M, i64 N, int cls, int variant, bool rowmajor) {
+  const std::vector<Region> whole{Region{0, 0, M, N, cls}};
+  if (!limb_per_class(variant) || cls != 0 || !rowmajor) return whole;
+  const i64 rm = M % 64, rn = N % 64;
+  const i64 m64 = (rm > 0 && rm <= 32) ? M - rm : M;
+  const i64 n64 = (rn > 0 && rn <= 32) ? N - rn : N;
+  if ((m64 == M && n64 == N) || m64 == 0 || n64 == 0) return whole;
   std::vector<Region> g{Region{0, 0, m64, n64, 0}};
-  if (m64 < r.M) g.push_back(Region{m64, 0, r.M - m64, n64, 1});
-  if (n64 < r.N) g.push_back(Region{0, n64, m64, r.N - n64, 2});
-  if (m64 < r.M && n64 < r.N) g.push_back(Region{m64, n64, r.M - m64, r.N - n64, 0});
-  const i64 rows = limb_rblocks(r.M) * 32, cols = limb_rblocks(r.N) * 32;
+  if (m64 < M) g.push_back(Region{m64, 0, M - m64, n64, 1});
+  if (n64 < N) g.push_back(Region{0, n64, m64, N - n64, 2});
+  if (m64 < M && n64 < N) g.push_back(Region{m64, n64, M - m64, N - n64, 0});
+  const i64 rows = limb_rblocks(M) * 32, cols = limb_rblocks(N) * 32;
+  i64 issued = 0;
   for (const Region& x : g) {
     int bm = 0, bn = 0;
     limb_class_shape(x.cls, &bm, &bn);
-    if (x.r0 + (x.m + bm - 1) / bm * bm > rows || x.c0 + (x.n + bn - 1) / bn * bn > cols) return whole;
+    const i64 tm = (x.m + bm - 1) / bm * bm, tn = (x.n + bn - 1) / bn * bn;
+    if (x.r0 + tm > rows || x.c0 + tn > cols) return whole;
+    issued += tm * tn;
   }
-  return g;
+  // a strip beside at most 64 rows (columns) of interior issues as much as
+  // the 64x64 tiles it replaces, in thinner tiles: keep the split only where
+  // it issues less
+  return issued < (M + 63) / 64 * 64 * ((N + 63) / 64 * 64) ? g : whole;
+}
+std::vector<Region> limb_regions(const LimbReq& r, const TileSched& ts) {
+  return limb_regions(r.M, r.N, r.cls, ts.variant, r.ep.view.ld_q == 0 && r.ep.view.n_div >= r.N);
 }
 
 // One pack launch over all jobs, then one GEMM launch per K chunk (a problem
@@ -2233,6 +2241,26 @@ mpc_status mpc_set_default_tile_config(mpc_ctx* c, const mpc_tile_config* cfg) {
   c->sched_default = TileSched{cfg->variant, cfg->group_m, cfg->xcd_remap ? 1 : 0};
   // an explicit schedule applies to thin products too
   c->class_tiles = false;
+  return MPC_OK;
+}
+
+mpc_status mpc_limb_plan(int64_t M, int64_t N, int variant, int* cls, int64_t* regions, int* count,
+                         int64_t* tiles) {
+  if (!cls || !regions || !count || variant < 0 || variant >= kLimbVariants) return MPC_E_INVAL;
+  if (M < 1 || N < 1 || !count_ok(M, N)) return MPC_E_SHAPE;
+  *cls = bucket_of(M, N);
+  const bool per_class = limb_per_class(variant);
+  const std::vector<Region> g = limb_regions(M, N, per_class ? *cls : 0, variant, true);
+  i64 nt = 0;
+  for (size_t i = 0; i < g.size(); ++i) {
+    int bm = limb_variant_bm(variant), bn = limb_variant_bn(variant);
+    if (per_class) limb_class_shape(g[i].cls, &bm, &bn);
+    const int64_t row[6] = {g[i].r0, g[i].c0, g[i].m, g[i].n, bm, bn};
+    for (int k = 0; k < 6; ++k) regions[6 * i + k] = row[k];
+    nt += ((g[i].m + bm - 1) / bm) * ((g[i].n + bn - 1) / bn);
+  }
+  *count = (int)g.size();
+  if (tiles) *tiles = nt;
   return MPC_OK;
 }
 
