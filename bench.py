@@ -523,6 +523,11 @@ def ring_gemm_forms(ctx, torch, X, Y):
         _event_time(torch, ctx.streams[0], lambda: ctx.dealer_into(mpc.TRIPLE_MATMUL, 93, 94, (M, N, K), tp), 3), 4)
     ex["dealer_matmul_4096_packed_ms"] = round(
         _event_time(torch, ctx.streams[0], lambda: ctx._dealer_packed_into(93, 94, (M, N, K), tp, packed), 3), 4)
+    # the Beaver matmul's own rate: 2 M N K ring operations over the online
+    # time (open, both parties' finish, truncation), the dealer apart
+    for key in ("online", "prepacked_online"):
+        ex[f"beaver_matmul_4096_{key}_tops"] = round(
+            2.0 * M * N * K / (ex[f"beaver_matmul_4096_{key}_ms"] * 1e-3) / 1e12, 3)
     log(f"bench: Beaver matmul 4096^3 online {ex['beaver_matmul_4096_online_ms']} ms, over a prepacked triple "
         f"{ex['beaver_matmul_4096_prepacked_online_ms']} ms; dealer {ex['dealer_matmul_4096_ms']} ms, with packing "
         f"{ex['dealer_matmul_4096_packed_ms']} ms")
