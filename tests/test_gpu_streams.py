@@ -88,3 +88,48 @@ def test_truncate_then_slow_reader_on_party1(m):
         finally:
             c.close()
     assert np.array_equal(got1, want1)
+
+
+def test_randomized_delays(m):
+    """Seeded random schedules around the hand-off: slow work of random length
+    on each party's stream, random host sleeps between enqueueing it and the
+    call, party 1's share written on either stream and read back on either
+    stream, ragged sizes.  Only stream order connects the steps."""
+    import time
+    g = workloads.rng(2109)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = m.Context(device=0, seed=7)
+        try:
+            for trial in range(8):
+                n = int(g.choice([1, 4097, (1 << 20) + 3, N]))
+                b0, b1 = int(g.integers(0, 4)), int(g.integers(0, 4))
+                w1, r1 = int(g.integers(0, 2)), int(g.integers(0, 2))
+                sleep_ms = float(g.uniform(0, 3))
+                say(f"streams: trial {trial} n={n} busy=({b0},{b1}) writer1={w1} reader1={r1} sleep={sleep_ms:.1f}ms")
+                s0h, s1h = workloads.uniform_u64(60 + 2 * trial, (n,)), workloads.uniform_u64(61 + 2 * trial, (n,))
+                src0, src1 = dev(s0h), dev(s1h)
+                s0, s1 = torch.zeros_like(src0), torch.zeros_like(src1)
+                torch.cuda.synchronize()
+                p0, p1 = c.streams
+                p0.wait_stream(side)
+                p1.wait_stream(side)
+                with torch.cuda.stream(p0):
+                    for _ in range(b0):
+                        busy(c.device)
+                    s0.copy_(src0)
+                with torch.cuda.stream(c.streams[w1]):
+                    for _ in range(b1):
+                        busy(c.device)
+                    s1.copy_(src1)
+                time.sleep(sleep_ms / 1e3)
+                c.truncate(m.SharedPair(s0, s1), BITS)
+                with torch.cuda.stream(p0):
+                    got0 = s0.clone()
+                with torch.cuda.stream(c.streams[r1]):
+                    got1 = s1.clone()
+                torch.cuda.synchronize()
+                assert np.array_equal(got0.cpu().numpy().view(np.uint64), oracle.truncate(s0h, BITS)), trial
+                assert np.array_equal(got1.cpu().numpy().view(np.uint64), oracle.truncate(s1h, BITS)), trial
+        finally:
+            c.close()
