@@ -584,29 +584,65 @@ __device__ __forceinline__ void store_tile(v4i (&acc)[HA][HB][8], cptr<LimbProbl
 #pragma unroll
       for (int y = 0; y < HB; ++y) asm volatile("s_nop 3" : "+a"(acc[x][y][s]));
   const Epilogue ep = pp->ep;
+  // Three passes over this lane's outputs: combine the limb diagonals, load
+  // every added term (the triple share, the previous K chunk's sum), then add,
+  // truncate and store.  With no store between them the loads are in flight
+  // together; interleaved with the stores, each would wait for the one before
+  // (the compiler cannot tell the output from the added terms).
+  u64 v[HB][HA][4];
+  i64 off[HB][HA][4];
+  bool ok[HB][HA][4];
 #pragma unroll
   for (int y = 0; y < HB; ++y) {
     const i64 n = tn * BN + wc * 16 * HB + y * 16 + (lane & 15);
     const bool n_ok = n < pp->N;
     const i64 coff = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
 #pragma unroll
-    for (int x = 0; x < HA; ++x) {
+    for (int x = 0; x < HA; ++x)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const i64 m = tm * BM + wr * 16 * HA + x * 16 + 4 * (lane >> 4) + e;
-        u64 v = 0;
+        u64 s8 = 0;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v += (u64)(i64)acc[x][y][s][e] << (8 * s);
-        if (n_ok && m < pp->M) {
-          const i64 off = m * ep.view.ld_m + coff;
-          if (ep.accumulate) v += ep.Out[off];
-          if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
-          if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
-          ep.Out[off] = v;
-        }
+        for (int s = 0; s < 8; ++s) s8 += (u64)(i64)acc[x][y][s][e] << (8 * s);
+        v[y][x][e] = s8;
+        ok[y][x][e] = n_ok && m < pp->M;
+        off[y][x][e] = m * ep.view.ld_m + coff;
       }
-    }
   }
+  // The loads are unconditional (no branch around each one): a lane whose
+  // output lies past the product's edge reads the product's first element,
+  // which exists, and masks it to nothing.
+  if (ep.accumulate) {
+#pragma unroll
+    for (int y = 0; y < HB; ++y)
+#pragma unroll
+      for (int x = 0; x < HA; ++x)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const u64 o = ep.Out[ok[y][x][e] ? off[y][x][e] : 0];
+          v[y][x][e] += o & (u64)0 - (u64)ok[y][x][e];
+        }
+  }
+  if (ep.Cadd) {
+    const u64 neg = ep.csign < 0 ? ~(u64)0 : 0;  // -c as (c ^ ~0) + 1
+#pragma unroll
+    for (int y = 0; y < HB; ++y)
+#pragma unroll
+      for (int x = 0; x < HA; ++x)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const u64 c = ep.Cadd[ok[y][x][e] ? off[y][x][e] : 0];
+          v[y][x][e] += ((c ^ neg) + (neg & 1)) & (u64)0 - (u64)ok[y][x][e];
+        }
+  }
+#pragma unroll
+  for (int y = 0; y < HB; ++y)
+#pragma unroll
+    for (int x = 0; x < HA; ++x)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (ok[y][x][e]) ep.Out[off[y][x][e]] = ep.trunc_bits ? (u64)((i64)v[y][x][e] >> ep.trunc_bits) : v[y][x][e];
 }
 
 // GEMM over a tile list.  Each wave streams its fragments straight from
