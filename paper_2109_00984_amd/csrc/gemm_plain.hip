@@ -51,7 +51,7 @@ __device__ __forceinline__ u64 load_b(const PlainProblem& p, i64 k, i64 n) {
   return 0;
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 2)
     k_plain_gemm(const PlainProblem* __restrict__ probs, TileMap map) {
   __shared__ u64 As[BK][BM];
   __shared__ u64 Bs[BK][BN];
@@ -143,21 +143,42 @@ __global__ void __launch_bounds__(kThreads)
     const i64 n = n0 + tx + 16 * j;
     coff[j] = (n / ep.view.n_div) * ep.view.ld_q + (n % ep.view.n_div);
   }
+  // Every added term is loaded before any store, unconditionally (a thread
+  // past the product's edge reads its first element, and stores nothing): with
+  // a store between two loads, each load would wait for the store before it,
+  // since the compiler cannot tell the output from the added terms.  Four
+  // rows (16 outputs) at a time, to stay within the registers of two
+  // workgroups per compute unit.
+  auto ok = [&](int i, int j) { return m0 + ty + 16 * i < p.M && n0 + tx + 16 * j < p.N; };
+  auto at = [&](int i, int j) { return ok(i, j) ? (m0 + ty + 16 * i) * ep.view.ld_m + coff[j] : (i64)0; };
+  const u64 neg = ep.csign < 0 ? ~(u64)0 : 0;  // -c as (c ^ ~0) + 1
+  constexpr int kRows = 4;
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    const i64 m = m0 + ty + 16 * i;
-    if (m >= p.M) continue;
+  for (int i0 = 0; i0 < TM; i0 += kRows) {
+    u64 v[kRows][TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const i64 n = n0 + tx + 16 * j;
-      if (n >= p.N) continue;
-      const i64 off = m * ep.view.ld_m + coff[j];
-      u64 v = lo[i][j] + ((u64)cr[i][j] << 32);
-      if (ep.accumulate) v += ep.Out[off];
-      if (ep.Cadd) v += (ep.csign < 0) ? (u64)0 - ep.Cadd[off] : ep.Cadd[off];
-      if (ep.trunc_bits) v = (u64)((i64)v >> ep.trunc_bits);
-      ep.Out[off] = v;
+    for (int i = 0; i < kRows; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) v[i][j] = lo[i0 + i][j] + ((u64)cr[i0 + i][j] << 32);
+    if (ep.accumulate) {
+#pragma unroll
+      for (int i = 0; i < kRows; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) v[i][j] += ep.Out[at(i0 + i, j)];
     }
+    if (ep.Cadd) {
+#pragma unroll
+      for (int i = 0; i < kRows; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          v[i][j] += (ep.Cadd[at(i0 + i, j)] ^ neg) + (neg & 1);
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (ok(i0 + i, j))
+          ep.Out[at(i0 + i, j)] = ep.trunc_bits ? (u64)((i64)v[i][j] >> ep.trunc_bits) : v[i][j];
   }
 }
 
