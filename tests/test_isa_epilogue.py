@@ -20,7 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # kernels whose lanes own 16 outputs (every limb GEMM but the 128x64 and
 # 64x128 tiles at one workgroup per compute unit, whose lanes own 32)
-KERNELS = ("k_limb_gemm_ldsILi2ELi2E", "k_limb_gemm_ldsILi1ELi4E", "k_limb_gemm_ldsILi4ELi1E",
+KERNELS = ("k_limb_gemmILi1ELi1E", "k_limb_gemm_ldsILi2ELi2E", "k_limb_gemm_ldsILi1ELi4E", "k_limb_gemm_ldsILi4ELi1E",
            "k_limb_gemm_sh", "k_limb_gemm_classes", "k_limb_gemm_persist")
 
 
@@ -53,10 +53,11 @@ def test_epilogue_loads_in_flight_together(tmp_path):
            os.path.join(b.CSRC, "gemm_limb.hip"), "-o", str(asm)]
     subprocess.run(cmd, check=True, capture_output=True)
     st = serial_loads(asm.read_text(), KERNELS)
-    # six LDS-staged forms (schedules 5 to 8, 12 and 13: the 64x64 tile, the
-    # three eight-wave tiles, the two thin tiles), the three both-in-LDS forms
-    # (9 to 11), the classes kernel and its persistent form
-    assert len(st) == 11, sorted(st)
+    # the direct 64x64 tile (schedule 2), six LDS-staged forms (schedules 5 to
+    # 8, 12 and 13: the 64x64 tile, the three eight-wave tiles, the two thin
+    # tiles), the three both-in-LDS forms (9 to 11), the classes kernel and
+    # its persistent form
+    assert len(st) == 12, sorted(st)
     for k, (loads, serial) in st.items():
         assert loads >= 32, (k, loads)  # the two groups of 16 added-term loads
         assert serial == 0, (k, loads, serial)
