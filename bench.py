@@ -757,11 +757,13 @@ def conv_bench(mpc, torch, workloads, cpu=True):
     c = mpc.Context(device=0, seed=pseed)
     dv = lambda a: torch.from_numpy(a).to(c.device)
     X = mpc.encode(workloads.uniform(data_seed, (cfg["batch"], cfg["channels"], cfg["length"]), cfg["lo"], cfg["hi"]), FRAC)
-    x0 = c.share(dv(X), 0, 1)
-    ws, ts, ps = [], [], []
+    Xd = dv(X)
+    x0 = c.share(Xd, 0, 1)
+    ws, ts, ps, Wd = [], [], [], []
     for i, (b, cin, L, cout, k, s, lout) in enumerate(layers):
         W = mpc.encode(workloads.uniform(data_seed + 100 + i, (cout, cin, k), cfg["lo"], cfg["hi"]), FRAC)
-        ws.append(c.share(dv(W), 1, 20 + i))
+        Wd.append(dv(W))
+        ws.append(c.share(Wd[-1], 1, 20 + i))
         ts.append(c.dealer(mpc.TRIPLE_CONV1D, dseed, 40 + i, (b, cin, L, cout, k, s)))
         if i < len(layers) - 1:
             ps.append(c.dealer(mpc.TRIPLE_SQUARE, dseed, 60 + i, (b * cout * lout,)))
@@ -790,6 +792,23 @@ def conv_bench(mpc, torch, workloads, cpu=True):
         out[f"conv_stack_{form}_ms"] = round(ms, 3)
         out[f"conv_stack_{form}_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
         log(f"bench: conv stack {form}: {ms:.3f} ms")
+    # the CPU sample's scope on the GPU: share the input and the weights, deal
+    # every triple, then the online phase (limb form), into the same buffers
+    def whole():
+        c.share(Xd, 0, 1, out=x0)
+        for i, (b, cin, L, cout, k, s, lout) in enumerate(layers):
+            c.share(Wd[i], 1, 20 + i, out=ws[i])
+            c.dealer_into(mpc.TRIPLE_CONV1D, dseed, 40 + i, (b, cin, L, cout, k, s), ts[i])
+            if i < len(layers) - 1:
+                c.dealer_into(mpc.TRIPLE_SQUARE, dseed, 60 + i, (b * cout * lout,), ps[i])
+        return forward("limb8")
+    h = whole()
+    c.sync()
+    same = same and all(np.array_equal(a.cpu().numpy().view(np.uint64), b) for a, b in zip((h.s0, h.s1), first))
+    ms = _event_time(torch, c.streams[0], whole, 3)
+    out["conv_stack_limb8_with_dealer_ms"] = round(ms, 3)
+    out["conv_stack_limb8_with_dealer_tops"] = round(2.0 * macs / (ms * 1e-3) / 1e12, 3)
+    log(f"bench: conv stack limb8 with sharing and dealer: {ms:.3f} ms")
     out["conv_stack_forms_bit_identical"] = bool(same)
     out["conv_stack_limb_over_plain_speedup"] = round(out["conv_stack_plain_ms"] / out["conv_stack_limb8_ms"], 2)
     out["conv_stack_limb_over_fp64limb_speedup"] = round(out["conv_stack_fp64limb_ms"] / out["conv_stack_limb8_ms"], 2)
