@@ -9,15 +9,8 @@ term before any store instead; this test compiles gemm_limb.hip for gfx950
 with the library's own flags and checks that no 8-byte global load in the
 kernels whose lanes own 16 outputs is followed at once by a full wait.  (No
 GPU needed; skipped where hipcc is absent.)"""
-import importlib.util
-import os
 import re
-import shutil
-import subprocess
 
-import pytest
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # kernels whose lanes own 16 outputs (every limb GEMM but the 128x64 and
 # 64x128 tiles at one workgroup per compute unit, whose lanes own 32)
 KERNELS = ("k_limb_gemmILi1ELi1E", "k_limb_gemm_ldsILi2ELi2E", "k_limb_gemm_ldsILi1ELi4E", "k_limb_gemm_ldsILi4ELi1E",
@@ -43,16 +36,8 @@ def serial_loads(asm, names):
     return out
 
 
-@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
-def test_epilogue_loads_in_flight_together(tmp_path):
-    spec = importlib.util.spec_from_file_location("mpc_build", os.path.join(ROOT, "paper_2109_00984_amd", "build.py"))
-    b = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(b)
-    asm = tmp_path / "gemm_limb.s"
-    cmd = ["hipcc", *[f for f in b.FLAGS if f != "-fPIC"], "-x", "hip", "--cuda-device-only", "-S",
-           os.path.join(b.CSRC, "gemm_limb.hip"), "-o", str(asm)]
-    subprocess.run(cmd, check=True, capture_output=True)
-    st = serial_loads(asm.read_text(), KERNELS)
+def test_epilogue_loads_in_flight_together(limb_gemm_asm):
+    st = serial_loads(limb_gemm_asm, KERNELS)
     # the direct 64x64 tile (schedule 2), six LDS-staged forms (schedules 5 to
     # 8, 12 and 13: the 64x64 tile, the three eight-wave tiles, the two thin
     # tiles), the three both-in-LDS forms (9 to 11), the classes kernel and

@@ -9,22 +9,7 @@ only if at least that many register loads follow the step's last copy in the
 machine code.  The compiler's scheduling decides the final order, so this
 test compiles the kernel for gfx950 with the library's own flags and checks
 every hand-over.  (No GPU needed; skipped where hipcc is absent.)"""
-import importlib.util
-import os
 import re
-import shutil
-import subprocess
-
-import pytest
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-
-
-def build_module():
-    spec = importlib.util.spec_from_file_location("mpc_build", os.path.join(ROOT, "paper_2109_00984_amd", "build.py"))
-    mod = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mod)
-    return mod
 
 
 KERNELS = ("k_limb_gemm_lds", "k_limb_gemm_classes", "k_limb_gemm_persist")
@@ -57,14 +42,8 @@ def handovers(asm):
     return out
 
 
-@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
-def test_lds_handover_waits_cover_the_copies(tmp_path):
-    b = build_module()
-    asm = tmp_path / "gemm_limb.s"
-    cmd = ["hipcc", *[f for f in b.FLAGS if f != "-fPIC"], "-x", "hip", "--cuda-device-only", "-S",
-           os.path.join(b.CSRC, "gemm_limb.hip"), "-o", str(asm)]
-    subprocess.run(cmd, check=True, capture_output=True)
-    hs = handovers(asm.read_text())
+def test_lds_handover_waits_cover_the_copies(limb_gemm_asm):
+    hs = handovers(limb_gemm_asm)
     kernels = {h[0] for h in hs}
     # the eight LDS geometries (two of them thin), the classes kernel and its
     # persistent form
