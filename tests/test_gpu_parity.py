@@ -565,6 +565,33 @@ def test_grouped_tile_classes(m):
     c.close()
 
 
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+def test_grouped_with_empty_products(m, form):
+    # a grouped call holding products with no rows, no columns, or no k beside
+    # a tiny one and ones whose edges run as strips: the empty ones do
+    # nothing (their outputs are left as they were), the others give the
+    # oracle's result, under the default and both classes schedules
+    say(f"grouped with empty products ({form})")
+    c = m.Context(device=0, seed=SEED)
+    shapes = [(0, 17, 40), (33, 0, 40), (1, 1, 1), (200, 136, 70), (33, 17, 0), (520, 65, 96), (0, 0, 0)]
+    probs, wants = [], []
+    for i, (M, N, K) in enumerate(shapes):
+        X, Y = rnd(80 + 2 * i, (M, K)), rnd(81 + 2 * i, (K, N))
+        probs.append((c.share(dev(X), 0, 90 + 2 * i), c.share(dev(Y), 1, 91 + 2 * i),
+                      c.dealer(m.TRIPLE_MATMUL, 9, i, (M, N, K))))
+        wants.append(oracle.beaver_matmul(oracle.share(X, 0, SEED, 90 + 2 * i), oracle.share(Y, 1, SEED, 91 + 2 * i),
+                                          oracle.dealer_matmul(9, i, M, N, K), 16))
+    for explicit in ([None, 14, 15] if form == "limb8" else [None]):
+        if explicit is not None:
+            c.set_default_tile_config(explicit, 8, True)
+        zs = c.beaver_matmul_grouped(probs, 16, form)
+        for (M, N, K), z, w in zip(shapes, zs, wants):
+            assert z.s0.shape == (M, N)
+            got = pair(c, z)
+            assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1]), (form, explicit, (M, N, K))
+    c.close()
+
+
 # ------------------------------------------------------------------ plain split-K
 @pytest.mark.parametrize("form", ["plain", "limb8"])
 @pytest.mark.parametrize("M,N,K", [(5, 7, 5000), (128, 10, 2048), (1, 1, 3000), (130, 70, 777),
