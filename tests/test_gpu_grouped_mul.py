@@ -76,6 +76,33 @@ def test_grouped_mul_matches_oracle_and_single_calls(m):
     c.close()
 
 
+def test_grouped_mul_with_empty_products(m):
+    # zero-length products and squares beside ordinary ones: they do nothing
+    # and take no open; the others give the oracle's result
+    say("grouped beaver mul: empty products")
+    c = m.Context(device=0, seed=SEED)
+    cases = [(0, False, False), (5, True, False), (0, True, True), (CHUNK + 3, False, True), (0, False, False)]
+    probs, outs, wants = [], [], []
+    for i, (n, sq, view) in enumerate(cases):
+        p, o, w = make_problem(m, c, 40 + i, n, sq, view)
+        probs.append(p)
+        outs.append(o)
+        wants.append(w)
+    before = c.stats()
+    zs = c.beaver_mul_grouped(probs, 16, outs=outs)
+    after = c.stats()
+    assert after["opens"] - before["opens"] == sum(1 for n, _, _ in cases if n)
+    assert after["launches"] - before["launches"] == 1
+    for (n, sq, view), z, w in zip(cases, zs, wants):
+        g0, g1 = pair(c, z)
+        assert g0.size == n and np.array_equal(g0, w[0]) and np.array_equal(g1, w[1]), (n, sq, view)
+    # all empty: nothing is launched
+    before = c.stats()
+    c.beaver_mul_grouped([probs[0], probs[2]], 16, outs=[outs[0], outs[2]])
+    assert c.stats()["launches"] == before["launches"]
+    c.close()
+
+
 def test_grouped_mul_graph_replay(m):
     say("grouped beaver mul: graph replay")
     side = torch.cuda.Stream()
