@@ -129,3 +129,22 @@ def test_binary_rounds_and_errors(m, ctx):
     t = ctx.dealer_and(1, 2, 12 * n)
     ctx.a2b(ctx.share(x, 0, 2), 3, t)
     assert ctx.stats()["opens"] - before == 7
+
+
+def test_binary_empty_inputs(m, ctx):
+    # n = 0 through every binary call: nothing is launched and nothing opened
+    say("binary empty inputs")
+    e = dev(np.zeros(0, np.uint64))
+    before = ctx.stats()
+    s = ctx.bin_share(e, 0, 1)
+    assert ctx.bin_reveal(s).numel() == 0
+    t = ctx.dealer_and(1, 2, 0)
+    assert ctx.bin_and(s, s, t).s0.numel() == 0
+    a = ctx.share(e, 0, 2)
+    assert ctx.a2b(a, 3, t).s0.numel() == 0
+    rb, ra = ctx.dealer_b2a(1, 4, 0)
+    assert ctx.b2a_bit(s, 0, rb, ra).s0.numel() == 0
+    tm = ctx.dealer(m.TRIPLE_MUL, 1, 5, (0,))
+    assert ctx.relu(a, 6, t, rb, ra, tm).s0.numel() == 0
+    after = ctx.stats()
+    assert after["opens"] == before["opens"] and after["launches"] == before["launches"]

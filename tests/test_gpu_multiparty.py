@@ -195,3 +195,28 @@ def test_mp_errors_and_counters(m, ctx):
     after = ctx.stats()
     assert after["opens"] - before["opens"] == 2
     assert after["truncations"] - before["truncations"] == 1
+
+
+def test_mp_empty_inputs(m, ctx):
+    # n = 0 and matrix products with no rows, no columns or no k among three
+    # parties: the empty calls do nothing; k = 0 leaves each party its c share
+    P = 3
+    say("mp empty inputs")
+    e = np.zeros(0, np.uint64)
+    s = ctx.mp_share(dev(e), P, 0, 7)
+    assert all(v.numel() == 0 for v in s.shares) and ctx.mp_reveal(s).numel() == 0
+    t = ctx.mp_dealer(P, m.TRIPLE_MUL, 31, 30, (0,))
+    assert ctx.mp_beaver_mul(s, s, t).shares[0].numel() == 0
+    r, th = ctx.mp_dealer_trunc(P, 31, 31, 0)
+    ctx.mp_truncate(s, 16, r, th)
+    for i, (M, N, K) in enumerate([(0, 5, 3), (4, 0, 3), (4, 5, 0)]):
+        xs = [workloads.uniform_u64(500 + p, (M, K)) for p in range(P)]
+        ys = [workloads.uniform_u64(600 + p, (K, N)) for p in range(P)]
+        t = ctx.mp_dealer(P, m.TRIPLE_MATMUL, 37, 40 + i, (M, N, K))
+        w = oracle.mp_dealer_matmul(37, 40 + i, P, M, N, K)
+        same(ctx, t.a, w.a, f"a {M}x{N}x{K}")
+        same(ctx, t.b, w.b, f"b {M}x{N}x{K}")
+        same(ctx, t.c, w.c, f"c {M}x{N}x{K}")
+        for form in ("plain", "limb8"):
+            z = ctx.mp_beaver_matmul(to_dev_shared(m, xs), to_dev_shared(m, ys), t, form)
+            same(ctx, z, oracle.mp_beaver_matmul(xs, ys, w), f"beaver matmul {form} {M}x{N}x{K}")
