@@ -357,7 +357,10 @@ def test_round_counters(m, ctx):
 
 # ------------------------------------------------------------------ conv1d
 CONV_SMALL = [(2, 3, 17, 4, 5, 2), (1, 40, 100, 16, 48, 2), (2, 8, 30, 8, 7, 1),
-              (1, 16, 40, 32, 1, 1), (4, 16, 300, 64, 7, 1)]
+              (1, 16, 40, 32, 1, 1), (4, 16, 300, 64, 7, 1),
+              # shorter than the kernel (no output), as long (one output
+              # position), stride 3 with a ragged tail, one channel in and out
+              (2, 3, 4, 5, 7, 1), (3, 2, 9, 5, 9, 1), (2, 5, 50, 3, 4, 3), (1, 1, 64, 1, 3, 2)]
 
 
 @pytest.mark.parametrize("form", ["plain", "limb8", "fp64limb"])
