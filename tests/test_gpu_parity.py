@@ -298,6 +298,21 @@ def test_beaver_matmul(m, ctx, form, M, N, K, trunc):
     assert_pair(ctx, z, want, "beaver matmul")
 
 
+@pytest.mark.parametrize("form", ["plain", "limb8"])
+@pytest.mark.parametrize("trunc", [1, 63])
+def test_beaver_matmul_truncation_extremes(m, ctx, form, trunc):
+    # the fused truncation at its narrowest and widest shifts, on uniform ring
+    # operands (every output's sign bit in play), split-K and one-launch sizes
+    for (M, N, K) in [(130, 70, 300), (5, 7, 3000)]:
+        say(f"beaver matmul {form} {M}x{N}x{K} trunc={trunc}")
+        X, Y = rnd(M + 7, (M, K)), rnd(N + 9, (K, N))
+        t = ctx.dealer(m.TRIPLE_MATMUL, 3011, 44, (M, N, K))
+        z = ctx.beaver_matmul(ctx.share(dev(X), 0, 45), ctx.share(dev(Y), 1, 46), t, trunc, form)
+        want = oracle.beaver_matmul(oracle.share(X, 0, SEED, 45), oracle.share(Y, 1, SEED, 46),
+                                    oracle.dealer_matmul(3011, 44, M, N, K), trunc)
+        assert_pair(ctx, z, want, f"beaver matmul trunc={trunc}")
+
+
 @pytest.mark.parametrize("M,N,K", [(4096, 64, 1), (3, 5, 7), (2, 3, 1024), (64, 32, 128), (33, 7, 1000)])
 @pytest.mark.parametrize("trunc", [0, 16])
 def test_small_beaver_matmul_one_launch(m, ctx, M, N, K, trunc):
