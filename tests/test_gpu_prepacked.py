@@ -49,7 +49,10 @@ def test_prepacked_matmul_matches_oracle(m, M, N, K, trunc):
 def test_prepacked_grouped_matches_oracle(m):
     say("prepacked grouped Beaver matmul")
     c = m.Context(device=0, seed=SEED)
-    shapes = [(300, 120, 500), (17, 200, 300), (150, 20, 260), (40, 600, 64), (9, 5, 70)]
+    # thin in M, thin in N, and two regular products whose edges run as
+    # strips (region offsets into the dealer's packed blocks)
+    shapes = [(300, 120, 500), (17, 200, 300), (150, 20, 260), (40, 600, 64), (9, 5, 70), (200, 136, 70),
+              (520, 65, 96)]
     probs, wants = [], []
     for i, (M, N, K) in enumerate(shapes):
         X, Y = rnd(100 + 2 * i, (M, K)), rnd(101 + 2 * i, (K, N))
@@ -57,10 +60,13 @@ def test_prepacked_grouped_matches_oracle(m):
         probs.append((c.share(dev(X), 0, 60 + 2 * i), c.share(dev(Y), 1, 61 + 2 * i), t, packed))
         wants.append(oracle.beaver_matmul(oracle.share(X, 0, SEED, 60 + 2 * i), oracle.share(Y, 1, SEED, 61 + 2 * i),
                                           oracle.dealer_matmul(DSEED, 50 + i, M, N, K), 16))
-    zs = c.beaver_matmul_grouped_prepacked(probs, 16)
-    for z, w in zip(zs, wants):
-        got = pair(c, z)
-        assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1])
+    for explicit in [None, 14, 15]:
+        if explicit is not None:
+            c.set_default_tile_config(explicit, 8, True)
+        zs = c.beaver_matmul_grouped_prepacked(probs, 16)
+        for (M, N, K), z, w in zip(shapes, zs, wants):
+            got = pair(c, z)
+            assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1]), (explicit, (M, N, K))
     c.close()
 
 
