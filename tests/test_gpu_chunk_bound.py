@@ -102,3 +102,27 @@ def test_beaver_matmul_worst_limbs(m, ctx, M, N, K):
     c_at = (cc[0][rows, cols], cc[1][rows, cols])
     want = oracle.beaver_matmul_at(x, y, a, b, c_at, 16, rows, cols)
     assert np.array_equal(got[0][rows, cols], want[0]) and np.array_equal(got[1][rows, cols], want[1])
+
+
+@pytest.mark.parametrize("sched", [14, 15])
+def test_ring_gemm_chunked_with_edge_strips(m, sched):
+    # the classes schedules split a product whose last rows and columns fill
+    # at most half a 64-wide tile into a 64x64 interior, two strips and a
+    # corner; with k past the chunk bound each region adds its second chunk
+    # into its own part of the output: every limb -128 gives the closed form
+    # at every output, strips and corner included
+    M, N, K = 2056, 2056, BOUND + 1
+    say(f"chunk bound with edge strips: schedule {sched}, ring GEMM {M}x{N}x{K}")
+    assert len(m.limb_plan(M, N, sched)[1]) == 4
+    c = m.Context(device=0, seed=79)
+    try:
+        c.set_default_tile_config(sched, 8, True)
+        A = torch.full((M, K), int(NEG.view(np.int64)), dtype=torch.int64, device=c.device)
+        B = torch.full((K, N), int(NEG.view(np.int64)), dtype=torch.int64, device=c.device)
+        c.profile(True)
+        c.profile_read()
+        C = host(c, c.ring_gemm(A, B, "limb8"))
+        assert c.profile_read()["limb8"]["launches"] == 2  # the two k chunks, one launch each
+        assert (C == closed_form(K, NEG, NEG)).all()
+    finally:
+        c.close()
