@@ -3,7 +3,8 @@
 // C = [A0 (+A0add) | A1] @ [B0 (+B0add) ; B1] mod 2^64 for a list of problems
 // in one launch.  A 256-thread workgroup computes a 128x64 tile; each thread
 // owns an 8x4 register block.  Operand tiles of 16 k are staged through LDS
-// (the left tile stored k-major) with the next tile prefetched into registers.
+// (the left tile stored k-major) with the next tile prefetched into registers;
+// the LDS tiles are double-buffered, so one barrier per step hands them over.
 //
 // One ring multiply-accumulate a*b on 32-bit halves a = aL + 2^32 aH,
 // b = bL + 2^32 bH:  a*b = aL*bL + 2^32 (aL*bH + aH*bL)  (mod 2^64).  The full
@@ -53,8 +54,10 @@ __device__ __forceinline__ u64 load_b(const PlainProblem& p, i64 k, i64 n) {
 
 __global__ void __launch_bounds__(kThreads, 2)
     k_plain_gemm(const PlainProblem* __restrict__ probs, TileMap map) {
-  __shared__ u64 As[BK][BM];
-  __shared__ u64 Bs[BK][BN];
+  // two buffers: a step computes from one while the next step's tiles are
+  // stored into the other, so one barrier per step hands them over
+  __shared__ u64 As[2][BK][BM];
+  __shared__ u64 Bs[2][BK][BN];
 
   const int t = blockIdx.x;
   const int pi = find_problem(map.tile_start, map.nprob, t);
@@ -92,22 +95,31 @@ __global__ void __launch_bounds__(kThreads, 2)
       cr[i][j] = 0;
     }
 
-  if (kbeg < Ktot) fetch(kbeg);
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[buf][la_k + q][la_row] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[buf][lb_k][lb_n + q] = rb[q];
+  };
+  if (kbeg < Ktot) {
+    fetch(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
   for (i64 k0 = kbeg; k0 < Ktot; k0 += BK) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) As[la_k + q][la_row] = ra[q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Bs[lb_k][lb_n + q] = rb[q];
-    __syncthreads();
-    if (k0 + BK < Ktot) fetch(k0 + BK);
+    // the next step's loads go out first and land during this step's
+    // multiply-adds; they are then stored into the other buffer, which every
+    // thread finished reading before the previous barrier
+    const bool more = k0 + BK < Ktot;
+    if (more) fetch(k0 + BK);
 #pragma unroll 4
     for (int kk = 0; kk < BK; ++kk) {
       u64 a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][kk][ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][kk][tx + 16 * j];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const u32 al = (u32)a[i], ah = (u32)(a[i] >> 32);
@@ -119,6 +131,9 @@ __global__ void __launch_bounds__(kThreads, 2)
         }
       }
     }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
 
   if (p.ksplit > 1) {
